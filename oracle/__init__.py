@@ -1,0 +1,356 @@
+"""FP64 CPU oracle of the aperture-block VP transport.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this package.  The HIP
+product library never calls it and shares no code with it; the two meet only
+through the seeded case objects of ``paper_2307_01416_amd.inputs``.
+
+Parity status of each function is listed in ``PINS`` below; the tests under
+``tests/test_oracle_*.py`` (``-m "not gpu"``) hold the pins.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional
+
+import numpy as np
+
+from . import build as _build
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+NE = 256
+E_LO, E_HI = 1.0, 256.0
+MATERIALS = ("water", "air", "pmma", "brass", "bone")
+M_WATER, M_AIR, M_PMMA, M_BRASS, M_BONE = range(5)
+LEDGER_NAMES = ("grid", "range_shifter", "aperture", "escaped", "nuclear_escaped", "spare")
+
+# what pins each oracle function (tests/test_oracle_*.py)
+PINS = {
+    "philox4x32_10": "published known-answer vectors (Random123)",
+    "normal_quantile": "scipy.special.ndtr round trip, symmetry",
+    "stopping_power": "NIST PSTAR water values (1 %), K from CODATA",
+    "range": "scipy quad of 1/S (1e-10), Bragg-Kleeman band, brass 30 mm ~ 155 MeV",
+    "omega2": "coefficient from CODATA constants; slab exit-energy variance",
+    "scatter_power": "slab exit-angle variance = Fermi-Eyges A0; Highland with its log term",
+    "nuclear": "slab survival = exp(-rho sigma L) above 20 MeV",
+    "crossing_number": "analytic circle and brute-force raster of concave polygons",
+    "straight_transport": "exact IDD closed form E(z) = R^-1(R(E0) - rho z); range scaling",
+    "source": "per-voxel lateral profile = N * erf differences (binomial 3 sigma)",
+    "energy_conservation": "per history, ledgers + grid = E0 to 1e-12",
+    "aperture": "wide aperture == no aperture (bitwise); closed aperture -> zero dose",
+    "scenarios": "integer-voxel setup shift == shifted dose (bitwise)",
+    "batches": "sigma of the mean vs spread over independent seeds (chi^2)",
+    "hu_lookup": "breakpoints of the piecewise-linear calibration",
+    "absolute_dosimetry": "parity unpinned (no measurement or comparison system available)",
+}
+
+
+class _Geom(C.Structure):
+    _fields_ = [("kind", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("sp", C.c_double * 3), ("org", C.c_double * 3), ("hu", C.c_void_p)]
+
+
+class _Field(C.Structure):
+    _fields_ = [("iso", C.c_double * 3), ("ex", C.c_double * 3), ("ey", C.c_double * 3),
+                ("ez", C.c_double * 3), ("has_block", C.c_int), ("nv", C.c_int),
+                ("poly", C.c_void_p), ("blk_t", C.c_double), ("blk_rho", C.c_double),
+                ("blk_d", C.c_double), ("has_rs", C.c_int), ("rs_t", C.c_double),
+                ("rs_diam", C.c_double), ("rs_d", C.c_double)]
+
+
+class _Spot(C.Structure):
+    _fields_ = [("x", C.c_double), ("y", C.c_double), ("e0", C.c_double), ("sigma", C.c_double),
+                ("esig", C.c_double), ("weight", C.c_double), ("nh", C.c_int64)]
+
+
+class _Scen(C.Structure):
+    _fields_ = [("shift", C.c_double * 3), ("range_scale", C.c_double)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("field_id", C.c_int), ("physics", C.c_int), ("k", C.c_int),
+                ("batch", C.c_int), ("n_batches", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = os.path.join(HERE, "liboracle.so")
+        if not os.path.exists(path):
+            _build.build()
+        L = C.CDLL(path)
+        d, i, i64, vp = C.c_double, C.c_int, C.c_int64, C.c_void_p
+        for name, res, args in [
+            ("orc_init", None, []),
+            ("orc_stopping_power", d, [i, d]), ("orc_omega2", d, [i, d]),
+            ("orc_scatter_power", d, [i, d]), ("orc_nuclear_coeff", d, [i, d]),
+            ("orc_range", d, [i, d]), ("orc_energy_of_range", d, [i, d]),
+            ("orc_table", i, [i, i, vp]), ("orc_material_density", d, [i]),
+            ("orc_hu_lookup", None, [vp, i64, vp, vp]),
+            ("orc_philox4x32_10", None, [vp, vp, vp]),
+            ("orc_uniform", d, [C.c_uint32]), ("orc_normal_quantile", d, [d]),
+            ("orc_in_polygon", i, [vp, i, d, d]), ("orc_edge_distance", d, [vp, i, d, d, d, d]),
+            ("orc_run", i64, [vp, vp, vp, i, i, vp, vp, vp, vp, i]),
+            ("orc_trace_history", None, [vp, vp, vp, i, i64, vp, vp, vp, vp, vp]),
+            ("orc_slab_exit", None, [i, d, d, d, i, C.c_uint64, i64, vp, i]),
+            ("orc_fixed_point_k", i, [d]), ("orc_rs_thickness", d, [d]),
+            ("orc_mev_to_joule", d, []),
+        ]:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        L.orc_init()
+        _lib = L
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+# ----------------------------------------------------------------- tables
+def table(material: int, which: str) -> np.ndarray:
+    w = {"E": 0, "R": 1, "omega2": 2, "T": 3, "sigma_nuc": 4}[which]
+    out = np.zeros(NE, np.float64)
+    lib().orc_table(material, w, _ptr(out))
+    return out
+
+
+def stopping_power(m, E):
+    return np.vectorize(lambda e: lib().orc_stopping_power(m, float(e)))(E)
+
+
+def csda_range(m, E):
+    return np.vectorize(lambda e: lib().orc_range(m, float(e)))(E)
+
+
+def energy_of_range(m, R):
+    return np.vectorize(lambda r: lib().orc_energy_of_range(m, float(r)))(R)
+
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.asarray(ctr, np.uint32)
+    k = np.asarray(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def uniform(w: int) -> float:
+    return lib().orc_uniform(int(w))
+
+
+def normal_quantile(u: float) -> float:
+    return lib().orc_normal_quantile(float(u))
+
+
+def in_polygon(poly: np.ndarray, x: float, y: float) -> bool:
+    p = np.ascontiguousarray(poly, np.float64)
+    return bool(lib().orc_in_polygon(_ptr(p), p.shape[0], float(x), float(y)))
+
+
+def edge_distance(poly, x, y, u, v) -> float:
+    p = np.ascontiguousarray(poly, np.float64)
+    return lib().orc_edge_distance(_ptr(p), p.shape[0], float(x), float(y), float(u), float(v))
+
+
+def hu_lookup(hu: np.ndarray):
+    h = np.ascontiguousarray(hu, np.int16).ravel()
+    mat = np.zeros(h.size, np.int32)
+    rho = np.zeros(h.size, np.float64)
+    lib().orc_hu_lookup(_ptr(h), h.size, _ptr(mat), _ptr(rho))
+    return mat.reshape(hu.shape), rho.reshape(hu.shape)
+
+
+def rs_thickness(wet_mm: float) -> float:
+    return lib().orc_rs_thickness(float(wet_mm))
+
+
+def slab_exit(material: int, rho: float, thickness_mm: float, e0: float, physics: int, n: int,
+              seed: int = 0, threads: int = 0) -> np.ndarray:
+    out = np.zeros((n, 8), np.float64)
+    lib().orc_slab_exit(material, rho, thickness_mm, e0, physics, seed, n, _ptr(out), threads)
+    return out
+
+
+# ----------------------------------------------------------- case -> structs
+class _Prepared:
+    def __init__(self, case, field_index: int, scenario_index: int):
+        g = case.geometry
+        self.geom = _Geom()
+        self.geom.kind = g.kind
+        self.geom.nx, self.geom.ny, self.geom.nz = g.shape
+        self.geom.sp = (C.c_double * 3)(*g.spacing)
+        self.geom.org = (C.c_double * 3)(*g.origin)
+        self.hu = None
+        if g.kind == 1:
+            self.hu = np.ascontiguousarray(g.hu, np.int16)
+            self.geom.hu = self.hu.ctypes.data
+        f = case.fields[field_index]
+        self.field = _Field()
+        b = f.beam
+        self.field.iso = (C.c_double * 3)(*b.iso)
+        self.field.ex = (C.c_double * 3)(*b.ex)
+        self.field.ey = (C.c_double * 3)(*b.ey)
+        self.field.ez = (C.c_double * 3)(*b.ez)
+        self.poly = None
+        if f.block is not None:
+            self.field.has_block = 1
+            self.field.blk_t = f.block.thickness_mm
+            self.field.blk_rho = f.block.density_gcc
+            self.field.blk_d = f.block.downstream_mm
+            if f.polygon is not None and len(f.polygon) > 0:
+                self.poly = np.ascontiguousarray(f.polygon, np.float64)
+                self.field.nv = self.poly.shape[0]
+                self.field.poly = self.poly.ctypes.data
+        if f.rs is not None:
+            self.field.has_rs = 1
+            self.field.rs_t = rs_thickness(f.rs.wet_mm)
+            self.field.rs_diam = f.rs.diameter_mm
+            self.field.rs_d = f.rs.downstream_mm
+        sp = f.spots
+        self.spots = (_Spot * len(sp))()
+        for i in range(len(sp)):
+            s = self.spots[i]
+            s.x, s.y = float(sp["x_mm"][i]), float(sp["y_mm"][i])
+            s.e0, s.sigma = float(sp["energy_mev"][i]), float(sp["sigma_mm"][i])
+            s.esig, s.weight = float(sp["energy_sigma_mev"][i]), float(sp["weight"][i])
+            s.nh = int(sp["n_histories"][i])
+        sc = case.scenarios[scenario_index]
+        self.scen = _Scen()
+        self.scen.shift = (C.c_double * 3)(*sc.shift_mm)
+        self.scen.range_scale = sc.range_scale
+        self.n_spots = len(sp)
+
+
+def energy_bound(case, fields=None) -> float:
+    """T = sum over spots of weight * maximum VP energy (bounds any tally)."""
+    T = 0.0
+    for fi, f in enumerate(case.fields):
+        if fields is not None and fi not in fields:
+            continue
+        sp = f.spots
+        emax = np.minimum(sp["energy_mev"].astype(np.float64) + 6.0 * sp["energy_sigma_mev"], E_HI)
+        T += float(np.sum(sp["weight"].astype(np.float64) * emax))
+    return T
+
+
+def fixed_point_k(case, fields=None) -> int:
+    return lib().orc_fixed_point_k(energy_bound(case, fields))
+
+
+def run_tally(case, field_index: int = 0, scenario_index: int = 0, k: Optional[int] = None,
+              batch: Optional[int] = None, n_batches: int = 1, spots=None, threads: int = 0,
+              physics: Optional[int] = None, seed: Optional[int] = None):
+    """Fixed-point tally of one field/scenario: (q int64[nz,ny,nx], ledger_q int64[6], k)."""
+    P = _Prepared(case, field_index, scenario_index)
+    if k is None:
+        k = fixed_point_k(case)
+    o = _Opts()
+    o.seed = case.seed if seed is None else seed
+    o.field_id = field_index
+    o.physics = case.physics if physics is None else physics
+    o.k = k
+    o.batch = 0 if batch is None else batch
+    o.n_batches = n_batches if batch is not None else 1
+    nx, ny, nz = case.geometry.shape
+    q = np.zeros(nx * ny * nz, np.int64)
+    led = np.zeros(6, np.int64)
+    s0, s1 = (0, P.n_spots) if spots is None else spots
+    lib().orc_run(C.byref(P.geom), C.byref(P.field), C.cast(P.spots, C.c_void_p), s0, s1,
+                  C.byref(P.scen), C.byref(o), _ptr(q), _ptr(led), threads)
+    return q.reshape(nz, ny, nx), led, k
+
+
+def trace_history(case, spot_index: int, h: int, field_index: int = 0, scenario_index: int = 0,
+                  want_grid: bool = False, physics: Optional[int] = None):
+    P = _Prepared(case, field_index, scenario_index)
+    o = _Opts()
+    o.seed = case.seed
+    o.field_id = field_index
+    o.physics = case.physics if physics is None else physics
+    led = np.zeros(6, np.float64)
+    info = np.zeros(4, np.int64)
+    grid = np.zeros(case.geometry.nvox, np.float64) if want_grid else None
+    lib().orc_trace_history(C.byref(P.geom), C.byref(P.field), C.byref(P.spots[spot_index]),
+                            spot_index, h, C.byref(P.scen), C.byref(o), _ptr(led), _ptr(grid),
+                            _ptr(info))
+    return led, info, grid
+
+
+def voxel_mass_g(case) -> np.ndarray:
+    g = case.geometry
+    vol_cm3 = g.spacing[0] * g.spacing[1] * g.spacing[2] * 1e-3
+    nx, ny, nz = g.shape
+    if g.kind == 0:
+        rho = np.ones((nz, ny, nx))
+    else:
+        _, rho = hu_lookup(g.hu)
+    return rho * vol_cm3
+
+
+def q_to_gy(case, q: np.ndarray, k: int) -> np.ndarray:
+    """Dose to medium (Gy per unit spot weight) from a fixed-point energy tally."""
+    mev = q.astype(np.float64) * 2.0 ** (-k)
+    return mev * lib().orc_mev_to_joule() / (voxel_mass_g(case) * 1e-3)
+
+
+def dose(case, scenario_index: int = 0, k: Optional[int] = None, n_batches: Optional[int] = None,
+         threads: int = 0, fields=None):
+    """Plan dose of all fields (FP64 dict): q, dose_gy, sigma_gy, ledger_mev, k,
+    uncertainty (mean sigma/D over voxels >= 50 % of the maximum)."""
+    B = case.n_batches if n_batches is None else n_batches
+    if k is None:
+        k = fixed_point_k(case)
+    nx, ny, nz = case.geometry.shape
+    q_tot = np.zeros((nz, ny, nx), np.int64)
+    s2 = np.zeros((nz, ny, nx), np.float64)
+    led = np.zeros(6, np.int64)
+    flist = range(len(case.fields)) if fields is None else fields
+    if B > 1:
+        for b in range(B):
+            qb = np.zeros((nz, ny, nx), np.int64)
+            for fi in flist:
+                q, l, _ = run_tally(case, fi, scenario_index, k, batch=b, n_batches=B, threads=threads)
+                qb += q
+                led += l
+            q_tot += qb
+            db = qb.astype(np.float64) * 2.0 ** (-k)
+            s2 += db * db
+    else:
+        for fi in flist:
+            q, l, _ = run_tally(case, fi, scenario_index, k, threads=threads)
+            q_tot += q
+            led += l
+    d_mev = q_tot.astype(np.float64) * 2.0 ** (-k)
+    conv = lib().orc_mev_to_joule() / (voxel_mass_g(case) * 1e-3)
+    out = {"q": q_tot, "k": k, "dose_gy": d_mev * conv, "ledger_mev": led * 2.0 ** (-k)}
+    if B > 1:
+        var = np.maximum(B * s2 - d_mev * d_mev, 0.0) / (B - 1)
+        out["sigma_gy"] = np.sqrt(var) * conv
+        out["uncertainty"] = uncertainty(out["dose_gy"], out["sigma_gy"])
+    return out
+
+
+def uncertainty(dose_gy: np.ndarray, sigma_gy: np.ndarray, threshold: float = 0.5) -> float:
+    """Mean relative standard error over voxels at or above threshold*max (R15)."""
+    m = dose_gy >= threshold * dose_gy.max()
+    return float(np.mean(sigma_gy[m] / dose_gy[m])) if m.any() else float("nan")
+
+
+def spot_tallies(case, field_index: int = 0, scenario_index: int = 0, k: Optional[int] = None,
+                 threads: int = 0) -> List[np.ndarray]:
+    """Per-spot fixed-point tallies (the influence-matrix rows before
+    compression), each int64[nz,ny,nx]."""
+    if k is None:
+        k = fixed_point_k(case)
+    rows = []
+    for s in range(len(case.fields[field_index].spots)):
+        q, _, _ = run_tally(case, field_index, scenario_index, k, spots=(s, s + 1), threads=threads)
+        rows.append(q)
+    return rows
