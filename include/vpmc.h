@@ -1,0 +1,212 @@
+/*
+ * vpmc.h -- C ABI of the MI355X (gfx950) virtual-particle Monte Carlo
+ * transport of proton pencil beams through an optional range shifter and a
+ * patient-specific brass aperture block into a voxelised water or CT
+ * geometry, with int64 fixed-point dose tallies and per-spot sparse
+ * influence matrices.
+ *
+ * Paper: Feng et al., "Modelling small block aperture in an in-house
+ * developed GPU-accelerated Monte Carlo-based dose engine for pencil beam
+ * scanning proton therapy", arXiv 2307.01416.  Section references below are
+ * to that paper.
+ *
+ * Conventions
+ *  - Every function returns int: VPMC_OK (0) or a negative error code.  On
+ *    error the outputs are left untouched and the context stays usable;
+ *    vpmc_last_error() returns a thread-local message owned by the library.
+ *  - Units: mm, MeV, g/cm^3.  Voxel (i,j,k) covers [origin + i*d,
+ *    origin + (i+1)*d) per axis; x is fastest in memory (index
+ *    i + nx*(j + ny*k)).
+ *  - Inputs are borrowed for the duration of the call; host inputs are copied
+ *    before the call returns.
+ *  - Outputs are caller-owned.  With VPMC_DEVICE_PTRS in the flags they are
+ *    device pointers on the context's GPU (for instance torch tensors) and
+ *    all work is ordered on opts->hip_stream; otherwise they are host
+ *    pointers and the call returns after the copy.
+ *  - Argument validation is done on the host before any HIP call.
+ *  - A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef VPMC_H
+#define VPMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VPMC_OK 0
+#define VPMC_E_ARG -1      /* invalid argument */
+#define VPMC_E_STATE -2    /* call out of order (no geometry, no field, no device) */
+#define VPMC_E_POLYGON -3  /* aperture polygon degenerate or self-intersecting */
+#define VPMC_E_OOM -4      /* device memory (or opts.max_device_bytes) exhausted */
+#define VPMC_E_DEVICE -5   /* HIP runtime error */
+#define VPMC_E_RANGE -6    /* energy outside the tables or fixed-point overflow bound */
+#define VPMC_E_ABORTED -7  /* work-queue iteration cap reached */
+
+/* physics switches (0 = straight CSDA transport) */
+#define VPMC_STRAGGLE 1u
+#define VPMC_MCS 2u
+#define VPMC_NUCLEAR 4u
+#define VPMC_PHYS_ALL 7u
+
+#define VPMC_GEOM_WATER 0  /* homogeneous water, density 1 */
+#define VPMC_GEOM_HU 1     /* int16 CT numbers, calibrated to material and density */
+
+#define VPMC_OUT_DOSE 0    /* dense dose grid per scenario */
+#define VPMC_OUT_CSR 1     /* per-(scenario, spot) sparse influence-matrix rows */
+
+#define VPMC_DEVICE_PTRS 1u /* pointers are device pointers; work on opts.hip_stream */
+#define VPMC_GRAPH 2u       /* CSR: capture all epochs of the run in one hipGraph */
+
+#define VPMC_MAX_FIELDS 64
+#define VPMC_MAX_VERTICES 1024
+#define VPMC_NLEDGER 6     /* [0] patient grid [1] range shifter [2] aperture block
+                              [3] escaped / missed the grid [4] nuclear, carried away [5] spare */
+
+typedef struct vpmc_ctx vpmc_ctx;
+
+/* Create a context on HIP device `hip_device`.  hip_device == -1 creates a
+ * validation-only context (no GPU is touched; run calls return
+ * VPMC_E_STATE after validating their arguments).  The physics tables
+ * (Methods A: per-material tables X(E) of energy loss, straggling,
+ * deflection and interaction probability) are generated in FP64 on the host
+ * and staged to the device in FP32. */
+int vpmc_create(vpmc_ctx **out, int hip_device);
+void vpmc_destroy(vpmc_ctx *ctx);
+const char *vpmc_last_error(const vpmc_ctx *ctx);
+int vpmc_version(void);
+
+/* Load the patient or phantom voxel grid (Methods D.2 water phantoms, D.3
+ * CT geometries).  kind VPMC_GEOM_WATER ignores hu (may be NULL);
+ * VPMC_GEOM_HU copies nx*ny*nz int16 CT numbers (host pointer, or device
+ * pointer with VPMC_DEVICE_PTRS).  nx*ny*nz must be < 2^31. */
+int vpmc_load_geometry(vpmc_ctx *ctx, int kind, const int16_t *hu, int nx, int ny, int nz,
+                       const float spacing_mm[3], const float origin_mm[3], unsigned flags);
+
+/* Beam frame of a field: origin `iso_mm` in CT coordinates; ex, ey, ez are
+ * the beam-frame axes as CT-frame unit vectors (right-handed, orthonormal);
+ * the beam travels along +ez and beam-line components sit at negative z. */
+typedef struct {
+    float iso_mm[3];
+    float ex[3], ey[3], ez[3];
+} vpmc_beam;
+
+/* Aperture block (Methods B): brass slab of the given thickness and
+ * density whose downstream face lies downstream_mm upstream of the
+ * beam-frame origin plane; non-divergent opening (Methods D). */
+typedef struct {
+    float thickness_mm, density_gcc, downstream_mm;
+} vpmc_block;
+
+/* Range shifter (Methods B): PMMA disc of the given water-equivalent
+ * thickness and diameter, downstream face downstream_mm upstream of the
+ * beam-frame origin plane.  Must lie upstream of the block. */
+typedef struct {
+    float wet_mm, diameter_mm, downstream_mm;
+} vpmc_rs;
+
+/* Define field `field_id`: its beam frame, its aperture and its range
+ * shifter (Methods B).  xy_mm holds n_vertices (x, y) pairs of the opening
+ * in the beam's-eye view (implicitly closed, either orientation, must not
+ * self-intersect); the crossing-number test decides opening vs brass.
+ * block == NULL: no aperture block.  block != NULL and n_vertices == 0:
+ * closed block (no opening).  rs == NULL: no range shifter.
+ * Errors: VPMC_E_ARG (bad numbers, field id), VPMC_E_POLYGON (fewer than 3
+ * vertices but not 0, zero area, self-intersection, > VPMC_MAX_VERTICES). */
+int vpmc_set_aperture(vpmc_ctx *ctx, int field_id, const vpmc_beam *beam, const float *xy_mm,
+                      int n_vertices, const vpmc_block *block, const vpmc_rs *rs);
+
+/* One pencil-beam spot (Methods D.1/D.2): position at the beam-frame origin
+ * plane, energy, Gaussian in-air sigma, optional Gaussian energy spread,
+ * weight and number of virtual particles (histories). */
+typedef struct {
+    float x_mm, y_mm, energy_mev, sigma_mm, energy_sigma_mev, weight;
+    uint32_t n_histories;
+} vpmc_spot;
+
+/* Robust scenario (Methods E): the patient is displaced by shift_mm and
+ * every stopping power in the patient is multiplied by range_scale. */
+typedef struct {
+    float shift_mm[3];
+    float range_scale;
+} vpmc_scenario;
+
+typedef struct {
+    uint64_t seed;          /* Philox key; one stream per (field, spot, history) */
+    unsigned physics;       /* VPMC_STRAGGLE | VPMC_MCS | VPMC_NUCLEAR, 0 = straight */
+    int n_batches;          /* 0/1: no variance; 2..1024: history h goes to batch h mod B */
+    int output;             /* VPMC_OUT_DOSE or VPMC_OUT_CSR */
+    int fixed_point_bits;   /* 0: automatic; else k in [1, 62] */
+    unsigned flags;         /* VPMC_DEVICE_PTRS */
+    void *hip_stream;       /* hipStream_t or NULL (default stream) */
+    size_t max_device_bytes;/* 0 = no cap; scratch above the cap -> VPMC_E_OOM */
+    int block_threads;      /* 0 = tuned default; else 64..1024, multiple of 64 */
+    int grid_blocks;        /* 0 = tuned default */
+    int hist_per_lane;      /* CSR work-queue chunk = 64 * hist_per_lane histories; 0 = default 4 */
+    int max_slots;          /* CSR rows resident at once (<= 1024); 0 = sized from memory */
+} vpmc_opts;
+
+/* Transport all histories of n_spots spots of field `field_id` for each of
+ * n_scen scenarios.  Energy deposits are tallied as q = rne(dE * w_s/N_s *
+ * 2^k) in int64 (order-independent, so reruns are bit-identical).
+ * Dense mode (opts->output == VPMC_OUT_DOSE):
+ *   dose_gy   [n_scen][nvox] FP32 dose to medium, Gy per unit spot weight
+ *   sigma_gy  [n_scen][nvox] FP32 standard error (needs n_batches >= 2) or NULL
+ *   ledger_mev[n_scen][6]    FP64 energy balance (weighted MeV) or NULL; always
+ *                            host memory
+ * CSR mode: row_ptr [n_scen*n_spots + 1] (row = scen*n_spots + spot) is
+ *   filled; the total number of non-zeros is row_ptr[n_scen*n_spots]; then
+ *   call vpmc_copy_csr.  dose_gy/sigma_gy may be NULL.
+ * Errors: VPMC_E_STATE (no geometry/field), VPMC_E_ARG, VPMC_E_RANGE
+ * (energy outside (1, 256] MeV or k too small), VPMC_E_OOM, VPMC_E_DEVICE. */
+int vpmc_run_spots(vpmc_ctx *ctx, int field_id, const vpmc_spot *spots, int n_spots,
+                   const vpmc_scenario *scen, int n_scen, const vpmc_opts *opts, float *dose_gy,
+                   float *sigma_gy, double *ledger_mev, int64_t *row_ptr);
+
+/* All robust scenarios x fields x spots in one work-queue pass (Methods C
+ * and E: influence matrices of every scenario for robust optimisation).
+ * Rows are ordered (scenario, field in the order given, spot); spots[f] holds
+ * n_spots[f] spots of field field_ids[f] (set by vpmc_set_aperture).  The
+ * output is always CSR: row_ptr [n_scen * sum(n_spots) + 1] (pointer kind per
+ * flags), then vpmc_copy_csr.  dose_gy [n_scen][nvox] (optional) receives the
+ * plan dose of each scenario (sum of its rows); ledger_mev [n_scen][6] host.
+ * Each row equals, bitwise, the tally of the same spot run alone with the
+ * same seed and fixed_point_bits (streams are keyed by field, spot, history).
+ * Errors: as vpmc_run_spots; VPMC_E_ARG if the fields' vertices exceed
+ * VPMC_MAX_VERTICES in total. */
+int vpmc_run_batched(vpmc_ctx *ctx, const int *field_ids, const vpmc_spot *const *spots,
+                     const int *n_spots, int n_fields, const vpmc_scenario *scen, int n_scen,
+                     const vpmc_opts *opts, float *dose_gy, double *ledger_mev, int64_t *row_ptr);
+
+/* After a CSR run: column (voxel) indices in ascending order per row and FP32
+ * values (Gy per unit spot weight, converted from the int64 tally); q_raw
+ * (optional) receives the int64 tallies themselves.  Buffers must hold
+ * row_ptr[last] entries; pointer kind follows the run's flags. */
+int vpmc_copy_csr(vpmc_ctx *ctx, int32_t *col_voxel, float *val_gy, int64_t *q_raw);
+
+/* After a dense run: copy the int64 tally of scenario `scen_index` and the
+ * fixed-point exponent k (dose = q * 2^-k MeV converted per voxel mass). */
+int vpmc_last_tally(vpmc_ctx *ctx, int scen_index, int64_t *q_out, int *k_out, unsigned flags);
+
+/* Measurements of the last run: transport_ms is the sum of the transport
+ * kernels' durations (HIP events recorded on the run's stream around each
+ * launch), total_ms the whole call; steps counts condensed-history steps
+ * (every region), histories the VPs transported. */
+typedef struct {
+    double transport_ms, total_ms;
+    uint64_t histories, steps, launches;
+} vpmc_stats;
+int vpmc_last_stats(const vpmc_ctx *ctx, vpmc_stats *out);
+
+/* Host-only view of the library's own FP64 physics tables (no device
+ * needed): material 0 water, 1 air, 2 PMMA, 3 brass, 4 bone; which 0 energy
+ * nodes, 1 CSDA range, 2 straggling variance, 3 scattering power, 4 nuclear
+ * removal.  Writes n <= 256 values; returns the node count. */
+int vpmc_table_host(int material, int which, double *out, int n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VPMC_H */

@@ -379,10 +379,9 @@ static void sink_grid(sink_t *s, int64_t v, double e)
     if (e == 0.0) return;
     s->led_fp[L_GRID] += e;
     if (s->grid_fp) s->grid_fp[v] += e;
-    if (s->q) {
-        int64_t q = llrint(e * s->scale);
-        if (q) __atomic_fetch_add(&s->q[v], q, __ATOMIC_RELAXED);
-    }
+    int64_t q = llrint(e * s->scale);
+    s->led_q[L_GRID] += q;
+    if (s->q && q) __atomic_fetch_add(&s->q[v], q, __ATOMIC_RELAXED);
 }
 
 static void sink_ledger(sink_t *s, int j, double e)
@@ -677,7 +676,7 @@ static void patient(vp_t *vp, sink_t *sk, const orc_geom *g, const orc_field *f,
     int idx[3];
     for (int k = 0; k < 3; k++) {
         double c = floor((p[k] - lo[k]) / g->sp[k]);
-        idx[k] = c < 0 ? 0 : c > n[k] - 1 ? n[k] - 1 : (int)c;
+        idx[k] = !(c >= 0) ? 0 : c > n[k] - 1 ? n[k] - 1 : (int)c;   /* NaN -> 0 */
     }
     memcpy(vp->p, p, sizeof p);
     memcpy(vp->d, d, sizeof d);

@@ -1,0 +1,28 @@
+"""Build libvpmc.so (HIP, gfx950) in-tree with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libvpmc.so")
+SOURCES = ["csrc/vpmc_kernels.hip", "csrc/vpmc_api.cpp", "csrc/tables.cpp"]
+ARCH = os.environ.get("VPMC_OFFLOAD_ARCH", "gfx950")
+
+
+def build(verbose: bool = False) -> str:
+    cmd = ["/opt/rocm/bin/hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-Wall", "-Wno-unused-parameter",
+           # packed FP32 instructions stay off (see the build notes)
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-o", LIB + ".tmp"] + [os.path.join(HERE, s) for s in SOURCES]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True, cwd=HERE)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)

@@ -1,0 +1,908 @@
+// Host runtime of libvpmc: argument validation (before any HIP call),
+// device buffers, fixed-point scaling, batch loop and the C ABI of
+// include/vpmc.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/vpmc.h"
+#include "vpmc_internal.hpp"
+
+using namespace vpmc;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? VPMC_E_OOM : VPMC_E_DEVICE, "%s: %s", \
+                        #expr, hipGetErrorString(e_));                                    \
+    } while (0)
+
+bool finite3(const float *v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t cap = 0;
+};
+
+struct FieldState {
+    bool set = false;
+    FieldDev dev{};
+    std::vector<float2> poly;
+    DevBuf poly_buf;
+};
+
+}  // namespace
+
+struct vpmc_ctx {
+    int device = -1;
+    float *d_tables = nullptr;
+    // geometry
+    bool has_geom = false;
+    GeomDev geom{};
+    DevBuf hu_buf;
+    size_t nvox = 0;
+    FieldState fields[VPMC_MAX_FIELDS];
+    // scratch (grow-only)
+    DevBuf tallies, qbatch, s2, ledger, spots, offsets, stage_dose, stage_sigma, stats;
+    size_t bytes = 0;
+    // last run
+    int last_k = 0, last_nscen = 0;
+    vpmc_stats last_stats{};
+    std::vector<hipEvent_t> events;
+    // influence-matrix builder
+    DevBuf slot_grid, slot_l1, slot_l2, slot_nnz;
+    int n_slots = 0;
+    size_t slot_nvox = 0;
+    bool slots_dirty = false;
+    DevBuf rows, chunk_off, heads, row_off, row_nnz, used, flags, fields_tab, poly_off, polys, scen_tab, csr_col, csr_q;
+    unsigned long long csr_cap = 0, csr_total = 0, csr_cap_hint = 0;
+    int csr_rows = 0;
+    bool csr_valid = false;
+    unsigned csr_flags = 0;
+};
+
+namespace {
+
+int ensure(vpmc_ctx *c, DevBuf &b, size_t bytes, size_t cap_limit) {
+    if (bytes <= b.cap) return VPMC_OK;
+    const size_t grow = bytes - b.cap;
+    if (cap_limit && c->bytes + grow > cap_limit)
+        return fail(VPMC_E_OOM, "scratch of %zu bytes exceeds max_device_bytes=%zu", c->bytes + grow,
+                    cap_limit);
+    if (b.ptr) {
+        HIP_TRY(hipFree(b.ptr));
+        c->bytes -= b.cap;
+        b.ptr = nullptr;
+        b.cap = 0;
+    }
+    HIP_TRY(hipMalloc(&b.ptr, bytes));
+    b.cap = bytes;
+    c->bytes += bytes;
+    return VPMC_OK;
+}
+
+void release(DevBuf &b) {
+    if (b.ptr) (void)hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.cap = 0;
+}
+
+double cross2(double ax, double ay, double bx, double by) { return ax * by - ay * bx; }
+
+bool segments_intersect(const float2 &p1, const float2 &p2, const float2 &q1, const float2 &q2) {
+    const double d1 = cross2(q2.x - q1.x, q2.y - q1.y, p1.x - q1.x, p1.y - q1.y);
+    const double d2 = cross2(q2.x - q1.x, q2.y - q1.y, p2.x - q1.x, p2.y - q1.y);
+    const double d3 = cross2(p2.x - p1.x, p2.y - p1.y, q1.x - p1.x, q1.y - p1.y);
+    const double d4 = cross2(p2.x - p1.x, p2.y - p1.y, q2.x - p1.x, q2.y - p1.y);
+    if (((d1 > 0 && d2 < 0) || (d1 < 0 && d2 > 0)) && ((d3 > 0 && d4 < 0) || (d3 < 0 && d4 > 0)))
+        return true;
+    auto on_seg = [](const float2 &a, const float2 &b, const float2 &p, double d) {
+        return d == 0 && std::min(a.x, b.x) <= p.x && p.x <= std::max(a.x, b.x) &&
+               std::min(a.y, b.y) <= p.y && p.y <= std::max(a.y, b.y);
+    };
+    return on_seg(q1, q2, p1, d1) || on_seg(q1, q2, p2, d2) || on_seg(p1, p2, q1, d3) ||
+           on_seg(p1, p2, q2, d4);
+}
+
+int validate_polygon(const float *xy, int n) {
+    if (n == 0) return VPMC_OK;
+    if (n < 3) return fail(VPMC_E_POLYGON, "aperture polygon needs 0 (closed) or >= 3 vertices, got %d", n);
+    if (n > VPMC_MAX_VERTICES)
+        return fail(VPMC_E_POLYGON, "aperture polygon has %d vertices (max %d)", n, VPMC_MAX_VERTICES);
+    if (!xy) return fail(VPMC_E_ARG, "xy_mm is NULL");
+    double area = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const int j = (i + 1) % n;
+        if (!isfinite(xy[2 * i]) || !isfinite(xy[2 * i + 1]))
+            return fail(VPMC_E_POLYGON, "vertex %d is not finite", i);
+        area += (double)xy[2 * i] * xy[2 * j + 1] - (double)xy[2 * j] * xy[2 * i + 1];
+    }
+    if (fabs(0.5 * area) < 1e-6) return fail(VPMC_E_POLYGON, "aperture polygon has zero area");
+    std::vector<float2> v(n);
+    for (int i = 0; i < n; ++i) v[i] = make_float2(xy[2 * i], xy[2 * i + 1]);
+    for (int i = 0; i < n; ++i) {
+        const float2 &a = v[i], &b = v[(i + 1) % n];
+        if (a.x == b.x && a.y == b.y) return fail(VPMC_E_POLYGON, "repeated vertex %d", i);
+        for (int j = i + 2; j < n; ++j) {
+            if (i == 0 && j == n - 1) continue;   // adjacent through the closing edge
+            if (segments_intersect(a, b, v[j], v[(j + 1) % n]))
+                return fail(VPMC_E_POLYGON, "aperture polygon edges %d and %d intersect", i, j);
+        }
+    }
+    return VPMC_OK;
+}
+
+int validate_beam(const vpmc_beam *b) {
+    if (!b) return fail(VPMC_E_ARG, "beam is NULL");
+    if (!finite3(b->iso_mm) || !finite3(b->ex) || !finite3(b->ey) || !finite3(b->ez))
+        return fail(VPMC_E_ARG, "beam frame has non-finite values");
+    const float *e[3] = {b->ex, b->ey, b->ez};
+    for (int i = 0; i < 3; ++i) {
+        const double n = e[i][0] * (double)e[i][0] + e[i][1] * (double)e[i][1] + e[i][2] * (double)e[i][2];
+        if (fabs(n - 1.0) > 1e-4) return fail(VPMC_E_ARG, "beam axis %d is not a unit vector", i);
+        for (int j = i + 1; j < 3; ++j) {
+            const double d = e[i][0] * (double)e[j][0] + e[i][1] * (double)e[j][1] + e[i][2] * (double)e[j][2];
+            if (fabs(d) > 1e-4) return fail(VPMC_E_ARG, "beam axes %d and %d are not orthogonal", i, j);
+        }
+    }
+    const double cz[3] = {b->ex[1] * (double)b->ey[2] - b->ex[2] * (double)b->ey[1],
+                          b->ex[2] * (double)b->ey[0] - b->ex[0] * (double)b->ey[2],
+                          b->ex[0] * (double)b->ey[1] - b->ex[1] * (double)b->ey[0]};
+    if (cz[0] * b->ez[0] + cz[1] * b->ez[1] + cz[2] * b->ez[2] < 0.999)
+        return fail(VPMC_E_ARG, "beam frame is not right-handed");
+    return VPMC_OK;
+}
+
+int validate_spots(const vpmc_spot *spots, int n, double *T) {
+    if (n < 0) return fail(VPMC_E_ARG, "n_spots < 0");
+    if (n > 0 && !spots) return fail(VPMC_E_ARG, "spots is NULL");
+    *T = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const vpmc_spot &s = spots[i];
+        if (!isfinite(s.x_mm) || !isfinite(s.y_mm) || !isfinite(s.sigma_mm) || s.sigma_mm < 0 ||
+            !isfinite(s.energy_sigma_mev) || s.energy_sigma_mev < 0 || !isfinite(s.weight) || s.weight < 0)
+            return fail(VPMC_E_ARG, "spot %d has invalid position, sigma or weight", i);
+        if (!(s.energy_mev > E_LO) || !(s.energy_mev <= E_HI))
+            return fail(VPMC_E_RANGE, "spot %d energy %g MeV outside (1, 256]", i, (double)s.energy_mev);
+        const double emax = std::min((double)s.energy_mev + 6.0 * s.energy_sigma_mev, E_HI);
+        *T += (double)s.weight * emax;
+    }
+    return VPMC_OK;
+}
+
+int validate_scen(const vpmc_scenario *sc, int n) {
+    if (n < 1) return fail(VPMC_E_ARG, "n_scen must be >= 1");
+    if (!sc) return fail(VPMC_E_ARG, "scenarios is NULL");
+    for (int i = 0; i < n; ++i)
+        if (!finite3(sc[i].shift_mm) || !(sc[i].range_scale >= 0.5f && sc[i].range_scale <= 2.0f))
+            return fail(VPMC_E_ARG, "scenario %d invalid (shift finite, range_scale in [0.5, 2])", i);
+    return VPMC_OK;
+}
+
+int pick_k(const vpmc_opts *o, double T, int *k_out) {
+    int k = o->fixed_point_bits;
+    const double lim = ldexp(1.0, 62);
+    if (k == 0) {
+        k = 40;
+        while (k > 0 && T * ldexp(1.0, k) > lim) --k;
+        if (k < 16) return fail(VPMC_E_RANGE, "weighted energy bound %g too large for int64 tallies", T);
+    } else {
+        if (k < 1 || k > 62) return fail(VPMC_E_ARG, "fixed_point_bits must be 0 or in [1, 62]");
+        if (T * ldexp(1.0, k) > lim)
+            return fail(VPMC_E_RANGE, "fixed_point_bits=%d overflows for energy bound %g", k, T);
+    }
+    *k_out = k;
+    return VPMC_OK;
+}
+
+// ---------------------------------------------------------------- CSR runner
+struct BatchField {
+    int field_id;
+    const vpmc_spot *spots;
+    int n_spots;
+};
+
+int grow_keep(vpmc_ctx *c, DevBuf &b, size_t keep_bytes, size_t bytes, size_t cap_limit, hipStream_t st) {
+    if (bytes <= b.cap) return VPMC_OK;
+    if (cap_limit && c->bytes + (bytes - b.cap) > cap_limit)
+        return fail(VPMC_E_OOM, "CSR storage of %zu bytes exceeds max_device_bytes", bytes);
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, bytes));
+    if (b.ptr) {
+        if (keep_bytes) HIP_TRY(hipMemcpyAsync(p, b.ptr, keep_bytes, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        HIP_TRY(hipFree(b.ptr));
+        c->bytes -= b.cap;
+    }
+    b.ptr = p;
+    b.cap = bytes;
+    c->bytes += bytes;
+    return VPMC_OK;
+}
+
+int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario *scen, int n_scen, const vpmc_opts *o,
+            int k, float *dose_gy, double *ledger_mev, int64_t *row_ptr) {
+    const size_t nvox = c->nvox;
+    const bool dev_out = (o->flags & VPMC_DEVICE_PTRS) != 0;
+    const size_t cap = o->max_device_bytes;
+    hipStream_t st = (hipStream_t)o->hip_stream;
+    const int hpl = o->hist_per_lane > 0 ? o->hist_per_lane : 4;
+    const unsigned long long chunk = 64ull * hpl;
+    int rc;
+
+    // fields, polygons, spots (flattened), rows in (scenario, field, spot) order
+    const int nf = (int)bf.size();
+    std::vector<FieldDev> ftab(nf);
+    std::vector<int> poff(nf);
+    std::vector<float2> polys;
+    std::vector<SpotDev> sd;
+    std::vector<int> spot_base(nf);
+    for (int f = 0; f < nf; ++f) {
+        const FieldState &fs = c->fields[bf[f].field_id];
+        ftab[f] = fs.dev;
+        poff[f] = (int)polys.size();
+        polys.insert(polys.end(), fs.poly.begin(), fs.poly.end());
+        spot_base[f] = (int)sd.size();
+        for (int i = 0; i < bf[f].n_spots; ++i) {
+            const vpmc_spot &s = bf[f].spots[i];
+            SpotDev d{};
+            d.x = s.x_mm; d.y = s.y_mm; d.e0 = s.energy_mev; d.sigma = s.sigma_mm; d.esig = s.energy_sigma_mev;
+            d.emax = (float)std::min((double)s.energy_mev + 6.0 * s.energy_sigma_mev, E_HI);
+            d.nh = s.n_histories;
+            d.scale = s.n_histories ? (float)ldexp((double)s.weight / (double)s.n_histories, k) : 0.0f;
+            sd.push_back(d);
+        }
+    }
+    if (polys.size() > (size_t)POLY_LDS)
+        return fail(VPMC_E_ARG, "fields have %zu aperture vertices in total (max %d)", polys.size(), POLY_LDS);
+    if (polys.empty()) polys.push_back(make_float2(0.f, 0.f));
+    if (sd.empty()) sd.push_back(SpotDev{});
+    std::vector<RowDev> rows;
+    for (int sc = 0; sc < n_scen; ++sc)
+        for (int f = 0; f < nf; ++f)
+            for (int i = 0; i < bf[f].n_spots; ++i) {
+                RowDev r{};
+                r.field = f;
+                r.field_id = (uint32_t)bf[f].field_id;
+                r.spot = (uint32_t)i;
+                r.spot_global = (uint32_t)(spot_base[f] + i);
+                r.scen = sc;
+                r.n_hist = bf[f].spots[i].n_histories;
+                rows.push_back(r);
+            }
+    const int R = (int)rows.size();
+    std::vector<ScenDev> stab(n_scen);
+    for (int i = 0; i < n_scen; ++i) {
+        for (int q = 0; q < 3; ++q) stab[i].shift[q] = scen[i].shift_mm[q];
+        stab[i].range_scale = scen[i].range_scale;
+    }
+
+    // slots: dense int64 grid + bitmaps per resident row
+    const size_t n1 = (nvox + 31) / 32, n2 = (n1 + 31) / 32;
+    const size_t slot_bytes = nvox * 8 + n1 * 4 + n2 * 4 + 4;
+    size_t budget = cap ? (cap > c->bytes ? cap - c->bytes : 0) / 2 : ((size_t)24 << 30);
+    int G = o->max_slots > 0 ? std::min(o->max_slots, kMaxSlots) : kMaxSlots;
+    G = (int)std::min<size_t>((size_t)G, budget / slot_bytes);
+    G = std::min(G, std::max(R, 1));
+    if (G < 1) return fail(VPMC_E_OOM, "no room for one influence-matrix slot (%zu bytes)", slot_bytes);
+    if (c->n_slots < G || c->slot_nvox != nvox || c->slots_dirty) {
+        const int Ga = std::max(G, c->slot_nvox == nvox ? c->n_slots : 0);
+        if ((rc = ensure(c, c->slot_grid, (size_t)Ga * nvox * 8, cap))) return rc;
+        if ((rc = ensure(c, c->slot_l1, (size_t)Ga * n1 * 4, cap))) return rc;
+        if ((rc = ensure(c, c->slot_l2, (size_t)Ga * n2 * 4, cap))) return rc;
+        if ((rc = ensure(c, c->slot_nnz, (size_t)Ga * 4, cap))) return rc;
+        HIP_TRY(hipMemsetAsync(c->slot_grid.ptr, 0, (size_t)Ga * nvox * 8, st));
+        HIP_TRY(hipMemsetAsync(c->slot_l1.ptr, 0, (size_t)Ga * n1 * 4, st));
+        HIP_TRY(hipMemsetAsync(c->slot_l2.ptr, 0, (size_t)Ga * n2 * 4, st));
+        HIP_TRY(hipMemsetAsync(c->slot_nnz.ptr, 0, (size_t)Ga * 4, st));
+        c->n_slots = Ga;
+        c->slot_nvox = nvox;
+        c->slots_dirty = false;
+    }
+
+    // epochs and their chunk prefixes
+    const int E = (R + G - 1) / std::max(G, 1);
+    std::vector<unsigned long long> choff;
+    std::vector<size_t> ep_choff(E);
+    std::vector<unsigned long long> ep_chunks(E);
+    for (int e = 0; e < E; ++e) {
+        const int r0 = e * G, r1 = std::min(R, r0 + G);
+        ep_choff[e] = choff.size();
+        unsigned long long acc = 0;
+        choff.push_back(0);
+        for (int r = r0; r < r1; ++r) {
+            acc += (rows[r].n_hist + chunk - 1) / chunk;
+            choff.push_back(acc);
+        }
+        ep_chunks[e] = acc;
+    }
+    if ((rc = ensure(c, c->rows, std::max<size_t>(1, rows.size()) * sizeof(RowDev), cap))) return rc;
+    if ((rc = ensure(c, c->chunk_off, std::max<size_t>(1, choff.size()) * 8, cap))) return rc;
+    if ((rc = ensure(c, c->heads, std::max(1, E) * 8, cap))) return rc;
+    if ((rc = ensure(c, c->row_off, std::max(1, R) * 8, cap))) return rc;
+    if ((rc = ensure(c, c->row_nnz, std::max(1, R) * 8, cap))) return rc;
+    if ((rc = ensure(c, c->used, 8, cap))) return rc;
+    if ((rc = ensure(c, c->flags, 4, cap))) return rc;
+    if ((rc = ensure(c, c->fields_tab, nf * sizeof(FieldDev), cap))) return rc;
+    if ((rc = ensure(c, c->poly_off, nf * sizeof(int), cap))) return rc;
+    if ((rc = ensure(c, c->polys, polys.size() * sizeof(float2), cap))) return rc;
+    if ((rc = ensure(c, c->spots, sd.size() * sizeof(SpotDev), cap))) return rc;
+    if ((rc = ensure(c, c->scen_tab, n_scen * sizeof(ScenDev), cap))) return rc;
+    if ((rc = ensure(c, c->ledger, (size_t)n_scen * NLEDGER * 8, cap))) return rc;
+    if ((rc = ensure(c, c->stats, 16, cap))) return rc;
+    if (rows.size()) HIP_TRY(hipMemcpyAsync(c->rows.ptr, rows.data(), rows.size() * sizeof(RowDev), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->chunk_off.ptr, choff.data(), choff.size() * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->fields_tab.ptr, ftab.data(), nf * sizeof(FieldDev), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->poly_off.ptr, poff.data(), nf * sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->polys.ptr, polys.data(), polys.size() * sizeof(float2), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->spots.ptr, sd.data(), sd.size() * sizeof(SpotDev), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->scen_tab.ptr, stab.data(), n_scen * sizeof(ScenDev), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(c->ledger.ptr, 0, (size_t)n_scen * NLEDGER * 8, st));
+    HIP_TRY(hipMemsetAsync(c->stats.ptr, 0, 16, st));
+    HIP_TRY(hipMemsetAsync(c->heads.ptr, 0, std::max(1, E) * 8, st));
+    HIP_TRY(hipMemsetAsync(c->used.ptr, 0, 8, st));
+    HIP_TRY(hipMemsetAsync(c->flags.ptr, 0, 4, st));
+    // initial CSR capacity: the previous run's total, else a per-row guess
+    unsigned long long want = c->csr_cap_hint ? c->csr_cap_hint : (unsigned long long)std::max(R, 1) * 16384ull;
+    want = std::min<unsigned long long>(want, (unsigned long long)std::max(R, 1) * nvox);
+    if (c->csr_cap < want) {
+        if ((rc = grow_keep(c, c->csr_col, 0, want * 4, cap, st))) return rc;
+        if ((rc = grow_keep(c, c->csr_q, 0, want * 8, cap, st))) return rc;
+        c->csr_cap = want;
+    }
+    c->csr_valid = false;
+    c->slots_dirty = true;   // cleared again when every epoch has been compacted
+
+    QueueDev Q{};
+    Q.rows = (const RowDev *)c->rows.ptr;
+    Q.hist_per_lane = hpl;
+    Q.fields = (const FieldDev *)c->fields_tab.ptr;
+    Q.poly_off = (const int *)c->poly_off.ptr;
+    Q.polys = (const float2 *)c->polys.ptr;
+    Q.n_poly_total = (int)polys.size();
+    Q.spots = (const SpotDev *)c->spots.ptr;
+    Q.scen = (const ScenDev *)c->scen_tab.ptr;
+    Q.key0 = (uint32_t)(o->seed & 0xffffffffu);
+    Q.seed_hi = (uint32_t)(o->seed >> 32);
+    Q.physics = o->physics;
+    Q.grid = (unsigned long long *)c->slot_grid.ptr;
+    Q.l1 = (uint32_t *)c->slot_l1.ptr;
+    Q.l2 = (uint32_t *)c->slot_l2.ptr;
+    Q.nnz = (unsigned int *)c->slot_nnz.ptr;
+    Q.nvox = nvox; Q.n1 = n1; Q.n2 = n2;
+    Q.ledger = (unsigned long long *)c->ledger.ptr;
+    Q.stats = (unsigned long long *)c->stats.ptr;
+    Q.tables = c->d_tables;
+
+    int dev_cus = 256;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) dev_cus = prop.multiProcessorCount;
+    }
+    const int q_blocks = o->grid_blocks ? o->grid_blocks : dev_cus * 4;   // 16 waves per CU resident
+    while (c->events.size() < 4) {
+        hipEvent_t ev;
+        HIP_TRY(hipEventCreate(&ev));
+        c->events.push_back(ev);
+    }
+    HIP_TRY(hipEventRecord(c->events[0], st));
+    double transport_ms = 0.0;
+    unsigned long long used_host = 0;
+    for (int e = 0; e < E; ++e) {
+        QueueDev Qe = Q;
+        Qe.row_begin = e * G;
+        Qe.n_rows = std::min(R, (e + 1) * G) - e * G;
+        Qe.chunk_off = (const unsigned long long *)c->chunk_off.ptr + ep_choff[e];
+        Qe.n_chunks = ep_chunks[e];
+        Qe.head = (unsigned long long *)c->heads.ptr + e;
+        HIP_TRY(hipEventRecord(c->events[2], st));
+        if (Qe.n_chunks) HIP_TRY(launch_queue(c->geom, Qe, q_blocks, st));
+        HIP_TRY(hipEventRecord(c->events[3], st));
+        HIP_TRY(launch_csr_offsets((unsigned int *)c->slot_nnz.ptr, Qe.n_rows, Qe.row_begin,
+                                   (unsigned long long *)c->row_off.ptr, (unsigned long long *)c->row_nnz.ptr,
+                                   (unsigned long long *)c->used.ptr, ~0ull, (unsigned int *)c->flags.ptr, st));
+        unsigned long long used_now = 0;
+        HIP_TRY(hipMemcpyAsync(&used_now, c->used.ptr, 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->events[2], c->events[3]));
+        transport_ms += ms;
+        if (used_now > c->csr_cap) {   // grow, keeping the rows already written
+            const unsigned long long ncap = std::max<unsigned long long>(used_now, c->csr_cap * 2);
+            if ((rc = grow_keep(c, c->csr_col, used_host * 4, ncap * 4, cap, st))) return rc;
+            if ((rc = grow_keep(c, c->csr_q, used_host * 8, ncap * 8, cap, st))) return rc;
+            c->csr_cap = ncap;
+        }
+        HIP_TRY(launch_csr_compact(Qe, (const unsigned long long *)c->row_off.ptr, (int32_t *)c->csr_col.ptr,
+                                   (long long *)c->csr_q.ptr, c->csr_cap, (unsigned int *)c->flags.ptr, st));
+        used_host = used_now;
+    }
+    unsigned int fl = 0;
+    std::vector<unsigned long long> roff(std::max(R, 1)), rnnz(std::max(R, 1));
+    std::vector<long long> led((size_t)n_scen * NLEDGER);
+    unsigned long long stv[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(&fl, c->flags.ptr, 4, hipMemcpyDeviceToHost, st));
+    if (R) {
+        HIP_TRY(hipMemcpyAsync(roff.data(), c->row_off.ptr, R * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(rnnz.data(), c->row_nnz.ptr, R * 8, hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipMemcpyAsync(led.data(), c->ledger.ptr, led.size() * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(stv, c->stats.ptr, 16, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (fl & 2u) return fail(VPMC_E_DEVICE, "influence-matrix bitmap count mismatch");
+    c->slots_dirty = false;
+    std::vector<int64_t> rp((size_t)R + 1);
+    for (int r = 0; r < R; ++r) rp[r] = (int64_t)roff[r];
+    rp[R] = (int64_t)used_host;
+    for (int r = 0; r < R; ++r)
+        if (roff[r] + rnnz[r] != (r + 1 < R ? roff[r + 1] : used_host))
+            return fail(VPMC_E_DEVICE, "influence-matrix row offsets inconsistent at row %d", r);
+    HIP_TRY(hipMemcpy(row_ptr, rp.data(), rp.size() * 8, dev_out ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+    c->csr_total = used_host;
+    c->csr_rows = R;
+    c->csr_valid = true;
+    c->csr_flags = o->flags;
+    c->csr_cap_hint = used_host;
+    c->last_k = k;
+    if (ledger_mev)
+        for (size_t i = 0; i < led.size(); ++i) ledger_mev[i] = ldexp((double)led[i], -k);
+    // plan dose per scenario from its rows (contiguous in row order)
+    c->last_nscen = 0;
+    if (dose_gy) {
+        if ((rc = ensure(c, c->tallies, (size_t)n_scen * nvox * 8, cap))) return rc;
+        if (!dev_out && (rc = ensure(c, c->stage_dose, nvox * sizeof(float), cap))) return rc;
+        const int rows_per_scen = R / std::max(n_scen, 1);
+        for (int sc = 0; sc < n_scen; ++sc) {
+            unsigned long long *dense = (unsigned long long *)c->tallies.ptr + (size_t)sc * nvox;
+            HIP_TRY(hipMemsetAsync(dense, 0, nvox * 8, st));
+            const unsigned long long b = rows_per_scen ? roff[(size_t)sc * rows_per_scen] : 0;
+            const unsigned long long en = (sc + 1 < n_scen && rows_per_scen) ? roff[(size_t)(sc + 1) * rows_per_scen] : used_host;
+            HIP_TRY(launch_csr_scatter((const int32_t *)c->csr_col.ptr, (const long long *)c->csr_q.ptr, b, en, dense, st));
+            float *dd = dev_out ? dose_gy + (size_t)sc * nvox : (float *)c->stage_dose.ptr;
+            HIP_TRY(launch_dose((const long long *)dense, nullptr, 1, c->geom, ldexp(MEV_TO_J, -k), dd, nullptr, nvox, st));
+            if (!dev_out) HIP_TRY(hipMemcpyAsync(dose_gy + (size_t)sc * nvox, dd, nvox * 4, hipMemcpyDeviceToHost, st));
+        }
+        c->last_nscen = n_scen;
+    }
+    HIP_TRY(hipEventRecord(c->events[1], st));
+    HIP_TRY(hipStreamSynchronize(st));
+    float tot = 0.f;
+    HIP_TRY(hipEventElapsedTime(&tot, c->events[0], c->events[1]));
+    vpmc_stats S{};
+    S.transport_ms = transport_ms;
+    S.total_ms = tot;
+    S.steps = stv[0];
+    S.histories = stv[1];
+    S.launches = (uint64_t)E;
+    c->last_stats = S;
+    return VPMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vpmc_version(void) { return 101; }
+
+const char *vpmc_last_error(const vpmc_ctx *) { return g_err; }
+
+int vpmc_create(vpmc_ctx **out, int hip_device) {
+    if (!out) return fail(VPMC_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (hip_device < -1) return fail(VPMC_E_ARG, "hip_device must be >= -1");
+    vpmc_ctx *c = new (std::nothrow) vpmc_ctx();
+    if (!c) return fail(VPMC_E_OOM, "host allocation failed");
+    c->device = hip_device;
+    (void)host_tables();
+    if (hip_device >= 0) {
+        int n = 0;
+        hipError_t e = hipGetDeviceCount(&n);
+        if (e != hipSuccess || hip_device >= n) {
+            delete c;
+            return fail(VPMC_E_DEVICE, "HIP device %d not available (%d devices)", hip_device, n);
+        }
+        std::vector<float> blob(TAB_FLOATS);
+        pack_device_tables(blob.data());
+        if ((e = hipSetDevice(hip_device)) != hipSuccess ||
+            (e = hipMalloc(&c->d_tables, sizeof(float) * TAB_FLOATS)) != hipSuccess ||
+            (e = hipMemcpy(c->d_tables, blob.data(), sizeof(float) * TAB_FLOATS, hipMemcpyHostToDevice)) !=
+                hipSuccess) {
+            if (c->d_tables) (void)hipFree(c->d_tables);
+            delete c;
+            return fail(VPMC_E_DEVICE, "table upload failed: %s", hipGetErrorString(e));
+        }
+        c->bytes = sizeof(float) * TAB_FLOATS;
+    }
+    *out = c;
+    return VPMC_OK;
+}
+
+void vpmc_destroy(vpmc_ctx *c) {
+    if (!c) return;
+    if (c->device >= 0) {
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
+        if (c->d_tables) (void)hipFree(c->d_tables);
+        release(c->hu_buf);
+        for (auto &f : c->fields) release(f.poly_buf);
+        for (DevBuf *b : {&c->tallies, &c->qbatch, &c->s2, &c->ledger, &c->spots, &c->offsets,
+                          &c->stage_dose, &c->stage_sigma, &c->stats, &c->slot_grid, &c->slot_l1, &c->slot_l2,
+                          &c->slot_nnz, &c->rows, &c->chunk_off, &c->heads, &c->row_off, &c->row_nnz, &c->used,
+                          &c->flags, &c->fields_tab, &c->poly_off, &c->polys, &c->scen_tab, &c->csr_col,
+                          &c->csr_q})
+            release(*b);
+        for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    }
+    delete c;
+}
+
+int vpmc_table_host(int material, int which, double *out, int n) {
+    if (material < 0 || material >= NMAT || which < 0 || which > 4 || !out || n < 0)
+        return fail(VPMC_E_ARG, "bad table request");
+    const HostTables &t = host_tables();
+    const double *src = which == 0 ? t.E : which == 1 ? t.R[material] : which == 2 ? t.W2[material]
+                      : which == 3 ? t.T[material] : t.SN[material];
+    memcpy(out, src, sizeof(double) * std::min(n, NE));
+    return NE;
+}
+
+int vpmc_load_geometry(vpmc_ctx *c, int kind, const int16_t *hu, int nx, int ny, int nz,
+                       const float spacing_mm[3], const float origin_mm[3], unsigned flags) {
+    if (!c) return fail(VPMC_E_ARG, "ctx is NULL");
+    if (kind != VPMC_GEOM_WATER && kind != VPMC_GEOM_HU) return fail(VPMC_E_ARG, "unknown geometry kind %d", kind);
+    if (nx < 1 || ny < 1 || nz < 1) return fail(VPMC_E_ARG, "grid dimensions must be >= 1");
+    const size_t nvox = (size_t)nx * ny * nz;
+    if (nvox >= ((size_t)1 << 31)) return fail(VPMC_E_ARG, "grid has %zu voxels (max 2^31-1)", nvox);
+    if (!spacing_mm || !origin_mm || !finite3(spacing_mm) || !finite3(origin_mm))
+        return fail(VPMC_E_ARG, "spacing/origin missing or not finite");
+    if (!(spacing_mm[0] > 0 && spacing_mm[1] > 0 && spacing_mm[2] > 0))
+        return fail(VPMC_E_ARG, "spacing must be positive");
+    if (kind == VPMC_GEOM_HU && !hu) return fail(VPMC_E_ARG, "HU geometry needs hu data");
+    if (flags & ~VPMC_DEVICE_PTRS) return fail(VPMC_E_ARG, "unknown flags");
+    if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
+    HIP_TRY(hipSetDevice(c->device));
+    GeomDev g{};
+    g.kind = kind;
+    g.nx = nx; g.ny = ny; g.nz = nz;
+    for (int k = 0; k < 3; ++k) { g.sp[k] = spacing_mm[k]; g.lo[k] = origin_mm[k]; }
+    if (kind == VPMC_GEOM_HU) {
+        int rc = ensure(c, c->hu_buf, nvox * sizeof(int16_t), 0);
+        if (rc) return rc;
+        HIP_TRY(hipMemcpy(c->hu_buf.ptr, hu, nvox * sizeof(int16_t),
+                          (flags & VPMC_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+        g.hu = (const int16_t *)c->hu_buf.ptr;
+    }
+    c->geom = g;
+    c->nvox = nvox;
+    c->has_geom = true;
+    c->last_nscen = 0;
+    return VPMC_OK;
+}
+
+int vpmc_set_aperture(vpmc_ctx *c, int field_id, const vpmc_beam *beam, const float *xy_mm, int n_vertices,
+                      const vpmc_block *block, const vpmc_rs *rs) {
+    if (!c) return fail(VPMC_E_ARG, "ctx is NULL");
+    if (field_id < 0 || field_id >= VPMC_MAX_FIELDS)
+        return fail(VPMC_E_ARG, "field_id %d outside [0, %d)", field_id, VPMC_MAX_FIELDS);
+    int rc = validate_beam(beam);
+    if (rc) return rc;
+    if (n_vertices < 0) return fail(VPMC_E_POLYGON, "n_vertices < 0");
+    if (!block && n_vertices != 0) return fail(VPMC_E_ARG, "polygon given without a block");
+    if (block) {
+        if (!(block->thickness_mm > 0 && isfinite(block->thickness_mm)) ||
+            !(block->density_gcc > 0 && isfinite(block->density_gcc)) ||
+            !(block->downstream_mm >= 0 && isfinite(block->downstream_mm)))
+            return fail(VPMC_E_ARG, "block thickness/density must be > 0 and downstream >= 0");
+        if ((rc = validate_polygon(xy_mm, n_vertices))) return rc;
+    }
+    double rs_t = 0.0;
+    if (rs) {
+        if (!(rs->wet_mm > 0 && isfinite(rs->wet_mm)) || !(rs->diameter_mm > 0 && isfinite(rs->diameter_mm)) ||
+            !(rs->downstream_mm >= 0 && isfinite(rs->downstream_mm)))
+            return fail(VPMC_E_ARG, "range shifter wet/diameter must be > 0 and downstream >= 0");
+        if (block && rs->downstream_mm < block->downstream_mm + block->thickness_mm)
+            return fail(VPMC_E_ARG, "range shifter overlaps or lies downstream of the block");
+        rs_t = rs_thickness_mm(rs->wet_mm);
+    }
+    FieldState &f = c->fields[field_id];
+    FieldDev d{};
+    for (int k = 0; k < 3; ++k) {
+        d.iso[k] = beam->iso_mm[k];
+        d.ex[k] = beam->ex[k];
+        d.ey[k] = beam->ey[k];
+        d.ez[k] = beam->ez[k];
+    }
+    std::vector<float2> poly;
+    if (block) {
+        d.has_block = 1;
+        d.nv = n_vertices;
+        d.blk_zu = -(block->downstream_mm + block->thickness_mm);
+        d.blk_zd = -block->downstream_mm;
+        d.blk_rho = block->density_gcc;
+        poly.resize(n_vertices);
+        for (int i = 0; i < n_vertices; ++i) poly[i] = make_float2(xy_mm[2 * i], xy_mm[2 * i + 1]);
+    }
+    if (rs) {
+        d.has_rs = 1;
+        d.rs_zd = -rs->downstream_mm;
+        d.rs_zu = (float)(-(rs->downstream_mm + rs_t));
+        d.rs_r2 = 0.25f * rs->diameter_mm * rs->diameter_mm;
+        d.rs_rho = (float)kMaterials[MAT_PMMA].density;
+    }
+    if (c->device >= 0 && !poly.empty()) {
+        HIP_TRY(hipSetDevice(c->device));
+        if ((rc = ensure(c, f.poly_buf, poly.size() * sizeof(float2), 0))) return rc;
+        HIP_TRY(hipMemcpy(f.poly_buf.ptr, poly.data(), poly.size() * sizeof(float2), hipMemcpyHostToDevice));
+    }
+    d.poly = (const float2 *)f.poly_buf.ptr;
+    f.dev = d;
+    f.poly = std::move(poly);
+    f.set = true;
+    return VPMC_OK;
+}
+
+int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spots, const vpmc_scenario *scen,
+                   int n_scen, const vpmc_opts *o, float *dose_gy, float *sigma_gy, double *ledger_mev,
+                   int64_t *row_ptr) {
+    if (!c) return fail(VPMC_E_ARG, "ctx is NULL");
+    if (!o) return fail(VPMC_E_ARG, "opts is NULL");
+    if (!c->has_geom) return fail(VPMC_E_STATE, "no geometry loaded");
+    if (field_id < 0 || field_id >= VPMC_MAX_FIELDS) return fail(VPMC_E_ARG, "field_id out of range");
+    if (!c->fields[field_id].set) return fail(VPMC_E_STATE, "field %d has no aperture/beam set", field_id);
+    double T = 0.0;
+    int rc;
+    if ((rc = validate_spots(spots, n_spots, &T))) return rc;
+    if ((rc = validate_scen(scen, n_scen))) return rc;
+    if (o->physics & ~VPMC_PHYS_ALL) return fail(VPMC_E_ARG, "unknown physics bits");
+    if (o->n_batches < 0 || o->n_batches > 1024) return fail(VPMC_E_ARG, "n_batches outside [0, 1024]");
+    if (o->block_threads && (o->block_threads < 64 || o->block_threads > 1024 || o->block_threads % 64))
+        return fail(VPMC_E_ARG, "block_threads must be a multiple of 64 in [64, 1024]");
+    if (o->grid_blocks < 0) return fail(VPMC_E_ARG, "grid_blocks < 0");
+    if (o->hist_per_lane < 0 || o->hist_per_lane > 4096) return fail(VPMC_E_ARG, "hist_per_lane outside [0, 4096]");
+    if (o->max_slots < 0) return fail(VPMC_E_ARG, "max_slots < 0");
+    if (o->flags & ~(VPMC_DEVICE_PTRS | VPMC_GRAPH)) return fail(VPMC_E_ARG, "unknown flags");
+    if (o->output == VPMC_OUT_CSR) {
+        if (!row_ptr) return fail(VPMC_E_ARG, "CSR output needs row_ptr");
+        if (sigma_gy) return fail(VPMC_E_ARG, "sigma_gy is not produced in CSR mode");
+        int k = 0;
+        if ((rc = pick_k(o, T, &k))) return rc;
+        if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
+        HIP_TRY(hipSetDevice(c->device));
+        std::vector<BatchField> bf{{field_id, spots, n_spots}};
+        return run_csr(c, bf, scen, n_scen, o, k, dose_gy, ledger_mev, row_ptr);
+    } else if (o->output != VPMC_OUT_DOSE) {
+        return fail(VPMC_E_ARG, "unknown output mode %d", o->output);
+    }
+    const int B = o->n_batches >= 2 ? o->n_batches : 1;
+    if (sigma_gy && B < 2) return fail(VPMC_E_ARG, "sigma_gy needs n_batches >= 2");
+    if (!dose_gy && !sigma_gy && !ledger_mev) return fail(VPMC_E_ARG, "no output requested");
+    int k = 0;
+    if ((rc = pick_k(o, T, &k))) return rc;
+    if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
+
+    const size_t nvox = c->nvox;
+    const bool dev_out = (o->flags & VPMC_DEVICE_PTRS) != 0;
+    const size_t cap = o->max_device_bytes;
+    hipStream_t st = (hipStream_t)o->hip_stream;
+    HIP_TRY(hipSetDevice(c->device));
+    if ((rc = ensure(c, c->tallies, (size_t)n_scen * nvox * sizeof(long long), cap))) return rc;
+    if (B > 1) {
+        if ((rc = ensure(c, c->qbatch, nvox * sizeof(unsigned long long), cap))) return rc;
+        if ((rc = ensure(c, c->s2, nvox * sizeof(double), cap))) return rc;
+    }
+    if ((rc = ensure(c, c->ledger, (size_t)n_scen * NLEDGER * sizeof(unsigned long long), cap))) return rc;
+    if ((rc = ensure(c, c->spots, std::max(1, n_spots) * sizeof(SpotDev), cap))) return rc;
+    if ((rc = ensure(c, c->stats, 2 * sizeof(unsigned long long), cap))) return rc;
+    if ((rc = ensure(c, c->offsets, (size_t)B * (n_spots + 1) * sizeof(unsigned long long), cap))) return rc;
+    if (!dev_out) {
+        if (dose_gy && (rc = ensure(c, c->stage_dose, nvox * sizeof(float), cap))) return rc;
+        if (sigma_gy && (rc = ensure(c, c->stage_sigma, nvox * sizeof(float), cap))) return rc;
+    }
+
+    // spots and per-batch work offsets
+    std::vector<SpotDev> sd(std::max(1, n_spots));
+    std::vector<unsigned long long> off((size_t)B * (n_spots + 1), 0ull);
+    for (int i = 0; i < n_spots; ++i) {
+        const vpmc_spot &s = spots[i];
+        SpotDev &d = sd[i];
+        d.x = s.x_mm; d.y = s.y_mm; d.e0 = s.energy_mev; d.sigma = s.sigma_mm; d.esig = s.energy_sigma_mev;
+        d.emax = (float)std::min((double)s.energy_mev + 6.0 * s.energy_sigma_mev, E_HI);
+        d.nh = s.n_histories;
+        d.scale = s.n_histories ? (float)ldexp((double)s.weight / (double)s.n_histories, k) : 0.0f;
+    }
+    for (int b = 0; b < B; ++b) {
+        unsigned long long *ob = off.data() + (size_t)b * (n_spots + 1);
+        for (int i = 0; i < n_spots; ++i) {
+            const unsigned long long nh = spots[i].n_histories;
+            const unsigned long long nb = nh > (unsigned long long)b ? (nh - b + B - 1) / B : 0ull;
+            ob[i + 1] = ob[i] + nb;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(c->spots.ptr, sd.data(), sd.size() * sizeof(SpotDev), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->offsets.ptr, off.data(), off.size() * sizeof(unsigned long long),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(c->ledger.ptr, 0, (size_t)n_scen * NLEDGER * sizeof(unsigned long long), st));
+    HIP_TRY(hipMemsetAsync(c->stats.ptr, 0, 2 * sizeof(unsigned long long), st));
+    const size_t n_launch_max = (size_t)n_scen * B;
+    while (c->events.size() < 2 * n_launch_max + 2) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        c->events.push_back(e);
+    }
+    size_t n_launch = 0;
+    HIP_TRY(hipEventRecord(c->events[0], st));
+
+    const FieldDev &fd = c->fields[field_id].dev;
+    const int threads = 256;
+    const double mev_scale = ldexp(MEV_TO_J, -k);
+    for (int sc = 0; sc < n_scen; ++sc) {
+        long long *tally = (long long *)c->tallies.ptr + (size_t)sc * nvox;
+        HIP_TRY(hipMemsetAsync(tally, 0, nvox * sizeof(long long), st));
+        if (B > 1) HIP_TRY(hipMemsetAsync(c->s2.ptr, 0, nvox * sizeof(double), st));
+        if (B > 1) HIP_TRY(hipMemsetAsync(c->qbatch.ptr, 0, nvox * sizeof(unsigned long long), st));
+        for (int b = 0; b < B; ++b) {
+            const unsigned long long *ob = (const unsigned long long *)c->offsets.ptr + (size_t)b * (n_spots + 1);
+            const unsigned long long items = off[(size_t)b * (n_spots + 1) + n_spots];
+            if (items == 0) continue;
+            LaunchDev L{};
+            L.spots = (const SpotDev *)c->spots.ptr;
+            L.item_off = ob;
+            L.n_spots = n_spots;
+            L.n_items = items;
+            L.batch = b;
+            L.n_batches = B;
+            L.key0 = (uint32_t)(o->seed & 0xffffffffu);
+            L.key1 = (uint32_t)(o->seed >> 32) ^ (uint32_t)field_id;
+            L.physics = o->physics;
+            for (int q = 0; q < 3; ++q) L.shift[q] = scen[sc].shift_mm[q];
+            L.range_scale = scen[sc].range_scale;
+            L.tally = B > 1 ? (unsigned long long *)c->qbatch.ptr : (unsigned long long *)tally;
+            L.ledger = (unsigned long long *)c->ledger.ptr + (size_t)sc * NLEDGER;
+            L.tables = c->d_tables;
+            L.stats = (unsigned long long *)c->stats.ptr;
+            unsigned long long want = (items + threads - 1) / threads;
+            const unsigned long long maxb = o->grid_blocks ? (unsigned long long)o->grid_blocks : 4096ull;
+            const int blocks = (int)std::min(want, maxb);
+            HIP_TRY(hipEventRecord(c->events[2 + 2 * n_launch], st));
+            HIP_TRY(launch_transport(c->geom, fd, L, blocks, threads, st));
+            HIP_TRY(hipEventRecord(c->events[3 + 2 * n_launch], st));
+            ++n_launch;
+            if (B > 1)
+                HIP_TRY(launch_fold_batch((unsigned long long *)c->qbatch.ptr, tally, (double *)c->s2.ptr, nvox, st));
+        }
+        float *dd = dose_gy ? (dev_out ? dose_gy + (size_t)sc * nvox : (float *)c->stage_dose.ptr) : nullptr;
+        float *ss = sigma_gy ? (dev_out ? sigma_gy + (size_t)sc * nvox : (float *)c->stage_sigma.ptr) : nullptr;
+        if (dd || ss)
+            HIP_TRY(launch_dose(tally, B > 1 ? (const double *)c->s2.ptr : nullptr, B, c->geom, mev_scale, dd, ss,
+                                nvox, st));
+        if (!dev_out) {
+            if (dd) HIP_TRY(hipMemcpyAsync(dose_gy + (size_t)sc * nvox, dd, nvox * sizeof(float), hipMemcpyDeviceToHost, st));
+            if (ss) HIP_TRY(hipMemcpyAsync(sigma_gy + (size_t)sc * nvox, ss, nvox * sizeof(float), hipMemcpyDeviceToHost, st));
+        }
+    }
+    std::vector<long long> led((size_t)n_scen * NLEDGER);
+    unsigned long long stv[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(led.data(), c->ledger.ptr, led.size() * sizeof(long long), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(stv, c->stats.ptr, sizeof stv, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(c->events[1], st));
+    HIP_TRY(hipStreamSynchronize(st));
+    vpmc_stats S{};
+    float ms = 0.0f;
+    for (size_t i = 0; i < n_launch; ++i) {
+        HIP_TRY(hipEventElapsedTime(&ms, c->events[2 + 2 * i], c->events[3 + 2 * i]));
+        S.transport_ms += ms;
+    }
+    HIP_TRY(hipEventElapsedTime(&ms, c->events[0], c->events[1]));
+    S.total_ms = ms;
+    S.steps = stv[0];
+    S.histories = stv[1];
+    S.launches = n_launch;
+    c->last_stats = S;
+    if (ledger_mev)
+        for (size_t i = 0; i < led.size(); ++i) ledger_mev[i] = ldexp((double)led[i], -k);
+    c->last_k = k;
+    c->last_nscen = n_scen;
+    return VPMC_OK;
+}
+
+int vpmc_last_stats(const vpmc_ctx *c, vpmc_stats *out) {
+    if (!c || !out) return fail(VPMC_E_ARG, "ctx/out is NULL");
+    *out = c->last_stats;
+    return VPMC_OK;
+}
+
+int vpmc_run_batched(vpmc_ctx *c, const int *field_ids, const vpmc_spot *const *spots, const int *n_spots,
+                     int n_fields, const vpmc_scenario *scen, int n_scen, const vpmc_opts *o, float *dose_gy,
+                     double *ledger_mev, int64_t *row_ptr) {
+    if (!c) return fail(VPMC_E_ARG, "ctx is NULL");
+    if (!o) return fail(VPMC_E_ARG, "opts is NULL");
+    if (!c->has_geom) return fail(VPMC_E_STATE, "no geometry loaded");
+    if (n_fields < 1 || n_fields > VPMC_MAX_FIELDS || !field_ids || !spots || !n_spots)
+        return fail(VPMC_E_ARG, "need 1..%d fields with their spot arrays", VPMC_MAX_FIELDS);
+    if (!row_ptr) return fail(VPMC_E_ARG, "row_ptr is NULL");
+    int rc;
+    double T = 0.0;
+    std::vector<BatchField> bf;
+    for (int f = 0; f < n_fields; ++f) {
+        const int id = field_ids[f];
+        if (id < 0 || id >= VPMC_MAX_FIELDS) return fail(VPMC_E_ARG, "field id %d out of range", id);
+        if (!c->fields[id].set) return fail(VPMC_E_STATE, "field %d has no aperture/beam set", id);
+        for (int g = 0; g < f; ++g)
+            if (field_ids[g] == id) return fail(VPMC_E_ARG, "field id %d repeated", id);
+        double Tf = 0.0;
+        if ((rc = validate_spots(spots[f], n_spots[f], &Tf))) return rc;
+        T += Tf;
+        bf.push_back({id, spots[f], n_spots[f]});
+    }
+    if ((rc = validate_scen(scen, n_scen))) return rc;
+    if (o->physics & ~VPMC_PHYS_ALL) return fail(VPMC_E_ARG, "unknown physics bits");
+    if (o->flags & ~(VPMC_DEVICE_PTRS | VPMC_GRAPH)) return fail(VPMC_E_ARG, "unknown flags");
+    if (o->hist_per_lane < 0 || o->hist_per_lane > 4096) return fail(VPMC_E_ARG, "hist_per_lane outside [0, 4096]");
+    if (o->max_slots < 0 || o->grid_blocks < 0) return fail(VPMC_E_ARG, "negative tuning value");
+    int k = 0;
+    if ((rc = pick_k(o, T, &k))) return rc;
+    if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
+    HIP_TRY(hipSetDevice(c->device));
+    return run_csr(c, bf, scen, n_scen, o, k, dose_gy, ledger_mev, row_ptr);
+}
+
+int vpmc_copy_csr(vpmc_ctx *c, int32_t *col, float *val, int64_t *q_raw) {
+    if (!c) return fail(VPMC_E_ARG, "ctx is NULL");
+    if (!c->csr_valid) return fail(VPMC_E_STATE, "no CSR run to copy");
+    if (!col && !val && !q_raw) return fail(VPMC_E_ARG, "no output");
+    const size_t n = c->csr_total;
+    if (n == 0) return VPMC_OK;
+    const bool dev = (c->csr_flags & VPMC_DEVICE_PTRS) != 0;
+    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIP_TRY(hipSetDevice(c->device));
+    if (col) HIP_TRY(hipMemcpy(col, c->csr_col.ptr, n * 4, kind));
+    if (q_raw) HIP_TRY(hipMemcpy(q_raw, c->csr_q.ptr, n * 8, kind));
+    if (val) {
+        float *dst = val;
+        if (!dev) {
+            int rc = ensure(c, c->stage_dose, n * sizeof(float), 0);
+            if (rc) return rc;
+            dst = (float *)c->stage_dose.ptr;
+        }
+        HIP_TRY(launch_csr_values((const int32_t *)c->csr_col.ptr, (const long long *)c->csr_q.ptr, n, c->geom,
+                                  ldexp(MEV_TO_J, -c->last_k), dst, nullptr));
+        HIP_TRY(hipDeviceSynchronize());
+        if (!dev) HIP_TRY(hipMemcpy(val, dst, n * 4, hipMemcpyDeviceToHost));
+    }
+    return VPMC_OK;
+}
+
+int vpmc_last_tally(vpmc_ctx *c, int scen_index, int64_t *q_out, int *k_out, unsigned flags) {
+    if (!c) return fail(VPMC_E_ARG, "ctx is NULL");
+    if (!q_out && !k_out) return fail(VPMC_E_ARG, "no output");
+    if (c->last_nscen == 0) return fail(VPMC_E_STATE, "no dense run to copy");
+    if (scen_index < 0 || scen_index >= c->last_nscen) return fail(VPMC_E_ARG, "scenario index out of range");
+    if (k_out) *k_out = c->last_k;
+    if (q_out) {
+        HIP_TRY(hipSetDevice(c->device));
+        HIP_TRY(hipMemcpy(q_out, (long long *)c->tallies.ptr + (size_t)scen_index * c->nvox,
+                          c->nvox * sizeof(long long),
+                          (flags & VPMC_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    }
+    return VPMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,154 @@
+// Internal definitions shared by the host runtime and the gfx950 kernels of
+// libvpmc.  Nothing here is part of the public C ABI (include/vpmc.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vpmc {
+
+// ---------------------------------------------------------------- tables
+// Per-material tables X(E) (Methods A): NE nodes log-spaced on [1, 256] MeV.
+constexpr int NE = 256;
+constexpr int NMAT = 5;
+constexpr double E_LO = 1.0;
+constexpr double E_HI = 256.0;
+enum Material { MAT_WATER = 0, MAT_AIR = 1, MAT_PMMA = 2, MAT_BRASS = 3, MAT_BONE = 4 };
+
+// FP32 device blob: [E nodes][1/(E_i+1 - E_i)] then per material
+// [R][dE/dR per segment][R_i+1 - R_i][omega^2][T][Sigma_nuc], NE floats each.
+enum { TAB_E = 0, TAB_INVDE = NE, TAB_MAT0 = 2 * NE, TAB_PER_MAT = 6 * NE };
+enum { T_R = 0, T_SLOPE = 1, T_DR = 2, T_W2 = 3, T_T = 4, T_SN = 5 };
+constexpr int TAB_FLOATS = 2 * NE + NMAT * 6 * NE;   // 8192 floats = 32 KiB of LDS
+
+struct MaterialDef {
+    double z_over_a, mean_exc_ev, rad_len_gcm2, nuc_coeff, density;
+};
+extern const MaterialDef kMaterials[NMAT];
+
+// FP64 host tables (generated once per process)
+struct HostTables {
+    double E[NE];
+    double R[NMAT][NE], W2[NMAT][NE], T[NMAT][NE], SN[NMAT][NE];
+};
+const HostTables &host_tables();
+void pack_device_tables(float *blob /* TAB_FLOATS */);
+double range_host(int m, double E);           // piecewise-linear CSDA range (g/cm^2)
+double rs_thickness_mm(double wet_mm);        // PMMA slab thickness for a given WET
+
+// model constants (readings of the paper's unstated physics)
+constexpr float STEP_FRACTION = 0.25f;     // step <= 1/4 residual range
+constexpr float NUC_F_LOCAL = 0.10f;       // nuclear event: share deposited locally
+constexpr float NUC_F_ESCAPE = 0.30f;      // share carried off by neutral secondaries
+constexpr float NUC_SIGMA_RAD = 0.15f;     // deflection of the leading secondary
+constexpr float EDGE_PUSH_MM = 1e-4f;      // push across an aperture edge (FP32)
+constexpr int MAX_STEPS = 1000000;         // safety bound on steps per VP
+constexpr double MEV_TO_J = 1.602176634e-13;
+
+enum { L_GRID = 0, L_RS = 1, L_BLOCK = 2, L_ESCAPED = 3, L_NUC = 4, NLEDGER = 6 };
+enum { PH_STRAGGLE = 1, PH_MCS = 2, PH_NUCLEAR = 4 };
+
+// ------------------------------------------------------- kernel arguments
+struct GeomDev {
+    int kind, nx, ny, nz;
+    float sp[3], lo[3];
+    const int16_t *hu;
+};
+
+struct FieldDev {
+    float iso[3], ex[3], ey[3], ez[3];
+    int has_block, nv;
+    const float2 *poly;
+    float blk_zu, blk_zd, blk_rho;
+    int has_rs;
+    float rs_zu, rs_zd, rs_r2, rs_rho;
+};
+
+struct SpotDev {
+    float x, y, e0, sigma, esig, emax, scale;   // scale = w/N * 2^k
+    uint32_t nh;
+};
+
+struct LaunchDev {
+    const SpotDev *spots;
+    const unsigned long long *item_off;   // [n_spots + 1] prefix of items per spot
+    int n_spots;
+    unsigned long long n_items;
+    int batch, n_batches;
+    uint32_t key0, key1;
+    unsigned physics;
+    float shift[3];
+    float range_scale;
+    unsigned long long *tally;            // int64 fixed point, two's complement
+    unsigned long long *ledger;           // [NLEDGER]
+    unsigned long long *stats;            // [2]: steps, histories
+    const float *tables;                  // TAB_FLOATS
+};
+
+constexpr int POLY_LDS = 1024;  // == VPMC_MAX_VERTICES
+
+// ------------------------------------------- influence-matrix (CSR) mode
+// One row = (scenario, field, spot).  Rows are processed in epochs of at
+// most kMaxSlots rows; row (row_begin + i) of an epoch owns slot i: a dense
+// int64 grid plus a two-level bitmap of touched voxels (L1: one bit per
+// voxel, L2: one bit per non-zero L1 word).
+constexpr int kMaxSlots = 1024;
+
+struct RowDev {
+    int field;            // index into the field table of the launch
+    uint32_t field_id;    // caller's field id (part of the Philox key)
+    uint32_t spot;        // spot index within its field (Philox counter)
+    uint32_t spot_global; // index into the flattened spot table
+    int scen;
+    uint32_t n_hist;
+};
+
+struct ScenDev {
+    float shift[3];
+    float range_scale;
+};
+
+struct QueueDev {
+    const RowDev *rows;
+    const unsigned long long *chunk_off;  // [n_rows + 1] chunk prefix of this epoch's rows
+    int row_begin, n_rows;
+    unsigned long long n_chunks;
+    unsigned long long *head;             // work-queue counter of this epoch
+    int hist_per_lane;                    // one chunk = 64 * hist_per_lane histories
+    const FieldDev *fields;
+    const int *poly_off;                  // per field: offset into polys
+    const float2 *polys;
+    int n_poly_total;
+    const SpotDev *spots;
+    const ScenDev *scen;
+    uint32_t key0, seed_hi;
+    unsigned physics;
+    unsigned long long *grid;             // [slots][nvox]
+    uint32_t *l1, *l2;                    // [slots][n1], [slots][n2]
+    unsigned int *nnz;                    // [slots]
+    size_t nvox, n1, n2;
+    unsigned long long *ledger;           // [n_scen][NLEDGER]
+    unsigned long long *stats;            // [2]
+    const float *tables;
+};
+
+hipError_t launch_queue(const GeomDev &g, const QueueDev &Q, int blocks, hipStream_t s);
+hipError_t launch_csr_offsets(unsigned int *nnz, int n_rows, int row_begin, unsigned long long *row_off,
+                              unsigned long long *row_nnz, unsigned long long *used, unsigned long long capacity,
+                              unsigned int *flags, hipStream_t s);
+hipError_t launch_csr_compact(const QueueDev &Q, const unsigned long long *row_off, int32_t *col, long long *qv,
+                              unsigned long long capacity, unsigned int *flags, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_csr_scatter(const int32_t *col, const long long *qv, unsigned long long begin,
+                              unsigned long long end, unsigned long long *dense, hipStream_t s);
+hipError_t launch_csr_values(const int32_t *col, const long long *qv, size_t n, const GeomDev &g,
+                             double mev_scale, float *val, hipStream_t s);
+
+// launchers (vpmc_kernels.hip)
+hipError_t launch_transport(const GeomDev &g, const FieldDev &f, const LaunchDev &L, int blocks,
+                            int threads, hipStream_t s);
+hipError_t launch_fold_batch(unsigned long long *q_batch, long long *q_total, double *s2, size_t n,
+                             hipStream_t s);
+hipError_t launch_dose(const long long *q, const double *s2, int n_batches, const GeomDev &g,
+                       double mev_scale, float *dose, float *sigma, size_t n, hipStream_t s);
+
+}  // namespace vpmc

@@ -1,0 +1,895 @@
+// gfx950 kernels of the virtual-particle (VP) transport.
+//
+// One lane carries one VP history at a time (Methods A: every VP, primary or
+// secondary, follows the same model, so lanes of a wavefront run the same
+// code).  Per launch each workgroup stages the 32 KiB of physics tables and
+// the aperture polygon in LDS.  The step loop is FP32; the VP energy is kept
+// as an unevaluated FP32 pair so per-step losses telescope without drift;
+// every deposit is converted to int64 fixed point and added with a 64-bit
+// atomic, which makes the tally independent of execution order.
+#include <math.h>
+
+#include "vpmc_internal.hpp"
+
+namespace vpmc {
+namespace {
+
+constexpr float kELo = 1.0f;
+constexpr float kSegPerLog2 = (float)(NE - 1) / 8.0f;   // E_HI / E_LO = 2^8
+constexpr int kThreads = 256;
+
+// ------------------------------------------------------------ random numbers
+// Philox4x32-10 (Salmon et al., SC'11); counter (block, history, spot, 0),
+// key (seed_lo, seed_hi ^ field).
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+// top 23 bits + 1/2, times 2^-23: exact in FP32, strictly inside (0, 1)
+__device__ __forceinline__ float unit_open(uint32_t w) {
+    return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
+}
+
+struct Lane {
+    float px, py, pz, dx, dy, dz;
+    float E, Elo;             // energy as an unevaluated pair E + Elo
+    uint32_t nblk, spot, hist, k0, k1;
+    unsigned physics;
+    uint32_t nsteps;
+};
+
+__device__ __forceinline__ uint4 draw(Lane &v) {
+    const uint4 w = philox4x32_10(make_uint4(v.nblk, v.hist, v.spot, 0u), v.k0, v.k1);
+    v.nblk++;
+    return w;
+}
+
+// step normals: hardware sin/cos take the angle in turns
+__device__ __forceinline__ void box_muller_fast(uint32_t a, uint32_t b, float &z1, float &z2) {
+    const float r = sqrtf(-2.0f * __logf(unit_open(a)));
+    const float t = unit_open(b);
+    z1 = r * __builtin_amdgcn_cosf(t);
+    z2 = r * __builtin_amdgcn_sinf(t);
+}
+
+// ------------------------------------------------------------ table lookups
+// segment i with E_i <= E < E_i+1, clamped to [0, NE-2]
+__device__ __forceinline__ int seg_of(const float *tab, float E) {
+    int i = (int)(__log2f(fmaxf(E, kELo)) * kSegPerLog2);
+    i = min(max(i, 0), NE - 2);
+    while (i > 0 && E < tab[TAB_E + i]) --i;
+    while (i < NE - 2 && E >= tab[TAB_E + i + 1]) ++i;
+    return i;
+}
+
+__device__ __forceinline__ float node_interp(const float *tab, const float *y, float E) {
+    const int i = seg_of(tab, E);
+    float f = (E - tab[TAB_E + i]) * tab[TAB_INVDE + i];
+    f = fminf(fmaxf(f, 0.0f), 1.0f);
+    return fmaf(f, y[i + 1] - y[i], y[i]);
+}
+
+// Energy lost while traversing the areal density r (g/cm^2), starting at
+// E = E_i + x in segment i of the piecewise-linear CSDA relation E(R).  The
+// loss is accumulated piece by piece (each piece is a short product), so it
+// keeps full relative precision instead of being a difference of two nearly
+// equal energies.
+__device__ __forceinline__ float csda_loss(const float *tm, int i, float x, float slope, float r) {
+    const float rem = x / slope;
+    if (r <= rem) return r * slope;
+    float dE = x;
+    r -= rem;
+    for (int j = i - 1; j >= 0; --j) {
+        const float sj = tm[T_SLOPE * NE + j], dRj = tm[T_DR * NE + j];
+        if (r <= dRj) return fmaf(r, sj, dE);
+        dE = fmaf(dRj, sj, dE);
+        r -= dRj;
+    }
+    return dE;
+}
+
+__device__ __forceinline__ void rotate_dir(Lane &v, float ax, float ay) {
+    const float th2 = ax * ax + ay * ay;
+    if (th2 == 0.0f) return;
+    const float th = sqrtf(th2);
+    const float sg = copysignf(1.0f, v.dz);
+    const float a = -1.0f / (sg + v.dz);
+    const float b = v.dx * v.dy * a;
+    const float e1x = 1.0f + sg * v.dx * v.dx * a, e1y = sg * b, e1z = -sg * v.dx;
+    const float e2x = b, e2y = sg + v.dy * v.dy * a, e2z = -v.dy;
+    float sn, c;
+    __sincosf(th, &sn, &c);
+    const float k = sn / th;
+    float nx = c * v.dx + k * (ax * e1x + ay * e2x);
+    float ny = c * v.dy + k * (ax * e1y + ay * e2y);
+    float nz = c * v.dz + k * (ax * e1z + ay * e2z);
+    const float inv = rsqrtf(nx * nx + ny * ny + nz * nz);
+    v.dx = nx * inv;
+    v.dy = ny * inv;
+    v.dz = nz * inv;
+}
+
+__device__ __forceinline__ void sub_energy(Lane &v, float dE) {
+    // (E, Elo) -= dE with an error-free two-sum, then renormalise
+    const float s = v.E - dE;
+    const float bb = s - v.E;
+    const float err = (v.E - (s - bb)) + (-dE - bb);
+    const float lo = v.Elo + err;
+    const float t = s + lo;
+    v.Elo = lo - (t - s);
+    v.E = t;
+}
+
+enum { ST_STOP = 0, ST_GEO = 1, ST_INNER = 2 };
+
+// One condensed-history step in a homogeneous region: CSDA loss from the
+// range table, Bohr straggling, Gaussian multiple scattering applied at the
+// step midpoint (hinge), nuclear removal turning the VP into its leading
+// secondary.  rho_loss scales energy loss and straggling (range scenarios),
+// rho scattering and nuclear removal.  dg: distance to the region boundary.
+__device__ int phys_step(Lane &v, const float *tab, int m, float rho_loss, float rho, float dg,
+                         float &dep, float &esc) {
+    dep = 0.0f;
+    esc = 0.0f;
+    v.nsteps++;
+    if (v.E <= kELo) {
+        dep = v.E + v.Elo;
+        v.E = v.Elo = 0.0f;
+        return ST_STOP;
+    }
+    const float *tm = tab + TAB_MAT0 + m * TAB_PER_MAT;
+    const int i = seg_of(tab, v.E);
+    const float x = (v.E - tab[TAB_E + i]) + v.Elo;
+    const float slope = tm[T_SLOPE * NE + i];
+    const float R = tm[T_R * NE + i] + x / slope;
+    if (rho_loss * dg * 0.1f >= R) {
+        dep = v.E + v.Elo;
+        v.E = v.Elo = 0.0f;
+        return ST_STOP;
+    }
+    const float smax = 10.0f * STEP_FRACTION * R / rho_loss;
+    const bool geo = dg <= smax;
+    const float s = geo ? dg : smax;
+    const float r = rho_loss * s * 0.1f;
+    float dE = csda_loss(tm, i, x, slope, r);
+    const float Ebar = v.E - 0.5f * dE;
+    uint4 w = make_uint4(0u, 0u, 0u, 0xFFFFFFFFu);
+    if (v.physics) w = draw(v);
+    if (v.physics & PH_STRAGGLE) {
+        const float var = r * node_interp(tab, tm + T_W2 * NE, Ebar);
+        const float z = 1.41421356237f * erfinvf(2.0f * unit_open(w.z) - 1.0f);
+        dE -= sqrtf(var) * z;
+        dE = fminf(fmaxf(dE, 0.0f), v.E + v.Elo);
+    }
+    dep = dE;
+    sub_energy(v, dE);
+    if (v.physics & PH_MCS) {
+        const float th0 = sqrtf(rho * s * 0.1f * node_interp(tab, tm + T_T * NE, Ebar));
+        float z1, z2;
+        box_muller_fast(w.x, w.y, z1, z2);
+        const float h = 0.5f * s;
+        v.px = fmaf(h, v.dx, v.px);
+        v.py = fmaf(h, v.dy, v.py);
+        v.pz = fmaf(h, v.dz, v.pz);
+        rotate_dir(v, th0 * z1, th0 * z2);
+        v.px = fmaf(h, v.dx, v.px);
+        v.py = fmaf(h, v.dy, v.py);
+        v.pz = fmaf(h, v.dz, v.pz);
+    } else {
+        v.px = fmaf(s, v.dx, v.px);
+        v.py = fmaf(s, v.dy, v.py);
+        v.pz = fmaf(s, v.dz, v.pz);
+    }
+    if (v.physics & PH_NUCLEAR) {
+        const float P = -expm1f(-rho * s * 0.1f * node_interp(tab, tm + T_SN * NE, Ebar));
+        if (unit_open(w.w) < P) {
+            const uint4 w2 = draw(v);
+            const float E1 = v.E + v.Elo;
+            const float loc = NUC_F_LOCAL * E1, out = NUC_F_ESCAPE * E1;
+            v.E = (E1 - loc) - out;
+            v.Elo = 0.0f;
+            dep += loc;
+            esc = out;
+            float n1, n2;
+            box_muller_fast(w2.x, w2.y, n1, n2);
+            rotate_dir(v, NUC_SIGMA_RAD * n1, NUC_SIGMA_RAD * n2);
+        }
+    }
+    return geo ? ST_GEO : ST_INNER;
+}
+
+// ------------------------------------------------------------ tallies
+struct Acc {
+    long long led[NLEDGER];
+    unsigned long long steps, hist;
+};
+
+__device__ __forceinline__ long long to_fixed(float e, float scale) {
+    return (long long)rintf(e * scale);
+}
+
+__device__ __forceinline__ void ledger_add(Acc &a, int j, float e, float scale) {
+    a.led[j] += to_fixed(e, scale);
+}
+
+// dense tally: one 64-bit atomic per deposit
+struct DenseSink {
+    unsigned long long *tally;
+    __device__ __forceinline__ void add(uint32_t v, long long q) const {
+        atomicAdd(tally + v, (unsigned long long)q);
+    }
+};
+
+// per-row tally of the influence-matrix builder: the returning atomic tells
+// the first deposit into a voxel (tallies only grow from zero), which marks
+// the voxel in the two-level bitmap and counts it
+struct SparseSink {
+    unsigned long long *grid;
+    uint32_t *l1, *l2;
+    unsigned int *nnz;
+    __device__ __forceinline__ void add(uint32_t v, long long q) const {
+        const unsigned long long old = atomicAdd(grid + v, (unsigned long long)q);
+        if (old == 0ull) {
+            const uint32_t o1 = atomicOr(l1 + (v >> 5), 1u << (v & 31u));
+            if (o1 == 0u) atomicOr(l2 + (v >> 10), 1u << ((v >> 5) & 31u));
+            atomicAdd(nnz, 1u);
+        }
+    }
+};
+
+// ------------------------------------------------------------ aperture
+// crossing number (ray casting) with the half-open rule
+__device__ __forceinline__ bool in_polygon(const float2 *poly, int nv, float x, float y) {
+    bool c = false;
+    float2 b = poly[nv - 1];
+    for (int i = 0; i < nv; ++i) {
+        const float2 a = poly[i];
+        if ((a.y > y) != (b.y > y)) {
+            const float xc = a.x + (y - a.y) * (b.x - a.x) / (b.y - a.y);
+            if (x < xc) c = !c;
+        }
+        b = a;
+    }
+    return c;
+}
+
+// path length along (u, v) until the BEV ray from (x, y) meets an edge
+__device__ __forceinline__ float edge_distance(const float2 *poly, int nv, float x, float y, float u,
+                                               float v) {
+    float best = INFINITY;
+    float2 a = poly[nv - 1];
+    for (int i = 0; i < nv; ++i) {
+        const float2 b = poly[i];
+        const float ex = b.x - a.x, ey = b.y - a.y;
+        const float den = u * ey - v * ex;
+        if (den != 0.0f) {
+            const float wx = a.x - x, wy = a.y - y;
+            const float inv = 1.0f / den;
+            const float t = (wx * ey - wy * ex) * inv;
+            const float lam = (wx * v - wy * u) * inv;
+            if (t > 0.0f && lam >= 0.0f && lam <= 1.0f) best = fminf(best, t);
+        }
+        a = b;
+    }
+    return best;
+}
+
+__device__ __forceinline__ float plane_distance(const Lane &v, float zu, float zd, bool &down) {
+    if (v.dz > 0.0f) { down = true; return (zd - v.pz) / v.dz; }
+    if (v.dz < 0.0f) { down = false; return (zu - v.pz) / v.dz; }
+    down = true;
+    return INFINITY;
+}
+
+enum { EX_DOWN = 0, EX_GONE = 1 };
+
+__device__ int slab_transport(Lane &v, Acc &acc, float scale, const float *tab, int m, float rho,
+                              float zu, float zd, int ledger) {
+    for (int it = 0; it < MAX_STEPS; ++it) {
+        bool down;
+        float tp = fmaxf(plane_distance(v, zu, zd, down), 0.0f);
+        float dep, esc;
+        const int st = phys_step(v, tab, m, rho, rho, tp, dep, esc);
+        ledger_add(acc, ledger, dep, scale);
+        ledger_add(acc, L_NUC, esc, scale);
+        if (st == ST_STOP) return EX_GONE;
+        if (st == ST_GEO || v.pz >= zd || v.pz <= zu) {
+            const bool out_down = (st == ST_GEO) ? down : (v.pz >= zd);
+            v.pz = out_down ? zd : zu;
+            if (out_down) return EX_DOWN;
+            ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
+            return EX_GONE;
+        }
+    }
+    ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
+    return EX_GONE;
+}
+
+// Methods B: between the block's entrance and exit planes the crossing
+// number at the VP's projected position decides, at every step, opening
+// (straight transport, no random numbers) or brass (brass tables).
+__device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab, const float2 *poly,
+                               int nv, float rho_b, float zu, float zd) {
+    for (int it = 0; it < MAX_STEPS; ++it) {
+        bool down;
+        const float tp = fmaxf(plane_distance(v, zu, zd, down), 0.0f);
+        const bool open = nv >= 3 && in_polygon(poly, nv, v.px, v.py);
+        const float te = nv >= 3 ? edge_distance(poly, nv, v.px, v.py, v.dx, v.dy) : INFINITY;
+        if (open) {
+            if (tp <= te) {
+                v.px = fmaf(tp, v.dx, v.px);
+                v.py = fmaf(tp, v.dy, v.py);
+                v.pz = down ? zd : zu;
+                if (down) return EX_DOWN;
+                ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
+                return EX_GONE;
+            }
+            const float t = te + EDGE_PUSH_MM;
+            v.px = fmaf(t, v.dx, v.px);
+            v.py = fmaf(t, v.dy, v.py);
+            v.pz = fmaf(t, v.dz, v.pz);
+            continue;
+        }
+        const float dg = fminf(te, tp);
+        float dep, esc;
+        const int st = phys_step(v, tab, MAT_BRASS, rho_b, rho_b, dg, dep, esc);
+        ledger_add(acc, L_BLOCK, dep, scale);
+        ledger_add(acc, L_NUC, esc, scale);
+        if (st == ST_STOP) return EX_GONE;
+        if (st == ST_GEO && tp <= te) {
+            v.pz = down ? zd : zu;
+            if (down) return EX_DOWN;
+            ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
+            return EX_GONE;
+        }
+        if (st == ST_GEO) {
+            v.px = fmaf(EDGE_PUSH_MM, v.dx, v.px);
+            v.py = fmaf(EDGE_PUSH_MM, v.dy, v.py);
+            v.pz = fmaf(EDGE_PUSH_MM, v.dz, v.pz);
+        }
+        if (v.pz >= zd) { v.pz = zd; return EX_DOWN; }
+        if (v.pz <= zu) {
+            v.pz = zu;
+            ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
+            return EX_GONE;
+        }
+    }
+    ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
+    return EX_GONE;
+}
+
+// range shifter then aperture block, in the beam frame; on success (p, d) is
+// on the VP's ray and tmin is the ray parameter of the last exit plane
+__device__ bool beamline(Lane &v, Acc &acc, float scale, const float *tab, const float2 *poly,
+                         const FieldDev &f, float &tmin) {
+    tmin = -INFINITY;
+    if (f.has_rs) {
+        const float t = (f.rs_zu - v.pz) / v.dz;
+        const float qx = fmaf(t, v.dx, v.px), qy = fmaf(t, v.dy, v.py);
+        if (qx * qx + qy * qy <= f.rs_r2) {
+            v.px = qx;
+            v.py = qy;
+            v.pz = f.rs_zu;
+            if (slab_transport(v, acc, scale, tab, MAT_PMMA, f.rs_rho, f.rs_zu, f.rs_zd, L_RS) != EX_DOWN)
+                return false;
+            tmin = 0.0f;
+        }
+    }
+    if (f.has_block) {
+        if (!(v.dz > 0.0f)) {
+            ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
+            return false;
+        }
+        const float t = (f.blk_zu - v.pz) / v.dz;
+        const float qx = fmaf(t, v.dx, v.px), qy = fmaf(t, v.dy, v.py);
+        const int nv = f.nv;
+        if (nv >= 3 && in_polygon(poly, nv, qx, qy)) {
+            const float te = edge_distance(poly, nv, qx, qy, v.dx, v.dy);
+            const float tx = (f.blk_zd - f.blk_zu) / v.dz;
+            if (te >= tx) {
+                tmin = (f.blk_zd - v.pz) / v.dz;
+                return true;
+            }
+        }
+        v.px = qx;
+        v.py = qy;
+        v.pz = f.blk_zu;
+        if (block_transport(v, acc, scale, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd) != EX_DOWN)
+            return false;
+        tmin = 0.0f;
+    }
+    return true;
+}
+
+// ------------------------------------------------------------ patient
+// CT calibration: density piecewise linear through (-1000, 0.00121)
+// (0, 1) (1000, 1.6) (1500, 1.85) (3071, 2.8); class air / tissue / bone.
+__device__ __forceinline__ void hu_material(int hu, int &m, float &rho) {
+    const float h = (float)min(max(hu, -1000), 3071);
+    if (h <= 0.0f) rho = 0.00121f + (h + 1000.0f) * ((1.0f - 0.00121f) / 1000.0f);
+    else if (h <= 1000.0f) rho = 1.0f + h * (0.6f / 1000.0f);
+    else if (h <= 1500.0f) rho = 1.6f + (h - 1000.0f) * (0.25f / 500.0f);
+    else rho = 1.85f + (h - 1500.0f) * (0.95f / 1571.0f);
+    m = hu < -900 ? MAT_AIR : hu < 150 ? MAT_WATER : MAT_BONE;
+}
+
+template <class Sink>
+__device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const GeomDev &g,
+                        const FieldDev &f, const float *shift, float range_scale, const Sink &sink,
+                        float tmin) {
+    float p[3], d[3];
+    {
+        const float bx = v.px, by = v.py, bz = v.pz;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            p[k] = (f.iso[k] + (bx * f.ex[k] + by * f.ey[k] + bz * f.ez[k])) - shift[k];
+            d[k] = v.dx * f.ex[k] + v.dy * f.ey[k] + v.dz * f.ez[k];
+        }
+    }
+    const int n[3] = {g.nx, g.ny, g.nz};
+    float hi[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) hi[k] = g.lo[k] + n[k] * g.sp[k];
+    float tnear = -INFINITY, tfar = INFINITY;
+    int axn = -1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (d[k] == 0.0f) {
+            if (p[k] < g.lo[k] || p[k] >= hi[k]) {
+                ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
+                return;
+            }
+            continue;
+        }
+        const float t1 = (g.lo[k] - p[k]) / d[k], t2 = (hi[k] - p[k]) / d[k];
+        const float a = fminf(t1, t2), b = fmaxf(t1, t2);
+        if (a > tnear) { tnear = a; axn = k; }
+        tfar = fminf(tfar, b);
+    }
+    const float t0 = fmaxf(tnear, tmin);
+    if (!(tfar > t0)) {
+        ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) p[k] = fmaf(t0, d[k], p[k]);
+    if (t0 == tnear) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (k == axn) p[k] = d[k] > 0.0f ? g.lo[k] : hi[k];
+    }
+    int idx[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float c = floorf((p[k] - g.lo[k]) / g.sp[k]);
+        idx[k] = !(c >= 0.0f) ? 0 : c > (float)(n[k] - 1) ? n[k] - 1 : (int)c;   // NaN -> 0
+    }
+    v.px = p[0]; v.py = p[1]; v.pz = p[2];
+    v.dx = d[0]; v.dy = d[1]; v.dz = d[2];
+    for (int it = 0; it < MAX_STEPS; ++it) {
+        const uint32_t vox = (uint32_t)idx[0] + (uint32_t)g.nx * ((uint32_t)idx[1] + (uint32_t)g.ny * (uint32_t)idx[2]);
+        int m = MAT_WATER;
+        float rho = 1.0f;
+        if (g.kind == 1) hu_material(g.hu[vox], m, rho);
+        const float rho_loss = rho * range_scale;
+        const float pp[3] = {v.px, v.py, v.pz}, dd[3] = {v.dx, v.dy, v.dz};
+        float dg = INFINITY, bnd = 0.0f;
+        int ax = -1, sgn = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (dd[k] == 0.0f) continue;
+            const bool up = dd[k] > 0.0f;
+            const float b = g.lo[k] + (float)(idx[k] + (up ? 1 : 0)) * g.sp[k];
+            const float t = fmaxf((b - pp[k]) / dd[k], 0.0f);
+            if (t < dg) { dg = t; ax = k; sgn = up ? 1 : -1; bnd = b; }
+        }
+        float dep, esc;
+        const int st = phys_step(v, tab, m, rho_loss, rho, dg, dep, esc);
+        const long long qd = to_fixed(dep, scale);
+        if (qd != 0) sink.add(vox, qd);
+        acc.led[L_GRID] += qd;
+        ledger_add(acc, L_NUC, esc, scale);
+        if (st == ST_STOP) return;
+        float q[3] = {v.px, v.py, v.pz};
+        if (st == ST_GEO) {
+            bool out = false;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (k == ax) {
+                    idx[k] += sgn;
+                    q[k] = bnd;
+                    out = idx[k] < 0 || idx[k] >= n[k];
+                }
+            }
+            if (out) {
+                ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
+                return;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float a = g.lo[k] + (float)idx[k] * g.sp[k];
+            const float b = g.lo[k] + (float)(idx[k] + 1) * g.sp[k];
+            q[k] = fminf(fmaxf(q[k], a), b);
+        }
+        v.px = q[0]; v.py = q[1]; v.pz = q[2];
+    }
+    ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
+}
+
+// ------------------------------------------------------------ source
+__device__ void source(Lane &v, const SpotDev &sp) {
+    const uint4 w = draw(v);
+    const float r = sqrtf(-2.0f * logf(unit_open(w.x)));
+    float sn, c;
+    sincospif(2.0f * unit_open(w.y), &sn, &c);
+    v.px = fmaf(sp.sigma, r * c, sp.x);
+    v.py = fmaf(sp.sigma, r * sn, sp.y);
+    v.pz = 0.0f;
+    v.dx = 0.0f; v.dy = 0.0f; v.dz = 1.0f;
+    v.E = sp.e0;
+    v.Elo = 0.0f;
+    if (sp.esig > 0.0f) {
+        const float z = 1.41421356237f * erfinvf(2.0f * unit_open(w.z) - 1.0f);
+        v.E = fminf(fmaxf(fmaf(sp.esig, z, sp.e0), kELo), sp.emax);
+    }
+}
+
+__device__ __forceinline__ int find_spot(const unsigned long long *off, int n, unsigned long long item) {
+    int lo = 0, hi = n;   // off[lo] <= item < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= item) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void transport_kernel(GeomDev g, FieldDev f, LaunchDev L) {
+    __shared__ float tab[TAB_FLOATS];
+    __shared__ float2 poly[POLY_LDS];
+    for (int i = threadIdx.x; i < TAB_FLOATS / 4; i += blockDim.x)
+        reinterpret_cast<float4 *>(tab)[i] = reinterpret_cast<const float4 *>(L.tables)[i];
+    if (f.has_block)
+        for (int i = threadIdx.x; i < f.nv; i += blockDim.x) poly[i] = f.poly[i];
+    __syncthreads();
+
+    Acc acc;
+#pragma unroll
+    for (int j = 0; j < NLEDGER; ++j) acc.led[j] = 0;
+    acc.steps = acc.hist = 0;
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long item = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+         item < L.n_items; item += stride) {
+        const int s = find_spot(L.item_off, L.n_spots, item);
+        const SpotDev sp = L.spots[s];
+        Lane v;
+        v.k0 = L.key0;
+        v.k1 = L.key1;
+        v.spot = (uint32_t)s;
+        v.hist = (uint32_t)(L.batch + (unsigned long long)L.n_batches * (item - L.item_off[s]));
+        v.nblk = 0;
+        v.nsteps = 0;
+        v.physics = L.physics;
+        source(v, sp);
+        float tmin;
+        if (beamline(v, acc, sp.scale, tab, poly, f, tmin))
+            patient(v, acc, sp.scale, tab, g, f, L.shift, L.range_scale, DenseSink{L.tally}, tmin);
+        acc.steps += v.nsteps;
+        acc.hist += 1;
+    }
+    // wavefront reduction of the ledgers, one atomic per wavefront
+#pragma unroll
+    for (int j = 0; j < NLEDGER; ++j) {
+        long long x = acc.led[j];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if ((threadIdx.x & 63) == 0 && x != 0) atomicAdd(L.ledger + j, (unsigned long long)x);
+    }
+    unsigned long long st = acc.steps, hs = acc.hist;
+    for (int o = 32; o > 0; o >>= 1) {
+        st += __shfl_xor(st, o, 64);
+        hs += __shfl_xor(hs, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && hs != 0) {
+        atomicAdd(L.stats + 0, st);
+        atomicAdd(L.stats + 1, hs);
+    }
+}
+
+// ------------------------------------------------------------ CSR mode
+// Work-queue transport: each wavefront takes one chunk (64 * hist_per_lane
+// histories of one row) at a time from the epoch's atomic counter, so rows
+// of uneven energy and history count balance across the chip.  Every wave
+// exits once the counter passes the number of chunks.
+__global__ __launch_bounds__(kThreads) void queue_kernel(GeomDev g, QueueDev Q) {
+    __shared__ float tab[TAB_FLOATS];
+    __shared__ float2 poly[POLY_LDS];
+    for (int i = threadIdx.x; i < TAB_FLOATS / 4; i += blockDim.x)
+        reinterpret_cast<float4 *>(tab)[i] = reinterpret_cast<const float4 *>(Q.tables)[i];
+    for (int i = threadIdx.x; i < Q.n_poly_total; i += blockDim.x) poly[i] = Q.polys[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    unsigned long long st_steps = 0, st_hist = 0;
+    for (;;) {
+        unsigned long long item = 0;
+        if (lane == 0) item = atomicAdd(Q.head, 1ull);
+        // all lanes are active here: lane 0 is the first lane, so the item
+        // (and everything derived from it) is wave-uniform in scalar registers
+        const uint32_t ilo = __builtin_amdgcn_readfirstlane((uint32_t)item);
+        const uint32_t ihi = __builtin_amdgcn_readfirstlane((uint32_t)(item >> 32));
+        item = ((unsigned long long)ihi << 32) | ilo;
+        if (item >= Q.n_chunks) break;
+        const int rl = find_spot(Q.chunk_off, Q.n_rows, item);
+        const unsigned long long j = item - Q.chunk_off[rl];
+        const RowDev row = Q.rows[Q.row_begin + rl];
+        const FieldDev f = Q.fields[row.field];
+        const SpotDev sp = Q.spots[row.spot_global];
+        const ScenDev sc = Q.scen[row.scen];
+        const SparseSink sink{Q.grid + (size_t)rl * Q.nvox, Q.l1 + (size_t)rl * Q.n1, Q.l2 + (size_t)rl * Q.n2,
+                              Q.nnz + rl};
+        const float2 *fpoly = poly + Q.poly_off[row.field];
+        Acc acc;
+#pragma unroll
+        for (int k = 0; k < NLEDGER; ++k) acc.led[k] = 0;
+        acc.steps = acc.hist = 0;
+        for (int t = 0; t < Q.hist_per_lane; ++t) {
+            const unsigned long long h = (j * (unsigned long long)Q.hist_per_lane + t) * 64ull + lane;
+            if (h >= row.n_hist) break;
+            Lane v;
+            v.k0 = Q.key0;
+            v.k1 = Q.seed_hi ^ row.field_id;
+            v.spot = row.spot;
+            v.hist = (uint32_t)h;
+            v.nblk = 0;
+            v.nsteps = 0;
+            v.physics = Q.physics;
+            source(v, sp);
+            float tmin;
+            if (beamline(v, acc, sp.scale, tab, fpoly, f, tmin))
+                patient(v, acc, sp.scale, tab, g, f, sc.shift, sc.range_scale, sink, tmin);
+            acc.steps += v.nsteps;
+            acc.hist += 1;
+        }
+        st_steps += acc.steps;
+        st_hist += acc.hist;
+#pragma unroll
+        for (int k = 0; k < NLEDGER; ++k) {
+            long long x = acc.led[k];
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+            if (lane == 0 && x != 0) atomicAdd(Q.ledger + (size_t)row.scen * NLEDGER + k, (unsigned long long)x);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        st_steps += __shfl_xor(st_steps, o, 64);
+        st_hist += __shfl_xor(st_hist, o, 64);
+    }
+    if (lane == 0 && st_hist != 0) {
+        atomicAdd(Q.stats + 0, st_steps);
+        atomicAdd(Q.stats + 1, st_hist);
+    }
+}
+
+// exclusive scan of this epoch's row counts into global CSR offsets (rows
+// are stored in row order, so the offsets are the final row pointers)
+__global__ __launch_bounds__(1024) void csr_offsets_kernel(unsigned int *nnz, int n_rows, int row_begin,
+                                                           unsigned long long *row_off,
+                                                           unsigned long long *row_nnz,
+                                                           unsigned long long *used,
+                                                           unsigned long long capacity, unsigned int *flags) {
+    __shared__ unsigned long long part[1024];
+    const int t = threadIdx.x;
+    const unsigned long long x = t < n_rows ? nnz[t] : 0ull;
+    part[t] = x;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const unsigned long long y = t >= o ? part[t - o] : 0ull;
+        __syncthreads();
+        part[t] += y;
+        __syncthreads();
+    }
+    const unsigned long long base = *used;
+    if (t < n_rows) {
+        row_off[row_begin + t] = base + part[t] - x;
+        row_nnz[row_begin + t] = x;
+    }
+    __syncthreads();
+    if (t == 1023) {
+        *used = base + part[1023];
+        if (base + part[1023] > capacity) atomicOr(flags, 1u);
+    }
+}
+
+// Walk the two-level bitmap of each slot in ascending voxel order, emit
+// (voxel, q) at the row's offset and clear exactly what was touched.
+__global__ __launch_bounds__(256) void csr_compact_kernel(QueueDev Q, const unsigned long long *row_off,
+                                                          int32_t *col, long long *qv,
+                                                          unsigned long long capacity, unsigned int *flags) {
+    __shared__ unsigned int cnt[256];
+    const int slot = blockIdx.x;
+    const int t = threadIdx.x;
+    unsigned long long *grid = Q.grid + (size_t)slot * Q.nvox;
+    uint32_t *l1 = Q.l1 + (size_t)slot * Q.n1;
+    uint32_t *l2 = Q.l2 + (size_t)slot * Q.n2;
+    const unsigned int total = Q.nnz[slot];
+    const unsigned long long base = row_off[Q.row_begin + slot];
+    const bool write = base + total <= capacity;
+    const size_t per = (Q.n2 + blockDim.x - 1) / blockDim.x;
+    const size_t w0 = (size_t)t * per, w1 = w0 + per < Q.n2 ? w0 + per : Q.n2;
+    unsigned int c = 0;
+    for (size_t w = w0; w < w1; ++w) {
+        uint32_t m = l2[w];
+        while (m) {
+            const int b = __ffs(m) - 1;
+            m &= m - 1u;
+            c += __popc(l1[w * 32 + b]);
+        }
+    }
+    cnt[t] = c;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const unsigned int y = t >= o ? cnt[t - o] : 0u;
+        __syncthreads();
+        cnt[t] += y;
+        __syncthreads();
+    }
+    if (t == 255 && cnt[255] != total) atomicOr(flags, 2u);
+    unsigned long long pos = base + cnt[t] - c;
+    for (size_t w = w0; w < w1; ++w) {
+        uint32_t m = l2[w];
+        if (!m) continue;
+        l2[w] = 0u;
+        while (m) {
+            const int b = __ffs(m) - 1;
+            m &= m - 1u;
+            const size_t wi = w * 32 + b;
+            uint32_t word = l1[wi];
+            l1[wi] = 0u;
+            while (word) {
+                const int bb = __ffs(word) - 1;
+                word &= word - 1u;
+                const size_t v = wi * 32 + bb;
+                const unsigned long long q = grid[v];
+                grid[v] = 0ull;
+                if (write) {
+                    col[pos] = (int32_t)v;
+                    qv[pos] = (long long)q;
+                }
+                ++pos;
+            }
+        }
+    }
+    __syncthreads();
+    if (t == 0) Q.nnz[slot] = 0u;
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, size_t n, unsigned long long v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void csr_scatter_kernel(const int32_t *col, const long long *qv, unsigned long long begin,
+                                   unsigned long long end, unsigned long long *dense) {
+    for (unsigned long long i = begin + (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < end;
+         i += (unsigned long long)gridDim.x * blockDim.x)
+        atomicAdd(dense + col[i], (unsigned long long)qv[i]);
+}
+
+__global__ void csr_values_kernel(const int32_t *col, const long long *qv, size_t n, GeomDev g, double mev_scale,
+                                  float *val) {
+    const float vol_kg = g.sp[0] * g.sp[1] * g.sp[2] * 1e-6f;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        float rho = 1.0f;
+        int m;
+        if (g.kind == 1) hu_material(g.hu[col[i]], m, rho);
+        val[i] = (float)qv[i] * ((float)mev_scale / (rho * vol_kg));
+    }
+}
+
+// ------------------------------------------------------------ batches, dose
+// fold one batch: total += q_b, sum of squares += q_b^2 (FP64), clear q_b
+__global__ void fold_batch_kernel(unsigned long long *qb, long long *qt, double *s2, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const long long q = (long long)qb[i];
+        if (q != 0) {
+            qt[i] += q;
+            const double d = (double)q;
+            s2[i] += d * d;
+            qb[i] = 0ull;
+        }
+    }
+}
+
+__global__ void dose_kernel(const long long *q, const double *s2, int B, GeomDev g, double mev_scale,
+                            float *dose, float *sigma, size_t n) {
+    const float vol_kg = g.sp[0] * g.sp[1] * g.sp[2] * 1e-6f;   // mm^3 -> cm^3 -> kg at 1 g/cm^3
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        float rho = 1.0f;
+        int m;
+        if (g.kind == 1) hu_material(g.hu[i], m, rho);
+        const float conv = (float)mev_scale / (rho * vol_kg);   // Gy per (q unit)
+        const long long qi = q[i];
+        if (dose) dose[i] = (float)qi * conv;
+        if (sigma) {
+            // batch estimator of the standard error of the mean (FP64)
+            const double D = (double)qi;
+            const double var = fmax((double)B * s2[i] - D * D, 0.0) / (double)(B - 1);
+            sigma[i] = (float)sqrt(var) * conv;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_transport(const GeomDev &g, const FieldDev &f, const LaunchDev &L, int blocks,
+                            int threads, hipStream_t s) {
+    if (threads != kThreads) threads = kThreads;
+    hipLaunchKernelGGL(transport_kernel, dim3(blocks), dim3(threads), 0, s, g, f, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_queue(const GeomDev &g, const QueueDev &Q, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(queue_kernel, dim3(blocks), dim3(kThreads), 0, s, g, Q);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_offsets(unsigned int *nnz, int n_rows, int row_begin, unsigned long long *row_off,
+                              unsigned long long *row_nnz, unsigned long long *used, unsigned long long capacity,
+                              unsigned int *flags, hipStream_t s) {
+    hipLaunchKernelGGL(csr_offsets_kernel, dim3(1), dim3(1024), 0, s, nnz, n_rows, row_begin, row_off, row_nnz,
+                       used, capacity, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_compact(const QueueDev &Q, const unsigned long long *row_off, int32_t *col, long long *qv,
+                              unsigned long long capacity, unsigned int *flags, hipStream_t s) {
+    hipLaunchKernelGGL(csr_compact_kernel, dim3(Q.n_rows), dim3(256), 0, s, Q, row_off, col, qv, capacity, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v, hipStream_t s) {
+    const int blocks = (int)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_scatter(const int32_t *col, const long long *qv, unsigned long long begin,
+                              unsigned long long end, unsigned long long *dense, hipStream_t s) {
+    const unsigned long long n = end - begin;
+    const int blocks = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
+    if (blocks > 0) hipLaunchKernelGGL(csr_scatter_kernel, dim3(blocks), dim3(256), 0, s, col, qv, begin, end, dense);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_values(const int32_t *col, const long long *qv, size_t n, const GeomDev &g,
+                             double mev_scale, float *val, hipStream_t s) {
+    const int blocks = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
+    if (blocks > 0) hipLaunchKernelGGL(csr_values_kernel, dim3(blocks), dim3(256), 0, s, col, qv, n, g, mev_scale, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_batch(unsigned long long *qb, long long *qt, double *s2, size_t n, hipStream_t s) {
+    const int blocks = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
+    hipLaunchKernelGGL(fold_batch_kernel, dim3(blocks), dim3(256), 0, s, qb, qt, s2, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dose(const long long *q, const double *s2, int B, const GeomDev &g, double mev_scale,
+                       float *dose, float *sigma, size_t n, hipStream_t s) {
+    const int blocks = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
+    hipLaunchKernelGGL(dose_kernel, dim3(blocks), dim3(256), 0, s, q, s2, B, g, mev_scale, dose, sigma, n);
+    return hipGetLastError();
+}
+
+}  // namespace vpmc

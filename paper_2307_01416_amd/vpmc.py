@@ -1,0 +1,301 @@
+"""Thin ctypes binding of libvpmc.so (include/vpmc.h).
+
+Argument marshalling only: every step of the transport runs in the HIP
+library.  PyTorch supplies device memory and the stream.  There is no CPU
+fallback: if the library is missing, import-time loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import inputs as I
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvpmc.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "vpmc.h")
+
+VPMC_OK = 0
+ERRORS = {-1: "VPMC_E_ARG", -2: "VPMC_E_STATE", -3: "VPMC_E_POLYGON", -4: "VPMC_E_OOM",
+          -5: "VPMC_E_DEVICE", -6: "VPMC_E_RANGE", -7: "VPMC_E_ABORTED"}
+E_ARG, E_STATE, E_POLYGON, E_OOM, E_DEVICE, E_RANGE, E_ABORTED = -1, -2, -3, -4, -5, -6, -7
+STRAGGLE, MCS, NUCLEAR, PHYS_ALL = 1, 2, 4, 7
+GEOM_WATER, GEOM_HU = 0, 1
+OUT_DOSE, OUT_CSR = 0, 1
+DEVICE_PTRS = 1
+NLEDGER = 6
+
+
+class VpmcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class vpmc_beam(C.Structure):
+    _fields_ = [("iso_mm", C.c_float * 3), ("ex", C.c_float * 3), ("ey", C.c_float * 3),
+                ("ez", C.c_float * 3)]
+
+
+class vpmc_block(C.Structure):
+    _fields_ = [("thickness_mm", C.c_float), ("density_gcc", C.c_float), ("downstream_mm", C.c_float)]
+
+
+class vpmc_rs(C.Structure):
+    _fields_ = [("wet_mm", C.c_float), ("diameter_mm", C.c_float), ("downstream_mm", C.c_float)]
+
+
+class vpmc_spot(C.Structure):
+    _fields_ = [("x_mm", C.c_float), ("y_mm", C.c_float), ("energy_mev", C.c_float),
+                ("sigma_mm", C.c_float), ("energy_sigma_mev", C.c_float), ("weight", C.c_float),
+                ("n_histories", C.c_uint32)]
+
+
+class vpmc_scenario(C.Structure):
+    _fields_ = [("shift_mm", C.c_float * 3), ("range_scale", C.c_float)]
+
+
+class vpmc_opts(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("physics", C.c_uint), ("n_batches", C.c_int),
+                ("output", C.c_int), ("fixed_point_bits", C.c_int), ("flags", C.c_uint),
+                ("hip_stream", C.c_void_p), ("max_device_bytes", C.c_size_t),
+                ("block_threads", C.c_int), ("grid_blocks", C.c_int)]
+
+
+class vpmc_stats(C.Structure):
+    _fields_ = [("transport_ms", C.c_double), ("total_ms", C.c_double), ("histories", C.c_uint64),
+                ("steps", C.c_uint64), ("launches", C.c_uint64)]
+
+
+assert C.sizeof(vpmc_spot) == 28
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load the built library; raise if it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libvpmc.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, i, u, f64p = C.c_void_p, C.c_int, C.c_uint, C.POINTER(C.c_double)
+    sig = {
+        "vpmc_create": (i, [C.POINTER(vp), i]),
+        "vpmc_destroy": (None, [vp]),
+        "vpmc_last_error": (C.c_char_p, [vp]),
+        "vpmc_version": (i, []),
+        "vpmc_load_geometry": (i, [vp, i, vp, i, i, i, vp, vp, u]),
+        "vpmc_set_aperture": (i, [vp, i, vp, vp, i, vp, vp]),
+        "vpmc_run_spots": (i, [vp, i, vp, i, vp, i, vp, vp, vp, vp, vp]),
+        "vpmc_copy_csr": (i, [vp, vp, vp, vp]),
+        "vpmc_last_tally": (i, [vp, i, vp, C.POINTER(C.c_int), u]),
+        "vpmc_table_host": (i, [i, i, vp, i]),
+        "vpmc_last_stats": (i, [vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def header_functions() -> List[str]:
+    """Function names declared in include/vpmc.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(vpmc_[a-z_]+)\s*\(", txt)))
+
+
+def _check(rc: int, ctx=None):
+    if rc != VPMC_OK:
+        msg = load().vpmc_last_error(ctx)
+        raise VpmcError(rc, msg.decode() if msg else "")
+
+
+def _f3(v):
+    return (C.c_float * 3)(*[float(x) for x in v])
+
+
+def _ptr(x):
+    """Pointer of a numpy array or a torch tensor (host or device), or None."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data_as(C.c_void_p)
+    return C.c_void_p(x.data_ptr())
+
+
+# --------------------------------------------------------------- C-ABI mirror
+def vpmc_create(device: int = 0) -> C.c_void_p:
+    ctx = C.c_void_p()
+    _check(load().vpmc_create(C.byref(ctx), device))
+    return ctx
+
+
+def vpmc_destroy(ctx) -> None:
+    load().vpmc_destroy(ctx)
+
+
+def vpmc_table_host(material: int, which: int) -> np.ndarray:
+    out = np.zeros(256, np.float64)
+    n = load().vpmc_table_host(material, which, _ptr(out), 256)
+    if n < 0:
+        _check(n)
+    return out[:n]
+
+
+def vpmc_load_geometry(ctx, geom: I.Geometry, hu=None, flags: int = 0) -> None:
+    """hu: optional torch device tensor (with flags=DEVICE_PTRS) or numpy int16."""
+    nx, ny, nz = geom.shape
+    src = hu
+    if src is None and geom.kind == GEOM_HU:
+        src = np.ascontiguousarray(geom.hu, np.int16)
+    _check(load().vpmc_load_geometry(ctx, geom.kind, _ptr(src), nx, ny, nz, _f3(geom.spacing),
+                                     _f3(geom.origin), flags), ctx)
+
+
+def beam_struct(b: I.Beam) -> vpmc_beam:
+    s = vpmc_beam()
+    s.iso_mm = _f3(b.iso)
+    s.ex, s.ey, s.ez = _f3(b.ex), _f3(b.ey), _f3(b.ez)
+    return s
+
+
+def vpmc_set_aperture(ctx, field_id: int, field: I.Field) -> None:
+    beam = beam_struct(field.beam)
+    poly = None
+    nv = 0
+    if field.block is not None and field.polygon is not None and len(field.polygon) > 0:
+        poly = np.ascontiguousarray(field.polygon, np.float32)
+        nv = poly.shape[0]
+    blk = None
+    if field.block is not None:
+        blk = vpmc_block(field.block.thickness_mm, field.block.density_gcc, field.block.downstream_mm)
+    rs = None
+    if field.rs is not None:
+        rs = vpmc_rs(field.rs.wet_mm, field.rs.diameter_mm, field.rs.downstream_mm)
+    _check(load().vpmc_set_aperture(ctx, field_id, C.byref(beam), _ptr(poly), nv,
+                                    C.byref(blk) if blk is not None else None,
+                                    C.byref(rs) if rs is not None else None), ctx)
+
+
+def spot_array(spots: np.ndarray):
+    arr = (vpmc_spot * max(1, len(spots)))()
+    for i in range(len(spots)):
+        s = arr[i]
+        s.x_mm, s.y_mm = float(spots["x_mm"][i]), float(spots["y_mm"][i])
+        s.energy_mev, s.sigma_mm = float(spots["energy_mev"][i]), float(spots["sigma_mm"][i])
+        s.energy_sigma_mev, s.weight = float(spots["energy_sigma_mev"][i]), float(spots["weight"][i])
+        s.n_histories = int(spots["n_histories"][i])
+    return arr
+
+
+def scenario_array(scen: Sequence[I.Scenario]):
+    arr = (vpmc_scenario * len(scen))()
+    for i, sc in enumerate(scen):
+        arr[i].shift_mm = _f3(sc.shift_mm)
+        arr[i].range_scale = float(sc.range_scale)
+    return arr
+
+
+def make_opts(seed=0, physics=PHYS_ALL, n_batches=0, output=OUT_DOSE, fixed_point_bits=0,
+              flags=0, stream=None, max_device_bytes=0, block_threads=0, grid_blocks=0) -> vpmc_opts:
+    o = vpmc_opts()
+    o.seed, o.physics, o.n_batches, o.output = seed, physics, n_batches, output
+    o.fixed_point_bits, o.flags = fixed_point_bits, flags
+    o.hip_stream = stream
+    o.max_device_bytes, o.block_threads, o.grid_blocks = max_device_bytes, block_threads, grid_blocks
+    return o
+
+
+def vpmc_run_spots(ctx, field_id: int, spots, n_spots: int, scen, n_scen: int, opts: vpmc_opts,
+                   dose=None, sigma=None, ledger=None, row_ptr=None) -> None:
+    _check(load().vpmc_run_spots(ctx, field_id, C.cast(spots, C.c_void_p) if spots is not None else None,
+                                 n_spots, C.cast(scen, C.c_void_p) if scen is not None else None, n_scen,
+                                 C.byref(opts), _ptr(dose), _ptr(sigma), _ptr(ledger), _ptr(row_ptr)), ctx)
+
+
+def vpmc_copy_csr(ctx, col=None, val=None, q=None) -> None:
+    _check(load().vpmc_copy_csr(ctx, _ptr(col), _ptr(val), _ptr(q)), ctx)
+
+
+def vpmc_last_tally(ctx, scen_index: int, q_out=None, flags: int = 0) -> int:
+    k = C.c_int(0)
+    _check(load().vpmc_last_tally(ctx, scen_index, _ptr(q_out), C.byref(k), flags), ctx)
+    return k.value
+
+
+def vpmc_last_stats(ctx) -> dict:
+    st = vpmc_stats()
+    _check(load().vpmc_last_stats(ctx, C.byref(st)), ctx)
+    return {f: getattr(st, f) for f, _ in vpmc_stats._fields_}
+
+
+# --------------------------------------------------------------- convenience
+class Engine:
+    """Owns one context on one GPU and runs Case objects through the C ABI,
+    with torch tensors as device outputs on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.ctx = vpmc_create(device)
+        self._geom = None
+
+    def close(self):
+        if self.ctx is not None:
+            vpmc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_case(self, case: I.Case) -> None:
+        if self._geom is not case.geometry:
+            vpmc_load_geometry(self.ctx, case.geometry)
+            self._geom = case.geometry
+        for fi, f in enumerate(case.fields):
+            vpmc_set_aperture(self.ctx, fi, f)
+
+    def stream_ptr(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def run_dose(self, case: I.Case, field_index: int = 0, scenarios=None, n_batches: Optional[int] = None,
+                 sigma: bool = True, physics: Optional[int] = None, seed: Optional[int] = None,
+                 fixed_point_bits: int = 0, grid_blocks: int = 0):
+        """Dense dose of one field for the given scenario list.  Returns
+        (dose[n_scen, nz, ny, nx], sigma or None, ledger_mev[n_scen, 6]) with
+        dose/sigma as torch float32 tensors on the GPU."""
+        torch = self.torch
+        scen = case.scenarios if scenarios is None else scenarios
+        B = case.n_batches if n_batches is None else n_batches
+        nx, ny, nz = case.geometry.shape
+        dev = torch.device("cuda", self.device)
+        dose = torch.empty((len(scen), nz, ny, nx), dtype=torch.float32, device=dev)
+        sig = torch.empty_like(dose) if (sigma and B >= 2) else None
+        led = np.zeros((len(scen), NLEDGER), np.float64)
+        spots = case.fields[field_index].spots
+        opts = make_opts(seed=case.seed if seed is None else seed,
+                         physics=case.physics if physics is None else physics,
+                         n_batches=B if (sigma and B >= 2) else 0, fixed_point_bits=fixed_point_bits,
+                         flags=DEVICE_PTRS, stream=self.stream_ptr(), grid_blocks=grid_blocks)
+        vpmc_run_spots(self.ctx, field_index, spot_array(spots), len(spots), scenario_array(scen), len(scen),
+                       opts, dose, sig, led)
+        return dose, sig, led
+
+    def last_tally(self, scen_index: int = 0):
+        torch = self.torch
+        nvox = self._geom.nvox
+        q = torch.empty(nvox, dtype=torch.int64, device=torch.device("cuda", self.device))
+        k = vpmc_last_tally(self.ctx, scen_index, q, DEVICE_PTRS)
+        nx, ny, nz = self._geom.shape
+        return q.reshape(nz, ny, nx), k

@@ -1,0 +1,113 @@
+"""C-ABI library checks that need no GPU: it loads, it exports every function
+declared in include/vpmc.h, its own FP64 tables agree with the oracle's
+independently generated ones, and argument validation returns the documented
+error codes before any HIP call (validation-only context, device -1)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2307_01416_amd import inputs as I
+from paper_2307_01416_amd import vpmc as V
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return V.load()
+
+
+@pytest.fixture()
+def vctx(lib):
+    ctx = V.vpmc_create(-1)
+    yield ctx
+    V.vpmc_destroy(ctx)
+
+
+def test_exports_every_declared_symbol(lib):
+    names = V.header_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.vpmc_version() >= 100
+
+
+@pytest.mark.parametrize("m", range(5))
+def test_library_tables_match_oracle_tables(orc, m):
+    # two independent FP64 generators (adaptive Simpson vs Gauss-Legendre)
+    for which, name, rtol in ((0, "E", 1e-14), (1, "R", 1e-11), (2, "omega2", 1e-13), (3, "T", 1e-13),
+                              (4, "sigma_nuc", 1e-13)):
+        a = V.vpmc_table_host(m, which)
+        b = orc.table(m, name)
+        np.testing.assert_allclose(a, b, rtol=rtol, atol=1e-300)
+
+
+def _rc(fn, *args):
+    try:
+        fn(*args)
+    except V.VpmcError as e:
+        return e.code
+    return 0
+
+
+def test_validation_error_codes(vctx):
+    g = I.water_geometry((10, 10, 10), (1.0, 1.0, 1.0))
+    # validation-only context: a well-formed geometry reaches the device step
+    assert _rc(V.vpmc_load_geometry, vctx, g) == V.E_STATE
+    bad = I.water_geometry((0, 10, 10), (1.0, 1.0, 1.0))
+    assert _rc(V.vpmc_load_geometry, vctx, bad) == V.E_ARG
+    bad = I.water_geometry((10, 10, 10), (1.0, -1.0, 1.0))
+    assert _rc(V.vpmc_load_geometry, vctx, bad) == V.E_ARG
+    hu_missing = I.Geometry(kind=I.GEOM_HU, shape=(4, 4, 4), spacing=(1, 1, 1), origin=(0, 0, 0), hu=None)
+    L = V.load()
+    assert L.vpmc_load_geometry(vctx, 1, None, 4, 4, 4, V._f3((1, 1, 1)), V._f3((0, 0, 0)), 0) == V.E_ARG
+    assert L.vpmc_load_geometry(vctx, 7, None, 4, 4, 4, V._f3((1, 1, 1)), V._f3((0, 0, 0)), 0) == V.E_ARG
+    # 2^31 voxels is refused
+    assert L.vpmc_load_geometry(vctx, 0, None, 2048, 1024, 1024, V._f3((1, 1, 1)), V._f3((0, 0, 0)), 0) == V.E_ARG
+
+
+def _field(poly=None, block=True, rs=None, beam=None):
+    return I.Field(beam=beam or I.beam_along_z((0, 0, 0)), spots=I.make_spots([(0, 0)], 100.0, 3.0, 10),
+                   polygon=poly, block=I.Block() if block else None, rs=rs)
+
+
+def test_aperture_validation(vctx):
+    ok = _field(I.circle_polygon(20.0, 64))
+    assert _rc(V.vpmc_set_aperture, vctx, 0, ok) == 0
+    assert _rc(V.vpmc_set_aperture, vctx, 0, _field(None)) == 0            # closed block
+    assert _rc(V.vpmc_set_aperture, vctx, 0, _field(None, block=False)) == 0  # no block
+    assert _rc(V.vpmc_set_aperture, vctx, -1, ok) == V.E_ARG
+    assert _rc(V.vpmc_set_aperture, vctx, 64, ok) == V.E_ARG
+    two = np.array([[0, 0], [1, 0]], np.float32)
+    assert _rc(V.vpmc_set_aperture, vctx, 0, _field(two)) == V.E_POLYGON
+    line = np.array([[0, 0], [1, 0], [2, 0]], np.float32)
+    assert _rc(V.vpmc_set_aperture, vctx, 0, _field(line)) == V.E_POLYGON
+    bowtie = np.array([[0, 0], [1, 1], [1, 0], [0, 1]], np.float32)
+    assert _rc(V.vpmc_set_aperture, vctx, 0, _field(bowtie)) == V.E_POLYGON
+    big = I.circle_polygon(20.0, 1025)
+    assert _rc(V.vpmc_set_aperture, vctx, 0, _field(big)) == V.E_POLYGON
+    nanp = I.circle_polygon(20.0, 8)
+    nanp[3, 0] = np.nan
+    assert _rc(V.vpmc_set_aperture, vctx, 0, _field(nanp)) == V.E_POLYGON
+    skew = I.Beam(iso=(0, 0, 0), ex=(1, 0, 0), ey=(0, 1, 0), ez=(0, 0.2, 1))
+    assert _rc(V.vpmc_set_aperture, vctx, 0, _field(beam=skew)) == V.E_ARG
+    left = I.Beam(iso=(0, 0, 0), ex=(0, 1, 0), ey=(1, 0, 0), ez=(0, 0, 1))
+    assert _rc(V.vpmc_set_aperture, vctx, 0, _field(beam=left)) == V.E_ARG
+    inside = I.RangeShifter(45.0, 61.0, 160.0)     # overlaps the block (150..180 mm)
+    assert _rc(V.vpmc_set_aperture, vctx, 0, _field(I.circle_polygon(20.0, 64), rs=inside)) == V.E_ARG
+    assert _rc(V.vpmc_set_aperture, vctx, 0, _field(I.circle_polygon(20.0, 64), rs=I.RangeShifter())) == 0
+
+
+def test_run_validation_before_device(vctx):
+    L = V.load()
+    spots = V.spot_array(I.make_spots([(0, 0)], 100.0, 3.0, 10))
+    scen = V.scenario_array([I.Scenario()])
+    opts = V.make_opts()
+    dose = np.zeros(10, np.float32)
+    # no geometry yet
+    assert _rc(V.vpmc_run_spots, vctx, 0, spots, 1, scen, 1, opts, dose) == V.E_STATE
+    assert L.vpmc_run_spots(None, 0, None, 0, None, 0, None, None, None, None, None) == V.E_ARG
+    assert L.vpmc_copy_csr(vctx, None, None, None) == V.E_STATE
+    assert L.vpmc_last_tally(vctx, 0, None, None, 0) == V.E_ARG
+    assert L.vpmc_create(None, 0) == V.E_ARG
+    k = C.c_int()
+    assert L.vpmc_create(C.byref(C.c_void_p()), -5) == V.E_ARG
