@@ -44,6 +44,7 @@ PINS = {
     "batches": "sigma of the mean vs spread over independent seeds (chi^2)",
     "hu_lookup": "breakpoints of the piecewise-linear calibration",
     "absolute_dosimetry": "parity unpinned (no measurement or comparison system available)",
+    "mlp": "gradients vs central finite differences; mixture NLL vs scipy for one component",
 }
 
 
@@ -100,6 +101,9 @@ def lib():
             ("orc_slab_exit", None, [i, d, d, d, i, C.c_uint64, i64, vp, i]),
             ("orc_fixed_point_k", i, [d]), ("orc_rs_thickness", d, [d]),
             ("orc_mev_to_joule", d, []),
+            ("mlp_num_params", i, []), ("mlp_forward", None, [vp, vp, i, vp]),
+            ("mlp_loss_grad", d, [vp, vp, vp, vp, i, vp]),
+            ("mlp_adam_step", None, [vp, vp, vp, vp, i, i, d, d, d, d]),
         ]:
             f = getattr(L, name)
             f.restype = res
@@ -301,9 +305,10 @@ def q_to_gy(case, q: np.ndarray, k: int) -> np.ndarray:
 
 
 def dose(case, scenario_index: int = 0, k: Optional[int] = None, n_batches: Optional[int] = None,
-         threads: int = 0, fields=None):
+         threads: int = 0, fields=None, keep_batches: bool = False):
     """Plan dose of all fields (FP64 dict): q, dose_gy, sigma_gy, ledger_mev, k,
-    uncertainty (mean sigma/D over voxels >= 50 % of the maximum)."""
+    uncertainty (mean sigma/D over voxels >= 50 % of the maximum); with
+    keep_batches also batch_dose_gy, the per-batch estimates B * d_b."""
     B = case.n_batches if n_batches is None else n_batches
     if k is None:
         k = fixed_point_k(case)
@@ -312,6 +317,7 @@ def dose(case, scenario_index: int = 0, k: Optional[int] = None, n_batches: Opti
     s2 = np.zeros((nz, ny, nx), np.float64)
     led = np.zeros(6, np.int64)
     flist = range(len(case.fields)) if fields is None else fields
+    batches = []
     if B > 1:
         for b in range(B):
             qb = np.zeros((nz, ny, nx), np.int64)
@@ -322,6 +328,8 @@ def dose(case, scenario_index: int = 0, k: Optional[int] = None, n_batches: Opti
             q_tot += qb
             db = qb.astype(np.float64) * 2.0 ** (-k)
             s2 += db * db
+            if keep_batches:
+                batches.append(B * db)
     else:
         for fi in flist:
             q, l, _ = run_tally(case, fi, scenario_index, k, threads=threads)
@@ -334,6 +342,8 @@ def dose(case, scenario_index: int = 0, k: Optional[int] = None, n_batches: Opti
         var = np.maximum(B * s2 - d_mev * d_mev, 0.0) / (B - 1)
         out["sigma_gy"] = np.sqrt(var) * conv
         out["uncertainty"] = uncertainty(out["dose_gy"], out["sigma_gy"])
+        if keep_batches:
+            out["batch_dose_gy"] = [b * conv for b in batches]
     return out
 
 
@@ -354,3 +364,39 @@ def spot_tallies(case, field_index: int = 0, scenario_index: int = 0, k: Optiona
         q, _, _ = run_tally(case, field_index, scenario_index, k, spots=(s, s + 1), threads=threads)
         rows.append(q)
     return rows
+
+
+# ------------------------------------------------------------ surrogate MLP
+MLP_DIMS = (8, 256, 256, 256, 256, 29)
+
+
+def mlp_num_params() -> int:
+    return lib().mlp_num_params()
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """He-style uniform initialisation (layer by layer W[out][in], b[out])."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ni, no in zip(MLP_DIMS[:-1], MLP_DIMS[1:]):
+        lim = np.sqrt(6.0 / ni)
+        parts.append(rng.uniform(-lim, lim, size=no * ni))
+        parts.append(np.zeros(no))
+    return np.concatenate(parts).astype(np.float64)
+
+
+def mlp_forward(params: np.ndarray, x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, np.float64)
+    out = np.zeros((x.shape[0], MLP_DIMS[-1]), np.float64)
+    lib().mlp_forward(_ptr(np.ascontiguousarray(params, np.float64)), _ptr(x), x.shape[0], _ptr(out))
+    return out
+
+
+def mlp_loss_grad(params, x, y, trans):
+    p = np.ascontiguousarray(params, np.float64)
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    t = np.ascontiguousarray(trans, np.float64)
+    g = np.zeros(p.size, np.float64)
+    loss = lib().mlp_loss_grad(_ptr(p), _ptr(x), _ptr(y), _ptr(t), x.shape[0], _ptr(g))
+    return loss, g

@@ -7,12 +7,12 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SRC = os.path.join(HERE, "vpmc_oracle.c")
+SRC = [os.path.join(HERE, "vpmc_oracle.c"), os.path.join(HERE, "vpmc_mlp.c")]
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-Wall", "-Wextra", "-fopenmp", "-fPIC",
-           "-shared", "-o", LIB + ".tmp", SRC, "-lm"]
+           "-shared", "-o", LIB + ".tmp"] + SRC + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
