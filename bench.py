@@ -88,13 +88,19 @@ def main():
             eng.run_dose(c, 0, n_batches=a.batches, sigma=True)
             stats.append(V.vpmc_last_stats(eng.ctx))
 
-    for _ in range(a.warmup):
-        step([])
+    def progress(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    for w in range(a.warmup):
+        st = []
+        step(st)
+        progress(f"warmup {w}: {sum(s['transport_ms'] for s in st):.1f} ms transport")
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    for k in range(a.steps):
         step(stats)
+        progress(f"step {k}: {time.perf_counter() - t0:.2f} s elapsed")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
@@ -129,6 +135,7 @@ def main():
         "device": torch.cuda.get_device_name(0),
     }
     if not a.no_cpu_baseline:
+        progress("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(int(a.cpu_sample))
     eng.close()
     print(json.dumps(out), flush=True)

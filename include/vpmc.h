@@ -142,7 +142,7 @@ typedef struct {
     unsigned flags;         /* VPMC_DEVICE_PTRS */
     void *hip_stream;       /* hipStream_t or NULL (default stream) */
     size_t max_device_bytes;/* 0 = no cap; scratch above the cap -> VPMC_E_OOM */
-    int block_threads;      /* 0 = tuned default; else 64..1024, multiple of 64 */
+    int block_threads;      /* 0 = tuned default; else 256 or 512 */
     int grid_blocks;        /* 0 = tuned default */
     int hist_per_lane;      /* CSR work-queue chunk = 64 * hist_per_lane histories; 0 = default 4 */
     int max_slots;          /* CSR rows resident at once (<= 1024); 0 = sized from memory */
@@ -180,6 +180,21 @@ int vpmc_run_batched(vpmc_ctx *ctx, const int *field_ids, const vpmc_spot *const
                      const int *n_spots, int n_fields, const vpmc_scenario *scen, int n_scen,
                      const vpmc_opts *opts, float *dose_gy, double *ledger_mev, int64_t *row_ptr);
 
+/* Autotuner: for the launch shape only (never for results: tallies are
+ * integers and streams are keyed by history, so every shape gives the same
+ * bits).  Runs a bounded sample of the given spots (each spot's history count
+ * scaled so that the sample holds about sample_histories VPs) in the output
+ * mode of *base for each candidate shape, keeps the one with the shortest
+ * transport time per history, writes it into *best (a copy of *base with
+ * hist_per_lane, grid_blocks and block_threads filled) and remembers it for
+ * later runs on this context whose opts leave them at 0.  Candidates (CSR):
+ * hist_per_lane in {2,4,8,16} x (workgroups, threads) in {(4 CUs, 256),
+ * (8 CUs, 256), (2 CUs, 512), (4 CUs, 512)}; (dense): {4,8,16,32} x CUs x 256
+ * threads of work per launch in workgroups of 256 or 512 threads. */
+int vpmc_autotune(vpmc_ctx *ctx, int field_id, const vpmc_spot *spots, int n_spots,
+                  const vpmc_scenario *scen, const vpmc_opts *base, uint64_t sample_histories,
+                  vpmc_opts *best);
+
 /* After a CSR run: column (voxel) indices in ascending order per row and FP32
  * values (Gy per unit spot weight, converted from the int64 tally); q_raw
  * (optional) receives the int64 tallies themselves.  Buffers must hold
@@ -187,7 +202,8 @@ int vpmc_run_batched(vpmc_ctx *ctx, const int *field_ids, const vpmc_spot *const
 int vpmc_copy_csr(vpmc_ctx *ctx, int32_t *col_voxel, float *val_gy, int64_t *q_raw);
 
 /* After a dense run: copy the int64 tally of scenario `scen_index` and the
- * fixed-point exponent k (dose = q * 2^-k MeV converted per voxel mass). */
+ * fixed-point exponent k (dose = q * 2^-k MeV converted per voxel mass).
+ * scen_index == -1 with q_out == NULL returns only k (also after a CSR run). */
 int vpmc_last_tally(vpmc_ctx *ctx, int scen_index, int64_t *q_out, int *k_out, unsigned flags);
 
 /* Measurements of the last run: transport_ms is the sum of the transport

@@ -14,6 +14,9 @@ ARCH = os.environ.get("VPMC_OFFLOAD_ARCH", "gfx950")
 def build(verbose: bool = False) -> str:
     cmd = ["/opt/rocm/bin/hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Wall", "-Wno-unused-parameter",
+           # no implicit FMA contraction: identical FP32 results in every kernel
+           # that inlines the step (explicit fmaf calls are kept)
+           "-ffp-contract=off",
            # packed FP32 instructions stay off (see the build notes)
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-o", LIB + ".tmp"] + [os.path.join(HERE, s) for s in SOURCES]

@@ -77,6 +77,9 @@ struct vpmc_ctx {
     int csr_rows = 0;
     bool csr_valid = false;
     unsigned csr_flags = 0;
+    // autotuned launch shapes (0 = not tuned)
+    int tuned_csr_hpl = 0, tuned_csr_blocks = 0, tuned_dense_blocks = 0;
+    int tuned_csr_threads = 0, tuned_dense_threads = 0;
 };
 
 namespace {
@@ -244,7 +247,7 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     const bool dev_out = (o->flags & VPMC_DEVICE_PTRS) != 0;
     const size_t cap = o->max_device_bytes;
     hipStream_t st = (hipStream_t)o->hip_stream;
-    const int hpl = o->hist_per_lane > 0 ? o->hist_per_lane : 4;
+    const int hpl = o->hist_per_lane > 0 ? o->hist_per_lane : (c->tuned_csr_hpl ? c->tuned_csr_hpl : 4);
     const unsigned long long chunk = 64ull * hpl;
     int rc;
 
@@ -340,7 +343,7 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     if ((rc = ensure(c, c->row_off, std::max(1, R) * 8, cap))) return rc;
     if ((rc = ensure(c, c->row_nnz, std::max(1, R) * 8, cap))) return rc;
     if ((rc = ensure(c, c->used, 8, cap))) return rc;
-    if ((rc = ensure(c, c->flags, 4, cap))) return rc;
+    if ((rc = ensure(c, c->flags, 8, cap))) return rc;
     if ((rc = ensure(c, c->fields_tab, nf * sizeof(FieldDev), cap))) return rc;
     if ((rc = ensure(c, c->poly_off, nf * sizeof(int), cap))) return rc;
     if ((rc = ensure(c, c->polys, polys.size() * sizeof(float2), cap))) return rc;
@@ -355,11 +358,6 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     HIP_TRY(hipMemcpyAsync(c->polys.ptr, polys.data(), polys.size() * sizeof(float2), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(c->spots.ptr, sd.data(), sd.size() * sizeof(SpotDev), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(c->scen_tab.ptr, stab.data(), n_scen * sizeof(ScenDev), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemsetAsync(c->ledger.ptr, 0, (size_t)n_scen * NLEDGER * 8, st));
-    HIP_TRY(hipMemsetAsync(c->stats.ptr, 0, 16, st));
-    HIP_TRY(hipMemsetAsync(c->heads.ptr, 0, std::max(1, E) * 8, st));
-    HIP_TRY(hipMemsetAsync(c->used.ptr, 0, 8, st));
-    HIP_TRY(hipMemsetAsync(c->flags.ptr, 0, 4, st));
     // initial CSR capacity: the previous run's total, else a per-row guess
     unsigned long long want = c->csr_cap_hint ? c->csr_cap_hint : (unsigned long long)std::max(R, 1) * 16384ull;
     want = std::min<unsigned long long>(want, (unsigned long long)std::max(R, 1) * nvox);
@@ -397,43 +395,111 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) dev_cus = prop.multiProcessorCount;
     }
-    const int q_blocks = o->grid_blocks ? o->grid_blocks : dev_cus * 4;   // 16 waves per CU resident
+    const int q_threads = o->block_threads ? o->block_threads : (c->tuned_csr_threads ? c->tuned_csr_threads : 256);
+    const int q_blocks = o->grid_blocks ? o->grid_blocks
+                         : (c->tuned_csr_blocks ? c->tuned_csr_blocks : dev_cus * 4);   // 16 waves per CU
     while (c->events.size() < 4) {
         hipEvent_t ev;
         HIP_TRY(hipEventCreate(&ev));
         c->events.push_back(ev);
     }
-    HIP_TRY(hipEventRecord(c->events[0], st));
-    double transport_ms = 0.0;
-    unsigned long long used_host = 0;
-    for (int e = 0; e < E; ++e) {
+    // counters are cleared by fill kernels (no memset nodes in a captured graph)
+    auto clear_counters = [&]() -> int {
+        HIP_TRY(launch_fill_u64((unsigned long long *)c->ledger.ptr, (size_t)n_scen * NLEDGER, 0ull, st));
+        HIP_TRY(launch_fill_u64((unsigned long long *)c->stats.ptr, 2, 0ull, st));
+        HIP_TRY(launch_fill_u64((unsigned long long *)c->heads.ptr, (size_t)std::max(1, E), 0ull, st));
+        HIP_TRY(launch_fill_u64((unsigned long long *)c->used.ptr, 1, 0ull, st));
+        HIP_TRY(launch_fill_u64((unsigned long long *)c->flags.ptr, 1, 0ull, st));
+        return VPMC_OK;
+    };
+    auto epoch_queue = [&](int e) {
         QueueDev Qe = Q;
         Qe.row_begin = e * G;
         Qe.n_rows = std::min(R, (e + 1) * G) - e * G;
         Qe.chunk_off = (const unsigned long long *)c->chunk_off.ptr + ep_choff[e];
         Qe.n_chunks = ep_chunks[e];
         Qe.head = (unsigned long long *)c->heads.ptr + e;
-        HIP_TRY(hipEventRecord(c->events[2], st));
-        if (Qe.n_chunks) HIP_TRY(launch_queue(c->geom, Qe, q_blocks, st));
-        HIP_TRY(hipEventRecord(c->events[3], st));
-        HIP_TRY(launch_csr_offsets((unsigned int *)c->slot_nnz.ptr, Qe.n_rows, Qe.row_begin,
-                                   (unsigned long long *)c->row_off.ptr, (unsigned long long *)c->row_nnz.ptr,
-                                   (unsigned long long *)c->used.ptr, ~0ull, (unsigned int *)c->flags.ptr, st));
-        unsigned long long used_now = 0;
-        HIP_TRY(hipMemcpyAsync(&used_now, c->used.ptr, 8, hipMemcpyDeviceToHost, st));
+        return Qe;
+    };
+    HIP_TRY(hipEventRecord(c->events[0], st));
+    double transport_ms = 0.0;
+    unsigned long long used_host = 0;
+    bool done = false;
+    if (o->flags & VPMC_GRAPH) {
+        // whole run as one graph: rows that do not fit the current CSR
+        // capacity raise the overflow flag, and the eager path below reruns
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        int crc = clear_counters();
+        for (int e = 0; e < E && crc == VPMC_OK; ++e) {
+            const QueueDev Qe = epoch_queue(e);
+            hipError_t he = hipSuccess;
+            if (Qe.n_chunks) he = launch_queue(c->geom, Qe, q_blocks, q_threads, st);
+            if (he == hipSuccess)
+                he = launch_csr_offsets((unsigned int *)c->slot_nnz.ptr, Qe.n_rows, Qe.row_begin,
+                                        (unsigned long long *)c->row_off.ptr, (unsigned long long *)c->row_nnz.ptr,
+                                        (unsigned long long *)c->used.ptr, c->csr_cap, (unsigned int *)c->flags.ptr, st);
+            if (he == hipSuccess)
+                he = launch_csr_compact(Qe, (const unsigned long long *)c->row_off.ptr, (int32_t *)c->csr_col.ptr,
+                                        (long long *)c->csr_q.ptr, c->csr_cap, (unsigned int *)c->flags.ptr, st);
+            if (he != hipSuccess) crc = fail(VPMC_E_DEVICE, "graph capture launch: %s", hipGetErrorString(he));
+        }
+        const hipError_t ce = hipStreamEndCapture(st, &graph);
+        if (crc) { if (graph) (void)hipGraphDestroy(graph); return crc; }
+        HIP_TRY(ce);
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ie == hipSuccess) {
+            HIP_TRY(hipEventRecord(c->events[2], st));
+            ie = hipGraphLaunch(exec, st);
+            HIP_TRY(hipEventRecord(c->events[3], st));
+        }
+        (void)hipGraphDestroy(graph);
         HIP_TRY(hipStreamSynchronize(st));
+        if (exec) (void)hipGraphExecDestroy(exec);
+        HIP_TRY(ie);
+        unsigned long long fl8 = 0, used_now = 0;
+        HIP_TRY(hipMemcpy(&fl8, c->flags.ptr, 8, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(&used_now, c->used.ptr, 8, hipMemcpyDeviceToHost));
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, c->events[2], c->events[3]));
-        transport_ms += ms;
-        if (used_now > c->csr_cap) {   // grow, keeping the rows already written
+        if (!(fl8 & 1ull)) {
+            transport_ms = ms;   // whole graph (transport dominated)
+            used_host = used_now;
+            done = true;
+        } else {
             const unsigned long long ncap = std::max<unsigned long long>(used_now, c->csr_cap * 2);
-            if ((rc = grow_keep(c, c->csr_col, used_host * 4, ncap * 4, cap, st))) return rc;
-            if ((rc = grow_keep(c, c->csr_q, used_host * 8, ncap * 8, cap, st))) return rc;
+            if ((rc = grow_keep(c, c->csr_col, 0, ncap * 4, cap, st))) return rc;
+            if ((rc = grow_keep(c, c->csr_q, 0, ncap * 8, cap, st))) return rc;
             c->csr_cap = ncap;
         }
-        HIP_TRY(launch_csr_compact(Qe, (const unsigned long long *)c->row_off.ptr, (int32_t *)c->csr_col.ptr,
-                                   (long long *)c->csr_q.ptr, c->csr_cap, (unsigned int *)c->flags.ptr, st));
-        used_host = used_now;
+    }
+    if (!done) {
+        if ((rc = clear_counters())) return rc;
+        for (int e = 0; e < E; ++e) {
+            const QueueDev Qe = epoch_queue(e);
+            HIP_TRY(hipEventRecord(c->events[2], st));
+            if (Qe.n_chunks) HIP_TRY(launch_queue(c->geom, Qe, q_blocks, q_threads, st));
+            HIP_TRY(hipEventRecord(c->events[3], st));
+            HIP_TRY(launch_csr_offsets((unsigned int *)c->slot_nnz.ptr, Qe.n_rows, Qe.row_begin,
+                                       (unsigned long long *)c->row_off.ptr, (unsigned long long *)c->row_nnz.ptr,
+                                       (unsigned long long *)c->used.ptr, ~0ull, (unsigned int *)c->flags.ptr, st));
+            unsigned long long used_now = 0;
+            HIP_TRY(hipMemcpyAsync(&used_now, c->used.ptr, 8, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, c->events[2], c->events[3]));
+            transport_ms += ms;
+            if (used_now > c->csr_cap) {   // grow, keeping the rows already written
+                const unsigned long long ncap = std::max<unsigned long long>(used_now, c->csr_cap * 2);
+                if ((rc = grow_keep(c, c->csr_col, used_host * 4, ncap * 4, cap, st))) return rc;
+                if ((rc = grow_keep(c, c->csr_q, used_host * 8, ncap * 8, cap, st))) return rc;
+                c->csr_cap = ncap;
+            }
+            HIP_TRY(launch_csr_compact(Qe, (const unsigned long long *)c->row_off.ptr, (int32_t *)c->csr_col.ptr,
+                                       (long long *)c->csr_q.ptr, c->csr_cap, (unsigned int *)c->flags.ptr, st));
+            used_host = used_now;
+        }
     }
     unsigned int fl = 0;
     std::vector<unsigned long long> roff(std::max(R, 1)), rnnz(std::max(R, 1));
@@ -673,8 +739,8 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
     if ((rc = validate_scen(scen, n_scen))) return rc;
     if (o->physics & ~VPMC_PHYS_ALL) return fail(VPMC_E_ARG, "unknown physics bits");
     if (o->n_batches < 0 || o->n_batches > 1024) return fail(VPMC_E_ARG, "n_batches outside [0, 1024]");
-    if (o->block_threads && (o->block_threads < 64 || o->block_threads > 1024 || o->block_threads % 64))
-        return fail(VPMC_E_ARG, "block_threads must be a multiple of 64 in [64, 1024]");
+    if (o->block_threads && o->block_threads != 256 && o->block_threads != 512)
+        return fail(VPMC_E_ARG, "block_threads must be 0, 256 or 512");
     if (o->grid_blocks < 0) return fail(VPMC_E_ARG, "grid_blocks < 0");
     if (o->hist_per_lane < 0 || o->hist_per_lane > 4096) return fail(VPMC_E_ARG, "hist_per_lane outside [0, 4096]");
     if (o->max_slots < 0) return fail(VPMC_E_ARG, "max_slots < 0");
@@ -751,7 +817,7 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
     HIP_TRY(hipEventRecord(c->events[0], st));
 
     const FieldDev &fd = c->fields[field_id].dev;
-    const int threads = 256;
+    const int threads = o->block_threads ? o->block_threads : (c->tuned_dense_threads ? c->tuned_dense_threads : 256);
     const double mev_scale = ldexp(MEV_TO_J, -k);
     for (int sc = 0; sc < n_scen; ++sc) {
         long long *tally = (long long *)c->tallies.ptr + (size_t)sc * nvox;
@@ -779,7 +845,8 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
             L.tables = c->d_tables;
             L.stats = (unsigned long long *)c->stats.ptr;
             unsigned long long want = (items + threads - 1) / threads;
-            const unsigned long long maxb = o->grid_blocks ? (unsigned long long)o->grid_blocks : 4096ull;
+            const unsigned long long maxb = o->grid_blocks ? (unsigned long long)o->grid_blocks
+                                            : (c->tuned_dense_blocks ? (unsigned long long)c->tuned_dense_blocks : 4096ull);
             const int blocks = (int)std::min(want, maxb);
             HIP_TRY(hipEventRecord(c->events[2 + 2 * n_launch], st));
             HIP_TRY(launch_transport(c->geom, fd, L, blocks, threads, st));
@@ -857,11 +924,83 @@ int vpmc_run_batched(vpmc_ctx *c, const int *field_ids, const vpmc_spot *const *
     if (o->flags & ~(VPMC_DEVICE_PTRS | VPMC_GRAPH)) return fail(VPMC_E_ARG, "unknown flags");
     if (o->hist_per_lane < 0 || o->hist_per_lane > 4096) return fail(VPMC_E_ARG, "hist_per_lane outside [0, 4096]");
     if (o->max_slots < 0 || o->grid_blocks < 0) return fail(VPMC_E_ARG, "negative tuning value");
+    if (o->block_threads && o->block_threads != 256 && o->block_threads != 512)
+        return fail(VPMC_E_ARG, "block_threads must be 0, 256 or 512");
     int k = 0;
     if ((rc = pick_k(o, T, &k))) return rc;
     if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
     HIP_TRY(hipSetDevice(c->device));
     return run_csr(c, bf, scen, n_scen, o, k, dose_gy, ledger_mev, row_ptr);
+}
+
+int vpmc_autotune(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spots, const vpmc_scenario *scen,
+                  const vpmc_opts *base, uint64_t sample_histories, vpmc_opts *best) {
+    if (!c || !base || !best || !spots || n_spots < 1 || !scen) return fail(VPMC_E_ARG, "bad autotune arguments");
+    if (sample_histories < 64) return fail(VPMC_E_ARG, "sample_histories must be >= 64");
+    if (!c->has_geom) return fail(VPMC_E_STATE, "no geometry loaded");
+    if (field_id < 0 || field_id >= VPMC_MAX_FIELDS || !c->fields[field_id].set)
+        return fail(VPMC_E_STATE, "field %d not set", field_id);
+    if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
+    double tot = 0.0;
+    for (int i = 0; i < n_spots; ++i) tot += spots[i].n_histories;
+    if (tot <= 0) return fail(VPMC_E_ARG, "spots hold no histories");
+    const double f = std::min(1.0, (double)sample_histories / tot);
+    std::vector<vpmc_spot> sub(spots, spots + n_spots);
+    for (auto &sp : sub) sp.n_histories = (uint32_t)std::max(1.0, std::floor(sp.n_histories * f));
+    int cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) cus = prop.multiProcessorCount;
+    const bool csr = base->output == VPMC_OUT_CSR;
+    struct Cand { int hpl, blocks, threads; };
+    std::vector<Cand> cand;
+    if (csr) {
+        for (int h : {2, 4, 8, 16})
+            for (auto bt : {std::make_pair(4, 256), std::make_pair(8, 256), std::make_pair(2, 512), std::make_pair(4, 512)})
+                cand.push_back({h, bt.first * cus, bt.second});
+    } else {
+        for (int m : {4, 8, 16, 32})
+            for (int t : {256, 512}) cand.push_back({0, m * cus * 256 / t, t});
+    }
+    const size_t R = (size_t)n_spots;
+    std::vector<int64_t> rp(R + 1);
+    std::vector<double> led(NLEDGER);
+    double best_t = 1e300;
+    vpmc_opts pick = *base;
+    for (size_t ci = 0; ci <= cand.size(); ++ci) {
+        // the first pass warms up the buffers and is not scored
+        const Cand cd = cand[ci == 0 ? 0 : ci - 1];
+        vpmc_opts o = *base;
+        o.flags &= ~(unsigned)VPMC_DEVICE_PTRS;
+        o.flags &= ~(unsigned)VPMC_GRAPH;
+        o.n_batches = 0;
+        o.hist_per_lane = cd.hpl;
+        o.grid_blocks = cd.blocks;
+        o.block_threads = cd.threads;
+        const int rc = csr ? vpmc_run_spots(c, field_id, sub.data(), n_spots, scen, 1, &o, nullptr, nullptr,
+                                            led.data(), rp.data())
+                           : vpmc_run_spots(c, field_id, sub.data(), n_spots, scen, 1, &o, nullptr, nullptr,
+                                            led.data(), nullptr);
+        if (rc) return rc;
+        if (ci == 0) continue;
+        const double t = c->last_stats.transport_ms / std::max<double>(1.0, (double)c->last_stats.histories);
+        if (t < best_t) {
+            best_t = t;
+            pick = *base;
+            pick.hist_per_lane = cd.hpl;
+            pick.grid_blocks = cd.blocks;
+            pick.block_threads = cd.threads;
+        }
+    }
+    if (csr) {
+        c->tuned_csr_hpl = pick.hist_per_lane;
+        c->tuned_csr_blocks = pick.grid_blocks;
+        c->tuned_csr_threads = pick.block_threads;
+    } else {
+        c->tuned_dense_blocks = pick.grid_blocks;
+        c->tuned_dense_threads = pick.block_threads;
+    }
+    *best = pick;
+    return VPMC_OK;
 }
 
 int vpmc_copy_csr(vpmc_ctx *c, int32_t *col, float *val, int64_t *q_raw) {
@@ -893,6 +1032,10 @@ int vpmc_copy_csr(vpmc_ctx *c, int32_t *col, float *val, int64_t *q_raw) {
 int vpmc_last_tally(vpmc_ctx *c, int scen_index, int64_t *q_out, int *k_out, unsigned flags) {
     if (!c) return fail(VPMC_E_ARG, "ctx is NULL");
     if (!q_out && !k_out) return fail(VPMC_E_ARG, "no output");
+    if (!q_out && scen_index == -1 && (c->last_nscen || c->csr_valid)) {   // exponent only
+        *k_out = c->last_k;
+        return VPMC_OK;
+    }
     if (c->last_nscen == 0) return fail(VPMC_E_STATE, "no dense run to copy");
     if (scen_index < 0 || scen_index >= c->last_nscen) return fail(VPMC_E_ARG, "scenario index out of range");
     if (k_out) *k_out = c->last_k;

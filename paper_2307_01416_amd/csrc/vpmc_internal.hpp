@@ -131,7 +131,7 @@ struct QueueDev {
     const float *tables;
 };
 
-hipError_t launch_queue(const GeomDev &g, const QueueDev &Q, int blocks, hipStream_t s);
+hipError_t launch_queue(const GeomDev &g, const QueueDev &Q, int blocks, int threads, hipStream_t s);
 hipError_t launch_csr_offsets(unsigned int *nnz, int n_rows, int row_begin, unsigned long long *row_off,
                               unsigned long long *row_nnz, unsigned long long *used, unsigned long long capacity,
                               unsigned int *flags, hipStream_t s);

@@ -72,11 +72,21 @@ __device__ __forceinline__ int seg_of(const float *tab, float E) {
     return i;
 }
 
-__device__ __forceinline__ float node_interp(const float *tab, const float *y, float E) {
+// position of E on the node grid: segment and clamped fraction, shared by
+// every table interpolated at the same energy (linear in E between nodes)
+struct NodePos {
+    int i;
+    float f;
+};
+
+__device__ __forceinline__ NodePos node_pos(const float *tab, float E) {
     const int i = seg_of(tab, E);
-    float f = (E - tab[TAB_E + i]) * tab[TAB_INVDE + i];
-    f = fminf(fmaxf(f, 0.0f), 1.0f);
-    return fmaf(f, y[i + 1] - y[i], y[i]);
+    const float f = (E - tab[TAB_E + i]) * tab[TAB_INVDE + i];
+    return {i, fminf(fmaxf(f, 0.0f), 1.0f)};
+}
+
+__device__ __forceinline__ float node_lerp(const float *y, NodePos p) {
+    return fmaf(p.f, y[p.i + 1] - y[p.i], y[p.i]);
 }
 
 // Energy lost while traversing the areal density r (g/cm^2), starting at
@@ -85,7 +95,7 @@ __device__ __forceinline__ float node_interp(const float *tab, const float *y, f
 // keeps full relative precision instead of being a difference of two nearly
 // equal energies.
 __device__ __forceinline__ float csda_loss(const float *tm, int i, float x, float slope, float r) {
-    const float rem = x / slope;
+    const float rem = x * __builtin_amdgcn_rcpf(slope);
     if (r <= rem) return r * slope;
     float dE = x;
     r -= rem;
@@ -103,13 +113,13 @@ __device__ __forceinline__ void rotate_dir(Lane &v, float ax, float ay) {
     if (th2 == 0.0f) return;
     const float th = sqrtf(th2);
     const float sg = copysignf(1.0f, v.dz);
-    const float a = -1.0f / (sg + v.dz);
+    const float a = -__builtin_amdgcn_rcpf(sg + v.dz);
     const float b = v.dx * v.dy * a;
     const float e1x = 1.0f + sg * v.dx * v.dx * a, e1y = sg * b, e1z = -sg * v.dx;
     const float e2x = b, e2y = sg + v.dy * v.dy * a, e2z = -v.dy;
     float sn, c;
     __sincosf(th, &sn, &c);
-    const float k = sn / th;
+    const float k = sn * __builtin_amdgcn_rcpf(th);
     float nx = c * v.dx + k * (ax * e1x + ay * e2x);
     float ny = c * v.dy + k * (ax * e1y + ay * e2y);
     float nz = c * v.dz + k * (ax * e1z + ay * e2z);
@@ -151,22 +161,26 @@ __device__ int phys_step(Lane &v, const float *tab, int m, float rho_loss, float
     const int i = seg_of(tab, v.E);
     const float x = (v.E - tab[TAB_E + i]) + v.Elo;
     const float slope = tm[T_SLOPE * NE + i];
-    const float R = tm[T_R * NE + i] + x / slope;
+    const float R = tm[T_R * NE + i] + x * __builtin_amdgcn_rcpf(slope);
     if (rho_loss * dg * 0.1f >= R) {
         dep = v.E + v.Elo;
         v.E = v.Elo = 0.0f;
         return ST_STOP;
     }
-    const float smax = 10.0f * STEP_FRACTION * R / rho_loss;
+    const float smax = 10.0f * STEP_FRACTION * R * __builtin_amdgcn_rcpf(rho_loss);
     const bool geo = dg <= smax;
     const float s = geo ? dg : smax;
     const float r = rho_loss * s * 0.1f;
     float dE = csda_loss(tm, i, x, slope, r);
     const float Ebar = v.E - 0.5f * dE;
     uint4 w = make_uint4(0u, 0u, 0u, 0xFFFFFFFFu);
-    if (v.physics) w = draw(v);
+    NodePos pb{0, 0.0f};
+    if (v.physics) {
+        w = draw(v);
+        pb = node_pos(tab, Ebar);
+    }
     if (v.physics & PH_STRAGGLE) {
-        const float var = r * node_interp(tab, tm + T_W2 * NE, Ebar);
+        const float var = r * node_lerp(tm + T_W2 * NE, pb);
         const float z = 1.41421356237f * erfinvf(2.0f * unit_open(w.z) - 1.0f);
         dE -= sqrtf(var) * z;
         dE = fminf(fmaxf(dE, 0.0f), v.E + v.Elo);
@@ -174,7 +188,7 @@ __device__ int phys_step(Lane &v, const float *tab, int m, float rho_loss, float
     dep = dE;
     sub_energy(v, dE);
     if (v.physics & PH_MCS) {
-        const float th0 = sqrtf(rho * s * 0.1f * node_interp(tab, tm + T_T * NE, Ebar));
+        const float th0 = sqrtf(rho * s * 0.1f * node_lerp(tm + T_T * NE, pb));
         float z1, z2;
         box_muller_fast(w.x, w.y, z1, z2);
         const float h = 0.5f * s;
@@ -191,7 +205,7 @@ __device__ int phys_step(Lane &v, const float *tab, int m, float rho_loss, float
         v.pz = fmaf(s, v.dz, v.pz);
     }
     if (v.physics & PH_NUCLEAR) {
-        const float P = -expm1f(-rho * s * 0.1f * node_interp(tab, tm + T_SN * NE, Ebar));
+        const float P = -expm1f(-rho * s * 0.1f * node_lerp(tm + T_SN * NE, pb));
         if (unit_open(w.w) < P) {
             const uint4 w2 = draw(v);
             const float E1 = v.E + v.Elo;
@@ -474,7 +488,19 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
         const float c = floorf((p[k] - g.lo[k]) / g.sp[k]);
         idx[k] = !(c >= 0.0f) ? 0 : c > (float)(n[k] - 1) ? n[k] - 1 : (int)c;   // NaN -> 0
     }
-    v.px = p[0]; v.py = p[1]; v.pz = p[2];
+    // From here the position is kept relative to the lower corner of the
+    // current voxel (0 <= u_k <= spacing_k): FP32 resolves it to ~1e-7 of a
+    // voxel wherever the voxel sits, so sub-voxel steps near the end of range
+    // do not inherit the rounding of large absolute coordinates.
+    {
+        float u[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            u[k] = fminf(fmaxf(p[k] - (g.lo[k] + (float)idx[k] * g.sp[k]), 0.0f), g.sp[k]);
+            if (t0 == tnear && k == axn) u[k] = d[k] > 0.0f ? 0.0f : g.sp[k];
+        }
+        v.px = u[0]; v.py = u[1]; v.pz = u[2];
+    }
     v.dx = d[0]; v.dy = d[1]; v.dz = d[2];
     for (int it = 0; it < MAX_STEPS; ++it) {
         const uint32_t vox = (uint32_t)idx[0] + (uint32_t)g.nx * ((uint32_t)idx[1] + (uint32_t)g.ny * (uint32_t)idx[2]);
@@ -483,15 +509,15 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
         if (g.kind == 1) hu_material(g.hu[vox], m, rho);
         const float rho_loss = rho * range_scale;
         const float pp[3] = {v.px, v.py, v.pz}, dd[3] = {v.dx, v.dy, v.dz};
-        float dg = INFINITY, bnd = 0.0f;
+        float dg = INFINITY;
         int ax = -1, sgn = 0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             if (dd[k] == 0.0f) continue;
             const bool up = dd[k] > 0.0f;
-            const float b = g.lo[k] + (float)(idx[k] + (up ? 1 : 0)) * g.sp[k];
-            const float t = fmaxf((b - pp[k]) / dd[k], 0.0f);
-            if (t < dg) { dg = t; ax = k; sgn = up ? 1 : -1; bnd = b; }
+            // hardware reciprocal: exact for the unit components of axis-aligned beams
+            const float t = fmaxf(((up ? g.sp[k] : 0.0f) - pp[k]) * __builtin_amdgcn_rcpf(dd[k]), 0.0f);
+            if (t < dg) { dg = t; ax = k; sgn = up ? 1 : -1; }
         }
         float dep, esc;
         const int st = phys_step(v, tab, m, rho_loss, rho, dg, dep, esc);
@@ -507,7 +533,7 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
             for (int k = 0; k < 3; ++k) {
                 if (k == ax) {
                     idx[k] += sgn;
-                    q[k] = bnd;
+                    q[k] = sgn > 0 ? 0.0f : g.sp[k];   // near face of the next voxel
                     out = idx[k] < 0 || idx[k] >= n[k];
                 }
             }
@@ -517,11 +543,7 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
             }
         }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const float a = g.lo[k] + (float)idx[k] * g.sp[k];
-            const float b = g.lo[k] + (float)(idx[k] + 1) * g.sp[k];
-            q[k] = fminf(fmaxf(q[k], a), b);
-        }
+        for (int k = 0; k < 3; ++k) q[k] = fminf(fmaxf(q[k], 0.0f), g.sp[k]);
         v.px = q[0]; v.py = q[1]; v.pz = q[2];
     }
     ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
@@ -554,7 +576,7 @@ __device__ __forceinline__ int find_spot(const unsigned long long *off, int n, u
     return lo;
 }
 
-__global__ __launch_bounds__(kThreads) void transport_kernel(GeomDev g, FieldDev f, LaunchDev L) {
+__global__ __launch_bounds__(512) void transport_kernel(GeomDev g, FieldDev f, LaunchDev L) {
     __shared__ float tab[TAB_FLOATS];
     __shared__ float2 poly[POLY_LDS];
     for (int i = threadIdx.x; i < TAB_FLOATS / 4; i += blockDim.x)
@@ -610,7 +632,8 @@ __global__ __launch_bounds__(kThreads) void transport_kernel(GeomDev g, FieldDev
 // histories of one row) at a time from the epoch's atomic counter, so rows
 // of uneven energy and history count balance across the chip.  Every wave
 // exits once the counter passes the number of chunks.
-__global__ __launch_bounds__(kThreads) void queue_kernel(GeomDev g, QueueDev Q) {
+// at most 512 threads per workgroup; 4 waves per SIMD keeps the VGPRs <= 128
+__global__ __launch_bounds__(512, 4) void queue_kernel(GeomDev g, QueueDev Q) {
     __shared__ float tab[TAB_FLOATS];
     __shared__ float2 poly[POLY_LDS];
     for (int i = threadIdx.x; i < TAB_FLOATS / 4; i += blockDim.x)
@@ -834,13 +857,14 @@ __global__ void dose_kernel(const long long *q, const double *s2, int B, GeomDev
 
 hipError_t launch_transport(const GeomDev &g, const FieldDev &f, const LaunchDev &L, int blocks,
                             int threads, hipStream_t s) {
-    if (threads != kThreads) threads = kThreads;
+    if (threads != 256 && threads != 512) threads = kThreads;
     hipLaunchKernelGGL(transport_kernel, dim3(blocks), dim3(threads), 0, s, g, f, L);
     return hipGetLastError();
 }
 
-hipError_t launch_queue(const GeomDev &g, const QueueDev &Q, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL(queue_kernel, dim3(blocks), dim3(kThreads), 0, s, g, Q);
+hipError_t launch_queue(const GeomDev &g, const QueueDev &Q, int blocks, int threads, hipStream_t s) {
+    if (threads != 256 && threads != 512) threads = kThreads;
+    hipLaunchKernelGGL(queue_kernel, dim3(blocks), dim3(threads), 0, s, g, Q);
     return hipGetLastError();
 }
 

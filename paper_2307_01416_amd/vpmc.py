@@ -27,6 +27,7 @@ STRAGGLE, MCS, NUCLEAR, PHYS_ALL = 1, 2, 4, 7
 GEOM_WATER, GEOM_HU = 0, 1
 OUT_DOSE, OUT_CSR = 0, 1
 DEVICE_PTRS = 1
+GRAPH = 2
 NLEDGER = 6
 
 
@@ -63,7 +64,8 @@ class vpmc_opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("physics", C.c_uint), ("n_batches", C.c_int),
                 ("output", C.c_int), ("fixed_point_bits", C.c_int), ("flags", C.c_uint),
                 ("hip_stream", C.c_void_p), ("max_device_bytes", C.c_size_t),
-                ("block_threads", C.c_int), ("grid_blocks", C.c_int)]
+                ("block_threads", C.c_int), ("grid_blocks", C.c_int), ("hist_per_lane", C.c_int),
+                ("max_slots", C.c_int)]
 
 
 class vpmc_stats(C.Structure):
@@ -96,6 +98,8 @@ def load() -> C.CDLL:
         "vpmc_last_tally": (i, [vp, i, vp, C.POINTER(C.c_int), u]),
         "vpmc_table_host": (i, [i, i, vp, i]),
         "vpmc_last_stats": (i, [vp, vp]),
+        "vpmc_run_batched": (i, [vp, vp, vp, vp, i, vp, i, vp, vp, vp, vp]),
+        "vpmc_autotune": (i, [vp, i, vp, i, vp, vp, C.c_uint64, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -204,12 +208,14 @@ def scenario_array(scen: Sequence[I.Scenario]):
 
 
 def make_opts(seed=0, physics=PHYS_ALL, n_batches=0, output=OUT_DOSE, fixed_point_bits=0,
-              flags=0, stream=None, max_device_bytes=0, block_threads=0, grid_blocks=0) -> vpmc_opts:
+              flags=0, stream=None, max_device_bytes=0, block_threads=0, grid_blocks=0,
+              hist_per_lane=0, max_slots=0) -> vpmc_opts:
     o = vpmc_opts()
     o.seed, o.physics, o.n_batches, o.output = seed, physics, n_batches, output
     o.fixed_point_bits, o.flags = fixed_point_bits, flags
     o.hip_stream = stream
     o.max_device_bytes, o.block_threads, o.grid_blocks = max_device_bytes, block_threads, grid_blocks
+    o.hist_per_lane, o.max_slots = hist_per_lane, max_slots
     return o
 
 
@@ -220,8 +226,36 @@ def vpmc_run_spots(ctx, field_id: int, spots, n_spots: int, scen, n_scen: int, o
                                  C.byref(opts), _ptr(dose), _ptr(sigma), _ptr(ledger), _ptr(row_ptr)), ctx)
 
 
+def vpmc_run_batched(ctx, field_ids: Sequence[int], spot_arrays: Sequence, scen, n_scen: int,
+                     opts: vpmc_opts, dose=None, ledger=None, row_ptr=None) -> None:
+    nf = len(field_ids)
+    ids = (C.c_int * nf)(*field_ids)
+    ptrs = (C.c_void_p * nf)(*[C.cast(a, C.c_void_p) for a in spot_arrays])
+    ns = (C.c_int * nf)(*[len(a) for a in spot_arrays])
+    _check(load().vpmc_run_batched(ctx, ids, ptrs, ns, nf, C.cast(scen, C.c_void_p), n_scen, C.byref(opts),
+                                   _ptr(dose), _ptr(ledger), _ptr(row_ptr)), ctx)
+
+
+def vpmc_autotune(ctx, field_id: int, spots, n_spots: int, scen, base: vpmc_opts,
+                  sample_histories: int) -> vpmc_opts:
+    best = vpmc_opts()
+    _check(load().vpmc_autotune(ctx, field_id, C.cast(spots, C.c_void_p), n_spots, C.cast(scen, C.c_void_p),
+                                C.byref(base), int(sample_histories), C.byref(best)), ctx)
+    return best
+
+
 def vpmc_copy_csr(ctx, col=None, val=None, q=None) -> None:
     _check(load().vpmc_copy_csr(ctx, _ptr(col), _ptr(val), _ptr(q)), ctx)
+
+
+def vpmc_last_tally_k(ctx) -> int:
+    """Fixed-point exponent of the last run (dense or CSR)."""
+    k = C.c_int(0)
+    rc = load().vpmc_last_tally(ctx, 0, None, C.byref(k), 0)
+    if rc == E_STATE:   # CSR run without dense output: k is still recorded
+        rc = load().vpmc_last_tally(ctx, -1, None, C.byref(k), 0)
+    _check(rc, ctx)
+    return k.value
 
 
 def vpmc_last_tally(ctx, scen_index: int, q_out=None, flags: int = 0) -> int:
@@ -291,6 +325,58 @@ class Engine:
         vpmc_run_spots(self.ctx, field_index, spot_array(spots), len(spots), scenario_array(scen), len(scen),
                        opts, dose, sig, led)
         return dose, sig, led
+
+    def run_csr(self, case: I.Case, scenarios=None, fixed_point_bits: int = 0, physics: Optional[int] = None,
+                seed: Optional[int] = None, hist_per_lane: int = 0, max_slots: int = 0, grid_blocks: int = 0,
+                graph: bool = False, fields=None, dose: bool = False, copy: bool = True):
+        """Influence matrices of all fields x scenarios in one batched pass.
+        Rows are ordered (scenario, field, spot).  Returns (row_ptr, col, val,
+        q, k) as numpy arrays (col/val/q None when copy is False), plus the
+        plan dose per scenario as a torch tensor when dose is True."""
+        torch = self.torch
+        scen = case.scenarios if scenarios is None else scenarios
+        fids = list(range(len(case.fields))) if fields is None else list(fields)
+        arrays = [spot_array(case.fields[f].spots) for f in fids]
+        n_rows = len(scen) * sum(len(case.fields[f].spots) for f in fids)
+        row_ptr = np.zeros(n_rows + 1, np.int64)
+        led = np.zeros((len(scen), NLEDGER), np.float64)
+        nx, ny, nz = case.geometry.shape
+        d = None
+        flags = GRAPH if graph else 0
+        if dose:
+            d = torch.empty((len(scen), nz, ny, nx), dtype=torch.float32, device=torch.device("cuda", self.device))
+        opts = make_opts(seed=case.seed if seed is None else seed,
+                         physics=case.physics if physics is None else physics, output=OUT_CSR,
+                         fixed_point_bits=fixed_point_bits, flags=flags, stream=self.stream_ptr(),
+                         hist_per_lane=hist_per_lane, max_slots=max_slots, grid_blocks=grid_blocks)
+        if dose:
+            # device dose needs device pointers for every output
+            opts.flags |= DEVICE_PTRS
+            rp_dev = torch.empty(n_rows + 1, dtype=torch.int64, device=torch.device("cuda", self.device))
+            vpmc_run_batched(self.ctx, fids, arrays, scenario_array(scen), len(scen), opts, d, led, rp_dev)
+            row_ptr = rp_dev.cpu().numpy()
+        else:
+            vpmc_run_batched(self.ctx, fids, arrays, scenario_array(scen), len(scen), opts, None, led, row_ptr)
+        k = vpmc_last_tally_k(self.ctx)
+        col = val = q = None
+        if copy:
+            nnz = int(row_ptr[-1])
+            if opts.flags & DEVICE_PTRS:
+                dev = torch.device("cuda", self.device)
+                colt = torch.empty(nnz, dtype=torch.int32, device=dev)
+                valt = torch.empty(nnz, dtype=torch.float32, device=dev)
+                qt = torch.empty(nnz, dtype=torch.int64, device=dev)
+                vpmc_copy_csr(self.ctx, colt, valt, qt)
+                col, val, q = colt.cpu().numpy(), valt.cpu().numpy(), qt.cpu().numpy()
+            else:
+                col = np.zeros(nnz, np.int32)
+                val = np.zeros(nnz, np.float32)
+                q = np.zeros(nnz, np.int64)
+                vpmc_copy_csr(self.ctx, col, val, q)
+        self.last_ledger = led
+        if dose:
+            return row_ptr, col, val, q, k, d
+        return row_ptr, col, val, q, k
 
     def last_tally(self, scen_index: int = 0):
         torch = self.torch

@@ -62,43 +62,57 @@ def source_xy_fp64(orc, case, spot_index, n):
     return xs, ys
 
 
-def ambiguous_columns(orc, case, tol=1e-4, edge_radius=None):
-    """(i, j) CT columns that an FP32/FP64 rounding difference could change
-    (beam along +z, axis-aligned)."""
+def ambiguous_mask(orc, case, tol=1e-4, edge_radius=None):
+    """Voxels an FP32/FP64 rounding difference of the source position could
+    change: the whole track line of every history that starts within tol of a
+    lateral voxel boundary (or within 2e-3 mm of the aperture edge), and the
+    neighbouring lines.  Beams must be axis-aligned."""
     g = case.geometry
     f = case.fields[0]
-    cols = set()
+    nx, ny, nz = g.shape
+    mask = np.zeros((nz, ny, nx), bool)
+    ez = np.asarray(f.beam.ez)
+    ax = int(np.argmax(np.abs(ez)))
+    lat = [k for k in range(3) if k != ax]
     for s in range(len(f.spots)):
         n = int(f.spots["n_histories"][s])
         x, y = source_xy_fp64(orc, case, s, n)
-        cx = f.beam.iso[0] + x - g.origin[0]
-        cy = f.beam.iso[1] + y - g.origin[1]
-        fx = cx / g.spacing[0]
-        fy = cy / g.spacing[1]
-        bad = (np.abs(fx - np.rint(fx)) * g.spacing[0] < tol) | (np.abs(fy - np.rint(fy)) * g.spacing[1] < tol)
+        p = np.asarray(f.beam.iso)[None, :] + x[:, None] * np.asarray(f.beam.ex)[None, :] \
+            + y[:, None] * np.asarray(f.beam.ey)[None, :]
+        fr = (p - np.asarray(g.origin)[None, :]) / np.asarray(g.spacing)[None, :]
+        bad = np.zeros(n, bool)
+        for k in lat:
+            bad |= np.abs(fr[:, k] - np.rint(fr[:, k])) * g.spacing[k] < tol
+        r = np.hypot(x, y)
         if edge_radius is not None:
-            r = np.hypot(x, y)
             bad |= np.abs(r - edge_radius) < 2e-3
-        for i, j in zip(np.floor(fx[bad]).astype(int), np.floor(fy[bad]).astype(int)):
-            for di in (-1, 0, 1):
-                for dj in (-1, 0, 1):
-                    cols.add((i + di, j + dj))
-    return cols
+        if f.rs is not None:
+            bad |= np.abs(r - 0.5 * f.rs.diameter_mm) < 2e-3
+        for h in np.nonzero(bad)[0]:
+            c = np.floor(fr[h]).astype(int)
+            for d0 in (-1, 0, 1):
+                for d1 in (-1, 0, 1):
+                    idx = [slice(None)] * 3
+                    i0, i1 = c[lat[0]] + d0, c[lat[1]] + d1
+                    if not (0 <= i0 < g.shape[lat[0]] and 0 <= i1 < g.shape[lat[1]]):
+                        continue
+                    idx[2 - lat[0]] = i0
+                    idx[2 - lat[1]] = i1
+                    mask[tuple(idx)] = True
+    return mask
 
 
-def assert_straight_parity(q_gpu, k_gpu, q_or, k_or, cols=()):
+def assert_straight_parity(q_gpu, k_gpu, q_or, k_or, excluded=None):
     a = q_gpu.astype(np.float64) * 2.0 ** -k_gpu
     b = q_or.astype(np.float64) * 2.0 ** -k_or
     dmax = b.max()
     assert dmax > 0
-    mask = np.ones(b.shape, bool)
-    for (i, j) in cols:
-        if 0 <= i < b.shape[2] and 0 <= j < b.shape[1]:
-            mask[:, j, i] = False
-    hi = (b > 1e-6 * dmax) & mask
+    keep = np.ones(b.shape, bool) if excluded is None else ~excluded
+    hi = (b > 1e-6 * dmax) & keep
     rel = np.abs(a[hi] - b[hi]) / b[hi]
-    lo = (~(b > 1e-6 * dmax)) & mask
-    say(f"  straight parity: {hi.sum()} voxels, max rel {rel.max():.3e}, excluded columns {len(cols)}")
+    lo = (~(b > 1e-6 * dmax)) & keep
+    say(f"  straight parity: {hi.sum()} voxels, max rel {rel.max():.3e}, "
+        f"excluded voxels {0 if excluded is None else int(excluded.sum())}")
     assert rel.max() <= 1e-5
     assert np.all(np.abs(a[lo] - b[lo]) <= 1e-11 * dmax)
 
@@ -110,8 +124,7 @@ def test_straight_parity_config1(eng, orc):
     qg, kg, dose, _, led = gpu_q(eng, c)
     qo, lo, ko = orc.run_tally(c)
     assert kg == ko
-    cols = ambiguous_columns(orc, c)
-    assert_straight_parity(qg, kg, qo, ko, cols)
+    assert_straight_parity(qg, kg, qo, ko, ambiguous_mask(orc, c))
     # dose conversion: FP32 dose equals the oracle conversion of the GPU tally
     ref = orc.q_to_gy(c, qg, kg)
     m = ref > 0
@@ -125,7 +138,7 @@ def test_straight_parity_range_scaled(eng, orc, scale):
     say(f"case config1 straight range_scale={scale}")
     qg, kg, _, _, _ = gpu_q(eng, c)
     qo, _, ko = orc.run_tally(c)
-    assert_straight_parity(qg, kg, qo, ko, ambiguous_columns(orc, c))
+    assert_straight_parity(qg, kg, qo, ko, ambiguous_mask(orc, c))
 
 
 @pytest.mark.parametrize("opening,rs", [(10.0, True), (20.0, False), (40.0, True)])
@@ -134,8 +147,7 @@ def test_straight_parity_water_aperture(eng, orc, opening, rs):
     say(f"case config2-small straight opening={opening} rs={rs} spots={len(c.fields[0].spots)}")
     qg, kg, _, _, lg = gpu_q(eng, c)
     qo, lo, ko = orc.run_tally(c)
-    cols = ambiguous_columns(orc, c, edge_radius=opening / 2)
-    assert_straight_parity(qg, kg, qo, ko, cols)
+    assert_straight_parity(qg, kg, qo, ko, ambiguous_mask(orc, c, edge_radius=opening / 2))
     e_or = lo * 2.0 ** -ko
     np.testing.assert_allclose(lg[1:3], e_or[1:3], rtol=1e-5, atol=1e-9 * e_or.sum())
 
@@ -148,14 +160,8 @@ def test_straight_parity_head_ct(eng, orc):
     say(f"case head straight spots={len(f.spots)}")
     qg, kg, _, _, _ = gpu_q(eng, c)
     qo, _, ko = orc.run_tally(c)
-    a = qg.astype(np.float64) * 2.0 ** -kg
-    b = qo.astype(np.float64) * 2.0 ** -ko
-    hi = b > 1e-6 * b.max()
-    rel = np.abs(a[hi] - b[hi]) / b[hi]
-    # beam along -x: rows along x hold whole histories; count outliers
-    bad = rel > 1e-5
-    say(f"  head straight: {hi.sum()} voxels, max rel {rel.max():.3e}, >1e-5: {bad.sum()}")
-    assert bad.sum() <= 0.002 * hi.sum()
+    r_edge = float(np.hypot(*f.polygon[0]))
+    assert_straight_parity(qg, kg, qo, ko, ambiguous_mask(orc, c, edge_radius=r_edge))
 
 
 # ------------------------------------------------------------- determinism
@@ -222,7 +228,12 @@ def test_lateral_shift_bitwise_gpu(eng):
 
 
 # ------------------------------------------------------------- full physics
-def stat_compare(orc, case, dg, sg, do, so, label):
+def stat_compare(orc, case, dg, sg, r, label):
+    """3-sigma voxel test and the mean dose over the high-dose region; the
+    mean-dose tolerance is 0.5 % or three standard errors of the difference
+    when the runs are noisier than that (error of the oracle's regional mean
+    from its batches, the same for the GPU run)."""
+    do, so = r["dose_gy"], r["sigma_gy"]
     dmax = do.max()
     m = do >= 0.1 * dmax
     comb = np.sqrt(sg ** 2 + so ** 2)
@@ -230,10 +241,14 @@ def stat_compare(orc, case, dg, sg, do, so, label):
     frac = within[m].mean()
     hi = do >= 0.5 * dmax
     ratio = dg[hi].mean() / do[hi].mean()
-    say(f"  {label}: 3-sigma fraction {frac:.4f} over {m.sum()} voxels; mean-dose ratio {ratio:.5f}; "
-        f"U_gpu {np.mean(sg[hi] / dg[hi]):.4f} U_or {np.mean(so[hi] / do[hi]):.4f}")
+    bm = np.array([b[hi].mean() for b in r["batch_dose_gy"]])
+    se_rel = bm.std(ddof=1) / np.sqrt(len(bm)) / do[hi].mean()
+    tol = max(0.005, 3.0 * np.sqrt(2.0) * se_rel)
+    say(f"  {label}: 3-sigma fraction {frac:.4f} over {m.sum()} voxels; mean-dose ratio {ratio:.5f} "
+        f"(tol {tol:.4f}, regional s.e. {se_rel:.4f}); U_gpu {np.mean(sg[hi] / dg[hi]):.4f} "
+        f"U_or {np.mean(so[hi] / do[hi]):.4f}")
     assert frac >= 0.99
-    assert abs(ratio - 1.0) <= 0.005
+    assert abs(ratio - 1.0) <= tol
     return frac, ratio
 
 
@@ -244,8 +259,8 @@ def test_full_physics_config1_statistical(eng, orc):
     say("case config1 full physics 2e6")
     _, _, dg, sg, _ = gpu_q(eng, c, n_batches=16)
     co = I.config1(n_histories=n, seed=12345)
-    r = orc.dose(co, n_batches=16)
-    stat_compare(orc, c, dg, sg, r["dose_gy"], r["sigma_gy"], "config1")
+    r = orc.dose(co, n_batches=16, keep_batches=True)
+    stat_compare(orc, c, dg, sg, r, "config1")
     rate = gamma_pass_rate(r["dose_gy"], dg, c.geometry.spacing, 0.01, 1.0)
     say(f"  gamma 1%/1mm pass rate {rate:.4f}")
     assert rate >= 0.99
@@ -256,12 +271,13 @@ def test_full_physics_config1_statistical(eng, orc):
 
 @pytest.mark.parametrize("opening,rs", [(10.0, True), (30.0, False)])
 def test_full_physics_water_aperture_statistical(eng, orc, opening, rs):
-    c = I.config2(opening, rs, histories_per_case=600_000, shape=(64, 64, 200), seed=0)
+    n = 3_000_000
+    c = I.config2(opening, rs, histories_per_case=n, shape=(64, 64, 200), seed=0)
     say(f"case config2-small full physics opening={opening} rs={rs}")
     _, _, dg, sg, lg = gpu_q(eng, c, n_batches=16)
-    co = I.config2(opening, rs, histories_per_case=600_000, shape=(64, 64, 200), seed=777)
-    r = orc.dose(co, n_batches=16)
-    stat_compare(orc, c, dg, sg, r["dose_gy"], r["sigma_gy"], f"config2 {opening} {rs}")
+    co = I.config2(opening, rs, histories_per_case=n, shape=(64, 64, 200), seed=777)
+    r = orc.dose(co, n_batches=16, keep_batches=True)
+    stat_compare(orc, c, dg, sg, r, f"config2 {opening} {rs}")
     # energy balance agrees statistically (block and range shifter ledgers)
     e_or = r["ledger_mev"]
     np.testing.assert_allclose(lg[1:3], e_or[1:3], rtol=0.01, atol=1e-3 * e_or.sum())
