@@ -56,8 +56,9 @@
 #define NUC_F_LOCAL 0.10         /* share of E deposited on a nuclear event (R2) */
 #define NUC_F_ESCAPE 0.30        /* share carried away by neutral secondaries (R2) */
 #define NUC_SIGMA_RAD 0.15       /* deflection of the leading secondary (R2) */
-#define EDGE_PUSH_MM 1e-6        /* push across an aperture edge (R5) */
+#define EDGE_PUSH_MM 1e-6        /* push across an aperture edge, in the aperture plane (R5) */
 #define MAX_ITER 1000000         /* safety bound on steps per VP */
+#define MAX_BLOCK_ITER 10000     /* safety bound on crossing-number tests per block traversal */
 
 enum { M_WATER = 0, M_AIR = 1, M_PMMA = 2, M_BRASS = 3, M_BONE = 4, NMAT = 5 };
 enum { L_GRID = 0, L_RS = 1, L_BLOCK = 2, L_ESCAPED = 3, L_NUC = 4, L_SPARE = 5, NLEDGER = 6 };
@@ -526,6 +527,18 @@ static double plane_distance(const vp_t *vp, double zu, double zd, int *down)
 
 enum { EX_DOWN = 0, EX_GONE = 1 };
 
+/* Move the VP's projected (BEV) position EDGE_PUSH_MM further along its
+ * projected direction, so that the next crossing-number test sees it on the
+ * far side of the edge it has just reached; its depth is unchanged (R5). */
+static void edge_push(vp_t *vp)
+{
+    double u = vp->d[0], v = vp->d[1], n = sqrt(u * u + v * v);
+    if (n > 0.0) {
+        vp->p[0] += EDGE_PUSH_MM * u / n;
+        vp->p[1] += EDGE_PUSH_MM * v / n;
+    }
+}
+
 /* homogeneous slab (range shifter): material m, density rho, z in [zu, zd] */
 static int slab_transport(vp_t *vp, sink_t *sk, int m, double rho, double zu, double zd, int ledger)
 {
@@ -555,7 +568,7 @@ static int slab_transport(vp_t *vp, sink_t *sk, int m, double rho, double zu, do
  * numbers) or brass (a condensed-history step with the brass tables) */
 static int block_transport(vp_t *vp, sink_t *sk, const orc_field *f, double zu, double zd)
 {
-    for (int it = 0; it < MAX_ITER; it++) {
+    for (int it = 0; it < MAX_BLOCK_ITER; it++) {
         int down;
         double tp = plane_distance(vp, zu, zd, &down);
         if (tp < 0.0) tp = 0.0;
@@ -570,7 +583,8 @@ static int block_transport(vp_t *vp, sink_t *sk, const orc_field *f, double zu, 
                 sink_ledger(sk, L_ESCAPED, vp->E);
                 return EX_GONE;
             }
-            for (int k = 0; k < 3; k++) vp->p[k] += (te + EDGE_PUSH_MM) * vp->d[k];
+            for (int k = 0; k < 3; k++) vp->p[k] += te * vp->d[k];
+            edge_push(vp);
             continue;
         }
         double dg = te < tp ? te : tp;
@@ -585,9 +599,7 @@ static int block_transport(vp_t *vp, sink_t *sk, const orc_field *f, double zu, 
             sink_ledger(sk, L_ESCAPED, vp->E);
             return EX_GONE;
         }
-        if (st == ST_GEO) {
-            for (int k = 0; k < 3; k++) vp->p[k] += EDGE_PUSH_MM * vp->d[k];
-        }
+        if (st == ST_GEO) edge_push(vp);
         if (vp->p[2] >= zd) { vp->p[2] = zd; return EX_DOWN; }
         if (vp->p[2] <= zu) { vp->p[2] = zu; sink_ledger(sk, L_ESCAPED, vp->E); return EX_GONE; }
     }
