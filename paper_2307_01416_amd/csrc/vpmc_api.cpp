@@ -80,6 +80,7 @@ struct vpmc_ctx {
     // autotuned launch shapes (0 = not tuned)
     int tuned_csr_hpl = 0, tuned_csr_blocks = 0, tuned_dense_blocks = 0;
     int tuned_csr_threads = 0, tuned_dense_threads = 0;
+    hipStream_t cap_stream = nullptr;   // private stream for graph capture
 };
 
 namespace {
@@ -430,6 +431,12 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
         // capacity raise the overflow flag, and the eager path below reruns
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
+        // capture on a private stream (the legacy default stream cannot be
+        // captured); the graph is then launched on the caller's stream
+        if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipStream_t user_st = st;
+        st = c->cap_stream;
+        HIP_TRY(hipStreamSynchronize(user_st));
         HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         int crc = clear_counters();
         for (int e = 0; e < E && crc == VPMC_OK; ++e) {
@@ -446,6 +453,7 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
             if (he != hipSuccess) crc = fail(VPMC_E_DEVICE, "graph capture launch: %s", hipGetErrorString(he));
         }
         const hipError_t ce = hipStreamEndCapture(st, &graph);
+        st = user_st;
         if (crc) { if (graph) (void)hipGraphDestroy(graph); return crc; }
         HIP_TRY(ce);
         hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -616,6 +624,7 @@ void vpmc_destroy(vpmc_ctx *c) {
                           &c->csr_q})
             release(*b);
         for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+        if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     }
     delete c;
 }
@@ -703,6 +712,7 @@ int vpmc_set_aperture(vpmc_ctx *c, int field_id, const vpmc_beam *beam, const fl
         d.blk_zu = -(block->downstream_mm + block->thickness_mm);
         d.blk_zd = -block->downstream_mm;
         d.blk_rho = block->density_gcc;
+        d.blk_t = block->thickness_mm;
         poly.resize(n_vertices);
         for (int i = 0; i < n_vertices; ++i) poly[i] = make_float2(xy_mm[2 * i], xy_mm[2 * i + 1]);
     }
@@ -712,6 +722,7 @@ int vpmc_set_aperture(vpmc_ctx *c, int field_id, const vpmc_beam *beam, const fl
         d.rs_zu = (float)(-(rs->downstream_mm + rs_t));
         d.rs_r2 = 0.25f * rs->diameter_mm * rs->diameter_mm;
         d.rs_rho = (float)kMaterials[MAT_PMMA].density;
+        d.rs_t = (float)rs_t;
     }
     if (c->device >= 0 && !poly.empty()) {
         HIP_TRY(hipSetDevice(c->device));

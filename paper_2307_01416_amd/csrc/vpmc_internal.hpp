@@ -40,8 +40,9 @@ constexpr float STEP_FRACTION = 0.25f;     // step <= 1/4 residual range
 constexpr float NUC_F_LOCAL = 0.10f;       // nuclear event: share deposited locally
 constexpr float NUC_F_ESCAPE = 0.30f;      // share carried off by neutral secondaries
 constexpr float NUC_SIGMA_RAD = 0.15f;     // deflection of the leading secondary
-constexpr float EDGE_PUSH_MM = 1e-4f;      // push across an aperture edge (FP32)
+constexpr float EDGE_PUSH_MM = 1e-4f;      // push across an aperture edge in the BEV plane (FP32)
 constexpr int MAX_STEPS = 1000000;         // safety bound on steps per VP
+constexpr int MAX_BLOCK_ITER = 10000;      // bound on crossing-number tests per block traversal
 constexpr double MEV_TO_J = 1.602176634e-13;
 
 enum { L_GRID = 0, L_RS = 1, L_BLOCK = 2, L_ESCAPED = 3, L_NUC = 4, NLEDGER = 6 };
@@ -58,9 +59,9 @@ struct FieldDev {
     float iso[3], ex[3], ey[3], ez[3];
     int has_block, nv;
     const float2 *poly;
-    float blk_zu, blk_zd, blk_rho;
+    float blk_zu, blk_zd, blk_rho, blk_t;
     int has_rs;
-    float rs_zu, rs_zd, rs_r2, rs_rho;
+    float rs_zu, rs_zd, rs_r2, rs_rho, rs_t;   // slab thicknesses rounded once from FP64
 };
 
 struct SpotDev {

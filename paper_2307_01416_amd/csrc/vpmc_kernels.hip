@@ -42,6 +42,7 @@ __device__ __forceinline__ float unit_open(uint32_t w) {
 
 struct Lane {
     float px, py, pz, dx, dy, dz;
+    float pzlo;               // low part of the slab depth (see plane_distance)
     float E, Elo;             // energy as an unevaluated pair E + Elo
     uint32_t nblk, spot, hist, k0, k1;
     unsigned physics;
@@ -140,6 +141,17 @@ __device__ __forceinline__ void sub_energy(Lane &v, float dE) {
     v.E = t;
 }
 
+// (pz, pzlo) += dz with an error-free two-sum
+__device__ __forceinline__ void add_depth(Lane &v, float dz) {
+    const float s = v.pz + dz;
+    const float bb = s - v.pz;
+    const float err = (v.pz - (s - bb)) + (dz - bb);
+    const float lo = v.pzlo + err;
+    const float t = s + lo;
+    v.pzlo = lo - (t - s);
+    v.pz = t;
+}
+
 enum { ST_STOP = 0, ST_GEO = 1, ST_INNER = 2 };
 
 // One condensed-history step in a homogeneous region: CSDA loss from the
@@ -147,6 +159,7 @@ enum { ST_STOP = 0, ST_GEO = 1, ST_INNER = 2 };
 // step midpoint (hinge), nuclear removal turning the VP into its leading
 // secondary.  rho_loss scales energy loss and straggling (range scenarios),
 // rho scattering and nuclear removal.  dg: distance to the region boundary.
+template <bool CompDepth>
 __device__ int phys_step(Lane &v, const float *tab, int m, float rho_loss, float rho, float dg,
                          float &dep, float &esc) {
     dep = 0.0f;
@@ -194,15 +207,15 @@ __device__ int phys_step(Lane &v, const float *tab, int m, float rho_loss, float
         const float h = 0.5f * s;
         v.px = fmaf(h, v.dx, v.px);
         v.py = fmaf(h, v.dy, v.py);
-        v.pz = fmaf(h, v.dz, v.pz);
+        if (CompDepth) add_depth(v, h * v.dz); else v.pz = fmaf(h, v.dz, v.pz);
         rotate_dir(v, th0 * z1, th0 * z2);
         v.px = fmaf(h, v.dx, v.px);
         v.py = fmaf(h, v.dy, v.py);
-        v.pz = fmaf(h, v.dz, v.pz);
+        if (CompDepth) add_depth(v, h * v.dz); else v.pz = fmaf(h, v.dz, v.pz);
     } else {
         v.px = fmaf(s, v.dx, v.px);
         v.py = fmaf(s, v.dy, v.py);
-        v.pz = fmaf(s, v.dz, v.pz);
+        if (CompDepth) add_depth(v, s * v.dz); else v.pz = fmaf(s, v.dz, v.pz);
     }
     if (v.physics & PH_NUCLEAR) {
         const float P = -expm1f(-rho * s * 0.1f * node_lerp(tm + T_SN * NE, pb));
@@ -298,28 +311,48 @@ __device__ __forceinline__ float edge_distance(const float2 *poly, int nv, float
     return best;
 }
 
-__device__ __forceinline__ float plane_distance(const Lane &v, float zu, float zd, bool &down) {
-    if (v.dz > 0.0f) { down = true; return (zd - v.pz) / v.dz; }
-    if (v.dz < 0.0f) { down = false; return (zu - v.pz) / v.dz; }
+// Inside a slab (range shifter or block) the depth is kept relative to the
+// slab's upstream face as a compensated pair (pz + pzlo), so the distance to
+// the exit plane stays exact to FP32 rounding of the step lengths rather than
+// of the absolute beam-frame depth.
+__device__ __forceinline__ float plane_distance(const Lane &v, float thick, bool &down) {
+    if (v.dz > 0.0f) { down = true; return ((thick - v.pz) - v.pzlo) / v.dz; }
+    if (v.dz < 0.0f) { down = false; return (-v.pz - v.pzlo) / v.dz; }
     down = true;
     return INFINITY;
 }
 
+// push the projected (beam's-eye-view) position EDGE_PUSH_MM further along
+// the projected direction, depth unchanged, across the edge just reached
+__device__ __forceinline__ void edge_push(Lane &v) {
+    const float n2 = v.dx * v.dx + v.dy * v.dy;
+    if (n2 > 0.0f) {
+        const float k = EDGE_PUSH_MM * rsqrtf(n2);
+        v.px = fmaf(k, v.dx, v.px);
+        v.py = fmaf(k, v.dy, v.py);
+    }
+}
+
 enum { EX_DOWN = 0, EX_GONE = 1 };
 
+// homogeneous slab (range shifter): local depth 0 .. thick; on return the
+// depth is the global plane z the VP left through
 __device__ int slab_transport(Lane &v, Acc &acc, float scale, const float *tab, int m, float rho,
-                              float zu, float zd, int ledger) {
+                              float zu, float zd, float thick, int ledger) {
+    v.pz = 0.0f;
+    v.pzlo = 0.0f;
     for (int it = 0; it < MAX_STEPS; ++it) {
         bool down;
-        float tp = fmaxf(plane_distance(v, zu, zd, down), 0.0f);
+        float tp = fmaxf(plane_distance(v, thick, down), 0.0f);
         float dep, esc;
-        const int st = phys_step(v, tab, m, rho, rho, tp, dep, esc);
+        const int st = phys_step<true>(v, tab, m, rho, rho, tp, dep, esc);
         ledger_add(acc, ledger, dep, scale);
         ledger_add(acc, L_NUC, esc, scale);
         if (st == ST_STOP) return EX_GONE;
-        if (st == ST_GEO || v.pz >= zd || v.pz <= zu) {
-            const bool out_down = (st == ST_GEO) ? down : (v.pz >= zd);
+        if (st == ST_GEO || v.pz >= thick || v.pz <= 0.0f) {
+            const bool out_down = (st == ST_GEO) ? down : (v.pz >= thick);
             v.pz = out_down ? zd : zu;
+            v.pzlo = 0.0f;
             if (out_down) return EX_DOWN;
             ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
             return EX_GONE;
@@ -333,10 +366,12 @@ __device__ int slab_transport(Lane &v, Acc &acc, float scale, const float *tab, 
 // number at the VP's projected position decides, at every step, opening
 // (straight transport, no random numbers) or brass (brass tables).
 __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab, const float2 *poly,
-                               int nv, float rho_b, float zu, float zd) {
-    for (int it = 0; it < MAX_STEPS; ++it) {
+                               int nv, float rho_b, float zu, float zd, float thick) {
+    v.pz = 0.0f;
+    v.pzlo = 0.0f;
+    for (int it = 0; it < MAX_BLOCK_ITER; ++it) {
         bool down;
-        const float tp = fmaxf(plane_distance(v, zu, zd, down), 0.0f);
+        const float tp = fmaxf(plane_distance(v, thick, down), 0.0f);
         const bool open = nv >= 3 && in_polygon(poly, nv, v.px, v.py);
         const float te = nv >= 3 ? edge_distance(poly, nv, v.px, v.py, v.dx, v.dy) : INFINITY;
         if (open) {
@@ -344,36 +379,35 @@ __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab,
                 v.px = fmaf(tp, v.dx, v.px);
                 v.py = fmaf(tp, v.dy, v.py);
                 v.pz = down ? zd : zu;
+                v.pzlo = 0.0f;
                 if (down) return EX_DOWN;
                 ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
                 return EX_GONE;
             }
-            const float t = te + EDGE_PUSH_MM;
-            v.px = fmaf(t, v.dx, v.px);
-            v.py = fmaf(t, v.dy, v.py);
-            v.pz = fmaf(t, v.dz, v.pz);
+            v.px = fmaf(te, v.dx, v.px);
+            v.py = fmaf(te, v.dy, v.py);
+            add_depth(v, te * v.dz);
+            edge_push(v);
             continue;
         }
         const float dg = fminf(te, tp);
         float dep, esc;
-        const int st = phys_step(v, tab, MAT_BRASS, rho_b, rho_b, dg, dep, esc);
+        const int st = phys_step<true>(v, tab, MAT_BRASS, rho_b, rho_b, dg, dep, esc);
         ledger_add(acc, L_BLOCK, dep, scale);
         ledger_add(acc, L_NUC, esc, scale);
         if (st == ST_STOP) return EX_GONE;
         if (st == ST_GEO && tp <= te) {
             v.pz = down ? zd : zu;
+            v.pzlo = 0.0f;
             if (down) return EX_DOWN;
             ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
             return EX_GONE;
         }
-        if (st == ST_GEO) {
-            v.px = fmaf(EDGE_PUSH_MM, v.dx, v.px);
-            v.py = fmaf(EDGE_PUSH_MM, v.dy, v.py);
-            v.pz = fmaf(EDGE_PUSH_MM, v.dz, v.pz);
-        }
-        if (v.pz >= zd) { v.pz = zd; return EX_DOWN; }
-        if (v.pz <= zu) {
+        if (st == ST_GEO) edge_push(v);
+        if (v.pz >= thick) { v.pz = zd; v.pzlo = 0.0f; return EX_DOWN; }
+        if (v.pz <= 0.0f) {
             v.pz = zu;
+            v.pzlo = 0.0f;
             ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
             return EX_GONE;
         }
@@ -394,7 +428,7 @@ __device__ bool beamline(Lane &v, Acc &acc, float scale, const float *tab, const
             v.px = qx;
             v.py = qy;
             v.pz = f.rs_zu;
-            if (slab_transport(v, acc, scale, tab, MAT_PMMA, f.rs_rho, f.rs_zu, f.rs_zd, L_RS) != EX_DOWN)
+            if (slab_transport(v, acc, scale, tab, MAT_PMMA, f.rs_rho, f.rs_zu, f.rs_zd, f.rs_t, L_RS) != EX_DOWN)
                 return false;
             tmin = 0.0f;
         }
@@ -409,7 +443,7 @@ __device__ bool beamline(Lane &v, Acc &acc, float scale, const float *tab, const
         const int nv = f.nv;
         if (nv >= 3 && in_polygon(poly, nv, qx, qy)) {
             const float te = edge_distance(poly, nv, qx, qy, v.dx, v.dy);
-            const float tx = (f.blk_zd - f.blk_zu) / v.dz;
+            const float tx = f.blk_t / v.dz;
             if (te >= tx) {
                 tmin = (f.blk_zd - v.pz) / v.dz;
                 return true;
@@ -418,7 +452,7 @@ __device__ bool beamline(Lane &v, Acc &acc, float scale, const float *tab, const
         v.px = qx;
         v.py = qy;
         v.pz = f.blk_zu;
-        if (block_transport(v, acc, scale, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd) != EX_DOWN)
+        if (block_transport(v, acc, scale, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, f.blk_t) != EX_DOWN)
             return false;
         tmin = 0.0f;
     }
@@ -520,7 +554,7 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
             if (t < dg) { dg = t; ax = k; sgn = up ? 1 : -1; }
         }
         float dep, esc;
-        const int st = phys_step(v, tab, m, rho_loss, rho, dg, dep, esc);
+        const int st = phys_step<false>(v, tab, m, rho_loss, rho, dg, dep, esc);
         const long long qd = to_fixed(dep, scale);
         if (qd != 0) sink.add(vox, qd);
         acc.led[L_GRID] += qd;
@@ -558,6 +592,7 @@ __device__ void source(Lane &v, const SpotDev &sp) {
     v.px = fmaf(sp.sigma, r * c, sp.x);
     v.py = fmaf(sp.sigma, r * sn, sp.y);
     v.pz = 0.0f;
+    v.pzlo = 0.0f;
     v.dx = 0.0f; v.dy = 0.0f; v.dz = 1.0f;
     v.E = sp.e0;
     v.Elo = 0.0f;

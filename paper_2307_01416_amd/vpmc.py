@@ -334,6 +334,7 @@ class Engine:
         q, k) as numpy arrays (col/val/q None when copy is False), plus the
         plan dose per scenario as a torch tensor when dose is True."""
         torch = self.torch
+        self.load_case(case)
         scen = case.scenarios if scenarios is None else scenarios
         fids = list(range(len(case.fields))) if fields is None else list(fields)
         arrays = [spot_array(case.fields[f].spots) for f in fids]
