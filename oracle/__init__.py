@@ -101,6 +101,8 @@ def lib():
             ("orc_slab_exit", None, [i, d, d, d, i, C.c_uint64, i64, vp, i]),
             ("orc_fixed_point_k", i, [d]), ("orc_rs_thickness", d, [d]),
             ("orc_mev_to_joule", d, []),
+            ("orc_polygon_distance", d, [vp, i, d, d]),
+            ("orc_block_traverse", None, [vp, vp, i64, C.c_uint64, i, i, vp, i]),
             ("mlp_num_params", i, []), ("mlp_forward", None, [vp, vp, i, vp]),
             ("mlp_loss_grad", d, [vp, vp, vp, vp, i, vp]),
             ("mlp_adam_step", None, [vp, vp, vp, vp, i, i, d, d, d, d]),
@@ -400,3 +402,19 @@ def mlp_loss_grad(params, x, y, trans):
     g = np.zeros(p.size, np.float64)
     loss = lib().mlp_loss_grad(_ptr(p), _ptr(x), _ptr(y), _ptr(t), x.shape[0], _ptr(g))
     return loss, g
+
+
+def block_traverse(case, entries: np.ndarray, seed: int = 0, field_index: int = 0, physics: Optional[int] = None,
+                   threads: int = 0) -> np.ndarray:
+    """Plain traversals of the field's block: out[n][8] (see the C function)."""
+    P = _Prepared(case, field_index, 0)
+    e = np.ascontiguousarray(entries, np.float64)
+    out = np.zeros((e.shape[0], 8), np.float64)
+    lib().orc_block_traverse(C.byref(P.field), _ptr(e), e.shape[0], seed, field_index,
+                             case.physics if physics is None else physics, _ptr(out), threads)
+    return out
+
+
+def polygon_distance(poly, x, y) -> float:
+    p = np.ascontiguousarray(poly, np.float64)
+    return lib().orc_polygon_distance(_ptr(p), p.shape[0], float(x), float(y))

@@ -852,6 +852,63 @@ void orc_slab_exit(int m, double rho, double L, double e0, int physics, uint64_t
     }
 }
 
+/* distance from (x, y) to the polygon's boundary (point-to-segment minimum) */
+double orc_polygon_distance(const double *poly, int nv, double x, double y)
+{
+    double best = INFINITY;
+    for (int i = 0, j = nv - 1; i < nv; j = i++) {
+        double ax = poly[2 * j], ay = poly[2 * j + 1];
+        double ex = poly[2 * i] - ax, ey = poly[2 * i + 1] - ay;
+        double wx = x - ax, wy = y - ay, l2 = ex * ex + ey * ey;
+        double t = l2 > 0.0 ? (wx * ex + wy * ey) / l2 : 0.0;
+        t = t < 0.0 ? 0.0 : t > 1.0 ? 1.0 : t;
+        double dx = wx - t * ex, dy = wy - t * ey, d2 = dx * dx + dy * dy;
+        if (d2 < best) best = d2;
+    }
+    return sqrt(best);
+}
+
+/* One plain traversal of the field's block per entry state (the surrogate's
+ * training data): entries[n][5] = (x, y) on the block's upstream face, (u, v)
+ * direction cosines, E.  Streams: key (seed, field id), counter (block, i,
+ * 0, 0).  out[n][8] = {outcome: 1 transmitted, 0 stopped or lost, -1 entered
+ * through the opening; E_out; u', v', w'; x', y' on the downstream face;
+ * distance of the entry point to the opening's edge}. */
+void orc_block_traverse(const orc_field *f, const double *entries, int64_t n, uint64_t seed, int field_id,
+                        int physics, double *out, int nthreads)
+{
+    orc_init();
+    double zu = -(f->blk_d + f->blk_t), zd = -f->blk_d;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 256)
+#endif
+    for (int64_t i = 0; i < n; i++) {
+        const double *e = entries + 5 * i;
+        double *o = out + 8 * i;
+        vp_t vp;
+        sink_t sk;
+        memset(&vp, 0, sizeof vp);
+        memset(&sk, 0, sizeof sk);
+        vp.key[0] = (uint32_t)(seed & 0xffffffffu);
+        vp.key[1] = (uint32_t)(seed >> 32) ^ (uint32_t)field_id;
+        vp.hist = (uint32_t)i;
+        vp.physics = physics;
+        vp.p[0] = e[0]; vp.p[1] = e[1]; vp.p[2] = zu;
+        vp.d[0] = e[2]; vp.d[1] = e[3];
+        vp.d[2] = sqrt(fmax(1.0 - e[2] * e[2] - e[3] * e[3], 0.0));
+        vp.E = e[4];
+        o[7] = f->nv >= 3 ? orc_polygon_distance(f->poly, f->nv, e[0], e[1]) : 1000.0;
+        if (f->nv >= 3 && orc_in_polygon(f->poly, f->nv, e[0], e[1])) {
+            o[0] = -1.0;
+            continue;
+        }
+        int ex = block_transport(&vp, &sk, f, zu, zd);
+        o[0] = ex == EX_DOWN ? 1.0 : 0.0;
+        o[1] = vp.E; o[2] = vp.d[0]; o[3] = vp.d[1]; o[4] = vp.d[2]; o[5] = vp.p[0]; o[6] = vp.p[1];
+    }
+}
+
 /* Largest fixed-point exponent k <= 40 with T * 2^k <= 2^62, where T bounds
  * the weighted energy any voxel or ledger can receive. */
 int orc_fixed_point_k(double T)
