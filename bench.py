@@ -1,10 +1,15 @@
-"""Throughput benchmark of the VP transport on one MI355X.
+"""Benchmark of the VP transport on one MI355X: the 13-scenario influence
+matrix of the synthetic head case.
 
-Workload (one step): the eight water-phantom cases with a 30 mm brass block
-(openings 10/20/30/40 mm, each without and with a 45 mm WET PMMA range
-shifter), water 200x200x300 at 1 mm, spots on a 2.5 mm grid over the
-opening + 5 mm, 1e7 virtual particles per case, full physics, 16 batches for
-the per-voxel standard error.  Inputs are synthetic and resident on the GPU
+Workload (one step): synthetic head CT 256x256x160 at 1x1x2 mm, 8 cc
+spherical target, 3 coplanar fields each with a 30 mm brass aperture
+(target projection + 5 mm) and a 45 mm WET PMMA range shifter, ~950 spots per
+field on a 2.5 mm grid, 13 robust scenarios (nominal + +-3 mm shifts along
+x/y/z at +-3.5 % range), uneven history counts per spot.  One batched
+work-queue pass builds all 13 x 3 x spots sparse rows in HBM, converted to
+device-resident CSR (int32 voxel, FP32 Gy per unit spot weight).  History counts are scaled before timing until the nominal
+uniform-weight plan dose has a mean relative standard error <= 0.5 % over
+voxels >= 50 % of its maximum.  Inputs are synthetic and resident on the GPU
 before the timed region.  Prints one JSON line.
 """
 from __future__ import annotations
@@ -12,7 +17,6 @@ from __future__ import annotations
 import argparse
 import json
 import os
-import platform
 import sys
 import time
 
@@ -21,11 +25,16 @@ sys.path.insert(0, ROOT)
 
 # VALU lane-operations per condensed-history step counted from the algorithm
 # (Philox4x32-10 ~100 integer ops, uniform/normal conversion ~40, three table
-# interpolations ~35, CSDA loss ~10, hinge rotation ~35, DDA ~15, nuclear
-# test ~5, fixed-point tally ~5, position updates ~10)
+# interpolations ~35, CSDA loss ~10, hinge rotation ~35, voxel traversal ~15,
+# nuclear test ~5, fixed-point tally ~5, position updates ~10)
 ALG_OPS_PER_STEP = 255.0
 # gfx950: 256 CUs x 64 FP32 lanes per clock x 2.4 GHz, single-issue VALU
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
+TARGET_U = 0.005
+
+
+def progress(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def parse():
@@ -33,25 +42,73 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--histories-per-case", type=float, default=1e7)
-    ap.add_argument("--batches", type=int, default=16)
+    ap.add_argument("--target-cc", type=float, default=8.0)
+    ap.add_argument("--histories-per-spot", type=float, default=1e4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=float, default=1.25e5, help="oracle histories per case")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--graph", action="store_true", help="capture the pass in one hipGraph")
+    ap.add_argument("--no-scale", action="store_true",
+                    help="keep --histories-per-spot as given (skip the scaling to 0.5 %% uncertainty)")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--shape", default="", help="HPL,BLOCKS,THREADS: fixed work-queue launch shape (no autotune)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="before the workload, run three plain 256 MiB device copies (HBM counter calibration)")
     return ap.parse_args()
 
 
-def cpu_baseline(n_per_case: int):
-    import numpy as np
+def copy_calibration():
+    """Three device-to-device copies of 256 MiB: a kernel of known traffic
+    (256 MiB read + 256 MiB written) for scaling the HBM byte counters."""
+    import torch
+    n = 1 << 26
+    a = torch.arange(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    progress(f"copy calibration: 3 x {4 * n >> 20} MiB copies done")
+    del a, b
+
+
+def plan_uncertainty(eng, case, I, V, np):
+    """U of the nominal uniform-weight plan dose (all fields, 16 batches)."""
+    import torch
+    nom = I.Case("nominal", case.geometry, case.fields, [I.Scenario()], seed=case.seed, physics=case.physics,
+                 n_batches=16)
+    eng.load_case(nom)
+    total = None
+    var = None
+    for fi in range(len(nom.fields)):
+        d, s, _ = eng.run_dose(nom, fi, n_batches=16, sigma=True)
+        d = d[0].double()
+        s = s[0].double()
+        total = d if total is None else total + d
+        var = s * s if var is None else var + s * s
+    sig = torch.sqrt(var)
+    m = total >= 0.5 * total.max()
+    return float((sig[m] / total[m]).mean())
+
+
+def cpu_baseline(case, seconds, np):
+    """The oracle on a bounded sample of the same workload: nominal scenario,
+    first field, every 10th spot, the same VP count per spot, grown until
+    one run takes at least 0.6 x `seconds`.  Returns histories/s."""
     import oracle
     from paper_2307_01416_amd import inputs as I
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
-    cases = I.config2_all(histories_per_case=n_per_case)
-    t0 = time.perf_counter()
-    n = 0
-    for c in cases:
-        oracle.run_tally(c, threads=threads)
-        n += int(np.sum(c.fields[0].spots["n_histories"]))
-    dt = time.perf_counter() - t0
+    f = case.fields[0]
+    sub = I.Field(beam=f.beam, spots=f.spots[::10].copy(), polygon=f.polygon, block=f.block, rs=f.rs)
+    probe = I.Case("probe", case.geometry, [sub], [I.Scenario()], seed=case.seed, physics=case.physics)
+    per_spot = 200
+    while True:
+        sub.spots["n_histories"] = per_spot
+        t0 = time.perf_counter()
+        oracle.run_tally(probe, threads=threads)
+        dt = time.perf_counter() - t0
+        n = int(np.sum(sub.spots["n_histories"]))
+        if dt >= 0.6 * seconds or per_spot >= 10_000_000:
+            break
+        per_spot = int(per_spot * min(50.0, max(2.0, 1.1 * seconds / max(dt, 1e-3))))
     cpu = "unknown"
     try:
         for line in open("/proc/cpuinfo"):
@@ -61,7 +118,8 @@ def cpu_baseline(n_per_case: int):
     except OSError:
         pass
     return {"value": n / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
-            "sample": f"8 water/brass cases x {n_per_case} VPs (full physics, single batch), {dt:.1f} s on {cpu}"}
+            "sample": f"nominal scenario, field 1, {len(sub.spots)} of {len(f.spots)} spots x {per_spot} VPs "
+                      f"({n} VPs, full physics, {dt:.1f} s on {cpu})"}
 
 
 def main():
@@ -75,31 +133,65 @@ def main():
     from paper_2307_01416_amd import inputs as I
     from paper_2307_01416_amd import vpmc as V
 
-    H = int(a.histories_per_case)
-    cases = I.config2_all(histories_per_case=H)
+    if a.copy_calibration:
+        copy_calibration()
+    progress("building the synthetic head case ...")
+    H = a.histories_per_spot
+    case = I.config4(a.target_cc, int(H))
+    base_nh = case.fields[0].spots["n_histories"].copy()
     eng = V.Engine(0)
-    eng.load_case(cases[0])
-    n_hist_step = sum(int(np.sum(c.fields[0].spots["n_histories"])) for c in cases)
+    eng.load_case(case)
 
-    def step(stats):
-        for c in cases:
-            for fi, f in enumerate(c.fields):
-                V.vpmc_set_aperture(eng.ctx, fi, f)
-            eng.run_dose(c, 0, n_batches=a.batches, sigma=True)
-            stats.append(V.vpmc_last_stats(eng.ctx))
+    # scale the history counts until the nominal plan dose reaches U <= 0.5 %
+    u = None if a.no_scale else plan_uncertainty(eng, case, I, V, np)
+    if u is not None:
+        progress(f"U at {H:.0f} VPs/spot (mean): {u:.4f}")
+    if u is not None and u > TARGET_U:
+        f = (u / TARGET_U) ** 2 * 1.05
+        for fl in case.fields:
+            fl.spots["n_histories"] = np.ceil(fl.spots["n_histories"] * f).astype(np.uint32)
+        H *= f
+        u = plan_uncertainty(eng, case, I, V, np)
+        progress(f"U at {H:.0f} VPs/spot (mean): {u:.4f}")
+    eng.load_case(case)
+    shape = dict(hist_per_lane=0, grid_blocks=0, block_threads=0)
+    if a.shape:
+        h, b, t = (int(v) for v in a.shape.split(","))
+        shape = dict(hist_per_lane=h, grid_blocks=b, block_threads=t)
+    elif not a.no_autotune:
+        # launch shape of the work queue (hist_per_lane, workgroups, threads)
+        # from a sample of field 1's spots; kept on the context
+        f0 = case.fields[0]
+        best = V.vpmc_autotune(eng.ctx, 0, V.spot_array(f0.spots), len(f0.spots), V.scenario_array([I.Scenario()]),
+                               V.make_opts(seed=case.seed, physics=case.physics, output=V.OUT_CSR),
+                               sample_histories=int(2e7))
+        progress(f"autotune: hist_per_lane={best.hist_per_lane} grid_blocks={best.grid_blocks} "
+                 f"threads={best.block_threads}")
+    shape_used = dict(shape)
+    if not a.shape and not a.no_autotune:
+        shape_used = dict(hist_per_lane=best.hist_per_lane, grid_blocks=best.grid_blocks,
+                          block_threads=best.block_threads)
+    n_rows = len(case.scenarios) * sum(len(fl.spots) for fl in case.fields)
+    n_hist_step = len(case.scenarios) * sum(int(np.sum(fl.spots["n_histories"])) for fl in case.fields)
 
-    def progress(msg):
-        print(msg, file=sys.stderr, flush=True)
+    def step():
+        # the influence matrices end as device-resident CSR (int32 voxel,
+        # FP32 Gy per unit weight); they are dropped after the step
+        rp, col, val, _, _ = eng.run_csr(case, graph=a.graph, device_out=True, **shape)
+        st = V.vpmc_last_stats(eng.ctx)
+        nnz = int(col.numel())
+        del col, val
+        return nnz, st
 
     for w in range(a.warmup):
-        st = []
-        step(st)
-        progress(f"warmup {w}: {sum(s['transport_ms'] for s in st):.1f} ms transport")
+        nnz, st = step()
+        progress(f"warmup {w}: {st['total_ms']:.0f} ms, nnz {nnz}")
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()
     for k in range(a.steps):
-        step(stats)
+        nnz, st = step()
+        stats.append(st)
         progress(f"step {k}: {time.perf_counter() - t0:.2f} s elapsed")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -123,20 +215,25 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32+int64",
         "data": "synthetic",
-        "config": {"workload": "water 200x200x300 @1 mm behind 30 mm brass block, openings 10/20/30/40 mm "
-                               "x {no RS, 45 mm WET PMMA RS}; 2.5 mm spot grid; 1e7 VPs per case; "
-                               "full physics; 16 batches",
-                   "histories_per_step": n_hist_step, "cases": len(cases)},
+        "s_per_13_scenario_im": dt / a.steps,
+        "config": {"workload": f"synthetic head CT 256x256x160 @1x1x2 mm, {a.target_cc} cc target, 3 coplanar "
+                               f"fields with brass aperture (+5 mm) and 45 mm WET PMMA range shifter, "
+                               f"13 robust scenarios, per-spot CSR influence matrices",
+                   "rows": n_rows, "histories_per_step": n_hist_step,
+                   "mean_histories_per_spot": float(H), "plan_dose_uncertainty": u, "nnz": nnz,
+                   "csr_gb": nnz * 8 / 1e9, "graph": bool(a.graph), "launch_shape": shape_used},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
-                     "kernel": "transport_kernel", "avg_launch_ms": 1e3 * transport_s / launches,
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "kernel": "queue_kernel", "avg_launch_ms": 1e3 * transport_s / max(1, launches),
                      "steps_per_s": steps_total / transport_s},
         "transport_fraction_of_wall": transport_s / dt,
+        "paper_context": "VPMC 41.6 s for 13 influence matrices (mean of 3 patients, 1-2 fields), "
+                         "EPYC 7543 + 4x A100",
         "device": torch.cuda.get_device_name(0),
     }
     if not a.no_cpu_baseline:
         progress("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(int(a.cpu_sample))
+        out["cpu_baseline"] = cpu_baseline(case, a.cpu_seconds, np)
     eng.close()
     print(json.dumps(out), flush=True)
 

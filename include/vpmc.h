@@ -59,6 +59,8 @@ extern "C" {
 
 #define VPMC_DEVICE_PTRS 1u /* pointers are device pointers; work on opts.hip_stream */
 #define VPMC_GRAPH 2u       /* CSR: capture all epochs of the run in one hipGraph */
+#define VPMC_SURROGATE 4u   /* dense: VPs entering the brass far from the opening's edge
+                               cross it by the learned surrogate (weights must be set) */
 
 #define VPMC_MAX_FIELDS 64
 #define VPMC_MAX_VERTICES 1024
@@ -182,18 +184,70 @@ int vpmc_run_batched(vpmc_ctx *ctx, const int *field_ids, const vpmc_spot *const
 
 /* Autotuner: for the launch shape only (never for results: tallies are
  * integers and streams are keyed by history, so every shape gives the same
- * bits).  Runs a bounded sample of the given spots (each spot's history count
- * scaled so that the sample holds about sample_histories VPs) in the output
- * mode of *base for each candidate shape, keeps the one with the shortest
+ * bits).  Runs a bounded sample of the given spots (every s-th spot with its
+ * own history count, s chosen so that the sample holds about
+ * sample_histories VPs) in the output mode of *base for each candidate
+ * shape, keeps the one with the shortest
  * transport time per history, writes it into *best (a copy of *base with
  * hist_per_lane, grid_blocks and block_threads filled) and remembers it for
  * later runs on this context whose opts leave them at 0.  Candidates (CSR):
- * hist_per_lane in {2,4,8,16} x (workgroups, threads) in {(4 CUs, 256),
+ * hist_per_lane in {4,8,16,32} x (workgroups, threads) in {(4 CUs, 256),
  * (8 CUs, 256), (2 CUs, 512), (4 CUs, 512)}; (dense): {4,8,16,32} x CUs x 256
  * threads of work per launch in workgroups of 256 or 512 threads. */
 int vpmc_autotune(vpmc_ctx *ctx, int field_id, const vpmc_spot *spots, int n_spots,
                   const vpmc_scenario *scen, const vpmc_opts *base, uint64_t sample_histories,
                   vpmc_opts *best);
+
+/* ---------------------------------------------------------------------------
+ * Learned aperture surrogate: a multilayer perceptron 8 -> 4 x 256 (SiLU) ->
+ * 29 run by BF16 matrix-core kernels with FP32 accumulation.  Inputs (one row
+ * per VP entering the block): normalised entry x, y, direction cosines u, v,
+ * energy, distance to the opening's edge, block thickness, material id.
+ * Outputs: [0] transmission logit, [1..4] mixture-weight logits, [5..16]
+ * means and [17..28] log standard deviations (3 per component) of the
+ * normalised outgoing energy loss, deflection angle and lateral offset.  It is
+ * trained on traversals produced by the plain brass transport (Methods B),
+ * which stays the fallback near the opening's edge.  Parameters are FP32,
+ * layer by layer as W[out][in] then b[out].  All pointers are host memory.
+ * ------------------------------------------------------------------------- */
+int vpmc_surrogate_param_count(void);
+/* Training data from the plain transport: entries [n][5] = (x, y) on the
+ * upstream face of field_id's block (BEV, mm), direction cosines (u, v),
+ * energy (MeV); each crosses the block with the plain brass transport
+ * (seeded streams, `physics` as in vpmc_opts).  Writes the network inputs
+ * x [n][8] = (x/20, y/20, u/0.05, v/0.05, (E-150)/50, min(d_edge,100)/10,
+ * thickness/30, material 0), targets y [n][3] = ((dE/E - 0.5)/0.25,
+ * angle/0.05 rad, offset/2 mm) and trans[n] = 1 transmitted, 0 stopped or
+ * lost, -1 entered through the opening (no brass traversal). */
+int vpmc_surrogate_sample(vpmc_ctx *ctx, int field_id, const float *entries, int n, uint64_t seed,
+                          unsigned physics, float *x, float *y, float *trans);
+int vpmc_surrogate_set_weights(vpmc_ctx *ctx, const float *params, int n_params);
+int vpmc_surrogate_get_weights(vpmc_ctx *ctx, float *params, int n_params);
+/* Use of the network in dense runs with VPMC_SURROGATE (Methods B; the
+ * paper's block model is the plain transport, the network is this library's
+ * replacement for the deep brass part of it).  A VP whose block entry point
+ * lies in the brass at least d_fallback_mm from the opening's polygon is
+ * queued; the network then gives its transmission probability p.  With
+ * p_lo <= p <= p_hi the plain brass transport crosses it from its unchanged
+ * state (so p_lo = 0, p_hi = 1 reproduces the run without the flag bit for
+ * bit); otherwise the outcome is sampled (stopped: its energy goes to the block ledger;
+ * transmitted: a mixture component, then energy loss, deflection and offset
+ * with a uniform azimuth) and the patient transport follows.  Defaults
+ * 3 mm, 0.02, 0.98.  Errors: VPMC_E_ARG unless d_fallback_mm >= 0 and
+ * 0 <= p_lo <= p_hi <= 1. */
+int vpmc_surrogate_config(vpmc_ctx *ctx, float d_fallback_mm, float p_lo, float p_hi);
+/* outputs [n][29] for inputs [n][8] */
+int vpmc_surrogate_forward(vpmc_ctx *ctx, const float *x, int n, float *out);
+/* mean loss over n <= 16384 samples (transmission cross-entropy + mixture
+ * negative log likelihood of y [n][3] for transmitted samples, trans[n] in
+ * {0,1}) and its gradient with respect to the parameters, without update */
+int vpmc_surrogate_loss_grad(vpmc_ctx *ctx, const float *x, const float *y, const float *trans, int n,
+                             float *grad, double *loss);
+/* Adam (lr, beta 0.9/0.999) on FP32 master weights over `epochs` shuffled
+ * passes of mini-batches of `batch` samples; mean loss per epoch written to
+ * loss_per_epoch[epochs] (optional). */
+int vpmc_surrogate_train(vpmc_ctx *ctx, const float *x, const float *y, const float *trans, int n, int epochs,
+                         int batch, float lr, uint64_t seed, float *loss_per_epoch);
 
 /* After a CSR run: column (voxel) indices in ascending order per row and FP32
  * values (Gy per unit spot weight, converted from the int64 tally); q_raw
@@ -208,11 +262,13 @@ int vpmc_last_tally(vpmc_ctx *ctx, int scen_index, int64_t *q_out, int *k_out, u
 
 /* Measurements of the last run: transport_ms is the sum of the transport
  * kernels' durations (HIP events recorded on the run's stream around each
- * launch), total_ms the whole call; steps counts condensed-history steps
- * (every region), histories the VPs transported. */
+ * launch; with VPMC_SURROGATE each interval also holds the network and
+ * resume kernels of that batch), total_ms the whole call; steps counts
+ * condensed-history steps (every region), histories the VPs transported. */
 typedef struct {
     double transport_ms, total_ms;
     uint64_t histories, steps, launches;
+    uint64_t deferred;      /* VPs handed to the aperture surrogate (VPMC_SURROGATE) */
 } vpmc_stats;
 int vpmc_last_stats(const vpmc_ctx *ctx, vpmc_stats *out);
 

@@ -120,6 +120,9 @@ const HostTables &host_tables() {
     return g_tables;
 }
 
+// Device tables are per unit of (density x path length in mm), i.e. 10x the
+// areal density in g/cm^2: a 1 mm step in water is then exactly 1.0 in FP32,
+// whereas 0.1 g/cm^2 is not representable and would bias every step alike.
 void pack_device_tables(float *blob) {
     const HostTables &t = host_tables();
     memset(blob, 0, sizeof(float) * TAB_FLOATS);
@@ -130,15 +133,15 @@ void pack_device_tables(float *blob) {
     for (int m = 0; m < NMAT; ++m) {
         float *b = blob + TAB_MAT0 + m * TAB_PER_MAT;
         for (int i = 0; i < NE; ++i) {
-            b[T_R * NE + i] = (float)t.R[m][i];
+            b[T_R * NE + i] = (float)(10.0 * t.R[m][i]);
             if (i + 1 < NE) {
-                const double dR = t.R[m][i + 1] - t.R[m][i];
+                const double dR = 10.0 * (t.R[m][i + 1] - t.R[m][i]);
                 b[T_SLOPE * NE + i] = (float)((t.E[i + 1] - t.E[i]) / dR);
                 b[T_DR * NE + i] = (float)dR;
             }
-            b[T_W2 * NE + i] = (float)t.W2[m][i];
-            b[T_T * NE + i] = (float)t.T[m][i];
-            b[T_SN * NE + i] = (float)t.SN[m][i];
+            b[T_W2 * NE + i] = (float)(0.1 * t.W2[m][i]);
+            b[T_T * NE + i] = (float)(0.1 * t.T[m][i]);
+            b[T_SN * NE + i] = (float)(0.1 * t.SN[m][i]);
         }
     }
 }

@@ -81,6 +81,13 @@ struct vpmc_ctx {
     int tuned_csr_hpl = 0, tuned_csr_blocks = 0, tuned_dense_blocks = 0;
     int tuned_csr_threads = 0, tuned_dense_threads = 0;
     hipStream_t cap_stream = nullptr;   // private stream for graph capture
+    // aperture surrogate
+    DevBuf mlp_w, mlp_wb, mlp_m, mlp_v, mlp_g, mlp_act, mlp_io, mlp_dx, mlp_dy, mlp_dt, mlp_idx;
+    bool mlp_ready = false;
+    int mlp_step = 0;
+    int mlp_batch_cap = 0;
+    DevBuf sur_rec, sur_cnt;
+    float sur_dfb = 3.0f, sur_plo = 0.02f, sur_phi = 0.98f;
 };
 
 namespace {
@@ -570,11 +577,208 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     return VPMC_OK;
 }
 
+// carve the activation buffers of a batch of up to `cap` samples
+int mlp_buffers(vpmc_ctx *c, int cap, MlpBuffers *b) {
+    const size_t H = MLP_HIDDEN;
+    const size_t bytes = (size_t)cap * (MLP_IN * 2 + 4 * H * 2 + 4 * H * 4 + MLP_OUT * 4 * 2 + MLP_OUT * 2 +
+                                        H * 4 * 3 + H * 2 * 2 + 4) + 32 * 256;   // 17 carvings, each rounded up to 256 B
+    if (c->mlp_batch_cap < cap) {
+        int rc = ensure(c, c->mlp_act, bytes, 0);
+        if (rc) return rc;
+        c->mlp_batch_cap = cap;
+    }
+    char *p = (char *)c->mlp_act.ptr;
+    char *const end = p + c->mlp_act.cap;
+    auto take = [&](size_t n) { char *q = p; p += (n + 255) & ~(size_t)255; return (void *)q; };
+    b->w = (float *)c->mlp_w.ptr;
+    b->wb = (__bf16 *)c->mlp_wb.ptr;
+    b->x = (__bf16 *)take((size_t)cap * MLP_IN * 2);
+    for (int i = 0; i < 4; ++i) b->h[i] = (__bf16 *)take((size_t)cap * H * 2);
+    for (int i = 0; i < 4; ++i) b->z[i] = (float *)take((size_t)cap * H * 4);
+    b->out = (float *)take((size_t)cap * MLP_OUT * 4);
+    b->dout = (float *)take((size_t)cap * MLP_OUT * 4);
+    b->dout_b = (__bf16 *)take((size_t)cap * MLP_OUT * 2);
+    b->dh = (float *)take((size_t)cap * H * 4);
+    b->dz_a = (float *)take((size_t)cap * H * 4);
+    b->dz_b = (float *)take((size_t)cap * H * 4);
+    b->dzb_a = (__bf16 *)take((size_t)cap * H * 2);
+    b->dzb_b = (__bf16 *)take((size_t)cap * H * 2);
+    b->loss = (float *)take((size_t)cap * 4);
+    if (p > end) return fail(VPMC_E_OOM, "surrogate activation buffer too small");
+    return VPMC_OK;
+}
+
+int mlp_require(vpmc_ctx *c) {
+    if (!c) return fail(VPMC_E_ARG, "ctx is NULL");
+    if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
+    if (!c->mlp_ready) return fail(VPMC_E_STATE, "surrogate weights not set");
+    HIP_TRY(hipSetDevice(c->device));
+    return VPMC_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int vpmc_version(void) { return 101; }
+int vpmc_version(void) { return 102; }
+
+int vpmc_surrogate_param_count(void) { return mlp_param_count(); }
+
+int vpmc_surrogate_set_weights(vpmc_ctx *c, const float *params, int n) {
+    if (!c || !params) return fail(VPMC_E_ARG, "ctx/params is NULL");
+    const int np = mlp_param_count();
+    if (n != np) return fail(VPMC_E_ARG, "surrogate has %d parameters, got %d", np, n);
+    for (int i = 0; i < n; ++i)
+        if (!isfinite(params[i])) return fail(VPMC_E_ARG, "parameter %d is not finite", i);
+    if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
+    HIP_TRY(hipSetDevice(c->device));
+    int rc;
+    if ((rc = ensure(c, c->mlp_w, np * 4, 0)) || (rc = ensure(c, c->mlp_wb, np * 2, 0)) ||
+        (rc = ensure(c, c->mlp_m, np * 4, 0)) || (rc = ensure(c, c->mlp_v, np * 4, 0)) ||
+        (rc = ensure(c, c->mlp_g, np * 4, 0)))
+        return rc;
+    HIP_TRY(hipMemcpy(c->mlp_w.ptr, params, np * 4, hipMemcpyHostToDevice));
+    HIP_TRY(mlp_to_bf16((const float *)c->mlp_w.ptr, (__bf16 *)c->mlp_wb.ptr, np, nullptr));
+    HIP_TRY(hipMemset(c->mlp_m.ptr, 0, np * 4));
+    HIP_TRY(hipMemset(c->mlp_v.ptr, 0, np * 4));
+    HIP_TRY(hipDeviceSynchronize());
+    c->mlp_ready = true;
+    c->mlp_step = 0;
+    return VPMC_OK;
+}
+
+int vpmc_surrogate_config(vpmc_ctx *c, float d_fallback_mm, float p_lo, float p_hi) {
+    if (!c) return fail(VPMC_E_ARG, "ctx is NULL");
+    if (!(d_fallback_mm >= 0.0f) || !isfinite(d_fallback_mm) || !(p_lo >= 0.0f) || !(p_lo <= p_hi) ||
+        !(p_hi <= 1.0f))
+        return fail(VPMC_E_ARG, "need d_fallback_mm >= 0 and 0 <= p_lo <= p_hi <= 1");
+    c->sur_dfb = d_fallback_mm;
+    c->sur_plo = p_lo;
+    c->sur_phi = p_hi;
+    return VPMC_OK;
+}
+
+int vpmc_surrogate_get_weights(vpmc_ctx *c, float *params, int n) {
+    int rc = mlp_require(c);
+    if (rc) return rc;
+    if (!params || n != mlp_param_count()) return fail(VPMC_E_ARG, "need %d parameters", mlp_param_count());
+    HIP_TRY(hipMemcpy(params, c->mlp_w.ptr, (size_t)n * 4, hipMemcpyDeviceToHost));
+    return VPMC_OK;
+}
+
+int vpmc_surrogate_sample(vpmc_ctx *c, int field_id, const float *entries, int n, uint64_t seed, unsigned physics,
+                          float *x, float *y, float *trans) {
+    if (!c || !entries || !x || !y || !trans || n < 1) return fail(VPMC_E_ARG, "bad sample arguments");
+    if (field_id < 0 || field_id >= VPMC_MAX_FIELDS || !c->fields[field_id].set)
+        return fail(VPMC_E_STATE, "field %d not set", field_id);
+    if (!c->fields[field_id].dev.has_block) return fail(VPMC_E_STATE, "field %d has no block", field_id);
+    if (physics & ~VPMC_PHYS_ALL) return fail(VPMC_E_ARG, "unknown physics bits");
+    for (int i = 0; i < n; ++i) {
+        const float *e = entries + (size_t)i * 5;
+        if (!isfinite(e[0]) || !isfinite(e[1]) || !(e[2] * e[2] + e[3] * e[3] < 1.0f) || !(e[4] > E_LO && e[4] <= E_HI))
+            return fail(e[4] > E_LO && e[4] <= E_HI ? VPMC_E_ARG : VPMC_E_RANGE, "entry %d invalid", i);
+    }
+    if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
+    HIP_TRY(hipSetDevice(c->device));
+    int rc;
+    if ((rc = ensure(c, c->mlp_io, (size_t)n * (5 + 8 + 3 + 1) * 4 + 64, 0))) return rc;
+    float *de = (float *)c->mlp_io.ptr, *dx = de + (size_t)n * 5, *dy = dx + (size_t)n * 8, *dt = dy + (size_t)n * 3;
+    HIP_TRY(hipMemcpy(de, entries, (size_t)n * 5 * 4, hipMemcpyHostToDevice));
+    HIP_TRY(launch_surrogate_sample(c->fields[field_id].dev, de, n, (uint32_t)(seed & 0xffffffffu),
+                                    (uint32_t)(seed >> 32) ^ (uint32_t)field_id, physics, c->d_tables, dx, dy, dt,
+                                    nullptr));
+    HIP_TRY(hipMemcpy(x, dx, (size_t)n * 8 * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(y, dy, (size_t)n * 3 * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(trans, dt, (size_t)n * 4, hipMemcpyDeviceToHost));
+    return VPMC_OK;
+}
+
+int vpmc_surrogate_forward(vpmc_ctx *c, const float *x, int n, float *out) {
+    int rc = mlp_require(c);
+    if (rc) return rc;
+    if (!x || !out || n < 0) return fail(VPMC_E_ARG, "bad forward arguments");
+    if (n == 0) return VPMC_OK;
+    MlpBuffers b;
+    const int cap = std::min(n, MLP_MAX_BATCH);
+    if ((rc = mlp_buffers(c, cap, &b))) return rc;
+    if ((rc = ensure(c, c->mlp_io, (size_t)cap * MLP_IN * 4, 0))) return rc;
+    for (int s0 = 0; s0 < n; s0 += cap) {
+        const int m = std::min(cap, n - s0);
+        HIP_TRY(hipMemcpy(c->mlp_io.ptr, x + (size_t)s0 * MLP_IN, (size_t)m * MLP_IN * 4, hipMemcpyHostToDevice));
+        HIP_TRY(mlp_to_bf16((const float *)c->mlp_io.ptr, b.x, (size_t)m * MLP_IN, nullptr));
+        HIP_TRY(mlp_forward(b, m, nullptr));
+        HIP_TRY(hipMemcpy(out + (size_t)s0 * MLP_OUT, b.out, (size_t)m * MLP_OUT * 4, hipMemcpyDeviceToHost));
+    }
+    return VPMC_OK;
+}
+
+int vpmc_surrogate_loss_grad(vpmc_ctx *c, const float *x, const float *y, const float *trans, int n, float *grad,
+                             double *loss) {
+    int rc = mlp_require(c);
+    if (rc) return rc;
+    if (!x || !y || !trans || !grad || n < 1 || n > MLP_MAX_BATCH)
+        return fail(VPMC_E_ARG, "need 1..%d samples and all buffers", MLP_MAX_BATCH);
+    MlpBuffers b;
+    if ((rc = mlp_buffers(c, n, &b))) return rc;
+    if ((rc = ensure(c, c->mlp_io, (size_t)n * (MLP_IN + 4) * 4 + 64, 0))) return rc;
+    float *dx = (float *)c->mlp_io.ptr, *dy = dx + (size_t)n * MLP_IN, *dt = dy + (size_t)n * 3, *dl = dt + n;
+    HIP_TRY(hipMemcpy(dx, x, (size_t)n * MLP_IN * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dy, y, (size_t)n * 3 * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dt, trans, (size_t)n * 4, hipMemcpyHostToDevice));
+    HIP_TRY(mlp_to_bf16(dx, b.x, (size_t)n * MLP_IN, nullptr));
+    HIP_TRY(mlp_loss_grad(b, dy, dt, n, (float *)c->mlp_g.ptr, dl, nullptr));
+    float lsum = 0.0f;
+    HIP_TRY(hipMemcpy(&lsum, dl, 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(grad, c->mlp_g.ptr, (size_t)mlp_param_count() * 4, hipMemcpyDeviceToHost));
+    if (loss) *loss = (double)lsum / n;
+    return VPMC_OK;
+}
+
+int vpmc_surrogate_train(vpmc_ctx *c, const float *x, const float *y, const float *trans, int n, int epochs, int batch,
+                         float lr, uint64_t seed, float *loss_per_epoch) {
+    int rc = mlp_require(c);
+    if (rc) return rc;
+    if (!x || !y || !trans || n < 1 || epochs < 1 || batch < 16 || batch > MLP_MAX_BATCH || !(lr > 0.0f))
+        return fail(VPMC_E_ARG, "bad training arguments");
+    MlpBuffers b;
+    if ((rc = mlp_buffers(c, batch, &b))) return rc;
+    if ((rc = ensure(c, c->mlp_dx, (size_t)n * MLP_IN * 4, 0)) || (rc = ensure(c, c->mlp_dy, (size_t)n * 3 * 4, 0)) ||
+        (rc = ensure(c, c->mlp_dt, (size_t)n * 4, 0)) || (rc = ensure(c, c->mlp_idx, (size_t)n * 4, 0)) ||
+        (rc = ensure(c, c->mlp_io, (size_t)batch * 4 * 4 + 64, 0)))
+        return rc;
+    HIP_TRY(hipMemcpy(c->mlp_dx.ptr, x, (size_t)n * MLP_IN * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->mlp_dy.ptr, y, (size_t)n * 3 * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->mlp_dt.ptr, trans, (size_t)n * 4, hipMemcpyHostToDevice));
+    float *by = (float *)c->mlp_io.ptr, *bt = by + (size_t)batch * 3, *bl = bt + batch;
+    std::vector<int> perm(n);
+    uint64_t st = seed ^ 0x9E3779B97F4A7C15ull;
+    const int np = mlp_param_count();
+    for (int ep = 0; ep < epochs; ++ep) {
+        for (int i = 0; i < n; ++i) perm[i] = i;
+        for (int i = n - 1; i > 0; --i) {   // Fisher-Yates with xorshift64*
+            st ^= st >> 12; st ^= st << 25; st ^= st >> 27;
+            const int j = (int)(((st * 0x2545F4914F6CDD1Dull) >> 11) % (uint64_t)(i + 1));
+            std::swap(perm[i], perm[j]);
+        }
+        HIP_TRY(hipMemcpy(c->mlp_idx.ptr, perm.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+        double lsum = 0.0;
+        int nb = 0;
+        for (int s0 = 0; s0 + batch <= n; s0 += batch, ++nb) {
+            const int *idx = (const int *)c->mlp_idx.ptr + s0;
+            HIP_TRY(mlp_gather((const float *)c->mlp_dx.ptr, idx, batch, MLP_IN, b.x, nullptr, nullptr));
+            HIP_TRY(mlp_gather((const float *)c->mlp_dy.ptr, idx, batch, 3, nullptr, by, nullptr));
+            HIP_TRY(mlp_gather((const float *)c->mlp_dt.ptr, idx, batch, 1, nullptr, bt, nullptr));
+            HIP_TRY(mlp_loss_grad(b, by, bt, batch, (float *)c->mlp_g.ptr, bl, nullptr));
+            HIP_TRY(mlp_adam((float *)c->mlp_w.ptr, (const float *)c->mlp_g.ptr, (float *)c->mlp_m.ptr,
+                             (float *)c->mlp_v.ptr, (__bf16 *)c->mlp_wb.ptr, np, lr, ++c->mlp_step, nullptr));
+            float l = 0.0f;
+            HIP_TRY(hipMemcpy(&l, bl, 4, hipMemcpyDeviceToHost));
+            lsum += l / batch;
+        }
+        if (loss_per_epoch) loss_per_epoch[ep] = nb ? (float)(lsum / nb) : 0.0f;
+    }
+    return VPMC_OK;
+}
 
 const char *vpmc_last_error(const vpmc_ctx *) { return g_err; }
 
@@ -621,7 +825,9 @@ void vpmc_destroy(vpmc_ctx *c) {
                           &c->stage_dose, &c->stage_sigma, &c->stats, &c->slot_grid, &c->slot_l1, &c->slot_l2,
                           &c->slot_nnz, &c->rows, &c->chunk_off, &c->heads, &c->row_off, &c->row_nnz, &c->used,
                           &c->flags, &c->fields_tab, &c->poly_off, &c->polys, &c->scen_tab, &c->csr_col,
-                          &c->csr_q})
+                          &c->csr_q, &c->mlp_w, &c->mlp_wb, &c->mlp_m, &c->mlp_v, &c->mlp_g, &c->mlp_act,
+                          &c->mlp_io, &c->mlp_dx, &c->mlp_dy, &c->mlp_dt, &c->mlp_idx, &c->sur_rec,
+                          &c->sur_cnt})
             release(*b);
         for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -755,7 +961,12 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
     if (o->grid_blocks < 0) return fail(VPMC_E_ARG, "grid_blocks < 0");
     if (o->hist_per_lane < 0 || o->hist_per_lane > 4096) return fail(VPMC_E_ARG, "hist_per_lane outside [0, 4096]");
     if (o->max_slots < 0) return fail(VPMC_E_ARG, "max_slots < 0");
-    if (o->flags & ~(VPMC_DEVICE_PTRS | VPMC_GRAPH)) return fail(VPMC_E_ARG, "unknown flags");
+    if (o->flags & ~(VPMC_DEVICE_PTRS | VPMC_GRAPH | VPMC_SURROGATE)) return fail(VPMC_E_ARG, "unknown flags");
+    const bool use_sur = (o->flags & VPMC_SURROGATE) != 0;
+    if (use_sur) {
+        if (o->output != VPMC_OUT_DOSE) return fail(VPMC_E_ARG, "VPMC_SURROGATE is a dense-mode option");
+        if (!c->mlp_ready) return fail(VPMC_E_STATE, "VPMC_SURROGATE needs surrogate weights");
+    }
     if (o->output == VPMC_OUT_CSR) {
         if (!row_ptr) return fail(VPMC_E_ARG, "CSR output needs row_ptr");
         if (sigma_gy) return fail(VPMC_E_ARG, "sigma_gy is not produced in CSR mode");
@@ -793,6 +1004,20 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
         if (dose_gy && (rc = ensure(c, c->stage_dose, nvox * sizeof(float), cap))) return rc;
         if (sigma_gy && (rc = ensure(c, c->stage_sigma, nvox * sizeof(float), cap))) return rc;
     }
+    // surrogate queue: records of one batch launch (VPs beyond it cross the
+    // block with the plain transport)
+    const FieldDev &fd = c->fields[field_id].dev;
+    const bool sur_on = use_sur && fd.has_block;
+    unsigned long long sur_cap = 0;
+    MlpBuffers mb{};
+    if (sur_on) {
+        unsigned long long per_batch = 0;
+        for (int i = 0; i < n_spots; ++i) per_batch += (spots[i].n_histories + B - 1) / B;
+        sur_cap = std::max(1ull, std::min(per_batch, kSurMaxRecords));
+        if ((rc = ensure(c, c->sur_rec, sur_cap * sizeof(DeferRec), cap))) return rc;
+        if ((rc = ensure(c, c->sur_cnt, sizeof(unsigned long long), cap))) return rc;
+        if ((rc = mlp_buffers(c, MLP_MAX_BATCH, &mb))) return rc;
+    }
 
     // spots and per-batch work offsets
     std::vector<SpotDev> sd(std::max(1, n_spots));
@@ -827,9 +1052,9 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
     size_t n_launch = 0;
     HIP_TRY(hipEventRecord(c->events[0], st));
 
-    const FieldDev &fd = c->fields[field_id].dev;
     const int threads = o->block_threads ? o->block_threads : (c->tuned_dense_threads ? c->tuned_dense_threads : 256);
     const double mev_scale = ldexp(MEV_TO_J, -k);
+    unsigned long long deferred = 0;
     for (int sc = 0; sc < n_scen; ++sc) {
         long long *tally = (long long *)c->tallies.ptr + (size_t)sc * nvox;
         HIP_TRY(hipMemsetAsync(tally, 0, nvox * sizeof(long long), st));
@@ -859,8 +1084,32 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
             const unsigned long long maxb = o->grid_blocks ? (unsigned long long)o->grid_blocks
                                             : (c->tuned_dense_blocks ? (unsigned long long)c->tuned_dense_blocks : 4096ull);
             const int blocks = (int)std::min(want, maxb);
+            if (sur_on) {
+                HIP_TRY(hipMemsetAsync(c->sur_cnt.ptr, 0, sizeof(unsigned long long), st));
+                L.sur.enabled = 1;
+                L.sur.d_fallback = c->sur_dfb;
+                L.sur.count = (unsigned long long *)c->sur_cnt.ptr;
+                L.sur.capacity = sur_cap;
+                L.sur.rec = (DeferRec *)c->sur_rec.ptr;
+            }
             HIP_TRY(hipEventRecord(c->events[2 + 2 * n_launch], st));
             HIP_TRY(launch_transport(c->geom, fd, L, blocks, threads, st));
+            if (sur_on) {
+                // the queue's length decides the network's launch shapes
+                unsigned long long cnt = 0;
+                HIP_TRY(hipMemcpyAsync(&cnt, c->sur_cnt.ptr, sizeof cnt, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                const unsigned long long nq = std::min(cnt, sur_cap);
+                deferred += nq;
+                const DeferRec *rec = (const DeferRec *)c->sur_rec.ptr;
+                for (unsigned long long s0 = 0; s0 < nq; s0 += MLP_MAX_BATCH) {
+                    const int m = (int)std::min<unsigned long long>(MLP_MAX_BATCH, nq - s0);
+                    HIP_TRY(launch_sur_features(rec + s0, m, fd.blk_t, mb.x, st));
+                    HIP_TRY(mlp_forward(mb, m, st));
+                    HIP_TRY(launch_sur_resume(c->geom, fd, L, rec + s0, mb.out, (unsigned long long)m, c->sur_plo,
+                                              c->sur_phi, st));
+                }
+            }
             HIP_TRY(hipEventRecord(c->events[3 + 2 * n_launch], st));
             ++n_launch;
             if (B > 1)
@@ -893,6 +1142,7 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
     S.steps = stv[0];
     S.histories = stv[1];
     S.launches = n_launch;
+    S.deferred = deferred;
     c->last_stats = S;
     if (ledger_mev)
         for (size_t i = 0; i < led.size(); ++i) ledger_mev[i] = ldexp((double)led[i], -k);
@@ -955,9 +1205,11 @@ int vpmc_autotune(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spots
     double tot = 0.0;
     for (int i = 0; i < n_spots; ++i) tot += spots[i].n_histories;
     if (tot <= 0) return fail(VPMC_E_ARG, "spots hold no histories");
-    const double f = std::min(1.0, (double)sample_histories / tot);
-    std::vector<vpmc_spot> sub(spots, spots + n_spots);
-    for (auto &sp : sub) sp.n_histories = (uint32_t)std::max(1.0, std::floor(sp.n_histories * f));
+    // the sample keeps the real per-spot history counts (the chunking and
+    // the tally footprint of a row depend on them) and takes every s-th spot
+    const int stride = std::max(1, (int)std::floor(tot / (double)sample_histories));
+    std::vector<vpmc_spot> sub;
+    for (int i = 0; i < n_spots; i += stride) sub.push_back(spots[i]);
     int cus = 256;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) cus = prop.multiProcessorCount;
@@ -965,14 +1217,15 @@ int vpmc_autotune(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spots
     struct Cand { int hpl, blocks, threads; };
     std::vector<Cand> cand;
     if (csr) {
-        for (int h : {2, 4, 8, 16})
+        for (int h : {4, 8, 16, 32})
             for (auto bt : {std::make_pair(4, 256), std::make_pair(8, 256), std::make_pair(2, 512), std::make_pair(4, 512)})
                 cand.push_back({h, bt.first * cus, bt.second});
     } else {
         for (int m : {4, 8, 16, 32})
             for (int t : {256, 512}) cand.push_back({0, m * cus * 256 / t, t});
     }
-    const size_t R = (size_t)n_spots;
+    const int n_sub = (int)sub.size();
+    const size_t R = (size_t)n_sub;
     std::vector<int64_t> rp(R + 1);
     std::vector<double> led(NLEDGER);
     double best_t = 1e300;
@@ -987,9 +1240,9 @@ int vpmc_autotune(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spots
         o.hist_per_lane = cd.hpl;
         o.grid_blocks = cd.blocks;
         o.block_threads = cd.threads;
-        const int rc = csr ? vpmc_run_spots(c, field_id, sub.data(), n_spots, scen, 1, &o, nullptr, nullptr,
+        const int rc = csr ? vpmc_run_spots(c, field_id, sub.data(), n_sub, scen, 1, &o, nullptr, nullptr,
                                             led.data(), rp.data())
-                           : vpmc_run_spots(c, field_id, sub.data(), n_spots, scen, 1, &o, nullptr, nullptr,
+                           : vpmc_run_spots(c, field_id, sub.data(), n_sub, scen, 1, &o, nullptr, nullptr,
                                             led.data(), nullptr);
         if (rc) return rc;
         if (ci == 0) continue;

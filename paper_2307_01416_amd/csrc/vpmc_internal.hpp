@@ -15,7 +15,8 @@ constexpr double E_HI = 256.0;
 enum Material { MAT_WATER = 0, MAT_AIR = 1, MAT_PMMA = 2, MAT_BRASS = 3, MAT_BONE = 4 };
 
 // FP32 device blob: [E nodes][1/(E_i+1 - E_i)] then per material
-// [R][dE/dR per segment][R_i+1 - R_i][omega^2][T][Sigma_nuc], NE floats each.
+// [R][dE/dR per segment][R_i+1 - R_i][omega^2][T][Sigma_nuc], NE floats each,
+// all per unit of density x path length in mm (10 x g/cm^2).
 enum { TAB_E = 0, TAB_INVDE = NE, TAB_MAT0 = 2 * NE, TAB_PER_MAT = 6 * NE };
 enum { T_R = 0, T_SLOPE = 1, T_DR = 2, T_W2 = 3, T_T = 4, T_SN = 5 };
 constexpr int TAB_FLOATS = 2 * NE + NMAT * 6 * NE;   // 8192 floats = 32 KiB of LDS
@@ -69,6 +70,23 @@ struct SpotDev {
     uint32_t nh;
 };
 
+// VP deferred at the block entry for the surrogate: its whole state on the
+// block's upstream face (E + Elo is the compensated energy, pzlo the low part
+// of the depth), so the plain transport can resume it unchanged
+struct DeferRec {
+    uint32_t spot, hist, nblk, pad;
+    float x, y, u, v, w, E, Elo, pzlo, d_edge, pad2[3];
+};
+static_assert(sizeof(DeferRec) == 64, "DeferRec is 64 bytes");
+
+struct SurDev {
+    int enabled;
+    float d_fallback;                 // VPs nearer the opening's edge stay on the plain transport
+    unsigned long long *count;        // records written (may exceed capacity: the rest ran plain)
+    unsigned long long capacity;
+    DeferRec *rec;
+};
+
 struct LaunchDev {
     const SpotDev *spots;
     const unsigned long long *item_off;   // [n_spots + 1] prefix of items per spot
@@ -83,6 +101,7 @@ struct LaunchDev {
     unsigned long long *ledger;           // [NLEDGER]
     unsigned long long *stats;            // [2]: steps, histories
     const float *tables;                  // TAB_FLOATS
+    SurDev sur;
 };
 
 constexpr int POLY_LDS = 1024;  // == VPMC_MAX_VERTICES
@@ -133,6 +152,47 @@ struct QueueDev {
 };
 
 hipError_t launch_queue(const GeomDev &g, const QueueDev &Q, int blocks, int threads, hipStream_t s);
+
+// ------------------------------------------------------- aperture surrogate
+// MLP 8 -> 256 -> 256 -> 256 -> 256 -> 29, parameters layer by layer as
+// W[out][in] then b[out] (FP32 master, BF16 copy in the same layout).
+constexpr int MLP_LAYERS = 5;
+constexpr int MLP_IN = 8;
+constexpr int MLP_OUT = 29;
+constexpr int MLP_HIDDEN = 256;
+constexpr int MLP_MAX_BATCH = 16384;
+constexpr unsigned long long kSurMaxRecords = 1ull << 22;   // surrogate queue (64 B each)
+
+struct MlpBuffers {
+    float *w;            // FP32 master parameters
+    __bf16 *wb;          // BF16 parameters
+    __bf16 *x;           // [n][8] inputs
+    __bf16 *h[4];        // [n][256] hidden activations
+    float *z[4];         // [n][256] hidden pre-activations
+    float *out;          // [n][29]
+    float *dout;         // [n][29] d loss / d out (batch mean)
+    __bf16 *dout_b;
+    float *dh;           // [n][256]
+    float *dz_a, *dz_b;  // [n][256]
+    __bf16 *dzb_a, *dzb_b;
+    float *loss;         // [n] per-sample loss
+};
+
+hipError_t launch_sur_features(const DeferRec *rec, int n, float thick, __bf16 *x, hipStream_t s);
+hipError_t launch_sur_resume(const GeomDev &g, const FieldDev &f, const LaunchDev &L, const DeferRec *rec,
+                             const float *out, unsigned long long n, float p_lo, float p_hi, hipStream_t s);
+hipError_t launch_surrogate_sample(const FieldDev &f, const float *entries, int n, uint32_t key0, uint32_t key1,
+                                   unsigned physics, const float *tables, float *x, float *y, float *t, hipStream_t s);
+int mlp_param_count();
+int mlp_param_offset(int layer);
+int mlp_dim(int i);
+hipError_t mlp_forward(const MlpBuffers &b, int n, hipStream_t s);
+hipError_t mlp_loss_grad(const MlpBuffers &b, const float *y, const float *trans, int n, float *grad, float *loss,
+                         hipStream_t s);
+hipError_t mlp_gather(const float *x, const int *idx, int n, int cols, __bf16 *xb, float *xf, hipStream_t s);
+hipError_t mlp_to_bf16(const float *x, __bf16 *y, size_t n, hipStream_t s);
+hipError_t mlp_adam(float *p, const float *g, float *m, float *v, __bf16 *pb, int np, float lr, int step,
+                    hipStream_t s);
 hipError_t launch_csr_offsets(unsigned int *nnz, int n_rows, int row_begin, unsigned long long *row_off,
                               unsigned long long *row_nnz, unsigned long long *used, unsigned long long capacity,
                               unsigned int *flags, hipStream_t s);

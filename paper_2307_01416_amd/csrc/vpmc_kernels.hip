@@ -175,15 +175,15 @@ __device__ int phys_step(Lane &v, const float *tab, int m, float rho_loss, float
     const float x = (v.E - tab[TAB_E + i]) + v.Elo;
     const float slope = tm[T_SLOPE * NE + i];
     const float R = tm[T_R * NE + i] + x * __builtin_amdgcn_rcpf(slope);
-    if (rho_loss * dg * 0.1f >= R) {
+    if (rho_loss * dg >= R) {
         dep = v.E + v.Elo;
         v.E = v.Elo = 0.0f;
         return ST_STOP;
     }
-    const float smax = 10.0f * STEP_FRACTION * R * __builtin_amdgcn_rcpf(rho_loss);
+    const float smax = STEP_FRACTION * R * __builtin_amdgcn_rcpf(rho_loss);
     const bool geo = dg <= smax;
     const float s = geo ? dg : smax;
-    const float r = rho_loss * s * 0.1f;
+    const float r = rho_loss * s;   // density x mm (the tables' unit)
     float dE = csda_loss(tm, i, x, slope, r);
     const float Ebar = v.E - 0.5f * dE;
     uint4 w = make_uint4(0u, 0u, 0u, 0xFFFFFFFFu);
@@ -201,7 +201,7 @@ __device__ int phys_step(Lane &v, const float *tab, int m, float rho_loss, float
     dep = dE;
     sub_energy(v, dE);
     if (v.physics & PH_MCS) {
-        const float th0 = sqrtf(rho * s * 0.1f * node_lerp(tm + T_T * NE, pb));
+        const float th0 = sqrtf(rho * s * node_lerp(tm + T_T * NE, pb));
         float z1, z2;
         box_muller_fast(w.x, w.y, z1, z2);
         const float h = 0.5f * s;
@@ -218,7 +218,7 @@ __device__ int phys_step(Lane &v, const float *tab, int m, float rho_loss, float
         if (CompDepth) add_depth(v, s * v.dz); else v.pz = fmaf(s, v.dz, v.pz);
     }
     if (v.physics & PH_NUCLEAR) {
-        const float P = -expm1f(-rho * s * 0.1f * node_lerp(tm + T_SN * NE, pb));
+        const float P = -expm1f(-rho * s * node_lerp(tm + T_SN * NE, pb));
         if (unit_open(w.w) < P) {
             const uint4 w2 = draw(v);
             const float E1 = v.E + v.Elo;
@@ -416,10 +416,31 @@ __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab,
     return EX_GONE;
 }
 
+// distance from (x, y) to the polygon's boundary (minimum over edges of the
+// point-to-segment distance)
+__device__ float dist_to_polygon(const float2 *poly, int nv, float x, float y) {
+    float best = INFINITY;
+    float2 a = poly[nv - 1];
+    for (int i = 0; i < nv; ++i) {
+        const float2 b = poly[i];
+        const float ex = b.x - a.x, ey = b.y - a.y;
+        const float wx = x - a.x, wy = y - a.y;
+        const float l2 = ex * ex + ey * ey;
+        float t = l2 > 0.0f ? (wx * ex + wy * ey) / l2 : 0.0f;
+        t = fminf(fmaxf(t, 0.0f), 1.0f);
+        const float dx = wx - t * ex, dy = wy - t * ey;
+        best = fminf(best, dx * dx + dy * dy);
+        a = b;
+    }
+    return sqrtf(best);
+}
+
 // range shifter then aperture block, in the beam frame; on success (p, d) is
 // on the VP's ray and tmin is the ray parameter of the last exit plane
-__device__ bool beamline(Lane &v, Acc &acc, float scale, const float *tab, const float2 *poly,
-                         const FieldDev &f, float &tmin) {
+enum { BL_STOP = 0, BL_PATIENT = 1, BL_DEFER = 2 };
+
+__device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const float2 *poly,
+                        const FieldDev &f, float &tmin, const SurDev *sur = nullptr) {
     tmin = -INFINITY;
     if (f.has_rs) {
         const float t = (f.rs_zu - v.pz) / v.dz;
@@ -429,14 +450,14 @@ __device__ bool beamline(Lane &v, Acc &acc, float scale, const float *tab, const
             v.py = qy;
             v.pz = f.rs_zu;
             if (slab_transport(v, acc, scale, tab, MAT_PMMA, f.rs_rho, f.rs_zu, f.rs_zd, f.rs_t, L_RS) != EX_DOWN)
-                return false;
+                return BL_STOP;
             tmin = 0.0f;
         }
     }
     if (f.has_block) {
         if (!(v.dz > 0.0f)) {
             ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
-            return false;
+            return BL_STOP;
         }
         const float t = (f.blk_zu - v.pz) / v.dz;
         const float qx = fmaf(t, v.dx, v.px), qy = fmaf(t, v.dy, v.py);
@@ -446,17 +467,43 @@ __device__ bool beamline(Lane &v, Acc &acc, float scale, const float *tab, const
             const float tx = f.blk_t / v.dz;
             if (te >= tx) {
                 tmin = (f.blk_zd - v.pz) / v.dz;
-                return true;
+                return BL_PATIENT;
+            }
+        } else if (sur && sur->enabled) {
+            // enters through brass: far enough from the opening's edge, the
+            // learned surrogate takes over the traversal (queued for it)
+            const float de = nv >= 3 ? dist_to_polygon(poly, nv, qx, qy) : 1000.0f;
+            if (de >= sur->d_fallback) {
+                const unsigned long long slot = atomicAdd(sur->count, 1ull);
+                if (slot < sur->capacity) {
+                    DeferRec r;
+                    r.spot = v.spot;
+                    r.hist = v.hist;
+                    r.nblk = v.nblk;
+                    r.pad = 0u;
+                    r.x = qx;
+                    r.y = qy;
+                    r.u = v.dx;
+                    r.v = v.dy;
+                    r.w = v.dz;
+                    r.E = v.E;
+                    r.Elo = v.Elo;
+                    r.pzlo = v.pzlo;
+                    r.d_edge = de;
+                    r.pad2[0] = r.pad2[1] = r.pad2[2] = 0.0f;
+                    sur->rec[slot] = r;
+                    return BL_DEFER;
+                }
             }
         }
         v.px = qx;
         v.py = qy;
         v.pz = f.blk_zu;
         if (block_transport(v, acc, scale, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, f.blk_t) != EX_DOWN)
-            return false;
+            return BL_STOP;
         tmin = 0.0f;
     }
-    return true;
+    return BL_PATIENT;
 }
 
 // ------------------------------------------------------------ patient
@@ -639,7 +686,7 @@ __global__ __launch_bounds__(512) void transport_kernel(GeomDev g, FieldDev f, L
         v.physics = L.physics;
         source(v, sp);
         float tmin;
-        if (beamline(v, acc, sp.scale, tab, poly, f, tmin))
+        if (beamline(v, acc, sp.scale, tab, poly, f, tmin, &L.sur) == BL_PATIENT)
             patient(v, acc, sp.scale, tab, g, f, L.shift, L.range_scale, DenseSink{L.tally}, tmin);
         acc.steps += v.nsteps;
         acc.hist += 1;
@@ -713,7 +760,7 @@ __global__ __launch_bounds__(512, 4) void queue_kernel(GeomDev g, QueueDev Q) {
             v.physics = Q.physics;
             source(v, sp);
             float tmin;
-            if (beamline(v, acc, sp.scale, tab, fpoly, f, tmin))
+            if (beamline(v, acc, sp.scale, tab, fpoly, f, tmin) == BL_PATIENT)
                 patient(v, acc, sp.scale, tab, g, f, sc.shift, sc.range_scale, sink, tmin);
             acc.steps += v.nsteps;
             acc.hist += 1;
@@ -853,6 +900,199 @@ __global__ void csr_values_kernel(const int32_t *col, const long long *qv, size_
     }
 }
 
+// ------------------------------------------------------------ surrogate data
+// Plain brass traversals for the surrogate's training data: each entry state
+// (x, y on the block's upstream face, direction cosines u, v, energy) crosses
+// the field's block with the plain transport (crossing number at every step).
+// Per VP: the 8 network inputs, the 3 normalised targets and the outcome
+// (1 transmitted, 0 stopped or lost, -1 entered through the opening).
+__global__ __launch_bounds__(256) void surrogate_sample_kernel(FieldDev f, const float *entries, int n,
+                                                               uint32_t key0, uint32_t key1, unsigned physics,
+                                                               const float *tables, float *xo, float *yo,
+                                                               float *to) {
+    __shared__ float tab[TAB_FLOATS];
+    __shared__ float2 poly[POLY_LDS];
+    for (int i = threadIdx.x; i < TAB_FLOATS / 4; i += blockDim.x)
+        reinterpret_cast<float4 *>(tab)[i] = reinterpret_cast<const float4 *>(tables)[i];
+    for (int i = threadIdx.x; i < f.nv; i += blockDim.x) poly[i] = f.poly[i];
+    __syncthreads();
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float *e = entries + (size_t)i * 5;
+        Lane v;
+        v.k0 = key0;
+        v.k1 = key1;
+        v.spot = 0;
+        v.hist = (uint32_t)i;
+        v.nblk = 0;
+        v.nsteps = 0;
+        v.physics = physics;
+        v.px = e[0];
+        v.py = e[1];
+        v.pz = f.blk_zu;
+        v.pzlo = 0.0f;
+        v.dx = e[2];
+        v.dy = e[3];
+        v.dz = sqrtf(fmaxf(1.0f - e[2] * e[2] - e[3] * e[3], 0.0f));
+        v.E = e[4];
+        v.Elo = 0.0f;
+        const float x0 = v.px, y0 = v.py, u0 = v.dx, w0 = v.dy, z0 = v.dz, E0 = v.E;
+        const int nv = f.nv;
+        const bool open = nv >= 3 && in_polygon(poly, nv, x0, y0);
+        const float de = nv >= 3 ? dist_to_polygon(poly, nv, x0, y0) : 1000.0f;
+        float *xr = xo + (size_t)i * 8;
+        xr[0] = x0 / 20.0f;
+        xr[1] = y0 / 20.0f;
+        xr[2] = u0 / 0.05f;
+        xr[3] = w0 / 0.05f;
+        xr[4] = (E0 - 150.0f) / 50.0f;
+        xr[5] = fminf(de, 100.0f) / 10.0f;
+        xr[6] = f.blk_t / 30.0f;
+        xr[7] = 0.0f;   // brass
+        float *yr = yo + (size_t)i * 3;
+        yr[0] = yr[1] = yr[2] = 0.0f;
+        if (open) {
+            to[i] = -1.0f;
+            continue;
+        }
+        Acc acc;
+#pragma unroll
+        for (int k = 0; k < NLEDGER; ++k) acc.led[k] = 0;
+        const int ex = block_transport(v, acc, 1.0f, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, f.blk_t);
+        if (ex != EX_DOWN) {
+            to[i] = 0.0f;
+            continue;
+        }
+        to[i] = 1.0f;
+        const float Eo = v.E + v.Elo;
+        const float c = fminf(fmaxf(u0 * v.dx + w0 * v.dy + z0 * v.dz, -1.0f), 1.0f);
+        const float tx = f.blk_t / z0;
+        const float xs = fmaf(tx, u0, x0), ys = fmaf(tx, w0, y0);
+        yr[0] = ((E0 - Eo) / E0 - 0.5f) / 0.25f;
+        yr[1] = acosf(c) / 0.05f;
+        yr[2] = sqrtf((v.px - xs) * (v.px - xs) + (v.py - ys) * (v.py - ys)) / 2.0f;
+    }
+}
+
+// network inputs of deferred VPs (same encoding as the training data)
+__global__ void sur_features_kernel(const DeferRec *rec, int n, float thick, __bf16 *x) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const DeferRec r = rec[i];
+        __bf16 *xr = x + (size_t)i * 8;
+        xr[0] = (__bf16)(r.x / 20.0f);
+        xr[1] = (__bf16)(r.y / 20.0f);
+        xr[2] = (__bf16)(r.u / 0.05f);
+        xr[3] = (__bf16)(r.v / 0.05f);
+        xr[4] = (__bf16)((r.E + r.Elo - 150.0f) / 50.0f);
+        xr[5] = (__bf16)(fminf(r.d_edge, 100.0f) / 10.0f);
+        xr[6] = (__bf16)(thick / 30.0f);
+        xr[7] = (__bf16)0.0f;
+    }
+}
+
+// Resume deferred VPs: where the network is confident the traversal is
+// sampled from it (transmission, then one mixture component and its
+// outgoing energy loss, angle and offset; azimuth uniform, shared by angle
+// and offset); otherwise the plain brass transport runs.  Then the patient.
+__global__ __launch_bounds__(256) void sur_resume_kernel(GeomDev g, FieldDev f, LaunchDev L, const DeferRec *rec,
+                                                         const float *out, unsigned long long n, float p_lo,
+                                                         float p_hi) {
+    __shared__ float tab[TAB_FLOATS];
+    __shared__ float2 poly[POLY_LDS];
+    for (int i = threadIdx.x; i < TAB_FLOATS / 4; i += blockDim.x)
+        reinterpret_cast<float4 *>(tab)[i] = reinterpret_cast<const float4 *>(L.tables)[i];
+    for (int i = threadIdx.x; i < f.nv; i += blockDim.x) poly[i] = f.poly[i];
+    __syncthreads();
+    Acc acc;
+#pragma unroll
+    for (int j = 0; j < NLEDGER; ++j) acc.led[j] = 0;
+    acc.steps = acc.hist = 0;
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const DeferRec r = rec[i];
+        const SpotDev sp = L.spots[r.spot];
+        const float scale = sp.scale;
+        Lane v;
+        v.k0 = L.key0;
+        v.k1 = L.key1;
+        v.spot = r.spot;
+        v.hist = r.hist;
+        v.nblk = r.nblk;
+        v.nsteps = 0;
+        v.physics = L.physics;
+        v.px = r.x;
+        v.py = r.y;
+        v.pz = f.blk_zu;
+        v.pzlo = r.pzlo;
+        v.dx = r.u;
+        v.dy = r.v;
+        v.dz = r.w;
+        v.E = r.E;
+        v.Elo = r.Elo;
+        const float *o = out + i * 29;
+        const float ptrans = 1.0f / (1.0f + __expf(-o[0]));
+        float tmin = 0.0f;
+        bool go = true;
+        if (!(ptrans < p_lo || ptrans > p_hi)) {
+            // uncertain: the plain transport crosses the block from the
+            // unchanged entry state
+            go = block_transport(v, acc, scale, tab, poly, f.nv, f.blk_rho, f.blk_zu, f.blk_zd, f.blk_t) == EX_DOWN;
+        } else {
+            v.E += v.Elo;
+            v.Elo = 0.0f;
+            const uint4 w = draw(v);
+            if (!(unit_open(w.x) < ptrans)) {
+                ledger_add(acc, L_BLOCK, v.E, scale);   // stopped in brass
+                go = false;
+            } else {
+                // mixture component from the softmax of the weight logits
+                float mw = o[1];
+                for (int c = 1; c < 4; ++c) mw = fmaxf(mw, o[1 + c]);
+                float pc[4], tot = 0.0f;
+                for (int c = 0; c < 4; ++c) { pc[c] = __expf(o[1 + c] - mw); tot += pc[c]; }
+                const float uc = unit_open(w.y) * tot;
+                int c = 0;
+                float acc_p = pc[0];
+                while (c < 3 && uc > acc_p) { ++c; acc_p += pc[c]; }
+                const uint4 w2 = draw(v);
+                float z0, z1, z2, z3;
+                box_muller_fast(w2.x, w2.y, z0, z1);
+                box_muller_fast(w2.z, w2.w, z2, z3);
+                const float y0 = o[5 + 3 * c + 0] + __expf(o[17 + 3 * c + 0]) * z0;
+                const float y1 = o[5 + 3 * c + 1] + __expf(o[17 + 3 * c + 1]) * z1;
+                const float y2 = o[5 + 3 * c + 2] + __expf(o[17 + 3 * c + 2]) * z2;
+                const float frac = fminf(fmaxf(0.5f + 0.25f * y0, 0.0f), 1.0f);
+                const float theta = fmaxf(y1, 0.0f) * 0.05f;
+                const float off = fmaxf(y2, 0.0f) * 2.0f;
+                const float phi = unit_open(w.z);   // turns
+                const float cph = __builtin_amdgcn_cosf(phi), sph = __builtin_amdgcn_sinf(phi);
+                const float Eout = v.E * (1.0f - frac);
+                ledger_add(acc, L_BLOCK, v.E - Eout, scale);
+                const float tx = f.blk_t / v.dz;
+                v.px = fmaf(tx, v.dx, v.px) + off * cph;
+                v.py = fmaf(tx, v.dy, v.py) + off * sph;
+                rotate_dir(v, theta * cph, theta * sph);
+                v.pz = f.blk_zd;
+                v.E = Eout;
+                if (!(v.dz > 0.0f) || Eout <= kELo) {
+                    ledger_add(acc, (v.dz > 0.0f) ? L_BLOCK : L_ESCAPED, Eout, scale);
+                    go = false;
+                }
+            }
+        }
+        if (go) patient(v, acc, scale, tab, g, f, L.shift, L.range_scale, DenseSink{L.tally}, tmin);
+        acc.steps += v.nsteps;
+    }
+#pragma unroll
+    for (int j = 0; j < NLEDGER; ++j) {
+        long long x = acc.led[j];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if ((threadIdx.x & 63) == 0 && x != 0) atomicAdd(L.ledger + j, (unsigned long long)x);
+    }
+    unsigned long long st = acc.steps;
+    for (int o = 32; o > 0; o >>= 1) st += __shfl_xor(st, o, 64);
+    if ((threadIdx.x & 63) == 0 && st != 0) atomicAdd(L.stats + 0, st);
+}
+
 // ------------------------------------------------------------ batches, dose
 // fold one batch: total += q_b, sum of squares += q_b^2 (FP64), clear q_b
 __global__ void fold_batch_kernel(unsigned long long *qb, long long *qt, double *s2, size_t n) {
@@ -935,6 +1175,27 @@ hipError_t launch_csr_values(const int32_t *col, const long long *qv, size_t n, 
                              double mev_scale, float *val, hipStream_t s) {
     const int blocks = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
     if (blocks > 0) hipLaunchKernelGGL(csr_values_kernel, dim3(blocks), dim3(256), 0, s, col, qv, n, g, mev_scale, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_features(const DeferRec *rec, int n, float thick, __bf16 *x, hipStream_t s) {
+    const int blocks = std::max(1, std::min((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(sur_features_kernel, dim3(blocks), dim3(256), 0, s, rec, n, thick, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_resume(const GeomDev &g, const FieldDev &f, const LaunchDev &L, const DeferRec *rec,
+                             const float *out, unsigned long long n, float p_lo, float p_hi, hipStream_t s) {
+    const int blocks = (int)std::max<unsigned long long>(1, std::min<unsigned long long>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(sur_resume_kernel, dim3(blocks), dim3(256), 0, s, g, f, L, rec, out, n, p_lo, p_hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_surrogate_sample(const FieldDev &f, const float *entries, int n, uint32_t key0, uint32_t key1,
+                                   unsigned physics, const float *tables, float *x, float *y, float *t, hipStream_t s) {
+    const int blocks = std::max(1, std::min((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(surrogate_sample_kernel, dim3(blocks), dim3(256), 0, s, f, entries, n, key0, key1, physics,
+                       tables, x, y, t);
     return hipGetLastError();
 }
 

@@ -28,6 +28,7 @@ GEOM_WATER, GEOM_HU = 0, 1
 OUT_DOSE, OUT_CSR = 0, 1
 DEVICE_PTRS = 1
 GRAPH = 2
+SURROGATE = 4
 NLEDGER = 6
 
 
@@ -70,7 +71,7 @@ class vpmc_opts(C.Structure):
 
 class vpmc_stats(C.Structure):
     _fields_ = [("transport_ms", C.c_double), ("total_ms", C.c_double), ("histories", C.c_uint64),
-                ("steps", C.c_uint64), ("launches", C.c_uint64)]
+                ("steps", C.c_uint64), ("launches", C.c_uint64), ("deferred", C.c_uint64)]
 
 
 assert C.sizeof(vpmc_spot) == 28
@@ -100,6 +101,14 @@ def load() -> C.CDLL:
         "vpmc_last_stats": (i, [vp, vp]),
         "vpmc_run_batched": (i, [vp, vp, vp, vp, i, vp, i, vp, vp, vp, vp]),
         "vpmc_autotune": (i, [vp, i, vp, i, vp, vp, C.c_uint64, vp]),
+        "vpmc_surrogate_param_count": (i, []),
+        "vpmc_surrogate_sample": (i, [vp, i, vp, i, C.c_uint64, u, vp, vp, vp]),
+        "vpmc_surrogate_set_weights": (i, [vp, vp, i]),
+        "vpmc_surrogate_config": (i, [vp, C.c_float, C.c_float, C.c_float]),
+        "vpmc_surrogate_get_weights": (i, [vp, vp, i]),
+        "vpmc_surrogate_forward": (i, [vp, vp, i, vp]),
+        "vpmc_surrogate_loss_grad": (i, [vp, vp, vp, vp, i, vp, C.POINTER(C.c_double)]),
+        "vpmc_surrogate_train": (i, [vp, vp, vp, vp, i, i, i, C.c_float, C.c_uint64, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -270,6 +279,77 @@ def vpmc_last_stats(ctx) -> dict:
     return {f: getattr(st, f) for f, _ in vpmc_stats._fields_}
 
 
+def _f32(a):
+    return np.ascontiguousarray(a, np.float32)
+
+
+def vpmc_surrogate_param_count() -> int:
+    return load().vpmc_surrogate_param_count()
+
+
+def vpmc_surrogate_set_weights(ctx, params) -> None:
+    p = _f32(params)
+    _check(load().vpmc_surrogate_set_weights(ctx, _ptr(p), p.size), ctx)
+
+
+SURROGATE_DIMS = (8, 256, 256, 256, 256, 29)
+
+
+def surrogate_init(seed: int = 0) -> np.ndarray:
+    """Initial surrogate parameters: He-uniform weights (the output layer
+    scaled by 0.1), zero biases; layer by layer W[out][in] then b[out]."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for li, (ni, no) in enumerate(zip(SURROGATE_DIMS[:-1], SURROGATE_DIMS[1:])):
+        lim = np.sqrt(6.0 / ni) * (0.1 if li == len(SURROGATE_DIMS) - 2 else 1.0)
+        parts += [rng.uniform(-lim, lim, size=no * ni), np.zeros(no)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def vpmc_surrogate_config(ctx, d_fallback_mm: float = 3.0, p_lo: float = 0.02, p_hi: float = 0.98) -> None:
+    _check(load().vpmc_surrogate_config(ctx, float(d_fallback_mm), float(p_lo), float(p_hi)), ctx)
+
+
+def vpmc_surrogate_get_weights(ctx) -> np.ndarray:
+    p = np.zeros(vpmc_surrogate_param_count(), np.float32)
+    _check(load().vpmc_surrogate_get_weights(ctx, _ptr(p), p.size), ctx)
+    return p
+
+
+def vpmc_surrogate_sample(ctx, field_id: int, entries, seed: int = 0, physics: int = PHYS_ALL):
+    """Plain brass traversals -> (x [n,8], y [n,3], trans [n])."""
+    e = _f32(entries)
+    n = e.shape[0]
+    x = np.zeros((n, 8), np.float32)
+    y = np.zeros((n, 3), np.float32)
+    t = np.zeros(n, np.float32)
+    _check(load().vpmc_surrogate_sample(ctx, field_id, _ptr(e), n, seed, physics, _ptr(x), _ptr(y), _ptr(t)), ctx)
+    return x, y, t
+
+
+def vpmc_surrogate_forward(ctx, x) -> np.ndarray:
+    x = _f32(x)
+    out = np.zeros((x.shape[0], 29), np.float32)
+    _check(load().vpmc_surrogate_forward(ctx, _ptr(x), x.shape[0], _ptr(out)), ctx)
+    return out
+
+
+def vpmc_surrogate_loss_grad(ctx, x, y, trans):
+    x, y, t = _f32(x), _f32(y), _f32(trans)
+    g = np.zeros(vpmc_surrogate_param_count(), np.float32)
+    loss = C.c_double(0.0)
+    _check(load().vpmc_surrogate_loss_grad(ctx, _ptr(x), _ptr(y), _ptr(t), x.shape[0], _ptr(g), C.byref(loss)), ctx)
+    return loss.value, g
+
+
+def vpmc_surrogate_train(ctx, x, y, trans, epochs: int, batch: int, lr: float, seed: int = 0) -> np.ndarray:
+    x, y, t = _f32(x), _f32(y), _f32(trans)
+    losses = np.zeros(epochs, np.float32)
+    _check(load().vpmc_surrogate_train(ctx, _ptr(x), _ptr(y), _ptr(t), x.shape[0], epochs, batch, float(lr), seed,
+                                       _ptr(losses)), ctx)
+    return losses
+
+
 # --------------------------------------------------------------- convenience
 class Engine:
     """Owns one context on one GPU and runs Case objects through the C ABI,
@@ -305,10 +385,11 @@ class Engine:
 
     def run_dose(self, case: I.Case, field_index: int = 0, scenarios=None, n_batches: Optional[int] = None,
                  sigma: bool = True, physics: Optional[int] = None, seed: Optional[int] = None,
-                 fixed_point_bits: int = 0, grid_blocks: int = 0):
+                 fixed_point_bits: int = 0, grid_blocks: int = 0, surrogate: bool = False):
         """Dense dose of one field for the given scenario list.  Returns
         (dose[n_scen, nz, ny, nx], sigma or None, ledger_mev[n_scen, 6]) with
-        dose/sigma as torch float32 tensors on the GPU."""
+        dose/sigma as torch float32 tensors on the GPU.  surrogate: deep
+        brass entries cross the block by the learned surrogate."""
         torch = self.torch
         scen = case.scenarios if scenarios is None else scenarios
         B = case.n_batches if n_batches is None else n_batches
@@ -321,18 +402,22 @@ class Engine:
         opts = make_opts(seed=case.seed if seed is None else seed,
                          physics=case.physics if physics is None else physics,
                          n_batches=B if (sigma and B >= 2) else 0, fixed_point_bits=fixed_point_bits,
-                         flags=DEVICE_PTRS, stream=self.stream_ptr(), grid_blocks=grid_blocks)
+                         flags=DEVICE_PTRS | (SURROGATE if surrogate else 0), stream=self.stream_ptr(),
+                         grid_blocks=grid_blocks)
         vpmc_run_spots(self.ctx, field_index, spot_array(spots), len(spots), scenario_array(scen), len(scen),
                        opts, dose, sig, led)
         return dose, sig, led
 
     def run_csr(self, case: I.Case, scenarios=None, fixed_point_bits: int = 0, physics: Optional[int] = None,
                 seed: Optional[int] = None, hist_per_lane: int = 0, max_slots: int = 0, grid_blocks: int = 0,
-                graph: bool = False, fields=None, dose: bool = False, copy: bool = True):
+                graph: bool = False, fields=None, dose: bool = False, copy: bool = True,
+                device_out: bool = False, block_threads: int = 0):
         """Influence matrices of all fields x scenarios in one batched pass.
         Rows are ordered (scenario, field, spot).  Returns (row_ptr, col, val,
         q, k) as numpy arrays (col/val/q None when copy is False), plus the
-        plan dose per scenario as a torch tensor when dose is True."""
+        plan dose per scenario as a torch tensor when dose is True.  With
+        device_out, row_ptr, col (int32) and val (FP32 Gy) stay on the GPU as
+        torch tensors and q is None."""
         torch = self.torch
         self.load_case(case)
         scen = case.scenarios if scenarios is None else scenarios
@@ -349,7 +434,22 @@ class Engine:
         opts = make_opts(seed=case.seed if seed is None else seed,
                          physics=case.physics if physics is None else physics, output=OUT_CSR,
                          fixed_point_bits=fixed_point_bits, flags=flags, stream=self.stream_ptr(),
-                         hist_per_lane=hist_per_lane, max_slots=max_slots, grid_blocks=grid_blocks)
+                         hist_per_lane=hist_per_lane, max_slots=max_slots, grid_blocks=grid_blocks,
+                         block_threads=block_threads)
+        if device_out:
+            opts.flags |= DEVICE_PTRS
+            dev = torch.device("cuda", self.device)
+            rp_dev = torch.empty(n_rows + 1, dtype=torch.int64, device=dev)
+            vpmc_run_batched(self.ctx, fids, arrays, scenario_array(scen), len(scen), opts, d, led, rp_dev)
+            nnz = int(rp_dev[-1].item())
+            colt = torch.empty(nnz, dtype=torch.int32, device=dev)
+            valt = torch.empty(nnz, dtype=torch.float32, device=dev)
+            vpmc_copy_csr(self.ctx, colt, valt, None)
+            self.last_ledger = led
+            k = vpmc_last_tally_k(self.ctx)
+            if dose:
+                return rp_dev, colt, valt, None, k, d
+            return rp_dev, colt, valt, None, k
         if dose:
             # device dose needs device pointers for every output
             opts.flags |= DEVICE_PTRS
@@ -378,6 +478,21 @@ class Engine:
         if dose:
             return row_ptr, col, val, q, k, d
         return row_ptr, col, val, q, k
+
+    def train_surrogate(self, case: I.Case, field_index: int = 0, n: int = 2_000_000, epochs: int = 6,
+                        batch: int = 4096, lr: float = 1e-3, seed: int = 0):
+        """Train the aperture surrogate on the GPU: n entry states near the
+        field's polygon edges (energies 71-229 MeV) cross its block with the
+        plain transport, then Adam over the brass entries.  Returns the mean
+        loss per epoch."""
+        self.load_case(case)
+        f = case.fields[field_index]
+        xy, ang, e = I.surrogate_training_entries(n, seed=seed, polygon=f.polygon)
+        ent = np.column_stack([xy, ang, e]).astype(np.float32)
+        x, y, t = vpmc_surrogate_sample(self.ctx, field_index, ent, seed=seed + 1)
+        keep = t >= 0
+        vpmc_surrogate_set_weights(self.ctx, surrogate_init(seed))
+        return vpmc_surrogate_train(self.ctx, x[keep], y[keep], t[keep], epochs, batch, lr, seed)
 
     def last_tally(self, scen_index: int = 0):
         torch = self.torch

@@ -111,3 +111,15 @@ def test_run_validation_before_device(vctx):
     assert L.vpmc_create(None, 0) == V.E_ARG
     k = C.c_int()
     assert L.vpmc_create(C.byref(C.c_void_p()), -5) == V.E_ARG
+
+
+def test_surrogate_config_validation(vctx):
+    assert _rc(V.vpmc_surrogate_config, vctx, 3.0, 0.02, 0.98) == 0
+    assert _rc(V.vpmc_surrogate_config, vctx, 0.0, 0.0, 1.0) == 0
+    assert _rc(V.vpmc_surrogate_config, vctx, -1.0, 0.02, 0.98) == V.E_ARG
+    assert _rc(V.vpmc_surrogate_config, vctx, float("nan"), 0.02, 0.98) == V.E_ARG
+    assert _rc(V.vpmc_surrogate_config, vctx, 3.0, 0.5, 0.4) == V.E_ARG
+    assert _rc(V.vpmc_surrogate_config, vctx, 3.0, -0.1, 0.5) == V.E_ARG
+    assert _rc(V.vpmc_surrogate_config, vctx, 3.0, 0.1, 1.5) == V.E_ARG
+    # forward/sample need a device and weights
+    assert _rc(V.vpmc_surrogate_forward, vctx, np.zeros((4, 8), np.float32)) == V.E_STATE

@@ -62,11 +62,24 @@ def source_xy_fp64(orc, case, spot_index, n):
     return xs, ys
 
 
-def ambiguous_mask(orc, case, tol=1e-4, edge_radius=None):
+def edge_distance(poly, x, y):
+    """Distance (mm) of BEV points (x, y) to the nearest polygon edge."""
+    a = np.asarray(poly, np.float64)
+    b = np.roll(a, -1, axis=0)
+    d = np.full(x.shape, np.inf)
+    for (ax_, ay_), (bx_, by_) in zip(a, b):
+        ex, ey = bx_ - ax_, by_ - ay_
+        t = np.clip(((x - ax_) * ex + (y - ay_) * ey) / (ex * ex + ey * ey), 0.0, 1.0)
+        d = np.minimum(d, np.hypot(x - ax_ - t * ex, y - ay_ - t * ey))
+    return d
+
+
+def ambiguous_mask(orc, case, tol=1e-4):
     """Voxels an FP32/FP64 rounding difference of the source position could
     change: the whole track line of every history that starts within tol of a
-    lateral voxel boundary (or within 2e-3 mm of the aperture edge), and the
-    neighbouring lines.  Beams must be axis-aligned."""
+    lateral voxel boundary (or within 2e-3 mm of an aperture polygon edge or
+    the range-shifter rim), and the neighbouring lines.  Beams must be
+    axis-aligned."""
     g = case.geometry
     f = case.fields[0]
     nx, ny, nz = g.shape
@@ -84,8 +97,8 @@ def ambiguous_mask(orc, case, tol=1e-4, edge_radius=None):
         for k in lat:
             bad |= np.abs(fr[:, k] - np.rint(fr[:, k])) * g.spacing[k] < tol
         r = np.hypot(x, y)
-        if edge_radius is not None:
-            bad |= np.abs(r - edge_radius) < 2e-3
+        if f.polygon is not None:
+            bad |= edge_distance(f.polygon, x, y) < 2e-3
         if f.rs is not None:
             bad |= np.abs(r - 0.5 * f.rs.diameter_mm) < 2e-3
         for h in np.nonzero(bad)[0]:
@@ -147,7 +160,7 @@ def test_straight_parity_water_aperture(eng, orc, opening, rs):
     say(f"case config2-small straight opening={opening} rs={rs} spots={len(c.fields[0].spots)}")
     qg, kg, _, _, lg = gpu_q(eng, c)
     qo, lo, ko = orc.run_tally(c)
-    assert_straight_parity(qg, kg, qo, ko, ambiguous_mask(orc, c, edge_radius=opening / 2))
+    assert_straight_parity(qg, kg, qo, ko, ambiguous_mask(orc, c))
     e_or = lo * 2.0 ** -ko
     np.testing.assert_allclose(lg[1:3], e_or[1:3], rtol=1e-5, atol=1e-9 * e_or.sum())
 
@@ -160,8 +173,7 @@ def test_straight_parity_head_ct(eng, orc):
     say(f"case head straight spots={len(f.spots)}")
     qg, kg, _, _, _ = gpu_q(eng, c)
     qo, _, ko = orc.run_tally(c)
-    r_edge = float(np.hypot(*f.polygon[0]))
-    assert_straight_parity(qg, kg, qo, ko, ambiguous_mask(orc, c, edge_radius=r_edge))
+    assert_straight_parity(qg, kg, qo, ko, ambiguous_mask(orc, c))
 
 
 # ------------------------------------------------------------- determinism
