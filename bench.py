@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-scale", action="store_true",
                     help="keep --histories-per-spot as given (skip the scaling to 0.5 %% uncertainty)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate comparison")
+    ap.add_argument("--sur-samples", type=int, default=3_000_000)
+    ap.add_argument("--sur-epochs", type=int, default=6)
     ap.add_argument("--shape", default="", help="HPL,BLOCKS,THREADS: fixed work-queue launch shape (no autotune)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="before the workload, run three plain 256 MiB device copies (HBM counter calibration)")
@@ -70,8 +73,9 @@ def copy_calibration():
     del a, b
 
 
-def plan_uncertainty(eng, case, I, V, np):
-    """U of the nominal uniform-weight plan dose (all fields, 16 batches)."""
+def plan_dose(eng, case, I, seed=None, surrogate=False):
+    """Nominal uniform-weight plan dose of all fields and its batch standard
+    error (16 batches), as FP64 torch tensors on the GPU."""
     import torch
     nom = I.Case("nominal", case.geometry, case.fields, [I.Scenario()], seed=case.seed, physics=case.physics,
                  n_batches=16)
@@ -79,14 +83,64 @@ def plan_uncertainty(eng, case, I, V, np):
     total = None
     var = None
     for fi in range(len(nom.fields)):
-        d, s, _ = eng.run_dose(nom, fi, n_batches=16, sigma=True)
+        d, s, _ = eng.run_dose(nom, fi, n_batches=16, sigma=True, seed=seed, surrogate=surrogate)
         d = d[0].double()
         s = s[0].double()
         total = d if total is None else total + d
         var = s * s if var is None else var + s * s
-    sig = torch.sqrt(var)
+    return total, torch.sqrt(var)
+
+
+def plan_uncertainty(eng, case, I, V, np):
+    """U of the nominal uniform-weight plan dose (all fields, 16 batches):
+    mean sigma/D over voxels >= 50 % of the maximum."""
+    total, sig = plan_dose(eng, case, I)
     m = total >= 0.5 * total.max()
     return float((sig[m] / total[m]).mean())
+
+
+def surrogate_comparison(eng, case, I, V, np, a, shape, plain_s, plain_steps):
+    """The learned aperture surrogate on the same influence matrices: train
+    it on the GPU (plain brass traversals near the three apertures' edges),
+    time one 13-scenario IM with it, and compare the nominal plan dose with
+    and without it (independent seeds): fraction of voxels >= 10 % of the
+    maximum within 3 combined standard errors, gamma 1 %/1 mm (global, 10 %
+    threshold), high-dose mean ratio."""
+    import torch
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gamma import gamma_pass_rate
+    t0 = time.perf_counter()
+    losses = eng.train_surrogate(case, n=a.sur_samples, epochs=a.sur_epochs, seed=3,
+                                 fields=range(len(case.fields)))
+    train_s = time.perf_counter() - t0
+    progress(f"surrogate trained in {train_s:.1f} s, losses {[round(float(x), 4) for x in losses]}")
+    V.vpmc_surrogate_config(eng.ctx)
+    eng.load_case(case)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, col, val, _, _ = eng.run_csr(case, device_out=True, surrogate=True, **shape)
+    st = V.vpmc_last_stats(eng.ctx)
+    del col, val
+    torch.cuda.synchronize()
+    sur_s = time.perf_counter() - t0
+    progress(f"IM with surrogate: {sur_s:.2f} s (plain {plain_s:.2f} s), deferred {st['deferred']}")
+    dp, sp = plan_dose(eng, case, I, seed=case.seed + 101)
+    ds, ss = plan_dose(eng, case, I, seed=case.seed + 202, surrogate=True)
+    dp, sp, ds, ss = (t.cpu().numpy() for t in (dp, sp, ds, ss))
+    m = dp >= 0.1 * dp.max()
+    frac = float(np.mean(np.abs(ds - dp)[m] <= 3.0 * np.sqrt(sp ** 2 + ss ** 2)[m]))
+    hi = dp >= 0.5 * dp.max()
+    ratio = float(ds[hi].mean() / dp[hi].mean())
+    # gamma on the bounding box of the 10 % region (+2 voxels)
+    idx = np.nonzero(m)
+    box = tuple(slice(max(0, int(i.min()) - 2), int(i.max()) + 3) for i in idx)
+    rate = gamma_pass_rate(dp[box], ds[box], case.geometry.spacing, 0.01, 1.0)
+    progress(f"surrogate vs plain: 3-sigma {frac:.4f}, gamma 1%/1mm {rate:.4f}, mean ratio {ratio:.5f}")
+    return {"s_per_13_scenario_im": sur_s, "speedup_vs_plain": plain_s / sur_s,
+            "deferred_fraction": st["deferred"] / max(1, st["histories"]), "training_s": train_s,
+            "training_traversals": a.sur_samples, "epochs": a.sur_epochs,
+            "plan_dose_3sigma_fraction": frac, "plan_dose_gamma_1pct_1mm": rate, "plan_dose_mean_ratio": ratio,
+            "steps_ratio": st["steps"] / max(1, plain_steps)}
 
 
 def cpu_baseline(case, seconds, np):
@@ -138,7 +192,6 @@ def main():
     progress("building the synthetic head case ...")
     H = a.histories_per_spot
     case = I.config4(a.target_cc, int(H))
-    base_nh = case.fields[0].spots["n_histories"].copy()
     eng = V.Engine(0)
     eng.load_case(case)
 
@@ -231,6 +284,9 @@ def main():
                          "EPYC 7543 + 4x A100",
         "device": torch.cuda.get_device_name(0),
     }
+    if not a.no_surrogate:
+        out["surrogate"] = surrogate_comparison(eng, case, I, V, np, a, shape, dt / a.steps,
+                                                steps_total / a.steps)
     if not a.no_cpu_baseline:
         progress("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(case, a.cpu_seconds, np)

@@ -59,8 +59,9 @@ extern "C" {
 
 #define VPMC_DEVICE_PTRS 1u /* pointers are device pointers; work on opts.hip_stream */
 #define VPMC_GRAPH 2u       /* CSR: capture all epochs of the run in one hipGraph */
-#define VPMC_SURROGATE 4u   /* dense: VPs entering the brass far from the opening's edge
-                               cross it by the learned surrogate (weights must be set) */
+#define VPMC_SURROGATE 4u   /* VPs entering the brass far from the opening's edge cross it
+                               by the learned surrogate (weights must be set; dense and
+                               eager CSR runs, not with VPMC_GRAPH) */
 
 #define VPMC_MAX_FIELDS 64
 #define VPMC_MAX_VERTICES 1024
@@ -223,7 +224,7 @@ int vpmc_surrogate_sample(vpmc_ctx *ctx, int field_id, const float *entries, int
                           unsigned physics, float *x, float *y, float *trans);
 int vpmc_surrogate_set_weights(vpmc_ctx *ctx, const float *params, int n_params);
 int vpmc_surrogate_get_weights(vpmc_ctx *ctx, float *params, int n_params);
-/* Use of the network in dense runs with VPMC_SURROGATE (Methods B; the
+/* Use of the network in runs with VPMC_SURROGATE (Methods B; the
  * paper's block model is the plain transport, the network is this library's
  * replacement for the deep brass part of it).  A VP whose block entry point
  * lies in the brass at least d_fallback_mm from the opening's polygon is

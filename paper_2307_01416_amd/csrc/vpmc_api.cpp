@@ -92,6 +92,8 @@ struct vpmc_ctx {
 
 namespace {
 
+int mlp_buffers(vpmc_ctx *c, int cap, MlpBuffers *b);
+
 int ensure(vpmc_ctx *c, DevBuf &b, size_t bytes, size_t cap_limit) {
     if (bytes <= b.cap) return VPMC_OK;
     const size_t grow = bytes - b.cap;
@@ -377,7 +379,31 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     c->csr_valid = false;
     c->slots_dirty = true;   // cleared again when every epoch has been compacted
 
+    // surrogate queue: sized for the largest epoch (VPs beyond it cross the
+    // block with the plain transport)
+    const bool sur_on = (o->flags & VPMC_SURROGATE) != 0;
+    unsigned long long sur_cap = 0, deferred = 0;
+    MlpBuffers mb{};
+    if (sur_on) {
+        for (int e = 0; e < E; ++e) {
+            unsigned long long h = 0;
+            for (int r = e * G; r < std::min(R, (e + 1) * G); ++r) h += rows[r].n_hist;
+            sur_cap = std::max(sur_cap, h);
+        }
+        sur_cap = std::max(1ull, std::min(sur_cap, kSurMaxRecords));
+        if ((rc = ensure(c, c->sur_rec, sur_cap * sizeof(DeferRec), cap))) return rc;
+        if ((rc = ensure(c, c->sur_cnt, sizeof(unsigned long long), cap))) return rc;
+        if ((rc = mlp_buffers(c, MLP_MAX_BATCH, &mb))) return rc;
+    }
+
     QueueDev Q{};
+    if (sur_on) {
+        Q.sur.enabled = 1;
+        Q.sur.d_fallback = c->sur_dfb;
+        Q.sur.count = (unsigned long long *)c->sur_cnt.ptr;
+        Q.sur.capacity = sur_cap;
+        Q.sur.rec = (DeferRec *)c->sur_rec.ptr;
+    }
     Q.rows = (const RowDev *)c->rows.ptr;
     Q.hist_per_lane = hpl;
     Q.fields = (const FieldDev *)c->fields_tab.ptr;
@@ -433,7 +459,7 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     double transport_ms = 0.0;
     unsigned long long used_host = 0;
     bool done = false;
-    if (o->flags & VPMC_GRAPH) {
+    if ((o->flags & VPMC_GRAPH) && !sur_on) {
         // whole run as one graph: rows that do not fit the current CSR
         // capacity raise the overflow flag, and the eager path below reruns
         hipGraph_t graph = nullptr;
@@ -493,8 +519,25 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
         if ((rc = clear_counters())) return rc;
         for (int e = 0; e < E; ++e) {
             const QueueDev Qe = epoch_queue(e);
+            if (sur_on) HIP_TRY(launch_fill_u64((unsigned long long *)c->sur_cnt.ptr, 1, 0ull, st));
             HIP_TRY(hipEventRecord(c->events[2], st));
             if (Qe.n_chunks) HIP_TRY(launch_queue(c->geom, Qe, q_blocks, q_threads, st));
+            if (sur_on && Qe.n_chunks) {
+                // deferred brass entries of this epoch: network, then resume
+                unsigned long long cnt = 0;
+                HIP_TRY(hipMemcpyAsync(&cnt, c->sur_cnt.ptr, sizeof cnt, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                const unsigned long long nq = std::min(cnt, sur_cap);
+                deferred += nq;
+                const DeferRec *rec = (const DeferRec *)c->sur_rec.ptr;
+                for (unsigned long long s0 = 0; s0 < nq; s0 += MLP_MAX_BATCH) {
+                    const int m = (int)std::min<unsigned long long>(MLP_MAX_BATCH, nq - s0);
+                    HIP_TRY(launch_sur_features(rec + s0, m, mb.x, st));
+                    HIP_TRY(mlp_forward(mb, m, st));
+                    HIP_TRY(launch_sur_resume_csr(c->geom, Qe, rec + s0, mb.out, (unsigned long long)m, c->sur_plo,
+                                                  c->sur_phi, st));
+                }
+            }
             HIP_TRY(hipEventRecord(c->events[3], st));
             HIP_TRY(launch_csr_offsets((unsigned int *)c->slot_nnz.ptr, Qe.n_rows, Qe.row_begin,
                                        (unsigned long long *)c->row_off.ptr, (unsigned long long *)c->row_nnz.ptr,
@@ -573,6 +616,7 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     S.steps = stv[0];
     S.histories = stv[1];
     S.launches = (uint64_t)E;
+    S.deferred = deferred;
     c->last_stats = S;
     return VPMC_OK;
 }
@@ -964,7 +1008,7 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
     if (o->flags & ~(VPMC_DEVICE_PTRS | VPMC_GRAPH | VPMC_SURROGATE)) return fail(VPMC_E_ARG, "unknown flags");
     const bool use_sur = (o->flags & VPMC_SURROGATE) != 0;
     if (use_sur) {
-        if (o->output != VPMC_OUT_DOSE) return fail(VPMC_E_ARG, "VPMC_SURROGATE is a dense-mode option");
+        if (o->flags & VPMC_GRAPH) return fail(VPMC_E_ARG, "VPMC_SURROGATE cannot be combined with VPMC_GRAPH");
         if (!c->mlp_ready) return fail(VPMC_E_STATE, "VPMC_SURROGATE needs surrogate weights");
     }
     if (o->output == VPMC_OUT_CSR) {
@@ -1104,7 +1148,7 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
                 const DeferRec *rec = (const DeferRec *)c->sur_rec.ptr;
                 for (unsigned long long s0 = 0; s0 < nq; s0 += MLP_MAX_BATCH) {
                     const int m = (int)std::min<unsigned long long>(MLP_MAX_BATCH, nq - s0);
-                    HIP_TRY(launch_sur_features(rec + s0, m, fd.blk_t, mb.x, st));
+                    HIP_TRY(launch_sur_features(rec + s0, m, mb.x, st));
                     HIP_TRY(mlp_forward(mb, m, st));
                     HIP_TRY(launch_sur_resume(c->geom, fd, L, rec + s0, mb.out, (unsigned long long)m, c->sur_plo,
                                               c->sur_phi, st));
@@ -1182,7 +1226,10 @@ int vpmc_run_batched(vpmc_ctx *c, const int *field_ids, const vpmc_spot *const *
     }
     if ((rc = validate_scen(scen, n_scen))) return rc;
     if (o->physics & ~VPMC_PHYS_ALL) return fail(VPMC_E_ARG, "unknown physics bits");
-    if (o->flags & ~(VPMC_DEVICE_PTRS | VPMC_GRAPH)) return fail(VPMC_E_ARG, "unknown flags");
+    if (o->flags & ~(VPMC_DEVICE_PTRS | VPMC_GRAPH | VPMC_SURROGATE)) return fail(VPMC_E_ARG, "unknown flags");
+    if ((o->flags & VPMC_SURROGATE) && (o->flags & VPMC_GRAPH))
+        return fail(VPMC_E_ARG, "VPMC_SURROGATE cannot be combined with VPMC_GRAPH");
+    if ((o->flags & VPMC_SURROGATE) && !c->mlp_ready) return fail(VPMC_E_STATE, "VPMC_SURROGATE needs surrogate weights");
     if (o->hist_per_lane < 0 || o->hist_per_lane > 4096) return fail(VPMC_E_ARG, "hist_per_lane outside [0, 4096]");
     if (o->max_slots < 0 || o->grid_blocks < 0) return fail(VPMC_E_ARG, "negative tuning value");
     if (o->block_threads && o->block_threads != 256 && o->block_threads != 512)

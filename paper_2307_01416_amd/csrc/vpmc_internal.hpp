@@ -74,8 +74,8 @@ struct SpotDev {
 // block's upstream face (E + Elo is the compensated energy, pzlo the low part
 // of the depth), so the plain transport can resume it unchanged
 struct DeferRec {
-    uint32_t spot, hist, nblk, pad;
-    float x, y, u, v, w, E, Elo, pzlo, d_edge, pad2[3];
+    uint32_t spot, hist, nblk, tag;   // tag: the row within the epoch (influence-matrix runs)
+    float x, y, u, v, w, E, Elo, pzlo, d_edge, thick, pad[2];
 };
 static_assert(sizeof(DeferRec) == 64, "DeferRec is 64 bytes");
 
@@ -149,6 +149,7 @@ struct QueueDev {
     unsigned long long *ledger;           // [n_scen][NLEDGER]
     unsigned long long *stats;            // [2]
     const float *tables;
+    SurDev sur;                           // surrogate queue (enabled = 0: off)
 };
 
 hipError_t launch_queue(const GeomDev &g, const QueueDev &Q, int blocks, int threads, hipStream_t s);
@@ -178,9 +179,11 @@ struct MlpBuffers {
     float *loss;         // [n] per-sample loss
 };
 
-hipError_t launch_sur_features(const DeferRec *rec, int n, float thick, __bf16 *x, hipStream_t s);
+hipError_t launch_sur_features(const DeferRec *rec, int n, __bf16 *x, hipStream_t s);
 hipError_t launch_sur_resume(const GeomDev &g, const FieldDev &f, const LaunchDev &L, const DeferRec *rec,
                              const float *out, unsigned long long n, float p_lo, float p_hi, hipStream_t s);
+hipError_t launch_sur_resume_csr(const GeomDev &g, const QueueDev &Q, const DeferRec *rec, const float *out,
+                                 unsigned long long n, float p_lo, float p_hi, hipStream_t s);
 hipError_t launch_surrogate_sample(const FieldDev &f, const float *entries, int n, uint32_t key0, uint32_t key1,
                                    unsigned physics, const float *tables, float *x, float *y, float *t, hipStream_t s);
 int mlp_param_count();

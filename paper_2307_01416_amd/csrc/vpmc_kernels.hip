@@ -440,7 +440,7 @@ __device__ float dist_to_polygon(const float2 *poly, int nv, float x, float y) {
 enum { BL_STOP = 0, BL_PATIENT = 1, BL_DEFER = 2 };
 
 __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const float2 *poly,
-                        const FieldDev &f, float &tmin, const SurDev *sur = nullptr) {
+                        const FieldDev &f, float &tmin, const SurDev *sur = nullptr, uint32_t tag = 0u) {
     tmin = -INFINITY;
     if (f.has_rs) {
         const float t = (f.rs_zu - v.pz) / v.dz;
@@ -480,7 +480,7 @@ __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const 
                     r.spot = v.spot;
                     r.hist = v.hist;
                     r.nblk = v.nblk;
-                    r.pad = 0u;
+                    r.tag = tag;
                     r.x = qx;
                     r.y = qy;
                     r.u = v.dx;
@@ -490,7 +490,8 @@ __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const 
                     r.Elo = v.Elo;
                     r.pzlo = v.pzlo;
                     r.d_edge = de;
-                    r.pad2[0] = r.pad2[1] = r.pad2[2] = 0.0f;
+                    r.thick = f.blk_t;
+                    r.pad[0] = r.pad[1] = 0.0f;
                     sur->rec[slot] = r;
                     return BL_DEFER;
                 }
@@ -760,7 +761,7 @@ __global__ __launch_bounds__(512, 4) void queue_kernel(GeomDev g, QueueDev Q) {
             v.physics = Q.physics;
             source(v, sp);
             float tmin;
-            if (beamline(v, acc, sp.scale, tab, fpoly, f, tmin) == BL_PATIENT)
+            if (beamline(v, acc, sp.scale, tab, fpoly, f, tmin, &Q.sur, (uint32_t)rl) == BL_PATIENT)
                 patient(v, acc, sp.scale, tab, g, f, sc.shift, sc.range_scale, sink, tmin);
             acc.steps += v.nsteps;
             acc.hist += 1;
@@ -974,7 +975,7 @@ __global__ __launch_bounds__(256) void surrogate_sample_kernel(FieldDev f, const
 }
 
 // network inputs of deferred VPs (same encoding as the training data)
-__global__ void sur_features_kernel(const DeferRec *rec, int n, float thick, __bf16 *x) {
+__global__ void sur_features_kernel(const DeferRec *rec, int n, __bf16 *x) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const DeferRec r = rec[i];
         __bf16 *xr = x + (size_t)i * 8;
@@ -984,15 +985,105 @@ __global__ void sur_features_kernel(const DeferRec *rec, int n, float thick, __b
         xr[3] = (__bf16)(r.v / 0.05f);
         xr[4] = (__bf16)((r.E + r.Elo - 150.0f) / 50.0f);
         xr[5] = (__bf16)(fminf(r.d_edge, 100.0f) / 10.0f);
-        xr[6] = (__bf16)(thick / 30.0f);
+        xr[6] = (__bf16)(r.thick / 30.0f);
         xr[7] = (__bf16)0.0f;
     }
 }
 
-// Resume deferred VPs: where the network is confident the traversal is
+// Resume one deferred VP: where the network is confident the traversal is
 // sampled from it (transmission, then one mixture component and its
 // outgoing energy loss, angle and offset; azimuth uniform, shared by angle
-// and offset); otherwise the plain brass transport runs.  Then the patient.
+// and offset); otherwise the plain brass transport runs from the recorded
+// state.  Then the patient.
+template <class Sink>
+__device__ void resume_deferred(Lane &v, Acc &acc, float scale, const float *tab, const float2 *poly,
+                                const FieldDev &f, const float *o, float p_lo, float p_hi, const GeomDev &g,
+                                const float *shift, float range_scale, const Sink &sink) {
+    const float ptrans = 1.0f / (1.0f + __expf(-o[0]));
+    bool go = true;
+    if (!(ptrans < p_lo || ptrans > p_hi)) {
+        go = block_transport(v, acc, scale, tab, poly, f.nv, f.blk_rho, f.blk_zu, f.blk_zd, f.blk_t) == EX_DOWN;
+    } else {
+        v.E += v.Elo;
+        v.Elo = 0.0f;
+        const uint4 w = draw(v);
+        if (!(unit_open(w.x) < ptrans)) {
+            ledger_add(acc, L_BLOCK, v.E, scale);   // stopped in brass
+            go = false;
+        } else {
+            // mixture component from the softmax of the weight logits
+            float mw = o[1];
+            for (int c = 1; c < 4; ++c) mw = fmaxf(mw, o[1 + c]);
+            float pc[4], tot = 0.0f;
+            for (int c = 0; c < 4; ++c) { pc[c] = __expf(o[1 + c] - mw); tot += pc[c]; }
+            const float uc = unit_open(w.y) * tot;
+            int c = 0;
+            float acc_p = pc[0];
+            while (c < 3 && uc > acc_p) { ++c; acc_p += pc[c]; }
+            const uint4 w2 = draw(v);
+            float z0, z1, z2, z3;
+            box_muller_fast(w2.x, w2.y, z0, z1);
+            box_muller_fast(w2.z, w2.w, z2, z3);
+            const float y0 = o[5 + 3 * c + 0] + __expf(o[17 + 3 * c + 0]) * z0;
+            const float y1 = o[5 + 3 * c + 1] + __expf(o[17 + 3 * c + 1]) * z1;
+            const float y2 = o[5 + 3 * c + 2] + __expf(o[17 + 3 * c + 2]) * z2;
+            const float frac = fminf(fmaxf(0.5f + 0.25f * y0, 0.0f), 1.0f);
+            const float theta = fmaxf(y1, 0.0f) * 0.05f;
+            const float off = fmaxf(y2, 0.0f) * 2.0f;
+            const float phi = unit_open(w.z);   // turns
+            const float cph = __builtin_amdgcn_cosf(phi), sph = __builtin_amdgcn_sinf(phi);
+            const float Eout = v.E * (1.0f - frac);
+            ledger_add(acc, L_BLOCK, v.E - Eout, scale);
+            const float tx = f.blk_t / v.dz;
+            v.px = fmaf(tx, v.dx, v.px) + off * cph;
+            v.py = fmaf(tx, v.dy, v.py) + off * sph;
+            rotate_dir(v, theta * cph, theta * sph);
+            v.pz = f.blk_zd;
+            v.E = Eout;
+            if (!(v.dz > 0.0f) || Eout <= kELo) {
+                ledger_add(acc, (v.dz > 0.0f) ? L_BLOCK : L_ESCAPED, Eout, scale);
+                go = false;
+            }
+        }
+    }
+    if (go) patient(v, acc, scale, tab, g, f, shift, range_scale, sink, 0.0f);
+}
+
+__device__ __forceinline__ void lane_from_record(Lane &v, const DeferRec &r, uint32_t k0, uint32_t k1,
+                                                 unsigned physics, float zu) {
+    v.k0 = k0;
+    v.k1 = k1;
+    v.spot = r.spot;
+    v.hist = r.hist;
+    v.nblk = r.nblk;
+    v.nsteps = 0;
+    v.physics = physics;
+    v.px = r.x;
+    v.py = r.y;
+    v.pz = zu;
+    v.pzlo = r.pzlo;
+    v.dx = r.u;
+    v.dy = r.v;
+    v.dz = r.w;
+    v.E = r.E;
+    v.Elo = r.Elo;
+}
+
+__device__ __forceinline__ void flush_ledger_steps(Acc &acc, unsigned long long *ledger, unsigned long long *stats) {
+#pragma unroll
+    for (int j = 0; j < NLEDGER; ++j) {
+        long long x = acc.led[j];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if ((threadIdx.x & 63) == 0 && x != 0) atomicAdd(ledger + j, (unsigned long long)x);
+        acc.led[j] = 0;
+    }
+    unsigned long long st = acc.steps;
+    for (int o = 32; o > 0; o >>= 1) st += __shfl_xor(st, o, 64);
+    if ((threadIdx.x & 63) == 0 && st != 0) atomicAdd(stats + 0, st);
+    acc.steps = 0;
+}
+
+// dense runs: one field, one scenario per launch
 __global__ __launch_bounds__(256) void sur_resume_kernel(GeomDev g, FieldDev f, LaunchDev L, const DeferRec *rec,
                                                          const float *out, unsigned long long n, float p_lo,
                                                          float p_hi) {
@@ -1009,88 +1100,64 @@ __global__ __launch_bounds__(256) void sur_resume_kernel(GeomDev g, FieldDev f, 
     const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
     for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const DeferRec r = rec[i];
-        const SpotDev sp = L.spots[r.spot];
-        const float scale = sp.scale;
         Lane v;
-        v.k0 = L.key0;
-        v.k1 = L.key1;
-        v.spot = r.spot;
-        v.hist = r.hist;
-        v.nblk = r.nblk;
-        v.nsteps = 0;
-        v.physics = L.physics;
-        v.px = r.x;
-        v.py = r.y;
-        v.pz = f.blk_zu;
-        v.pzlo = r.pzlo;
-        v.dx = r.u;
-        v.dy = r.v;
-        v.dz = r.w;
-        v.E = r.E;
-        v.Elo = r.Elo;
-        const float *o = out + i * 29;
-        const float ptrans = 1.0f / (1.0f + __expf(-o[0]));
-        float tmin = 0.0f;
-        bool go = true;
-        if (!(ptrans < p_lo || ptrans > p_hi)) {
-            // uncertain: the plain transport crosses the block from the
-            // unchanged entry state
-            go = block_transport(v, acc, scale, tab, poly, f.nv, f.blk_rho, f.blk_zu, f.blk_zd, f.blk_t) == EX_DOWN;
-        } else {
-            v.E += v.Elo;
-            v.Elo = 0.0f;
-            const uint4 w = draw(v);
-            if (!(unit_open(w.x) < ptrans)) {
-                ledger_add(acc, L_BLOCK, v.E, scale);   // stopped in brass
-                go = false;
-            } else {
-                // mixture component from the softmax of the weight logits
-                float mw = o[1];
-                for (int c = 1; c < 4; ++c) mw = fmaxf(mw, o[1 + c]);
-                float pc[4], tot = 0.0f;
-                for (int c = 0; c < 4; ++c) { pc[c] = __expf(o[1 + c] - mw); tot += pc[c]; }
-                const float uc = unit_open(w.y) * tot;
-                int c = 0;
-                float acc_p = pc[0];
-                while (c < 3 && uc > acc_p) { ++c; acc_p += pc[c]; }
-                const uint4 w2 = draw(v);
-                float z0, z1, z2, z3;
-                box_muller_fast(w2.x, w2.y, z0, z1);
-                box_muller_fast(w2.z, w2.w, z2, z3);
-                const float y0 = o[5 + 3 * c + 0] + __expf(o[17 + 3 * c + 0]) * z0;
-                const float y1 = o[5 + 3 * c + 1] + __expf(o[17 + 3 * c + 1]) * z1;
-                const float y2 = o[5 + 3 * c + 2] + __expf(o[17 + 3 * c + 2]) * z2;
-                const float frac = fminf(fmaxf(0.5f + 0.25f * y0, 0.0f), 1.0f);
-                const float theta = fmaxf(y1, 0.0f) * 0.05f;
-                const float off = fmaxf(y2, 0.0f) * 2.0f;
-                const float phi = unit_open(w.z);   // turns
-                const float cph = __builtin_amdgcn_cosf(phi), sph = __builtin_amdgcn_sinf(phi);
-                const float Eout = v.E * (1.0f - frac);
-                ledger_add(acc, L_BLOCK, v.E - Eout, scale);
-                const float tx = f.blk_t / v.dz;
-                v.px = fmaf(tx, v.dx, v.px) + off * cph;
-                v.py = fmaf(tx, v.dy, v.py) + off * sph;
-                rotate_dir(v, theta * cph, theta * sph);
-                v.pz = f.blk_zd;
-                v.E = Eout;
-                if (!(v.dz > 0.0f) || Eout <= kELo) {
-                    ledger_add(acc, (v.dz > 0.0f) ? L_BLOCK : L_ESCAPED, Eout, scale);
-                    go = false;
-                }
-            }
-        }
-        if (go) patient(v, acc, scale, tab, g, f, L.shift, L.range_scale, DenseSink{L.tally}, tmin);
+        lane_from_record(v, r, L.key0, L.key1, L.physics, f.blk_zu);
+        resume_deferred(v, acc, L.spots[r.spot].scale, tab, poly, f, out + i * MLP_OUT, p_lo, p_hi, g, L.shift,
+                        L.range_scale, DenseSink{L.tally});
         acc.steps += v.nsteps;
     }
+    flush_ledger_steps(acc, L.ledger, L.stats);
+}
+
+// influence-matrix runs: the record's tag is its row within the epoch, which
+// selects the field, spot, scenario and the row's sparse slot
+__global__ __launch_bounds__(256) void sur_resume_csr_kernel(GeomDev g, QueueDev Q, const DeferRec *rec,
+                                                             const float *out, unsigned long long n, float p_lo,
+                                                             float p_hi) {
+    __shared__ float tab[TAB_FLOATS];
+    __shared__ float2 poly[POLY_LDS];
+    for (int i = threadIdx.x; i < TAB_FLOATS / 4; i += blockDim.x)
+        reinterpret_cast<float4 *>(tab)[i] = reinterpret_cast<const float4 *>(Q.tables)[i];
+    for (int i = threadIdx.x; i < Q.n_poly_total; i += blockDim.x) poly[i] = Q.polys[i];
+    __syncthreads();
+    Acc acc;
 #pragma unroll
-    for (int j = 0; j < NLEDGER; ++j) {
-        long long x = acc.led[j];
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-        if ((threadIdx.x & 63) == 0 && x != 0) atomicAdd(L.ledger + j, (unsigned long long)x);
+    for (int j = 0; j < NLEDGER; ++j) acc.led[j] = 0;
+    acc.steps = acc.hist = 0;
+    int cur_scen = -1;   // scenario whose ledger this lane is accumulating
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const DeferRec r = rec[i];
+        const int rl = (int)r.tag;
+        const RowDev row = Q.rows[Q.row_begin + rl];
+        const FieldDev f = Q.fields[row.field];
+        const ScenDev sc = Q.scen[row.scen];
+        const SparseSink sink{Q.grid + (size_t)rl * Q.nvox, Q.l1 + (size_t)rl * Q.n1, Q.l2 + (size_t)rl * Q.n2,
+                              Q.nnz + rl};
+        if (row.scen != cur_scen) {
+            // ledgers are per scenario: this lane's sums so far go out with
+            // plain per-lane atomics (lanes of a wave may differ in scenario)
+            if (cur_scen >= 0)
+                for (int j = 0; j < NLEDGER; ++j)
+                    if (acc.led[j] != 0) {
+                        atomicAdd(Q.ledger + (size_t)cur_scen * NLEDGER + j, (unsigned long long)acc.led[j]);
+                        acc.led[j] = 0;
+                    }
+            cur_scen = row.scen;
+        }
+        Lane v;
+        lane_from_record(v, r, Q.key0, Q.seed_hi ^ row.field_id, Q.physics, f.blk_zu);
+        resume_deferred(v, acc, Q.spots[row.spot_global].scale, tab, poly + Q.poly_off[row.field], f,
+                        out + i * MLP_OUT, p_lo, p_hi, g, sc.shift, sc.range_scale, sink);
+        acc.steps += v.nsteps;
     }
+    if (cur_scen >= 0)
+        for (int j = 0; j < NLEDGER; ++j)
+            if (acc.led[j] != 0) atomicAdd(Q.ledger + (size_t)cur_scen * NLEDGER + j, (unsigned long long)acc.led[j]);
+    // every lane of the wave is back here: the step count reduces per wave
     unsigned long long st = acc.steps;
     for (int o = 32; o > 0; o >>= 1) st += __shfl_xor(st, o, 64);
-    if ((threadIdx.x & 63) == 0 && st != 0) atomicAdd(L.stats + 0, st);
+    if ((threadIdx.x & 63) == 0 && st != 0) atomicAdd(Q.stats + 0, st);
 }
 
 // ------------------------------------------------------------ batches, dose
@@ -1178,9 +1245,9 @@ hipError_t launch_csr_values(const int32_t *col, const long long *qv, size_t n, 
     return hipGetLastError();
 }
 
-hipError_t launch_sur_features(const DeferRec *rec, int n, float thick, __bf16 *x, hipStream_t s) {
+hipError_t launch_sur_features(const DeferRec *rec, int n, __bf16 *x, hipStream_t s) {
     const int blocks = std::max(1, std::min((n + 255) / 256, 4096));
-    hipLaunchKernelGGL(sur_features_kernel, dim3(blocks), dim3(256), 0, s, rec, n, thick, x);
+    hipLaunchKernelGGL(sur_features_kernel, dim3(blocks), dim3(256), 0, s, rec, n, x);
     return hipGetLastError();
 }
 
@@ -1188,6 +1255,13 @@ hipError_t launch_sur_resume(const GeomDev &g, const FieldDev &f, const LaunchDe
                              const float *out, unsigned long long n, float p_lo, float p_hi, hipStream_t s) {
     const int blocks = (int)std::max<unsigned long long>(1, std::min<unsigned long long>((n + 255) / 256, 4096));
     hipLaunchKernelGGL(sur_resume_kernel, dim3(blocks), dim3(256), 0, s, g, f, L, rec, out, n, p_lo, p_hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_resume_csr(const GeomDev &g, const QueueDev &Q, const DeferRec *rec, const float *out,
+                                 unsigned long long n, float p_lo, float p_hi, hipStream_t s) {
+    const int blocks = (int)std::max<unsigned long long>(1, std::min<unsigned long long>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(sur_resume_csr_kernel, dim3(blocks), dim3(256), 0, s, g, Q, rec, out, n, p_lo, p_hi);
     return hipGetLastError();
 }
 

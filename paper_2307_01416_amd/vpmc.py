@@ -411,13 +411,14 @@ class Engine:
     def run_csr(self, case: I.Case, scenarios=None, fixed_point_bits: int = 0, physics: Optional[int] = None,
                 seed: Optional[int] = None, hist_per_lane: int = 0, max_slots: int = 0, grid_blocks: int = 0,
                 graph: bool = False, fields=None, dose: bool = False, copy: bool = True,
-                device_out: bool = False, block_threads: int = 0):
+                device_out: bool = False, block_threads: int = 0, surrogate: bool = False):
         """Influence matrices of all fields x scenarios in one batched pass.
         Rows are ordered (scenario, field, spot).  Returns (row_ptr, col, val,
         q, k) as numpy arrays (col/val/q None when copy is False), plus the
         plan dose per scenario as a torch tensor when dose is True.  With
         device_out, row_ptr, col (int32) and val (FP32 Gy) stay on the GPU as
-        torch tensors and q is None."""
+        torch tensors and q is None.  surrogate: deep brass entries cross the
+        block by the learned surrogate."""
         torch = self.torch
         self.load_case(case)
         scen = case.scenarios if scenarios is None else scenarios
@@ -428,7 +429,7 @@ class Engine:
         led = np.zeros((len(scen), NLEDGER), np.float64)
         nx, ny, nz = case.geometry.shape
         d = None
-        flags = GRAPH if graph else 0
+        flags = (GRAPH if graph else 0) | (SURROGATE if surrogate else 0)
         if dose:
             d = torch.empty((len(scen), nz, ny, nx), dtype=torch.float32, device=torch.device("cuda", self.device))
         opts = make_opts(seed=case.seed if seed is None else seed,
@@ -480,19 +481,24 @@ class Engine:
         return row_ptr, col, val, q, k
 
     def train_surrogate(self, case: I.Case, field_index: int = 0, n: int = 2_000_000, epochs: int = 6,
-                        batch: int = 4096, lr: float = 1e-3, seed: int = 0):
+                        batch: int = 4096, lr: float = 1e-3, seed: int = 0, fields=None):
         """Train the aperture surrogate on the GPU: n entry states near the
-        field's polygon edges (energies 71-229 MeV) cross its block with the
-        plain transport, then Adam over the brass entries.  Returns the mean
-        loss per epoch."""
+        polygon edges of the given fields (default: field_index only;
+        energies 71-229 MeV) cross their block with the plain transport,
+        then Adam over the brass entries.  Returns the mean loss per epoch."""
         self.load_case(case)
-        f = case.fields[field_index]
-        xy, ang, e = I.surrogate_training_entries(n, seed=seed, polygon=f.polygon)
-        ent = np.column_stack([xy, ang, e]).astype(np.float32)
-        x, y, t = vpmc_surrogate_sample(self.ctx, field_index, ent, seed=seed + 1)
-        keep = t >= 0
+        fids = [field_index] if fields is None else list(fields)
+        xs, ys, ts = [], [], []
+        for j, fi in enumerate(fids):
+            m = n // len(fids) + (1 if j < n % len(fids) else 0)
+            xy, ang, e = I.surrogate_training_entries(m, seed=seed + 7919 * j, polygon=case.fields[fi].polygon)
+            ent = np.column_stack([xy, ang, e]).astype(np.float32)
+            x, y, t = vpmc_surrogate_sample(self.ctx, fi, ent, seed=seed + 1 + j)
+            keep = t >= 0
+            xs.append(x[keep]); ys.append(y[keep]); ts.append(t[keep])
         vpmc_surrogate_set_weights(self.ctx, surrogate_init(seed))
-        return vpmc_surrogate_train(self.ctx, x[keep], y[keep], t[keep], epochs, batch, lr, seed)
+        return vpmc_surrogate_train(self.ctx, np.concatenate(xs), np.concatenate(ys), np.concatenate(ts), epochs,
+                                    batch, lr, seed)
 
     def last_tally(self, scen_index: int = 0):
         torch = self.torch

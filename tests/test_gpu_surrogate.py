@@ -227,3 +227,31 @@ def test_trained_surrogate_matches_plain_transport(opening, rs, energy):
     assert frac >= 0.99
     assert abs(ratio - 1.0) <= max(0.005, 3.0 * se)
     assert rate >= 0.99
+
+
+def test_surrogate_uncertain_band_csr_bitwise():
+    """Influence-matrix (work-queue) runs: with the whole probability range
+    uncertain, deferral and resume into the rows' sparse slots give the same
+    rows, values and ledgers as the run without the surrogate."""
+    from paper_2307_01416_amd import inputs as I
+    from paper_2307_01416_amd import vpmc as V
+    c = I.config2(10.0, True, histories_per_case=100_000, shape=(64, 64, 200))
+    c.scenarios = [I.Scenario(), I.Scenario(shift_mm=(3.0, 0.0, 0.0), range_scale=1.035)]
+    eng = V.Engine(0)
+    try:
+        eng.load_case(c)
+        V.vpmc_surrogate_set_weights(eng.ctx, V.surrogate_init(4))
+        V.vpmc_surrogate_config(eng.ctx, 0.0, 0.0, 1.0)
+        say("case config2 10mm RS CSR surrogate identity band")
+        rp0, col0, _, q0, k0 = eng.run_csr(c)
+        l0 = eng.last_ledger.copy()
+        rp1, col1, _, q1, k1 = eng.run_csr(c, surrogate=True)
+        st = V.vpmc_last_stats(eng.ctx)
+        l1 = eng.last_ledger.copy()
+    finally:
+        eng.close()
+    say(f"  deferred {st['deferred']} of {st['histories']} VPs, nnz {rp1[-1]}")
+    assert st["deferred"] > 0.2 * st["histories"]
+    assert k0 == k1
+    assert np.array_equal(rp0, rp1) and np.array_equal(col0, col1) and np.array_equal(q0, q1)
+    assert np.array_equal(l0, l1)

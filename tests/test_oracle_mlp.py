@@ -46,3 +46,29 @@ def test_single_component_loss_is_gaussian_nll(orc):
     assert loss == pytest.approx(bce + nll, rel=1e-9)
     loss0, _ = orc.mlp_loss_grad(p, x, y, np.array([0.0]))
     assert loss0 == pytest.approx(0.3 + np.log1p(np.exp(-0.3)), rel=1e-12)
+
+
+def test_forward_layout_one_hot_path(orc):
+    """Weights W[out][in] then b[out], layer by layer: a single non-zero
+    weight per layer routes input 3 through four SiLU units to output 7, so
+    out[7] = silu^4(x3) (silu(z) = z * logistic(z)), out[j] = b_j elsewhere."""
+    from scipy.special import expit
+    dims = orc.MLP_DIMS
+    p = np.zeros(orc.mlp_num_params())
+    off = 0
+    picks = [(5, 3), (9, 5), (2, 9), (200, 2), (7, 200)]   # (out, in) per layer
+    for (ni, no), (o, i) in zip(zip(dims[:-1], dims[1:]), picks):
+        p[off + o * ni + i] = 1.0
+        off += no * ni + no
+    p[-29:] += np.linspace(-1.0, 1.0, 29) * (np.arange(29) != 7)
+    x = np.zeros((2, 8))
+    x[0, 3], x[1, 3] = 1.7, -0.6
+    out = orc.mlp_forward(p, x)
+    for r in range(2):
+        z = x[r, 3]
+        for _ in range(4):
+            z = z * expit(z)
+        assert out[r, 7] == pytest.approx(z, rel=1e-13)
+        others = np.delete(out[r], 7)
+        ref = np.delete(np.linspace(-1.0, 1.0, 29), 7)
+        np.testing.assert_allclose(others, ref, rtol=0, atol=1e-15)
