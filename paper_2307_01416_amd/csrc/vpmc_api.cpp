@@ -68,7 +68,7 @@ struct vpmc_ctx {
     vpmc_stats last_stats{};
     std::vector<hipEvent_t> events;
     // influence-matrix builder
-    DevBuf slot_grid, slot_l1, slot_l2, slot_nnz;
+    DevBuf slot_grid, slot_mark, slot_cnt, slot_coff, slot_rowcnt;
     int n_slots = 0;
     size_t slot_nvox = 0;
     bool slots_dirty = false;
@@ -308,9 +308,10 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
         stab[i].range_scale = scen[i].range_scale;
     }
 
-    // slots: dense int64 grid + bitmaps per resident row
-    const size_t n1 = (nvox + 31) / 32, n2 = (n1 + 31) / 32;
-    const size_t slot_bytes = nvox * 8 + n1 * 4 + n2 * 4 + 4;
+    // slots: dense int64 grid + touched-block bytes per resident row
+    const size_t nblk = (nvox + 31) / 32, nchunk = (nblk + 255) / 256;
+    const size_t gstride = nblk * 32, mstride = (nblk + 255) & ~(size_t)255;
+    const size_t slot_bytes = gstride * 8 + mstride + nchunk * 8 + 4;
     size_t budget = cap ? (cap > c->bytes ? cap - c->bytes : 0) / 2 : ((size_t)24 << 30);
     int G = o->max_slots > 0 ? std::min(o->max_slots, kMaxSlots) : kMaxSlots;
     G = (int)std::min<size_t>((size_t)G, budget / slot_bytes);
@@ -318,14 +319,13 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     if (G < 1) return fail(VPMC_E_OOM, "no room for one influence-matrix slot (%zu bytes)", slot_bytes);
     if (c->n_slots < G || c->slot_nvox != nvox || c->slots_dirty) {
         const int Ga = std::max(G, c->slot_nvox == nvox ? c->n_slots : 0);
-        if ((rc = ensure(c, c->slot_grid, (size_t)Ga * nvox * 8, cap))) return rc;
-        if ((rc = ensure(c, c->slot_l1, (size_t)Ga * n1 * 4, cap))) return rc;
-        if ((rc = ensure(c, c->slot_l2, (size_t)Ga * n2 * 4, cap))) return rc;
-        if ((rc = ensure(c, c->slot_nnz, (size_t)Ga * 4, cap))) return rc;
-        HIP_TRY(hipMemsetAsync(c->slot_grid.ptr, 0, (size_t)Ga * nvox * 8, st));
-        HIP_TRY(hipMemsetAsync(c->slot_l1.ptr, 0, (size_t)Ga * n1 * 4, st));
-        HIP_TRY(hipMemsetAsync(c->slot_l2.ptr, 0, (size_t)Ga * n2 * 4, st));
-        HIP_TRY(hipMemsetAsync(c->slot_nnz.ptr, 0, (size_t)Ga * 4, st));
+        if ((rc = ensure(c, c->slot_grid, (size_t)Ga * gstride * 8, cap))) return rc;
+        if ((rc = ensure(c, c->slot_mark, (size_t)Ga * mstride, cap))) return rc;
+        if ((rc = ensure(c, c->slot_cnt, (size_t)Ga * nchunk * 4, cap))) return rc;
+        if ((rc = ensure(c, c->slot_coff, (size_t)Ga * nchunk * 4, cap))) return rc;
+        if ((rc = ensure(c, c->slot_rowcnt, (size_t)Ga * 4, cap))) return rc;
+        HIP_TRY(hipMemsetAsync(c->slot_grid.ptr, 0, (size_t)Ga * gstride * 8, st));
+        HIP_TRY(hipMemsetAsync(c->slot_mark.ptr, 0, (size_t)Ga * mstride, st));
         c->n_slots = Ga;
         c->slot_nvox = nvox;
         c->slots_dirty = false;
@@ -416,10 +416,9 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     Q.seed_hi = (uint32_t)(o->seed >> 32);
     Q.physics = o->physics;
     Q.grid = (unsigned long long *)c->slot_grid.ptr;
-    Q.l1 = (uint32_t *)c->slot_l1.ptr;
-    Q.l2 = (uint32_t *)c->slot_l2.ptr;
-    Q.nnz = (unsigned int *)c->slot_nnz.ptr;
-    Q.nvox = nvox; Q.n1 = n1; Q.n2 = n2;
+    Q.mark = (uint8_t *)c->slot_mark.ptr;
+    Q.nvox = nvox; Q.nblk = nblk; Q.nchunk = nchunk;
+    Q.gstride = gstride; Q.mstride = mstride;
     Q.ledger = (unsigned long long *)c->ledger.ptr;
     Q.stats = (unsigned long long *)c->stats.ptr;
     Q.tables = c->d_tables;
@@ -455,6 +454,20 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
         Qe.head = (unsigned long long *)c->heads.ptr + e;
         return Qe;
     };
+    // compaction passes of one epoch (count per chunk, scan per row; emit)
+    auto count_rows = [&](const QueueDev &Qe) -> hipError_t {
+        hipError_t he = launch_csr_count(Qe, (unsigned int *)c->slot_cnt.ptr, st);
+        if (he == hipSuccess)
+            he = launch_csr_chunk_scan((const unsigned int *)c->slot_cnt.ptr, (unsigned int *)c->slot_coff.ptr,
+                                       (unsigned int *)c->slot_rowcnt.ptr, Qe.n_rows, nchunk, st);
+        return he;
+    };
+    auto emit_rows = [&](const QueueDev &Qe) -> hipError_t {
+        return launch_csr_emit(Qe, (const unsigned int *)c->slot_cnt.ptr, (const unsigned int *)c->slot_coff.ptr,
+                               (const unsigned long long *)c->row_off.ptr, (const unsigned long long *)c->row_nnz.ptr,
+                               (int32_t *)c->csr_col.ptr, (long long *)c->csr_q.ptr, c->csr_cap,
+                               (unsigned int *)c->flags.ptr, st);
+    };
     HIP_TRY(hipEventRecord(c->events[0], st));
     double transport_ms = 0.0;
     unsigned long long used_host = 0;
@@ -476,13 +489,12 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
             const QueueDev Qe = epoch_queue(e);
             hipError_t he = hipSuccess;
             if (Qe.n_chunks) he = launch_queue(c->geom, Qe, q_blocks, q_threads, st);
+            if (he == hipSuccess) he = count_rows(Qe);
             if (he == hipSuccess)
-                he = launch_csr_offsets((unsigned int *)c->slot_nnz.ptr, Qe.n_rows, Qe.row_begin,
+                he = launch_csr_offsets((const unsigned int *)c->slot_rowcnt.ptr, Qe.n_rows, Qe.row_begin,
                                         (unsigned long long *)c->row_off.ptr, (unsigned long long *)c->row_nnz.ptr,
                                         (unsigned long long *)c->used.ptr, c->csr_cap, (unsigned int *)c->flags.ptr, st);
-            if (he == hipSuccess)
-                he = launch_csr_compact(Qe, (const unsigned long long *)c->row_off.ptr, (int32_t *)c->csr_col.ptr,
-                                        (long long *)c->csr_q.ptr, c->csr_cap, (unsigned int *)c->flags.ptr, st);
+            if (he == hipSuccess) he = emit_rows(Qe);
             if (he != hipSuccess) crc = fail(VPMC_E_DEVICE, "graph capture launch: %s", hipGetErrorString(he));
         }
         const hipError_t ce = hipStreamEndCapture(st, &graph);
@@ -539,7 +551,8 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
                 }
             }
             HIP_TRY(hipEventRecord(c->events[3], st));
-            HIP_TRY(launch_csr_offsets((unsigned int *)c->slot_nnz.ptr, Qe.n_rows, Qe.row_begin,
+            HIP_TRY(count_rows(Qe));
+            HIP_TRY(launch_csr_offsets((const unsigned int *)c->slot_rowcnt.ptr, Qe.n_rows, Qe.row_begin,
                                        (unsigned long long *)c->row_off.ptr, (unsigned long long *)c->row_nnz.ptr,
                                        (unsigned long long *)c->used.ptr, ~0ull, (unsigned int *)c->flags.ptr, st));
             unsigned long long used_now = 0;
@@ -554,8 +567,7 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
                 if ((rc = grow_keep(c, c->csr_q, used_host * 8, ncap * 8, cap, st))) return rc;
                 c->csr_cap = ncap;
             }
-            HIP_TRY(launch_csr_compact(Qe, (const unsigned long long *)c->row_off.ptr, (int32_t *)c->csr_col.ptr,
-                                       (long long *)c->csr_q.ptr, c->csr_cap, (unsigned int *)c->flags.ptr, st));
+            HIP_TRY(emit_rows(Qe));
             used_host = used_now;
         }
     }
@@ -571,7 +583,7 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     HIP_TRY(hipMemcpyAsync(led.data(), c->ledger.ptr, led.size() * 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(stv, c->stats.ptr, 16, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (fl & 2u) return fail(VPMC_E_DEVICE, "influence-matrix bitmap count mismatch");
+    if (fl & 2u) return fail(VPMC_E_DEVICE, "influence-matrix count and emit passes disagree");
     c->slots_dirty = false;
     std::vector<int64_t> rp((size_t)R + 1);
     for (int r = 0; r < R; ++r) rp[r] = (int64_t)roff[r];
@@ -866,8 +878,8 @@ void vpmc_destroy(vpmc_ctx *c) {
         release(c->hu_buf);
         for (auto &f : c->fields) release(f.poly_buf);
         for (DevBuf *b : {&c->tallies, &c->qbatch, &c->s2, &c->ledger, &c->spots, &c->offsets,
-                          &c->stage_dose, &c->stage_sigma, &c->stats, &c->slot_grid, &c->slot_l1, &c->slot_l2,
-                          &c->slot_nnz, &c->rows, &c->chunk_off, &c->heads, &c->row_off, &c->row_nnz, &c->used,
+                          &c->stage_dose, &c->stage_sigma, &c->stats, &c->slot_grid, &c->slot_mark, &c->slot_cnt,
+                          &c->slot_coff, &c->slot_rowcnt, &c->rows, &c->chunk_off, &c->heads, &c->row_off, &c->row_nnz, &c->used,
                           &c->flags, &c->fields_tab, &c->poly_off, &c->polys, &c->scen_tab, &c->csr_col,
                           &c->csr_q, &c->mlp_w, &c->mlp_wb, &c->mlp_m, &c->mlp_v, &c->mlp_g, &c->mlp_act,
                           &c->mlp_io, &c->mlp_dx, &c->mlp_dy, &c->mlp_dt, &c->mlp_idx, &c->sur_rec,

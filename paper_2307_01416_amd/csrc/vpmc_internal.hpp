@@ -109,8 +109,8 @@ constexpr int POLY_LDS = 1024;  // == VPMC_MAX_VERTICES
 // ------------------------------------------- influence-matrix (CSR) mode
 // One row = (scenario, field, spot).  Rows are processed in epochs of at
 // most kMaxSlots rows; row (row_begin + i) of an epoch owns slot i: a dense
-// int64 grid plus a two-level bitmap of touched voxels (L1: one bit per
-// voxel, L2: one bit per non-zero L1 word).
+// int64 grid plus one byte per block of 32 voxels that is set when the block
+// receives a deposit.  Compaction counts and emits per chunk of 256 blocks.
 constexpr int kMaxSlots = 1024;
 
 struct RowDev {
@@ -142,10 +142,10 @@ struct QueueDev {
     const ScenDev *scen;
     uint32_t key0, seed_hi;
     unsigned physics;
-    unsigned long long *grid;             // [slots][nvox]
-    uint32_t *l1, *l2;                    // [slots][n1], [slots][n2]
-    unsigned int *nnz;                    // [slots]
-    size_t nvox, n1, n2;
+    unsigned long long *grid;             // [slots][gstride] int64 tallies
+    uint8_t *mark;                        // [slots][mstride] touched-block bytes (32 voxels each)
+    size_t nvox, nblk, nchunk;            // blocks = ceil(nvox/32), chunks = ceil(blocks/256)
+    size_t gstride, mstride;              // gstride = 32 * nblk voxels, mstride >= nblk bytes
     unsigned long long *ledger;           // [n_scen][NLEDGER]
     unsigned long long *stats;            // [2]
     const float *tables;
@@ -196,11 +196,15 @@ hipError_t mlp_gather(const float *x, const int *idx, int n, int cols, __bf16 *x
 hipError_t mlp_to_bf16(const float *x, __bf16 *y, size_t n, hipStream_t s);
 hipError_t mlp_adam(float *p, const float *g, float *m, float *v, __bf16 *pb, int np, float lr, int step,
                     hipStream_t s);
-hipError_t launch_csr_offsets(unsigned int *nnz, int n_rows, int row_begin, unsigned long long *row_off,
+hipError_t launch_csr_count(const QueueDev &Q, unsigned int *cnt, hipStream_t s);
+hipError_t launch_csr_chunk_scan(const unsigned int *cnt, unsigned int *coff, unsigned int *rowcnt, int n_rows,
+                                 size_t nchunk, hipStream_t s);
+hipError_t launch_csr_offsets(const unsigned int *nnz, int n_rows, int row_begin, unsigned long long *row_off,
                               unsigned long long *row_nnz, unsigned long long *used, unsigned long long capacity,
                               unsigned int *flags, hipStream_t s);
-hipError_t launch_csr_compact(const QueueDev &Q, const unsigned long long *row_off, int32_t *col, long long *qv,
-                              unsigned long long capacity, unsigned int *flags, hipStream_t s);
+hipError_t launch_csr_emit(const QueueDev &Q, const unsigned int *cnt, const unsigned int *coff,
+                           const unsigned long long *row_off, const unsigned long long *row_nnz, int32_t *col,
+                           long long *qv, unsigned long long capacity, unsigned int *flags, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_csr_scatter(const int32_t *col, const long long *qv, unsigned long long begin,
                               unsigned long long end, unsigned long long *dense, hipStream_t s);

@@ -257,20 +257,16 @@ struct DenseSink {
     }
 };
 
-// per-row tally of the influence-matrix builder: the returning atomic tells
-// the first deposit into a voxel (tallies only grow from zero), which marks
-// the voxel in the two-level bitmap and counts it
+// per-row tally of the influence-matrix builder: a non-returning 64-bit
+// atomic into the row's dense slot grid and a plain store of 1 into the
+// touched-block byte map (one byte per 32 voxels; every writer stores the
+// same value, so the stores need no atomicity and the wave never waits)
 struct SparseSink {
     unsigned long long *grid;
-    uint32_t *l1, *l2;
-    unsigned int *nnz;
+    uint8_t *mark;
     __device__ __forceinline__ void add(uint32_t v, long long q) const {
-        const unsigned long long old = atomicAdd(grid + v, (unsigned long long)q);
-        if (old == 0ull) {
-            const uint32_t o1 = atomicOr(l1 + (v >> 5), 1u << (v & 31u));
-            if (o1 == 0u) atomicOr(l2 + (v >> 10), 1u << ((v >> 5) & 31u));
-            atomicAdd(nnz, 1u);
-        }
+        atomicAdd(grid + v, (unsigned long long)q);
+        __hip_atomic_store(mark + (v >> 5), (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 };
 
@@ -741,8 +737,7 @@ __global__ __launch_bounds__(512, 4) void queue_kernel(GeomDev g, QueueDev Q) {
         const FieldDev f = Q.fields[row.field];
         const SpotDev sp = Q.spots[row.spot_global];
         const ScenDev sc = Q.scen[row.scen];
-        const SparseSink sink{Q.grid + (size_t)rl * Q.nvox, Q.l1 + (size_t)rl * Q.n1, Q.l2 + (size_t)rl * Q.n2,
-                              Q.nnz + rl};
+        const SparseSink sink{Q.grid + (size_t)rl * Q.gstride, Q.mark + (size_t)rl * Q.mstride};
         const float2 *fpoly = poly + Q.poly_off[row.field];
         Acc acc;
 #pragma unroll
@@ -785,9 +780,82 @@ __global__ __launch_bounds__(512, 4) void queue_kernel(GeomDev g, QueueDev Q) {
     }
 }
 
+// ---- compaction of an epoch's rows into CSR (three passes per epoch)
+// A chunk is 256 touched-block bytes (8192 voxels) of one row.  The marked
+// blocks of a chunk are listed in ascending order in LDS; then 32 lanes read
+// one block's 32 slot values (coalesced 256 B) at a time.
+
+// lists the marked blocks of this workgroup's chunk; returns their count
+__device__ __forceinline__ int marked_blocks(const uint8_t *mark, size_t nblk, size_t b0, int *list, int *wsum) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const size_t b = b0 + t;
+    const bool m = b < nblk && mark[b] != 0;
+    const unsigned long long bal = __ballot(m);
+    const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[w] = __popcll(bal);
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int k = 0; k < 4; ++k) {
+        base += k < w ? wsum[k] : 0;
+        tot += wsum[k];
+    }
+    if (m) list[base + pre] = (int)(b - b0);
+    __syncthreads();
+    return tot;
+}
+
+// pass 1: non-zero count of every (row, chunk)
+__global__ __launch_bounds__(256) void csr_count_kernel(QueueDev Q, unsigned int *cnt) {
+    __shared__ int list[256];
+    __shared__ int wsum[4];
+    __shared__ unsigned int red[4];
+    const int row = blockIdx.y, chunk = blockIdx.x, t = threadIdx.x;
+    const size_t b0 = (size_t)chunk * 256;
+    const uint8_t *mark = Q.mark + (size_t)row * Q.mstride;
+    const unsigned long long *grid = Q.grid + (size_t)row * Q.gstride;
+    const int nm = marked_blocks(mark, Q.nblk, b0, list, wsum);
+    unsigned int c = 0;
+    for (int p = 0; p * 8 < nm; ++p) {
+        const int idx = p * 8 + (t >> 5);
+        if (idx < nm) c += grid[(b0 + list[idx]) * 32 + (t & 31)] != 0ull;
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((t & 63) == 0) red[t >> 6] = c;
+    __syncthreads();
+    if (t == 0) cnt[(size_t)row * Q.nchunk + chunk] = red[0] + red[1] + red[2] + red[3];
+}
+
+// pass 2: per row, exclusive prefix of its chunk counts and the row total
+__global__ __launch_bounds__(1024) void csr_chunk_scan_kernel(const unsigned int *cnt, unsigned int *coff,
+                                                              unsigned int *rowcnt, size_t nchunk) {
+    __shared__ unsigned int part[1024];
+    __shared__ unsigned int carry;
+    const int row = blockIdx.x, t = threadIdx.x;
+    const unsigned int *c = cnt + (size_t)row * nchunk;
+    unsigned int *o = coff + (size_t)row * nchunk;
+    if (t == 0) carry = 0u;
+    __syncthreads();
+    for (size_t s0 = 0; s0 < nchunk; s0 += 1024) {
+        const unsigned int x = s0 + t < nchunk ? c[s0 + t] : 0u;
+        part[t] = x;
+        __syncthreads();
+        for (int k = 1; k < 1024; k <<= 1) {
+            const unsigned int y = t >= k ? part[t - k] : 0u;
+            __syncthreads();
+            part[t] += y;
+            __syncthreads();
+        }
+        if (s0 + t < nchunk) o[s0 + t] = carry + part[t] - x;
+        __syncthreads();
+        if (t == 1023) carry += part[1023];
+        __syncthreads();
+    }
+    if (t == 0) rowcnt[row] = carry;
+}
+
 // exclusive scan of this epoch's row counts into global CSR offsets (rows
 // are stored in row order, so the offsets are the final row pointers)
-__global__ __launch_bounds__(1024) void csr_offsets_kernel(unsigned int *nnz, int n_rows, int row_begin,
+__global__ __launch_bounds__(1024) void csr_offsets_kernel(const unsigned int *nnz, int n_rows, int row_begin,
                                                            unsigned long long *row_off,
                                                            unsigned long long *row_nnz,
                                                            unsigned long long *used,
@@ -815,67 +883,51 @@ __global__ __launch_bounds__(1024) void csr_offsets_kernel(unsigned int *nnz, in
     }
 }
 
-// Walk the two-level bitmap of each slot in ascending voxel order, emit
-// (voxel, q) at the row's offset and clear exactly what was touched.
-__global__ __launch_bounds__(256) void csr_compact_kernel(QueueDev Q, const unsigned long long *row_off,
-                                                          int32_t *col, long long *qv,
-                                                          unsigned long long capacity, unsigned int *flags) {
-    __shared__ unsigned int cnt[256];
-    const int slot = blockIdx.x;
-    const int t = threadIdx.x;
-    unsigned long long *grid = Q.grid + (size_t)slot * Q.nvox;
-    uint32_t *l1 = Q.l1 + (size_t)slot * Q.n1;
-    uint32_t *l2 = Q.l2 + (size_t)slot * Q.n2;
-    const unsigned int total = Q.nnz[slot];
-    const unsigned long long base = row_off[Q.row_begin + slot];
-    const bool write = base + total <= capacity;
-    const size_t per = (Q.n2 + blockDim.x - 1) / blockDim.x;
-    const size_t w0 = (size_t)t * per, w1 = w0 + per < Q.n2 ? w0 + per : Q.n2;
-    unsigned int c = 0;
-    for (size_t w = w0; w < w1; ++w) {
-        uint32_t m = l2[w];
-        while (m) {
-            const int b = __ffs(m) - 1;
-            m &= m - 1u;
-            c += __popc(l1[w * 32 + b]);
+// pass 3: emit (voxel, q) of every chunk at its place in ascending voxel
+// order and clear exactly the touched blocks and their marks
+__global__ __launch_bounds__(256) void csr_emit_kernel(QueueDev Q, const unsigned int *cnt, const unsigned int *coff,
+                                                       const unsigned long long *row_off,
+                                                       const unsigned long long *row_nnz, int32_t *col,
+                                                       long long *qv, unsigned long long capacity,
+                                                       unsigned int *flags) {
+    __shared__ int list[256];
+    __shared__ int wsum[4];
+    __shared__ unsigned int wz[4];
+    const int row = blockIdx.y, chunk = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const size_t b0 = (size_t)chunk * 256;
+    uint8_t *mark = Q.mark + (size_t)row * Q.mstride;
+    unsigned long long *grid = Q.grid + (size_t)row * Q.gstride;
+    const int nm = marked_blocks(mark, Q.nblk, b0, list, wsum);
+    if (nm == 0) return;
+    const size_t ci = (size_t)row * Q.nchunk + chunk;
+    const unsigned long long rb = row_off[Q.row_begin + row];
+    const bool write = rb + row_nnz[Q.row_begin + row] <= capacity;
+    unsigned long long pos = rb + coff[ci];
+    for (int p = 0; p * 8 < nm; ++p) {
+        const int idx = p * 8 + (t >> 5);
+        const size_t v = idx < nm ? (b0 + list[idx]) * 32 + (t & 31) : 0;
+        const unsigned long long q = idx < nm ? grid[v] : 0ull;
+        const unsigned long long bal = __ballot(q != 0ull);
+        if (lane == 0) wz[w] = __popcll(bal);
+        __syncthreads();
+        unsigned long long wb = 0, tot = 0;
+        for (int k = 0; k < 4; ++k) {
+            wb += k < w ? wz[k] : 0u;
+            tot += wz[k];
         }
-    }
-    cnt[t] = c;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        const unsigned int y = t >= o ? cnt[t - o] : 0u;
-        __syncthreads();
-        cnt[t] += y;
-        __syncthreads();
-    }
-    if (t == 255 && cnt[255] != total) atomicOr(flags, 2u);
-    unsigned long long pos = base + cnt[t] - c;
-    for (size_t w = w0; w < w1; ++w) {
-        uint32_t m = l2[w];
-        if (!m) continue;
-        l2[w] = 0u;
-        while (m) {
-            const int b = __ffs(m) - 1;
-            m &= m - 1u;
-            const size_t wi = w * 32 + b;
-            uint32_t word = l1[wi];
-            l1[wi] = 0u;
-            while (word) {
-                const int bb = __ffs(word) - 1;
-                word &= word - 1u;
-                const size_t v = wi * 32 + bb;
-                const unsigned long long q = grid[v];
-                grid[v] = 0ull;
-                if (write) {
-                    col[pos] = (int32_t)v;
-                    qv[pos] = (long long)q;
-                }
-                ++pos;
+        if (q != 0ull) {
+            const unsigned long long at = pos + wb + __popcll(bal & ((1ull << lane) - 1ull));
+            if (write) {
+                col[at] = (int32_t)v;
+                qv[at] = (long long)q;
             }
         }
+        if (idx < nm) grid[v] = 0ull;
+        pos += tot;
+        __syncthreads();
     }
-    __syncthreads();
-    if (t == 0) Q.nnz[slot] = 0u;
+    if (t < nm) mark[b0 + list[t]] = 0;
+    if (t == 0 && pos - rb - coff[ci] != cnt[ci]) atomicOr(flags, 2u);
 }
 
 __global__ void fill_u64_kernel(unsigned long long *p, size_t n, unsigned long long v) {
@@ -1132,8 +1184,7 @@ __global__ __launch_bounds__(256) void sur_resume_csr_kernel(GeomDev g, QueueDev
         const RowDev row = Q.rows[Q.row_begin + rl];
         const FieldDev f = Q.fields[row.field];
         const ScenDev sc = Q.scen[row.scen];
-        const SparseSink sink{Q.grid + (size_t)rl * Q.nvox, Q.l1 + (size_t)rl * Q.n1, Q.l2 + (size_t)rl * Q.n2,
-                              Q.nnz + rl};
+        const SparseSink sink{Q.grid + (size_t)rl * Q.gstride, Q.mark + (size_t)rl * Q.mstride};
         if (row.scen != cur_scen) {
             // ledgers are per scenario: this lane's sums so far go out with
             // plain per-lane atomics (lanes of a wave may differ in scenario)
@@ -1210,17 +1261,30 @@ hipError_t launch_queue(const GeomDev &g, const QueueDev &Q, int blocks, int thr
     return hipGetLastError();
 }
 
-hipError_t launch_csr_offsets(unsigned int *nnz, int n_rows, int row_begin, unsigned long long *row_off,
-                              unsigned long long *row_nnz, unsigned long long *used, unsigned long long capacity,
-                              unsigned int *flags, hipStream_t s) {
-    hipLaunchKernelGGL(csr_offsets_kernel, dim3(1), dim3(1024), 0, s, nnz, n_rows, row_begin, row_off, row_nnz,
-                       used, capacity, flags);
+hipError_t launch_csr_count(const QueueDev &Q, unsigned int *cnt, hipStream_t s) {
+    hipLaunchKernelGGL(csr_count_kernel, dim3((unsigned)Q.nchunk, Q.n_rows), dim3(256), 0, s, Q, cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_csr_compact(const QueueDev &Q, const unsigned long long *row_off, int32_t *col, long long *qv,
-                              unsigned long long capacity, unsigned int *flags, hipStream_t s) {
-    hipLaunchKernelGGL(csr_compact_kernel, dim3(Q.n_rows), dim3(256), 0, s, Q, row_off, col, qv, capacity, flags);
+hipError_t launch_csr_chunk_scan(const unsigned int *cnt, unsigned int *coff, unsigned int *rowcnt, int n_rows,
+                                 size_t nchunk, hipStream_t s) {
+    hipLaunchKernelGGL(csr_chunk_scan_kernel, dim3(n_rows), dim3(1024), 0, s, cnt, coff, rowcnt, nchunk);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_offsets(const unsigned int *nnz, int n_rows, int row_begin, unsigned long long *row_off,
+                              unsigned long long *row_nnz, unsigned long long *used, unsigned long long capacity,
+                              unsigned int *flags, hipStream_t s) {
+    hipLaunchKernelGGL(csr_offsets_kernel, dim3(1), dim3(1024), 0, s, nnz, n_rows, row_begin, row_off, row_nnz, used,
+                       capacity, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_emit(const QueueDev &Q, const unsigned int *cnt, const unsigned int *coff,
+                           const unsigned long long *row_off, const unsigned long long *row_nnz, int32_t *col,
+                           long long *qv, unsigned long long capacity, unsigned int *flags, hipStream_t s) {
+    hipLaunchKernelGGL(csr_emit_kernel, dim3((unsigned)Q.nchunk, Q.n_rows), dim3(256), 0, s, Q, cnt, coff, row_off,
+                       row_nnz, col, qv, capacity, flags);
     return hipGetLastError();
 }
 
