@@ -580,11 +580,12 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
         v.px = u[0]; v.py = u[1]; v.pz = u[2];
     }
     v.dx = d[0]; v.dy = d[1]; v.dz = d[2];
+    uint32_t vox = (uint32_t)idx[0] + (uint32_t)g.nx * ((uint32_t)idx[1] + (uint32_t)g.ny * (uint32_t)idx[2]);
+    int hu = g.kind == 1 ? (int)g.hu[vox] : 0;
     for (int it = 0; it < MAX_STEPS; ++it) {
-        const uint32_t vox = (uint32_t)idx[0] + (uint32_t)g.nx * ((uint32_t)idx[1] + (uint32_t)g.ny * (uint32_t)idx[2]);
         int m = MAT_WATER;
         float rho = 1.0f;
-        if (g.kind == 1) hu_material(g.hu[vox], m, rho);
+        if (g.kind == 1) hu_material(hu, m, rho);
         const float rho_loss = rho * range_scale;
         const float pp[3] = {v.px, v.py, v.pz}, dd[3] = {v.dx, v.dy, v.dz};
         float dg = INFINITY;
@@ -596,6 +597,22 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
             // hardware reciprocal: exact for the unit components of axis-aligned beams
             const float t = fmaxf(((up ? g.sp[k] : 0.0f) - pp[k]) * __builtin_amdgcn_rcpf(dd[k]), 0.0f);
             if (t < dg) { dg = t; ax = k; sgn = up ? 1 : -1; }
+        }
+        // the CT number behind the face this step may cross is fetched now,
+        // so its latency overlaps the step's arithmetic
+        int nidx = -1;
+        uint32_t nvox = vox;
+        int hu_next = hu;
+        if (ax >= 0) {
+            // selects, not indexing: the per-axis arrays stay in registers
+            const int ia = ax == 0 ? idx[0] : ax == 1 ? idx[1] : idx[2];
+            const int na = ax == 0 ? n[0] : ax == 1 ? n[1] : n[2];
+            const int sa = ax == 0 ? 1 : ax == 1 ? g.nx : g.nx * g.ny;
+            nidx = ia + sgn;
+            if (nidx >= 0 && nidx < na) {
+                nvox = vox + (uint32_t)(sgn * sa);
+                if (g.kind == 1) hu_next = (int)g.hu[nvox];
+            }
         }
         float dep, esc;
         const int st = phys_step<false>(v, tab, m, rho_loss, rho, dg, dep, esc);
@@ -610,15 +627,17 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 if (k == ax) {
-                    idx[k] += sgn;
+                    idx[k] = nidx;
                     q[k] = sgn > 0 ? 0.0f : g.sp[k];   // near face of the next voxel
-                    out = idx[k] < 0 || idx[k] >= n[k];
+                    out = nidx < 0 || nidx >= n[k];
                 }
             }
             if (out) {
                 ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
                 return;
             }
+            vox = nvox;
+            hu = hu_next;
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) q[k] = fminf(fmaxf(q[k], 0.0f), g.sp[k]);
