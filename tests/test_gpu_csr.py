@@ -101,3 +101,50 @@ def test_batched_rows_equal_single_spot_dense_runs(eng):
             cc, qq = rows[sc * n_sp + s]
             assert np.array_equal(np.nonzero(qd)[0], cc)
             assert np.array_equal(qd[cc], qq)
+
+
+def test_graph_capture_equals_eager(eng):
+    """The whole multi-epoch pass captured in one hipGraph gives the eager
+    rows bit for bit, also when its first capacity is too small (the graph
+    reports the overflow and the eager path reruns)."""
+    c = small_case(I.PHYS_ALL, n=4000)
+    c.scenarios = I.scenarios_13()[:2]
+    say("case csr graph vs eager")
+    rp, col, _, q, _ = eng.run_csr(c, fixed_point_bits=36, max_slots=4)
+    rpg, colg, _, qg, _ = eng.run_csr(c, fixed_point_bits=36, max_slots=4, graph=True)
+    assert np.array_equal(rp, rpg) and np.array_equal(col, colg) and np.array_equal(q, qg)
+    big = small_case(I.PHYS_ALL, n=40000)
+    big.scenarios = I.scenarios_13()[:2]
+    rp2, col2, _, q2, _ = eng.run_csr(big, fixed_point_bits=36, max_slots=4, graph=True)
+    rp3, col3, _, q3, _ = eng.run_csr(big, fixed_point_bits=36, max_slots=4)
+    assert rp2[-1] > rp[-1]
+    assert np.array_equal(rp2, rp3) and np.array_equal(col2, col3) and np.array_equal(q2, q3)
+
+
+def test_head_three_fields_rows_sum_to_dense(eng):
+    """Synthetic head, three fields with their own apertures and range
+    shifters, two scenarios, one work queue: per scenario, the rows of all
+    fields sum to the sum of the three fields' dense tallies, bit for bit."""
+    g = I.head_ct(0, shape=(128, 128, 80), spacing=(2.0, 2.0, 2.0))
+    c = I.config3(8.0, 300, geometry=g)
+    for f in c.fields:
+        f.spots = f.spots[:: max(1, len(f.spots) // 12)].copy()
+    c.scenarios = [I.Scenario(), I.Scenario(shift_mm=(0.0, 3.0, 0.0), range_scale=0.965)]
+    say(f"case head 3 fields csr: spots {[len(f.spots) for f in c.fields]}")
+    rp, col, _, q, _ = eng.run_csr(c, fixed_point_bits=34)
+    rows = rows_of(rp, col, q)
+    n_per_scen = sum(len(f.spots) for f in c.fields)
+    assert len(rows) == 2 * n_per_scen
+    eng.load_case(c)
+    for sc in range(2):
+        dense = np.zeros(g.nvox, np.int64)
+        for fi in range(3):
+            eng.run_dose(c, fi, scenarios=[c.scenarios[sc]], sigma=False, fixed_point_bits=34)
+            qd, _ = eng.last_tally(0)
+            dense += qd.cpu().numpy().ravel()
+        acc = np.zeros(g.nvox, np.int64)
+        for r in range(sc * n_per_scen, (sc + 1) * n_per_scen):
+            cc, qq = rows[r]
+            assert np.all(np.diff(cc) > 0)
+            np.add.at(acc, cc, qq)
+        assert dense.any() and np.array_equal(acc, dense)
