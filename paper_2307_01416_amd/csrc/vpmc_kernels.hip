@@ -258,15 +258,17 @@ struct DenseSink {
 };
 
 // per-row tally of the influence-matrix builder: a non-returning 64-bit
-// atomic into the row's dense slot grid and a plain store of 1 into the
-// touched-block byte map (one byte per 32 voxels; every writer stores the
-// same value, so the stores need no atomicity and the wave never waits)
+// atomic into the row's dense slot grid and a store of 1 into the
+// touched-block byte map (one byte per 32 voxels).  Every writer stores the
+// same value and the marks are read only by later kernels, so the store is
+// relaxed at workgroup scope: it stays in L2 (write-back, merged per line)
+// instead of being written through to memory on every step.
 struct SparseSink {
     unsigned long long *grid;
     uint8_t *mark;
     __device__ __forceinline__ void add(uint32_t v, long long q) const {
         atomicAdd(grid + v, (unsigned long long)q);
-        __hip_atomic_store(mark + (v >> 5), (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(mark + (v >> 5), (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 };
 
