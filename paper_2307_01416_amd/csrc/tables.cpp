@@ -123,12 +123,20 @@ const HostTables &host_tables() {
 // Device tables are per unit of (density x path length in mm), i.e. 10x the
 // areal density in g/cm^2: a 1 mm step in water is then exactly 1.0 in FP32,
 // whereas 0.1 g/cm^2 is not representable and would bias every step alike.
+namespace {
+// FP64 value as an unevaluated pair of FP32 (high part, rounded remainder)
+void split_pair(double x, float *hi, float *lo) {
+    *hi = (float)x;
+    *lo = (float)(x - (double)*hi);
+}
+}  // namespace
+
 void pack_device_tables(float *blob) {
     const HostTables &t = host_tables();
     memset(blob, 0, sizeof(float) * TAB_FLOATS);
     for (int i = 0; i < NE; ++i) {
-        blob[TAB_E + i] = (float)t.E[i];
-        blob[TAB_INVDE + i] = i + 1 < NE ? (float)(1.0 / (t.E[i + 1] - t.E[i])) : 0.0f;
+        split_pair(t.E[i], blob + TAB_E + i, blob + TAB_EL + i);
+        if (i + 1 < NE) split_pair(t.E[i + 1] - t.E[i], blob + TAB_DWH + i, blob + TAB_DWL + i);
     }
     for (int m = 0; m < NMAT; ++m) {
         float *b = blob + TAB_MAT0 + m * TAB_PER_MAT;
@@ -136,8 +144,8 @@ void pack_device_tables(float *blob) {
             b[T_R * NE + i] = (float)(10.0 * t.R[m][i]);
             if (i + 1 < NE) {
                 const double dR = 10.0 * (t.R[m][i + 1] - t.R[m][i]);
-                b[T_SLOPE * NE + i] = (float)((t.E[i + 1] - t.E[i]) / dR);
-                b[T_DR * NE + i] = (float)dR;
+                split_pair((t.E[i + 1] - t.E[i]) / dR, b + T_SH * NE + i, b + T_SL * NE + i);
+                split_pair(dR, b + T_DH * NE + i, b + T_DL * NE + i);
             }
             b[T_W2 * NE + i] = (float)(0.1 * t.W2[m][i]);
             b[T_T * NE + i] = (float)(0.1 * t.T[m][i]);

@@ -975,6 +975,7 @@ int vpmc_set_aperture(vpmc_ctx *c, int field_id, const vpmc_beam *beam, const fl
         d.blk_zd = -block->downstream_mm;
         d.blk_rho = block->density_gcc;
         d.blk_t = block->thickness_mm;
+        d.blk_tl = 0.0f;   // the caller's thickness is an FP32 value
         poly.resize(n_vertices);
         for (int i = 0; i < n_vertices; ++i) poly[i] = make_float2(xy_mm[2 * i], xy_mm[2 * i + 1]);
     }
@@ -984,7 +985,9 @@ int vpmc_set_aperture(vpmc_ctx *c, int field_id, const vpmc_beam *beam, const fl
         d.rs_zu = (float)(-(rs->downstream_mm + rs_t));
         d.rs_r2 = 0.25f * rs->diameter_mm * rs->diameter_mm;
         d.rs_rho = (float)kMaterials[MAT_PMMA].density;
+        d.rs_rhol = (float)(kMaterials[MAT_PMMA].density - (double)d.rs_rho);
         d.rs_t = (float)rs_t;
+        d.rs_tl = (float)(rs_t - (double)d.rs_t);
     }
     if (c->device >= 0 && !poly.empty()) {
         HIP_TRY(hipSetDevice(c->device));

@@ -14,12 +14,15 @@ constexpr double E_LO = 1.0;
 constexpr double E_HI = 256.0;
 enum Material { MAT_WATER = 0, MAT_AIR = 1, MAT_PMMA = 2, MAT_BRASS = 3, MAT_BONE = 4 };
 
-// FP32 device blob: [E nodes][1/(E_i+1 - E_i)] then per material
-// [R][dE/dR per segment][R_i+1 - R_i][omega^2][T][Sigma_nuc], NE floats each,
-// all per unit of density x path length in mm (10 x g/cm^2).
-enum { TAB_E = 0, TAB_INVDE = NE, TAB_MAT0 = 2 * NE, TAB_PER_MAT = 6 * NE };
-enum { T_R = 0, T_SLOPE = 1, T_DR = 2, T_W2 = 3, T_T = 4, T_SN = 5 };
-constexpr int TAB_FLOATS = 2 * NE + NMAT * 6 * NE;   // 8192 floats = 32 KiB of LDS
+// FP32 device blob.  Shared: energy nodes as (high, low) FP32 pairs of the
+// FP64 nodes, segment energy widths E_i+1 - E_i as pairs.
+// Per material: R, dE/dR per segment as a pair, R_i+1 - R_i as a pair,
+// omega^2, T, Sigma_nuc; NE floats each, all per unit of density x path
+// length in mm (10 x g/cm^2).  The pairs carry the FP64 table values to
+// ~1e-14 so the energy-loss bookkeeping can run in double-float arithmetic.
+enum { TAB_E = 0, TAB_EL = NE, TAB_DWH = 2 * NE, TAB_DWL = 3 * NE, TAB_MAT0 = 4 * NE, TAB_PER_MAT = 8 * NE };
+enum { T_R = 0, T_SH = 1, T_SL = 2, T_DH = 3, T_DL = 4, T_W2 = 5, T_T = 6, T_SN = 7 };
+constexpr int TAB_FLOATS = 4 * NE + NMAT * 8 * NE;   // 11264 floats = 44 KiB of LDS
 
 struct MaterialDef {
     double z_over_a, mean_exc_ev, rad_len_gcm2, nuc_coeff, density;
@@ -60,9 +63,9 @@ struct FieldDev {
     float iso[3], ex[3], ey[3], ez[3];
     int has_block, nv;
     const float2 *poly;
-    float blk_zu, blk_zd, blk_rho, blk_t;
+    float blk_zu, blk_zd, blk_rho, blk_t, blk_tl;
     int has_rs;
-    float rs_zu, rs_zd, rs_r2, rs_rho, rs_t;   // slab thicknesses rounded once from FP64
+    float rs_zu, rs_zd, rs_r2, rs_rho, rs_rhol, rs_t, rs_tl;   // *_l: low parts of the FP64 values
 };
 
 struct SpotDev {

@@ -42,12 +42,63 @@ __device__ __forceinline__ float unit_open(uint32_t w) {
 
 struct Lane {
     float px, py, pz, dx, dy, dz;
-    float pzlo;               // low part of the slab depth (see plane_distance)
+    float pzlo;               // low part of the depth (slab depth, or voxel-local z)
+    float pxlo, pylo;         // low parts of the voxel-local x, y (patient only)
     float E, Elo;             // energy as an unevaluated pair E + Elo
     uint32_t nblk, spot, hist, k0, k1;
     unsigned physics;
     uint32_t nsteps;
 };
+
+// ---------------------------------------------------- double-float values
+// An unevaluated FP32 pair h + l with |l| <= ulp(h)/2, built from error-free
+// transformations: Knuth's TwoSum, Dekker's Fast2Sum (|a| >= |b| or a = 0)
+// and the FMA-based exact product.  The CSDA bookkeeping (energy, residual
+// range, path lengths, densities) runs on pairs, so a track's energy does not
+// drift by FP32 rounding step after step; the drift would otherwise reach the
+// residual deposit at the end of range amplified by S(E_end)/S(E_start).
+struct DF {
+    float h, l;
+};
+
+__device__ __forceinline__ DF fast2(float a, float b) {
+    const float s = a + b;
+    return {s, b - (s - a)};
+}
+
+__device__ __forceinline__ DF two_sum(float a, float b) {
+    const float s = a + b;
+    const float bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+
+__device__ __forceinline__ DF df_add(DF a, DF b) {
+    const DF s = two_sum(a.h, b.h);
+    return fast2(s.h, s.l + (a.l + b.l));
+}
+
+__device__ __forceinline__ DF df_sub(DF a, DF b) { return df_add(a, {-b.h, -b.l}); }
+
+__device__ __forceinline__ DF df_mul(DF a, DF b) {
+    const float p = a.h * b.h;
+    const float e = fmaf(a.h, b.h, -p) + (a.h * b.l + a.l * b.h);
+    return fast2(p, e);
+}
+
+__device__ __forceinline__ DF df_mul_f(DF a, float b) {
+    const float p = a.h * b;
+    return fast2(p, fmaf(a.l, b, fmaf(a.h, b, -p)));
+}
+
+// a / b: FP32 quotient, then one correction from the exact remainder
+__device__ __forceinline__ DF df_div(DF a, DF b) {
+    const float rb = __builtin_amdgcn_rcpf(b.h);
+    const float q = a.h * rb;
+    const DF r = df_sub(a, df_mul_f(b, q));
+    return fast2(q, (r.h + r.l) * rb);
+}
+
+__device__ __forceinline__ bool df_le(DF a, DF b) { return a.h < b.h || (a.h == b.h && a.l <= b.l); }
 
 __device__ __forceinline__ uint4 draw(Lane &v) {
     const uint4 w = philox4x32_10(make_uint4(v.nblk, v.hist, v.spot, 0u), v.k0, v.k1);
@@ -82,7 +133,9 @@ struct NodePos {
 
 __device__ __forceinline__ NodePos node_pos(const float *tab, float E) {
     const int i = seg_of(tab, E);
-    const float f = (E - tab[TAB_E + i]) * tab[TAB_INVDE + i];
+    // interpolation weight of the physics tables: an approximate reciprocal
+    // of the node spacing is ample here
+    const float f = (E - tab[TAB_E + i]) * __builtin_amdgcn_rcpf(tab[TAB_DWH + i]);
     return {i, fminf(fmaxf(f, 0.0f), 1.0f)};
 }
 
@@ -90,21 +143,19 @@ __device__ __forceinline__ float node_lerp(const float *y, NodePos p) {
     return fmaf(p.f, y[p.i + 1] - y[p.i], y[p.i]);
 }
 
-// Energy lost while traversing the areal density r (g/cm^2), starting at
-// E = E_i + x in segment i of the piecewise-linear CSDA relation E(R).  The
-// loss is accumulated piece by piece (each piece is a short product), so it
-// keeps full relative precision instead of being a difference of two nearly
-// equal energies.
-__device__ __forceinline__ float csda_loss(const float *tm, int i, float x, float slope, float r) {
-    const float rem = x * __builtin_amdgcn_rcpf(slope);
-    if (r <= rem) return r * slope;
-    float dE = x;
-    r -= rem;
+// Energy lost while traversing r (density x mm), starting at E = E_i + x in
+// segment i of the piecewise-linear CSDA relation E(R), whose range within
+// the segment is rem = x / slope_i.  Whole segments crossed contribute their
+// exact energy width; the last partial segment r * slope_j.  All in pairs.
+__device__ __forceinline__ DF csda_loss(const float *tab, const float *tm, int i, DF x, DF rem, DF r) {
+    if (df_le(r, rem)) return df_mul(r, {tm[T_SH * NE + i], tm[T_SL * NE + i]});
+    DF dE = x;
+    r = df_sub(r, rem);
     for (int j = i - 1; j >= 0; --j) {
-        const float sj = tm[T_SLOPE * NE + j], dRj = tm[T_DR * NE + j];
-        if (r <= dRj) return fmaf(r, sj, dE);
-        dE = fmaf(dRj, sj, dE);
-        r -= dRj;
+        const DF dRj = {tm[T_DH * NE + j], tm[T_DL * NE + j]};
+        if (df_le(r, dRj)) return df_add(dE, df_mul(r, {tm[T_SH * NE + j], tm[T_SL * NE + j]}));
+        dE = df_add(dE, {tab[TAB_DWH + j], tab[TAB_DWL + j]});
+        r = df_sub(r, dRj);
     }
     return dE;
 }
@@ -130,15 +181,10 @@ __device__ __forceinline__ void rotate_dir(Lane &v, float ax, float ay) {
     v.dz = nz * inv;
 }
 
-__device__ __forceinline__ void sub_energy(Lane &v, float dE) {
-    // (E, Elo) -= dE with an error-free two-sum, then renormalise
-    const float s = v.E - dE;
-    const float bb = s - v.E;
-    const float err = (v.E - (s - bb)) + (-dE - bb);
-    const float lo = v.Elo + err;
-    const float t = s + lo;
-    v.Elo = lo - (t - s);
-    v.E = t;
+__device__ __forceinline__ void sub_energy(Lane &v, DF dE) {
+    const DF e = df_sub({v.E, v.Elo}, dE);
+    v.E = e.h;
+    v.Elo = e.l;
 }
 
 // (pz, pzlo) += dz with an error-free two-sum
@@ -154,38 +200,73 @@ __device__ __forceinline__ void add_depth(Lane &v, float dz) {
 
 enum { ST_STOP = 0, ST_GEO = 1, ST_INNER = 2 };
 
+__device__ __forceinline__ DF df_div_f(DF a, float b) {
+    const float rb = __builtin_amdgcn_rcpf(b);
+    const float q = a.h * rb;
+    const DF r = df_sub(a, df_mul_f({q, 0.0f}, b));
+    return fast2(q, (r.h + r.l) * rb);
+}
+
+// move by the path length h along d: the depth always as a pair; in the
+// patient (voxel-local frame) x and y as pairs too, in a slab plain FP32
+template <bool Slab>
+__device__ __forceinline__ void move(Lane &v, DF h) {
+    const DF z = df_add({v.pz, v.pzlo}, df_mul_f(h, v.dz));
+    v.pz = z.h;
+    v.pzlo = z.l;
+    if (Slab) {
+        v.px = fmaf(h.h, v.dx, v.px);
+        v.py = fmaf(h.h, v.dy, v.py);
+    } else {
+        const DF x = df_add({v.px, v.pxlo}, df_mul_f(h, v.dx));
+        const DF y = df_add({v.py, v.pylo}, df_mul_f(h, v.dy));
+        v.px = x.h;
+        v.pxlo = x.l;
+        v.py = y.h;
+        v.pylo = y.l;
+    }
+}
+
 // One condensed-history step in a homogeneous region: CSDA loss from the
 // range table, Bohr straggling, Gaussian multiple scattering applied at the
 // step midpoint (hinge), nuclear removal turning the VP into its leading
 // secondary.  rho_loss scales energy loss and straggling (range scenarios),
 // rho scattering and nuclear removal.  dg: distance to the region boundary.
-template <bool CompDepth>
-__device__ int phys_step(Lane &v, const float *tab, int m, float rho_loss, float rho, float dg,
-                         float &dep, float &esc) {
+// Energy, residual range, path and density are pairs (double-float); the
+// decisions (range-out, step length) and the physics sampling use FP32.
+template <bool Slab>
+__device__ int phys_step(Lane &v, const float *tab, int m, DF rho_loss, float rho, DF dg, float &dep,
+                         float &esc) {
     dep = 0.0f;
     esc = 0.0f;
     v.nsteps++;
-    if (v.E <= kELo) {
+    if (v.E + v.Elo <= kELo) {
         dep = v.E + v.Elo;
         v.E = v.Elo = 0.0f;
         return ST_STOP;
     }
     const float *tm = tab + TAB_MAT0 + m * TAB_PER_MAT;
-    const int i = seg_of(tab, v.E);
-    const float x = (v.E - tab[TAB_E + i]) + v.Elo;
-    const float slope = tm[T_SLOPE * NE + i];
-    const float R = tm[T_R * NE + i] + x * __builtin_amdgcn_rcpf(slope);
-    if (rho_loss * dg >= R) {
+    int i = seg_of(tab, v.E);
+    // E - E_i: the high parts subtract exactly (same binade), the low parts add
+    DF x = two_sum(v.E - tab[TAB_E + i], v.Elo - tab[TAB_EL + i]);
+    if (x.h < 0.0f && i > 0) {
+        --i;
+        x = two_sum(v.E - tab[TAB_E + i], v.Elo - tab[TAB_EL + i]);
+    }
+    const DF S = {tm[T_SH * NE + i], tm[T_SL * NE + i]};
+    const DF rem = df_div(x, S);
+    const float R = tm[T_R * NE + i] + rem.h;
+    if (rho_loss.h * dg.h >= R) {
         dep = v.E + v.Elo;
         v.E = v.Elo = 0.0f;
         return ST_STOP;
     }
-    const float smax = STEP_FRACTION * R * __builtin_amdgcn_rcpf(rho_loss);
-    const bool geo = dg <= smax;
-    const float s = geo ? dg : smax;
-    const float r = rho_loss * s;   // density x mm (the tables' unit)
-    float dE = csda_loss(tm, i, x, slope, r);
-    const float Ebar = v.E - 0.5f * dE;
+    const float smax = STEP_FRACTION * R * __builtin_amdgcn_rcpf(rho_loss.h);
+    const bool geo = dg.h <= smax;
+    const DF s = geo ? dg : DF{smax, 0.0f};
+    const DF r = df_mul(rho_loss, s);   // density x mm (the tables' unit)
+    DF dE = csda_loss(tab, tm, i, x, rem, r);
+    const float Ebar = v.E - 0.5f * dE.h;
     uint4 w = make_uint4(0u, 0u, 0u, 0xFFFFFFFFu);
     NodePos pb{0, 0.0f};
     if (v.physics) {
@@ -193,32 +274,28 @@ __device__ int phys_step(Lane &v, const float *tab, int m, float rho_loss, float
         pb = node_pos(tab, Ebar);
     }
     if (v.physics & PH_STRAGGLE) {
-        const float var = r * node_lerp(tm + T_W2 * NE, pb);
+        const float var = r.h * node_lerp(tm + T_W2 * NE, pb);
         const float z = 1.41421356237f * erfinvf(2.0f * unit_open(w.z) - 1.0f);
-        dE -= sqrtf(var) * z;
-        dE = fminf(fmaxf(dE, 0.0f), v.E + v.Elo);
+        dE = df_add(dE, {-(sqrtf(var) * z), 0.0f});
+        const float tot = v.E + v.Elo;
+        if (!(dE.h + dE.l > 0.0f)) dE = {0.0f, 0.0f};
+        else if (dE.h + dE.l > tot) dE = {v.E, v.Elo};
     }
-    dep = dE;
+    dep = dE.h + dE.l;
     sub_energy(v, dE);
     if (v.physics & PH_MCS) {
-        const float th0 = sqrtf(rho * s * node_lerp(tm + T_T * NE, pb));
+        const float th0 = sqrtf(rho * s.h * node_lerp(tm + T_T * NE, pb));
         float z1, z2;
         box_muller_fast(w.x, w.y, z1, z2);
-        const float h = 0.5f * s;
-        v.px = fmaf(h, v.dx, v.px);
-        v.py = fmaf(h, v.dy, v.py);
-        if (CompDepth) add_depth(v, h * v.dz); else v.pz = fmaf(h, v.dz, v.pz);
+        const DF h = {0.5f * s.h, 0.5f * s.l};
+        move<Slab>(v, h);
         rotate_dir(v, th0 * z1, th0 * z2);
-        v.px = fmaf(h, v.dx, v.px);
-        v.py = fmaf(h, v.dy, v.py);
-        if (CompDepth) add_depth(v, h * v.dz); else v.pz = fmaf(h, v.dz, v.pz);
+        move<Slab>(v, h);
     } else {
-        v.px = fmaf(s, v.dx, v.px);
-        v.py = fmaf(s, v.dy, v.py);
-        if (CompDepth) add_depth(v, s * v.dz); else v.pz = fmaf(s, v.dz, v.pz);
+        move<Slab>(v, s);
     }
     if (v.physics & PH_NUCLEAR) {
-        const float P = -expm1f(-rho * s * node_lerp(tm + T_SN * NE, pb));
+        const float P = -expm1f(-rho * s.h * node_lerp(tm + T_SN * NE, pb));
         if (unit_open(w.w) < P) {
             const uint4 w2 = draw(v);
             const float E1 = v.E + v.Elo;
@@ -310,14 +387,15 @@ __device__ __forceinline__ float edge_distance(const float2 *poly, int nv, float
 }
 
 // Inside a slab (range shifter or block) the depth is kept relative to the
-// slab's upstream face as a compensated pair (pz + pzlo), so the distance to
-// the exit plane stays exact to FP32 rounding of the step lengths rather than
-// of the absolute beam-frame depth.
-__device__ __forceinline__ float plane_distance(const Lane &v, float thick, bool &down) {
-    if (v.dz > 0.0f) { down = true; return ((thick - v.pz) - v.pzlo) / v.dz; }
-    if (v.dz < 0.0f) { down = false; return (-v.pz - v.pzlo) / v.dz; }
+// slab's upstream face as a pair (pz + pzlo) and the thickness is a pair, so
+// the path to the exit plane is exact to the pairs' precision rather than to
+// FP32 rounding of the step lengths or of the absolute beam-frame depth.
+__device__ __forceinline__ DF plane_distance(const Lane &v, DF thick, bool &down) {
+    DF t = {INFINITY, 0.0f};
     down = true;
-    return INFINITY;
+    if (v.dz > 0.0f) t = df_div_f(df_sub(thick, {v.pz, v.pzlo}), v.dz);
+    else if (v.dz < 0.0f) { down = false; t = df_div_f({-v.pz, -v.pzlo}, v.dz); }
+    return t.h > 0.0f ? t : DF{0.0f, 0.0f};
 }
 
 // push the projected (beam's-eye-view) position EDGE_PUSH_MM further along
@@ -335,20 +413,20 @@ enum { EX_DOWN = 0, EX_GONE = 1 };
 
 // homogeneous slab (range shifter): local depth 0 .. thick; on return the
 // depth is the global plane z the VP left through
-__device__ int slab_transport(Lane &v, Acc &acc, float scale, const float *tab, int m, float rho,
-                              float zu, float zd, float thick, int ledger) {
+__device__ int slab_transport(Lane &v, Acc &acc, float scale, const float *tab, int m, DF rho,
+                              float zu, float zd, DF thick, int ledger) {
     v.pz = 0.0f;
     v.pzlo = 0.0f;
     for (int it = 0; it < MAX_STEPS; ++it) {
         bool down;
-        float tp = fmaxf(plane_distance(v, thick, down), 0.0f);
+        const DF tp = plane_distance(v, thick, down);
         float dep, esc;
-        const int st = phys_step<true>(v, tab, m, rho, rho, tp, dep, esc);
+        const int st = phys_step<true>(v, tab, m, rho, rho.h, tp, dep, esc);
         ledger_add(acc, ledger, dep, scale);
         ledger_add(acc, L_NUC, esc, scale);
         if (st == ST_STOP) return EX_GONE;
-        if (st == ST_GEO || v.pz >= thick || v.pz <= 0.0f) {
-            const bool out_down = (st == ST_GEO) ? down : (v.pz >= thick);
+        if (st == ST_GEO || v.pz >= thick.h || v.pz <= 0.0f) {
+            const bool out_down = (st == ST_GEO) ? down : (v.pz >= thick.h);
             v.pz = out_down ? zd : zu;
             v.pzlo = 0.0f;
             if (out_down) return EX_DOWN;
@@ -364,12 +442,13 @@ __device__ int slab_transport(Lane &v, Acc &acc, float scale, const float *tab, 
 // number at the VP's projected position decides, at every step, opening
 // (straight transport, no random numbers) or brass (brass tables).
 __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab, const float2 *poly,
-                               int nv, float rho_b, float zu, float zd, float thick) {
+                               int nv, float rho_b, float zu, float zd, DF thick) {
     v.pz = 0.0f;
     v.pzlo = 0.0f;
     for (int it = 0; it < MAX_BLOCK_ITER; ++it) {
         bool down;
-        const float tp = fmaxf(plane_distance(v, thick, down), 0.0f);
+        const DF tpp = plane_distance(v, thick, down);
+        const float tp = tpp.h;
         const bool open = nv >= 3 && in_polygon(poly, nv, v.px, v.py);
         const float te = nv >= 3 ? edge_distance(poly, nv, v.px, v.py, v.dx, v.dy) : INFINITY;
         if (open) {
@@ -382,15 +461,13 @@ __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab,
                 ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
                 return EX_GONE;
             }
-            v.px = fmaf(te, v.dx, v.px);
-            v.py = fmaf(te, v.dy, v.py);
-            add_depth(v, te * v.dz);
+            move<true>(v, {te, 0.0f});
             edge_push(v);
             continue;
         }
-        const float dg = fminf(te, tp);
+        const DF dg = te < tp ? DF{te, 0.0f} : tpp;
         float dep, esc;
-        const int st = phys_step<true>(v, tab, MAT_BRASS, rho_b, rho_b, dg, dep, esc);
+        const int st = phys_step<true>(v, tab, MAT_BRASS, {rho_b, 0.0f}, rho_b, dg, dep, esc);
         ledger_add(acc, L_BLOCK, dep, scale);
         ledger_add(acc, L_NUC, esc, scale);
         if (st == ST_STOP) return EX_GONE;
@@ -402,7 +479,7 @@ __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab,
             return EX_GONE;
         }
         if (st == ST_GEO) edge_push(v);
-        if (v.pz >= thick) { v.pz = zd; v.pzlo = 0.0f; return EX_DOWN; }
+        if (v.pz >= thick.h) { v.pz = zd; v.pzlo = 0.0f; return EX_DOWN; }
         if (v.pz <= 0.0f) {
             v.pz = zu;
             v.pzlo = 0.0f;
@@ -447,7 +524,8 @@ __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const 
             v.px = qx;
             v.py = qy;
             v.pz = f.rs_zu;
-            if (slab_transport(v, acc, scale, tab, MAT_PMMA, f.rs_rho, f.rs_zu, f.rs_zd, f.rs_t, L_RS) != EX_DOWN)
+            if (slab_transport(v, acc, scale, tab, MAT_PMMA, {f.rs_rho, f.rs_rhol}, f.rs_zu, f.rs_zd,
+                               {f.rs_t, f.rs_tl}, L_RS) != EX_DOWN)
                 return BL_STOP;
             tmin = 0.0f;
         }
@@ -498,7 +576,7 @@ __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const 
         v.px = qx;
         v.py = qy;
         v.pz = f.blk_zu;
-        if (block_transport(v, acc, scale, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, f.blk_t) != EX_DOWN)
+        if (block_transport(v, acc, scale, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl}) != EX_DOWN)
             return BL_STOP;
         tmin = 0.0f;
     }
@@ -508,13 +586,36 @@ __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const 
 // ------------------------------------------------------------ patient
 // CT calibration: density piecewise linear through (-1000, 0.00121)
 // (0, 1) (1000, 1.6) (1500, 1.85) (3071, 2.8); class air / tissue / bone.
-__device__ __forceinline__ void hu_material(int hu, int &m, float &rho) {
-    const float h = (float)min(max(hu, -1000), 3071);
-    if (h <= 0.0f) rho = 0.00121f + (h + 1000.0f) * ((1.0f - 0.00121f) / 1000.0f);
-    else if (h <= 1000.0f) rho = 1.0f + h * (0.6f / 1000.0f);
-    else if (h <= 1500.0f) rho = 1.6f + (h - 1000.0f) * (0.25f / 500.0f);
-    else rho = 1.85f + (h - 1500.0f) * (0.95f / 1571.0f);
+// The density is a pair: node values and slopes are FP64 constants split at
+// compile time, the CT number is an exact integer.
+struct PairC {
+    float h, l;
+};
+constexpr PairC pairc(double x) { return {(float)x, (float)(x - (double)(float)x)}; }
+constexpr PairC kCalY[4] = {pairc(0.00121), pairc(1.0), pairc(1.6), pairc(1.85)};
+constexpr PairC kCalB[4] = {pairc((1.0 - 0.00121) / 1000.0), pairc(0.6 / 1000.0), pairc(0.25 / 500.0),
+                            pairc(0.95 / 1571.0)};
+constexpr float kCalX[4] = {-1000.0f, 0.0f, 1000.0f, 1500.0f};
+
+__device__ __forceinline__ DF hu_density(int hu, int &m) {
+    const int hc = min(max(hu, -1000), 3071);
+    const int k = hc <= 0 ? 0 : hc <= 1000 ? 1 : hc <= 1500 ? 2 : 3;
+    const PairC y = k == 0 ? kCalY[0] : k == 1 ? kCalY[1] : k == 2 ? kCalY[2] : kCalY[3];
+    const PairC b = k == 0 ? kCalB[0] : k == 1 ? kCalB[1] : k == 2 ? kCalB[2] : kCalB[3];
+    const float x0 = k == 0 ? kCalX[0] : k == 1 ? kCalX[1] : k == 2 ? kCalX[2] : kCalX[3];
     m = hu < -900 ? MAT_AIR : hu < 150 ? MAT_WATER : MAT_BONE;
+    return df_add({y.h, y.l}, df_mul_f({b.h, b.l}, (float)hc - x0));
+}
+
+__device__ __forceinline__ void hu_material(int hu, int &m, float &rho) {
+    const DF d = hu_density(hu, m);
+    rho = d.h + d.l;
+}
+
+// keep a voxel-local coordinate pair inside [0, sp]
+__device__ __forceinline__ void clamp_pair(float &h, float &l, float sp) {
+    if (h < 0.0f || (h == 0.0f && l < 0.0f)) { h = 0.0f; l = 0.0f; }
+    else if (h > sp || (h == sp && l > 0.0f)) { h = sp; l = 0.0f; }
 }
 
 template <class Sink>
@@ -580,25 +681,39 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
             if (t0 == tnear && k == axn) u[k] = d[k] > 0.0f ? 0.0f : g.sp[k];
         }
         v.px = u[0]; v.py = u[1]; v.pz = u[2];
+        v.pxlo = v.pylo = v.pzlo = 0.0f;
     }
     v.dx = d[0]; v.dy = d[1]; v.dz = d[2];
     uint32_t vox = (uint32_t)idx[0] + (uint32_t)g.nx * ((uint32_t)idx[1] + (uint32_t)g.ny * (uint32_t)idx[2]);
     int hu = g.kind == 1 ? (int)g.hu[vox] : 0;
     for (int it = 0; it < MAX_STEPS; ++it) {
         int m = MAT_WATER;
-        float rho = 1.0f;
-        if (g.kind == 1) hu_material(hu, m, rho);
-        const float rho_loss = rho * range_scale;
-        const float pp[3] = {v.px, v.py, v.pz}, dd[3] = {v.dx, v.dy, v.dz};
-        float dg = INFINITY;
+        DF rho = {1.0f, 0.0f};
+        if (g.kind == 1) rho = hu_density(hu, m);
+        const DF rho_loss = df_mul_f(rho, range_scale);
+        // exit face: the axis with the shortest FP32 distance, then that
+        // distance as a pair from the pair coordinate
+        float dgf = INFINITY;
         int ax = -1, sgn = 0;
+        {
+            const float pp[3] = {v.px, v.py, v.pz}, pl[3] = {v.pxlo, v.pylo, v.pzlo}, dd[3] = {v.dx, v.dy, v.dz};
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            if (dd[k] == 0.0f) continue;
-            const bool up = dd[k] > 0.0f;
-            // hardware reciprocal: exact for the unit components of axis-aligned beams
-            const float t = fmaxf(((up ? g.sp[k] : 0.0f) - pp[k]) * __builtin_amdgcn_rcpf(dd[k]), 0.0f);
-            if (t < dg) { dg = t; ax = k; sgn = up ? 1 : -1; }
+            for (int k = 0; k < 3; ++k) {
+                if (dd[k] == 0.0f) continue;
+                const bool up = dd[k] > 0.0f;
+                const float t = fmaxf((((up ? g.sp[k] : 0.0f) - pp[k]) - pl[k]) * __builtin_amdgcn_rcpf(dd[k]), 0.0f);
+                if (t < dgf) { dgf = t; ax = k; sgn = up ? 1 : -1; }
+            }
+        }
+        DF dg = {INFINITY, 0.0f};
+        if (ax >= 0) {
+            // selects, not indexing: the per-axis values stay in registers
+            const float pa = ax == 0 ? v.px : ax == 1 ? v.py : v.pz;
+            const float la = ax == 0 ? v.pxlo : ax == 1 ? v.pylo : v.pzlo;
+            const float da = ax == 0 ? v.dx : ax == 1 ? v.dy : v.dz;
+            const float spa = ax == 0 ? g.sp[0] : ax == 1 ? g.sp[1] : g.sp[2];
+            dg = df_div_f(df_sub({sgn > 0 ? spa : 0.0f, 0.0f}, {pa, la}), da);
+            if (!(dg.h > 0.0f)) dg = {0.0f, 0.0f};
         }
         // the CT number behind the face this step may cross is fetched now,
         // so its latency overlaps the step's arithmetic
@@ -606,7 +721,6 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
         uint32_t nvox = vox;
         int hu_next = hu;
         if (ax >= 0) {
-            // selects, not indexing: the per-axis arrays stay in registers
             const int ia = ax == 0 ? idx[0] : ax == 1 ? idx[1] : idx[2];
             const int na = ax == 0 ? n[0] : ax == 1 ? n[1] : n[2];
             const int sa = ax == 0 ? 1 : ax == 1 ? g.nx : g.nx * g.ny;
@@ -617,20 +731,18 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
             }
         }
         float dep, esc;
-        const int st = phys_step<false>(v, tab, m, rho_loss, rho, dg, dep, esc);
+        const int st = phys_step<false>(v, tab, m, rho_loss, rho.h, dg, dep, esc);
         const long long qd = to_fixed(dep, scale);
         if (qd != 0) sink.add(vox, qd);
         acc.led[L_GRID] += qd;
         ledger_add(acc, L_NUC, esc, scale);
         if (st == ST_STOP) return;
-        float q[3] = {v.px, v.py, v.pz};
         if (st == ST_GEO) {
             bool out = false;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 if (k == ax) {
                     idx[k] = nidx;
-                    q[k] = sgn > 0 ? 0.0f : g.sp[k];   // near face of the next voxel
                     out = nidx < 0 || nidx >= n[k];
                 }
             }
@@ -638,12 +750,17 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
                 ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
                 return;
             }
+            // near face of the next voxel, exactly
+            const float face_next = sgn > 0 ? 0.0f : (ax == 0 ? g.sp[0] : ax == 1 ? g.sp[1] : g.sp[2]);
+            if (ax == 0) { v.px = face_next; v.pxlo = 0.0f; }
+            else if (ax == 1) { v.py = face_next; v.pylo = 0.0f; }
+            else { v.pz = face_next; v.pzlo = 0.0f; }
             vox = nvox;
             hu = hu_next;
         }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) q[k] = fminf(fmaxf(q[k], 0.0f), g.sp[k]);
-        v.px = q[0]; v.py = q[1]; v.pz = q[2];
+        clamp_pair(v.px, v.pxlo, g.sp[0]);
+        clamp_pair(v.py, v.pylo, g.sp[1]);
+        clamp_pair(v.pz, v.pzlo, g.sp[2]);
     }
     ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
 }
@@ -658,6 +775,7 @@ __device__ void source(Lane &v, const SpotDev &sp) {
     v.py = fmaf(sp.sigma, r * sn, sp.y);
     v.pz = 0.0f;
     v.pzlo = 0.0f;
+    v.pxlo = v.pylo = 0.0f;
     v.dx = 0.0f; v.dy = 0.0f; v.dz = 1.0f;
     v.E = sp.e0;
     v.Elo = 0.0f;
@@ -732,8 +850,8 @@ __global__ __launch_bounds__(512) void transport_kernel(GeomDev g, FieldDev f, L
 // histories of one row) at a time from the epoch's atomic counter, so rows
 // of uneven energy and history count balance across the chip.  Every wave
 // exits once the counter passes the number of chunks.
-// at most 512 threads per workgroup; 4 waves per SIMD keeps the VGPRs <= 128
-__global__ __launch_bounds__(512, 4) void queue_kernel(GeomDev g, QueueDev Q) {
+// at most 512 threads per workgroup; 3 waves per SIMD leave the step 168 VGPRs (no spills)
+__global__ __launch_bounds__(512, 3) void queue_kernel(GeomDev g, QueueDev Q) {
     __shared__ float tab[TAB_FLOATS];
     __shared__ float2 poly[POLY_LDS];
     for (int i = threadIdx.x; i < TAB_FLOATS / 4; i += blockDim.x)
@@ -1004,6 +1122,7 @@ __global__ __launch_bounds__(256) void surrogate_sample_kernel(FieldDev f, const
         v.py = e[1];
         v.pz = f.blk_zu;
         v.pzlo = 0.0f;
+        v.pxlo = v.pylo = 0.0f;
         v.dx = e[2];
         v.dy = e[3];
         v.dz = sqrtf(fmaxf(1.0f - e[2] * e[2] - e[3] * e[3], 0.0f));
@@ -1031,7 +1150,7 @@ __global__ __launch_bounds__(256) void surrogate_sample_kernel(FieldDev f, const
         Acc acc;
 #pragma unroll
         for (int k = 0; k < NLEDGER; ++k) acc.led[k] = 0;
-        const int ex = block_transport(v, acc, 1.0f, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, f.blk_t);
+        const int ex = block_transport(v, acc, 1.0f, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl});
         if (ex != EX_DOWN) {
             to[i] = 0.0f;
             continue;
@@ -1075,7 +1194,7 @@ __device__ void resume_deferred(Lane &v, Acc &acc, float scale, const float *tab
     const float ptrans = 1.0f / (1.0f + __expf(-o[0]));
     bool go = true;
     if (!(ptrans < p_lo || ptrans > p_hi)) {
-        go = block_transport(v, acc, scale, tab, poly, f.nv, f.blk_rho, f.blk_zu, f.blk_zd, f.blk_t) == EX_DOWN;
+        go = block_transport(v, acc, scale, tab, poly, f.nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl}) == EX_DOWN;
     } else {
         v.E += v.Elo;
         v.Elo = 0.0f;
@@ -1135,6 +1254,7 @@ __device__ __forceinline__ void lane_from_record(Lane &v, const DeferRec &r, uin
     v.py = r.y;
     v.pz = zu;
     v.pzlo = r.pzlo;
+    v.pxlo = v.pylo = 0.0f;
     v.dx = r.u;
     v.dy = r.v;
     v.dz = r.w;

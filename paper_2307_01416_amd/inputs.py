@@ -62,10 +62,24 @@ class Geometry:
     origin: tuple                  # corner of voxel (0,0,0), mm
     hu: Optional[np.ndarray] = None  # int16 [nz, ny, nx] for GEOM_HU
 
+    def __post_init__(self):
+        self.spacing = tuple(float(np.float32(x)) for x in self.spacing)
+        self.origin = tuple(float(np.float32(x)) for x in self.origin)
+
     @property
     def nvox(self) -> int:
         nx, ny, nz = self.shape
         return nx * ny * nz
+
+
+def f32(x) -> float:
+    """The value as the C ABI receives it (FP32), so that every consumer of a
+    case (library and reference alike) sees the same numbers."""
+    return float(np.float32(x))
+
+
+def f32s(xs) -> tuple:
+    return tuple(f32(x) for x in xs)
 
 
 @dataclasses.dataclass
@@ -77,6 +91,9 @@ class Beam:
     ey: tuple
     ez: tuple
 
+    def __post_init__(self):
+        self.iso, self.ex, self.ey, self.ez = f32s(self.iso), f32s(self.ex), f32s(self.ey), f32s(self.ez)
+
 
 @dataclasses.dataclass
 class Block:
@@ -84,12 +101,19 @@ class Block:
     density_gcc: float = 8.5
     downstream_mm: float = 150.0   # downstream face to the beam-frame origin
 
+    def __post_init__(self):
+        self.thickness_mm, self.density_gcc, self.downstream_mm = f32s(
+            (self.thickness_mm, self.density_gcc, self.downstream_mm))
+
 
 @dataclasses.dataclass
 class RangeShifter:
     wet_mm: float = 45.0
     diameter_mm: float = 61.0
     downstream_mm: float = 190.0   # downstream face to the beam-frame origin
+
+    def __post_init__(self):
+        self.wet_mm, self.diameter_mm, self.downstream_mm = f32s((self.wet_mm, self.diameter_mm, self.downstream_mm))
 
 
 @dataclasses.dataclass
@@ -105,6 +129,10 @@ class Field:
 class Scenario:
     shift_mm: tuple = (0.0, 0.0, 0.0)
     range_scale: float = 1.0
+
+    def __post_init__(self):
+        self.shift_mm = f32s(self.shift_mm)
+        self.range_scale = f32(self.range_scale)
 
 
 @dataclasses.dataclass

@@ -33,6 +33,7 @@ def test_straight_idd_closed_form(orc, scale):
     # E(z_k) - E(z_k+1) exactly; the VP stops where R(E) <= rho_s * dz.
     c = I.config1(n_histories=10, physics=0)
     c.scenarios = [I.Scenario(range_scale=scale)]
+    scale = c.scenarios[0].range_scale   # the FP32 value the case carries
     led, info, grid = orc.trace_history(c, 0, 3, want_grid=True)
     idd = grid.reshape(100, 50, 50).sum(axis=(1, 2))
     E0, dz = 100.0, 2.0
