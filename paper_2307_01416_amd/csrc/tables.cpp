@@ -140,12 +140,13 @@ void pack_device_tables(float *blob) {
     }
     for (int m = 0; m < NMAT; ++m) {
         float *b = blob + TAB_MAT0 + m * TAB_PER_MAT;
+        float *bl = blob + TAB_LMAT0 + m * TAB_PER_LMAT;
         for (int i = 0; i < NE; ++i) {
             b[T_R * NE + i] = (float)(10.0 * t.R[m][i]);
             if (i + 1 < NE) {
                 const double dR = 10.0 * (t.R[m][i + 1] - t.R[m][i]);
-                split_pair((t.E[i + 1] - t.E[i]) / dR, b + T_SH * NE + i, b + T_SL * NE + i);
-                split_pair(dR, b + T_DH * NE + i, b + T_DL * NE + i);
+                split_pair((t.E[i + 1] - t.E[i]) / dR, b + T_SH * NE + i, bl + L_SL * NE + i);
+                split_pair(dR, b + T_DH * NE + i, bl + L_DL * NE + i);
             }
             b[T_W2 * NE + i] = (float)(0.1 * t.W2[m][i]);
             b[T_T * NE + i] = (float)(0.1 * t.T[m][i]);

@@ -14,15 +14,20 @@ constexpr double E_LO = 1.0;
 constexpr double E_HI = 256.0;
 enum Material { MAT_WATER = 0, MAT_AIR = 1, MAT_PMMA = 2, MAT_BRASS = 3, MAT_BONE = 4 };
 
-// FP32 device blob.  Shared: energy nodes as (high, low) FP32 pairs of the
-// FP64 nodes, segment energy widths E_i+1 - E_i as pairs.
-// Per material: R, dE/dR per segment as a pair, R_i+1 - R_i as a pair,
+// FP32 device blob, high parts first.  Shared: energy nodes, segment energy
+// widths E_i+1 - E_i.  Per material: R, dE/dR per segment, R_i+1 - R_i,
 // omega^2, T, Sigma_nuc; NE floats each, all per unit of density x path
-// length in mm (10 x g/cm^2).  The pairs carry the FP64 table values to
-// ~1e-14 so the energy-loss bookkeeping can run in double-float arithmetic.
-enum { TAB_E = 0, TAB_EL = NE, TAB_DWH = 2 * NE, TAB_DWL = 3 * NE, TAB_MAT0 = 4 * NE, TAB_PER_MAT = 8 * NE };
-enum { T_R = 0, T_SH = 1, T_SL = 2, T_DH = 3, T_DL = 4, T_W2 = 5, T_T = 6, T_SN = 7 };
-constexpr int TAB_FLOATS = 4 * NE + NMAT * 8 * NE;   // 11264 floats = 44 KiB of LDS
+// length in mm (10 x g/cm^2).  Then the low parts that make the node, width,
+// slope and range-width tables (high, low) FP32 pairs of the FP64 values, for
+// the double-float bookkeeping of the deterministic mode; the physics-mode
+// kernels stage only the high block (32 KiB) in LDS.
+enum { TAB_E = 0, TAB_DWH = NE, TAB_MAT0 = 2 * NE, TAB_PER_MAT = 6 * NE };
+enum { T_R = 0, T_SH = 1, T_DH = 2, T_W2 = 3, T_T = 4, T_SN = 5 };
+constexpr int TAB_HI_FLOATS = 2 * NE + NMAT * 6 * NE;    // 8192 floats = 32 KiB
+enum { TAB_EL = TAB_HI_FLOATS, TAB_DWL = TAB_HI_FLOATS + NE, TAB_LMAT0 = TAB_HI_FLOATS + 2 * NE,
+       TAB_PER_LMAT = 2 * NE };
+enum { L_SL = 0, L_DL = 1 };
+constexpr int TAB_FLOATS = TAB_HI_FLOATS + 2 * NE + NMAT * 2 * NE;   // 11264 floats = 44 KiB
 
 struct MaterialDef {
     double z_over_a, mean_exc_ev, rad_len_gcm2, nuc_coeff, density;

@@ -147,18 +147,7 @@ __device__ __forceinline__ float node_lerp(const float *y, NodePos p) {
 // segment i of the piecewise-linear CSDA relation E(R), whose range within
 // the segment is rem = x / slope_i.  Whole segments crossed contribute their
 // exact energy width; the last partial segment r * slope_j.  All in pairs.
-__device__ __forceinline__ DF csda_loss(const float *tab, const float *tm, int i, DF x, DF rem, DF r) {
-    if (df_le(r, rem)) return df_mul(r, {tm[T_SH * NE + i], tm[T_SL * NE + i]});
-    DF dE = x;
-    r = df_sub(r, rem);
-    for (int j = i - 1; j >= 0; --j) {
-        const DF dRj = {tm[T_DH * NE + j], tm[T_DL * NE + j]};
-        if (df_le(r, dRj)) return df_add(dE, df_mul(r, {tm[T_SH * NE + j], tm[T_SL * NE + j]}));
-        dE = df_add(dE, {tab[TAB_DWH + j], tab[TAB_DWL + j]});
-        r = df_sub(r, dRj);
-    }
-    return dE;
-}
+
 
 __device__ __forceinline__ void rotate_dir(Lane &v, float ax, float ay) {
     const float th2 = ax * ax + ay * ay;
@@ -181,11 +170,7 @@ __device__ __forceinline__ void rotate_dir(Lane &v, float ax, float ay) {
     v.dz = nz * inv;
 }
 
-__device__ __forceinline__ void sub_energy(Lane &v, DF dE) {
-    const DF e = df_sub({v.E, v.Elo}, dE);
-    v.E = e.h;
-    v.Elo = e.l;
-}
+
 
 // (pz, pzlo) += dz with an error-free two-sum
 __device__ __forceinline__ void add_depth(Lane &v, float dz) {
@@ -207,14 +192,54 @@ __device__ __forceinline__ DF df_div_f(DF a, float b) {
     return fast2(q, (r.h + r.l) * rb);
 }
 
-// move by the path length h along d: the depth always as a pair; in the
-// patient (voxel-local frame) x and y as pairs too, in a slab plain FP32
-template <bool Slab>
+// 1/b to within about half an ulp: hardware estimate and one Newton step
+// (the raw estimate's error has a fixed sign)
+__device__ __forceinline__ float rcp_nr(float b) {
+    const float r = __builtin_amdgcn_rcpf(b);
+    return fmaf(r, fmaf(-b, r, 1.0f), r);
+}
+
+// Arithmetic of the two transport instantiations.  Exact (deterministic
+// mode, checked against the FP64 reference to 1e-5 per voxel): double-float
+// pairs.  Physics mode: plain FP32 on the high parts, the low parts constant
+// zero and folded away; the per-step losses carry the straggling noise, next
+// to which FP32 rounding is immaterial.
+template <bool X>
+struct Ar;
+
+template <>
+struct Ar<true> {
+    static __device__ __forceinline__ DF pair(float h, float l) { return {h, l}; }
+    static __device__ __forceinline__ DF add(DF a, DF b) { return df_add(a, b); }
+    static __device__ __forceinline__ DF sub(DF a, DF b) { return df_sub(a, b); }
+    static __device__ __forceinline__ DF mul(DF a, DF b) { return df_mul(a, b); }
+    static __device__ __forceinline__ DF mul_f(DF a, float b) { return df_mul_f(a, b); }
+    static __device__ __forceinline__ DF div(DF a, DF b) { return df_div(a, b); }
+    static __device__ __forceinline__ DF div_f(DF a, float b) { return df_div_f(a, b); }
+    static __device__ __forceinline__ bool le(DF a, DF b) { return df_le(a, b); }
+};
+
+template <>
+struct Ar<false> {
+    static __device__ __forceinline__ DF pair(float h, float) { return {h, 0.0f}; }
+    static __device__ __forceinline__ DF add(DF a, DF b) { return {a.h + b.h, 0.0f}; }
+    static __device__ __forceinline__ DF sub(DF a, DF b) { return {a.h - b.h, 0.0f}; }
+    static __device__ __forceinline__ DF mul(DF a, DF b) { return {a.h * b.h, 0.0f}; }
+    static __device__ __forceinline__ DF mul_f(DF a, float b) { return {a.h * b, 0.0f}; }
+    static __device__ __forceinline__ DF div(DF a, DF b) { return {a.h * rcp_nr(b.h), 0.0f}; }
+    static __device__ __forceinline__ DF div_f(DF a, float b) { return {a.h * rcp_nr(b), 0.0f}; }
+    static __device__ __forceinline__ bool le(DF a, DF b) { return a.h <= b.h; }
+};
+
+// move by the path length h along d: the depth as a pair; in the patient
+// (voxel-local frame) x and y as pairs too, in a slab plain FP32
+template <bool Slab, bool X>
 __device__ __forceinline__ void move(Lane &v, DF h) {
-    const DF z = df_add({v.pz, v.pzlo}, df_mul_f(h, v.dz));
+    using A = Ar<X>;
+    const DF z = A::add(A::pair(v.pz, v.pzlo), A::mul_f(h, v.dz));
     v.pz = z.h;
     v.pzlo = z.l;
-    if (Slab) {
+    if (Slab || !X) {
         v.px = fmaf(h.h, v.dx, v.px);
         v.py = fmaf(h.h, v.dy, v.py);
     } else {
@@ -227,6 +252,32 @@ __device__ __forceinline__ void move(Lane &v, DF h) {
     }
 }
 
+// (E, Elo) -= dE: exact pair arithmetic, or in physics mode the FP32 loss
+// compensated into the pair (so the energy still telescopes)
+template <bool X>
+__device__ __forceinline__ void sub_energy(Lane &v, DF dE) {
+    const DF e = df_sub({v.E, v.Elo}, X ? dE : DF{dE.h, 0.0f});
+    v.E = e.h;
+    v.Elo = e.l;
+}
+
+// tm: the material's high tables, tl: its low tables (read only when X)
+template <bool X>
+__device__ __forceinline__ DF csda_loss(const float *tab, const float *tm, const float *tl, int i, DF x, DF rem,
+                                        DF r) {
+    using A = Ar<X>;
+    if (A::le(r, rem)) return A::mul(r, A::pair(tm[T_SH * NE + i], X ? tl[L_SL * NE + i] : 0.0f));
+    DF dE = x;
+    r = A::sub(r, rem);
+    for (int j = i - 1; j >= 0; --j) {
+        const DF dRj = A::pair(tm[T_DH * NE + j], X ? tl[L_DL * NE + j] : 0.0f);
+        if (A::le(r, dRj)) return A::add(dE, A::mul(r, A::pair(tm[T_SH * NE + j], X ? tl[L_SL * NE + j] : 0.0f)));
+        dE = A::add(dE, A::pair(tab[TAB_DWH + j], X ? tab[TAB_DWL + j] : 0.0f));
+        r = A::sub(r, dRj);
+    }
+    return dE;
+}
+
 // One condensed-history step in a homogeneous region: CSDA loss from the
 // range table, Bohr straggling, Gaussian multiple scattering applied at the
 // step midpoint (hinge), nuclear removal turning the VP into its leading
@@ -234,9 +285,10 @@ __device__ __forceinline__ void move(Lane &v, DF h) {
 // rho scattering and nuclear removal.  dg: distance to the region boundary.
 // Energy, residual range, path and density are pairs (double-float); the
 // decisions (range-out, step length) and the physics sampling use FP32.
-template <bool Slab>
+template <bool Slab, bool X>
 __device__ int phys_step(Lane &v, const float *tab, int m, DF rho_loss, float rho, DF dg, float &dep,
                          float &esc) {
+    using A = Ar<X>;
     dep = 0.0f;
     esc = 0.0f;
     v.nsteps++;
@@ -246,15 +298,18 @@ __device__ int phys_step(Lane &v, const float *tab, int m, DF rho_loss, float rh
         return ST_STOP;
     }
     const float *tm = tab + TAB_MAT0 + m * TAB_PER_MAT;
+    const float *tl = tab + TAB_LMAT0 + m * TAB_PER_LMAT;
     int i = seg_of(tab, v.E);
     // E - E_i: the high parts subtract exactly (same binade), the low parts add
-    DF x = two_sum(v.E - tab[TAB_E + i], v.Elo - tab[TAB_EL + i]);
+    DF x = X ? two_sum(v.E - tab[TAB_E + i], v.Elo - tab[TAB_EL + i])
+             : DF{(v.E - tab[TAB_E + i]) + v.Elo, 0.0f};
     if (x.h < 0.0f && i > 0) {
         --i;
-        x = two_sum(v.E - tab[TAB_E + i], v.Elo - tab[TAB_EL + i]);
+        x = X ? two_sum(v.E - tab[TAB_E + i], v.Elo - tab[TAB_EL + i])
+              : DF{(v.E - tab[TAB_E + i]) + v.Elo, 0.0f};
     }
-    const DF S = {tm[T_SH * NE + i], tm[T_SL * NE + i]};
-    const DF rem = df_div(x, S);
+    const DF S = A::pair(tm[T_SH * NE + i], X ? tl[L_SL * NE + i] : 0.0f);
+    const DF rem = A::div(x, S);
     const float R = tm[T_R * NE + i] + rem.h;
     if (rho_loss.h * dg.h >= R) {
         dep = v.E + v.Elo;
@@ -264,8 +319,8 @@ __device__ int phys_step(Lane &v, const float *tab, int m, DF rho_loss, float rh
     const float smax = STEP_FRACTION * R * __builtin_amdgcn_rcpf(rho_loss.h);
     const bool geo = dg.h <= smax;
     const DF s = geo ? dg : DF{smax, 0.0f};
-    const DF r = df_mul(rho_loss, s);   // density x mm (the tables' unit)
-    DF dE = csda_loss(tab, tm, i, x, rem, r);
+    const DF r = A::mul(rho_loss, s);   // density x mm (the tables' unit)
+    DF dE = csda_loss<X>(tab, tm, tl, i, x, rem, r);
     const float Ebar = v.E - 0.5f * dE.h;
     uint4 w = make_uint4(0u, 0u, 0u, 0xFFFFFFFFu);
     NodePos pb{0, 0.0f};
@@ -276,23 +331,23 @@ __device__ int phys_step(Lane &v, const float *tab, int m, DF rho_loss, float rh
     if (v.physics & PH_STRAGGLE) {
         const float var = r.h * node_lerp(tm + T_W2 * NE, pb);
         const float z = 1.41421356237f * erfinvf(2.0f * unit_open(w.z) - 1.0f);
-        dE = df_add(dE, {-(sqrtf(var) * z), 0.0f});
+        dE = A::add(dE, {-(sqrtf(var) * z), 0.0f});
         const float tot = v.E + v.Elo;
         if (!(dE.h + dE.l > 0.0f)) dE = {0.0f, 0.0f};
         else if (dE.h + dE.l > tot) dE = {v.E, v.Elo};
     }
     dep = dE.h + dE.l;
-    sub_energy(v, dE);
+    sub_energy<X>(v, dE);
     if (v.physics & PH_MCS) {
         const float th0 = sqrtf(rho * s.h * node_lerp(tm + T_T * NE, pb));
         float z1, z2;
         box_muller_fast(w.x, w.y, z1, z2);
         const DF h = {0.5f * s.h, 0.5f * s.l};
-        move<Slab>(v, h);
+        move<Slab, X>(v, h);
         rotate_dir(v, th0 * z1, th0 * z2);
-        move<Slab>(v, h);
+        move<Slab, X>(v, h);
     } else {
-        move<Slab>(v, s);
+        move<Slab, X>(v, s);
     }
     if (v.physics & PH_NUCLEAR) {
         const float P = -expm1f(-rho * s.h * node_lerp(tm + T_SN * NE, pb));
@@ -390,11 +445,13 @@ __device__ __forceinline__ float edge_distance(const float2 *poly, int nv, float
 // slab's upstream face as a pair (pz + pzlo) and the thickness is a pair, so
 // the path to the exit plane is exact to the pairs' precision rather than to
 // FP32 rounding of the step lengths or of the absolute beam-frame depth.
+template <bool X>
 __device__ __forceinline__ DF plane_distance(const Lane &v, DF thick, bool &down) {
+    using A = Ar<X>;
     DF t = {INFINITY, 0.0f};
     down = true;
-    if (v.dz > 0.0f) t = df_div_f(df_sub(thick, {v.pz, v.pzlo}), v.dz);
-    else if (v.dz < 0.0f) { down = false; t = df_div_f({-v.pz, -v.pzlo}, v.dz); }
+    if (v.dz > 0.0f) t = A::div_f(A::sub(thick, A::pair(v.pz, v.pzlo)), v.dz);
+    else if (v.dz < 0.0f) { down = false; t = A::div_f(A::pair(-v.pz, -v.pzlo), v.dz); }
     return t.h > 0.0f ? t : DF{0.0f, 0.0f};
 }
 
@@ -413,15 +470,16 @@ enum { EX_DOWN = 0, EX_GONE = 1 };
 
 // homogeneous slab (range shifter): local depth 0 .. thick; on return the
 // depth is the global plane z the VP left through
+template <bool X>
 __device__ int slab_transport(Lane &v, Acc &acc, float scale, const float *tab, int m, DF rho,
                               float zu, float zd, DF thick, int ledger) {
     v.pz = 0.0f;
     v.pzlo = 0.0f;
     for (int it = 0; it < MAX_STEPS; ++it) {
         bool down;
-        const DF tp = plane_distance(v, thick, down);
+        const DF tp = plane_distance<X>(v, thick, down);
         float dep, esc;
-        const int st = phys_step<true>(v, tab, m, rho, rho.h, tp, dep, esc);
+        const int st = phys_step<true, X>(v, tab, m, rho, rho.h, tp, dep, esc);
         ledger_add(acc, ledger, dep, scale);
         ledger_add(acc, L_NUC, esc, scale);
         if (st == ST_STOP) return EX_GONE;
@@ -441,13 +499,14 @@ __device__ int slab_transport(Lane &v, Acc &acc, float scale, const float *tab, 
 // Methods B: between the block's entrance and exit planes the crossing
 // number at the VP's projected position decides, at every step, opening
 // (straight transport, no random numbers) or brass (brass tables).
+template <bool X>
 __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab, const float2 *poly,
                                int nv, float rho_b, float zu, float zd, DF thick) {
     v.pz = 0.0f;
     v.pzlo = 0.0f;
     for (int it = 0; it < MAX_BLOCK_ITER; ++it) {
         bool down;
-        const DF tpp = plane_distance(v, thick, down);
+        const DF tpp = plane_distance<X>(v, thick, down);
         const float tp = tpp.h;
         const bool open = nv >= 3 && in_polygon(poly, nv, v.px, v.py);
         const float te = nv >= 3 ? edge_distance(poly, nv, v.px, v.py, v.dx, v.dy) : INFINITY;
@@ -461,13 +520,13 @@ __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab,
                 ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
                 return EX_GONE;
             }
-            move<true>(v, {te, 0.0f});
+            move<true, X>(v, {te, 0.0f});
             edge_push(v);
             continue;
         }
         const DF dg = te < tp ? DF{te, 0.0f} : tpp;
         float dep, esc;
-        const int st = phys_step<true>(v, tab, MAT_BRASS, {rho_b, 0.0f}, rho_b, dg, dep, esc);
+        const int st = phys_step<true, X>(v, tab, MAT_BRASS, {rho_b, 0.0f}, rho_b, dg, dep, esc);
         ledger_add(acc, L_BLOCK, dep, scale);
         ledger_add(acc, L_NUC, esc, scale);
         if (st == ST_STOP) return EX_GONE;
@@ -514,6 +573,7 @@ __device__ float dist_to_polygon(const float2 *poly, int nv, float x, float y) {
 // on the VP's ray and tmin is the ray parameter of the last exit plane
 enum { BL_STOP = 0, BL_PATIENT = 1, BL_DEFER = 2 };
 
+template <bool X>
 __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const float2 *poly,
                         const FieldDev &f, float &tmin, const SurDev *sur = nullptr, uint32_t tag = 0u) {
     tmin = -INFINITY;
@@ -524,7 +584,7 @@ __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const 
             v.px = qx;
             v.py = qy;
             v.pz = f.rs_zu;
-            if (slab_transport(v, acc, scale, tab, MAT_PMMA, {f.rs_rho, f.rs_rhol}, f.rs_zu, f.rs_zd,
+            if (slab_transport<X>(v, acc, scale, tab, MAT_PMMA, {f.rs_rho, f.rs_rhol}, f.rs_zu, f.rs_zd,
                                {f.rs_t, f.rs_tl}, L_RS) != EX_DOWN)
                 return BL_STOP;
             tmin = 0.0f;
@@ -576,7 +636,8 @@ __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const 
         v.px = qx;
         v.py = qy;
         v.pz = f.blk_zu;
-        if (block_transport(v, acc, scale, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl}) != EX_DOWN)
+        if (block_transport<X>(v, acc, scale, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl}) !=
+            EX_DOWN)
             return BL_STOP;
         tmin = 0.0f;
     }
@@ -597,6 +658,7 @@ constexpr PairC kCalB[4] = {pairc((1.0 - 0.00121) / 1000.0), pairc(0.6 / 1000.0)
                             pairc(0.95 / 1571.0)};
 constexpr float kCalX[4] = {-1000.0f, 0.0f, 1000.0f, 1500.0f};
 
+template <bool X>
 __device__ __forceinline__ DF hu_density(int hu, int &m) {
     const int hc = min(max(hu, -1000), 3071);
     const int k = hc <= 0 ? 0 : hc <= 1000 ? 1 : hc <= 1500 ? 2 : 3;
@@ -604,11 +666,12 @@ __device__ __forceinline__ DF hu_density(int hu, int &m) {
     const PairC b = k == 0 ? kCalB[0] : k == 1 ? kCalB[1] : k == 2 ? kCalB[2] : kCalB[3];
     const float x0 = k == 0 ? kCalX[0] : k == 1 ? kCalX[1] : k == 2 ? kCalX[2] : kCalX[3];
     m = hu < -900 ? MAT_AIR : hu < 150 ? MAT_WATER : MAT_BONE;
+    if (!X) return {fmaf(b.h, (float)hc - x0, y.h), 0.0f};
     return df_add({y.h, y.l}, df_mul_f({b.h, b.l}, (float)hc - x0));
 }
 
 __device__ __forceinline__ void hu_material(int hu, int &m, float &rho) {
-    const DF d = hu_density(hu, m);
+    const DF d = hu_density<true>(hu, m);
     rho = d.h + d.l;
 }
 
@@ -618,7 +681,7 @@ __device__ __forceinline__ void clamp_pair(float &h, float &l, float sp) {
     else if (h > sp || (h == sp && l > 0.0f)) { h = sp; l = 0.0f; }
 }
 
-template <class Sink>
+template <class Sink, bool X>
 __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const GeomDev &g,
                         const FieldDev &f, const float *shift, float range_scale, const Sink &sink,
                         float tmin) {
@@ -689,8 +752,8 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
     for (int it = 0; it < MAX_STEPS; ++it) {
         int m = MAT_WATER;
         DF rho = {1.0f, 0.0f};
-        if (g.kind == 1) rho = hu_density(hu, m);
-        const DF rho_loss = df_mul_f(rho, range_scale);
+        if (g.kind == 1) rho = hu_density<X>(hu, m);
+        const DF rho_loss = Ar<X>::mul_f(rho, range_scale);
         // exit face: the axis with the shortest FP32 distance, then that
         // distance as a pair from the pair coordinate
         float dgf = INFINITY;
@@ -705,8 +768,8 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
                 if (t < dgf) { dgf = t; ax = k; sgn = up ? 1 : -1; }
             }
         }
-        DF dg = {INFINITY, 0.0f};
-        if (ax >= 0) {
+        DF dg = {dgf, 0.0f};
+        if (X && ax >= 0) {
             // selects, not indexing: the per-axis values stay in registers
             const float pa = ax == 0 ? v.px : ax == 1 ? v.py : v.pz;
             const float la = ax == 0 ? v.pxlo : ax == 1 ? v.pylo : v.pzlo;
@@ -731,7 +794,7 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
             }
         }
         float dep, esc;
-        const int st = phys_step<false>(v, tab, m, rho_loss, rho.h, dg, dep, esc);
+        const int st = phys_step<false, X>(v, tab, m, rho_loss, rho.h, dg, dep, esc);
         const long long qd = to_fixed(dep, scale);
         if (qd != 0) sink.add(vox, qd);
         acc.led[L_GRID] += qd;
@@ -794,10 +857,11 @@ __device__ __forceinline__ int find_spot(const unsigned long long *off, int n, u
     return lo;
 }
 
+template <bool X>
 __global__ __launch_bounds__(512) void transport_kernel(GeomDev g, FieldDev f, LaunchDev L) {
-    __shared__ float tab[TAB_FLOATS];
+    __shared__ float tab[X ? TAB_FLOATS : TAB_HI_FLOATS];
     __shared__ float2 poly[POLY_LDS];
-    for (int i = threadIdx.x; i < TAB_FLOATS / 4; i += blockDim.x)
+    for (int i = threadIdx.x; i < (X ? TAB_FLOATS : TAB_HI_FLOATS) / 4; i += blockDim.x)
         reinterpret_cast<float4 *>(tab)[i] = reinterpret_cast<const float4 *>(L.tables)[i];
     if (f.has_block)
         for (int i = threadIdx.x; i < f.nv; i += blockDim.x) poly[i] = f.poly[i];
@@ -822,8 +886,8 @@ __global__ __launch_bounds__(512) void transport_kernel(GeomDev g, FieldDev f, L
         v.physics = L.physics;
         source(v, sp);
         float tmin;
-        if (beamline(v, acc, sp.scale, tab, poly, f, tmin, &L.sur) == BL_PATIENT)
-            patient(v, acc, sp.scale, tab, g, f, L.shift, L.range_scale, DenseSink{L.tally}, tmin);
+        if (beamline<X>(v, acc, sp.scale, tab, poly, f, tmin, &L.sur) == BL_PATIENT)
+            patient<DenseSink, X>(v, acc, sp.scale, tab, g, f, L.shift, L.range_scale, DenseSink{L.tally}, tmin);
         acc.steps += v.nsteps;
         acc.hist += 1;
     }
@@ -850,11 +914,13 @@ __global__ __launch_bounds__(512) void transport_kernel(GeomDev g, FieldDev f, L
 // histories of one row) at a time from the epoch's atomic counter, so rows
 // of uneven energy and history count balance across the chip.  Every wave
 // exits once the counter passes the number of chunks.
-// at most 512 threads per workgroup; 3 waves per SIMD leave the step 168 VGPRs (no spills)
-__global__ __launch_bounds__(512, 3) void queue_kernel(GeomDev g, QueueDev Q) {
-    __shared__ float tab[TAB_FLOATS];
+// at most 512 threads per workgroup; physics mode keeps 4 waves per SIMD
+// (<= 128 VGPRs), the double-float mode needs about 160 VGPRs (3 waves)
+template <bool X>
+__global__ __launch_bounds__(512, X ? 3 : 4) void queue_kernel(GeomDev g, QueueDev Q) {
+    __shared__ float tab[X ? TAB_FLOATS : TAB_HI_FLOATS];
     __shared__ float2 poly[POLY_LDS];
-    for (int i = threadIdx.x; i < TAB_FLOATS / 4; i += blockDim.x)
+    for (int i = threadIdx.x; i < (X ? TAB_FLOATS : TAB_HI_FLOATS) / 4; i += blockDim.x)
         reinterpret_cast<float4 *>(tab)[i] = reinterpret_cast<const float4 *>(Q.tables)[i];
     for (int i = threadIdx.x; i < Q.n_poly_total; i += blockDim.x) poly[i] = Q.polys[i];
     __syncthreads();
@@ -895,8 +961,8 @@ __global__ __launch_bounds__(512, 3) void queue_kernel(GeomDev g, QueueDev Q) {
             v.physics = Q.physics;
             source(v, sp);
             float tmin;
-            if (beamline(v, acc, sp.scale, tab, fpoly, f, tmin, &Q.sur, (uint32_t)rl) == BL_PATIENT)
-                patient(v, acc, sp.scale, tab, g, f, sc.shift, sc.range_scale, sink, tmin);
+            if (beamline<X>(v, acc, sp.scale, tab, fpoly, f, tmin, &Q.sur, (uint32_t)rl) == BL_PATIENT)
+                patient<SparseSink, X>(v, acc, sp.scale, tab, g, f, sc.shift, sc.range_scale, sink, tmin);
             acc.steps += v.nsteps;
             acc.hist += 1;
         }
@@ -1102,9 +1168,9 @@ __global__ __launch_bounds__(256) void surrogate_sample_kernel(FieldDev f, const
                                                                uint32_t key0, uint32_t key1, unsigned physics,
                                                                const float *tables, float *xo, float *yo,
                                                                float *to) {
-    __shared__ float tab[TAB_FLOATS];
+    __shared__ float tab[TAB_HI_FLOATS];
     __shared__ float2 poly[POLY_LDS];
-    for (int i = threadIdx.x; i < TAB_FLOATS / 4; i += blockDim.x)
+    for (int i = threadIdx.x; i < TAB_HI_FLOATS / 4; i += blockDim.x)
         reinterpret_cast<float4 *>(tab)[i] = reinterpret_cast<const float4 *>(tables)[i];
     for (int i = threadIdx.x; i < f.nv; i += blockDim.x) poly[i] = f.poly[i];
     __syncthreads();
@@ -1150,7 +1216,8 @@ __global__ __launch_bounds__(256) void surrogate_sample_kernel(FieldDev f, const
         Acc acc;
 #pragma unroll
         for (int k = 0; k < NLEDGER; ++k) acc.led[k] = 0;
-        const int ex = block_transport(v, acc, 1.0f, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl});
+        const int ex =
+            block_transport<false>(v, acc, 1.0f, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl});
         if (ex != EX_DOWN) {
             to[i] = 0.0f;
             continue;
@@ -1187,14 +1254,15 @@ __global__ void sur_features_kernel(const DeferRec *rec, int n, __bf16 *x) {
 // outgoing energy loss, angle and offset; azimuth uniform, shared by angle
 // and offset); otherwise the plain brass transport runs from the recorded
 // state.  Then the patient.
-template <class Sink>
+template <class Sink, bool X>
 __device__ void resume_deferred(Lane &v, Acc &acc, float scale, const float *tab, const float2 *poly,
                                 const FieldDev &f, const float *o, float p_lo, float p_hi, const GeomDev &g,
                                 const float *shift, float range_scale, const Sink &sink) {
     const float ptrans = 1.0f / (1.0f + __expf(-o[0]));
     bool go = true;
     if (!(ptrans < p_lo || ptrans > p_hi)) {
-        go = block_transport(v, acc, scale, tab, poly, f.nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl}) == EX_DOWN;
+        go = block_transport<X>(v, acc, scale, tab, poly, f.nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl}) ==
+             EX_DOWN;
     } else {
         v.E += v.Elo;
         v.Elo = 0.0f;
@@ -1238,7 +1306,7 @@ __device__ void resume_deferred(Lane &v, Acc &acc, float scale, const float *tab
             }
         }
     }
-    if (go) patient(v, acc, scale, tab, g, f, shift, range_scale, sink, 0.0f);
+    if (go) patient<Sink, X>(v, acc, scale, tab, g, f, shift, range_scale, sink, 0.0f);
 }
 
 __device__ __forceinline__ void lane_from_record(Lane &v, const DeferRec &r, uint32_t k0, uint32_t k1,
@@ -1277,12 +1345,13 @@ __device__ __forceinline__ void flush_ledger_steps(Acc &acc, unsigned long long 
 }
 
 // dense runs: one field, one scenario per launch
+template <bool X>
 __global__ __launch_bounds__(256) void sur_resume_kernel(GeomDev g, FieldDev f, LaunchDev L, const DeferRec *rec,
                                                          const float *out, unsigned long long n, float p_lo,
                                                          float p_hi) {
-    __shared__ float tab[TAB_FLOATS];
+    __shared__ float tab[X ? TAB_FLOATS : TAB_HI_FLOATS];
     __shared__ float2 poly[POLY_LDS];
-    for (int i = threadIdx.x; i < TAB_FLOATS / 4; i += blockDim.x)
+    for (int i = threadIdx.x; i < (X ? TAB_FLOATS : TAB_HI_FLOATS) / 4; i += blockDim.x)
         reinterpret_cast<float4 *>(tab)[i] = reinterpret_cast<const float4 *>(L.tables)[i];
     for (int i = threadIdx.x; i < f.nv; i += blockDim.x) poly[i] = f.poly[i];
     __syncthreads();
@@ -1295,7 +1364,7 @@ __global__ __launch_bounds__(256) void sur_resume_kernel(GeomDev g, FieldDev f, 
         const DeferRec r = rec[i];
         Lane v;
         lane_from_record(v, r, L.key0, L.key1, L.physics, f.blk_zu);
-        resume_deferred(v, acc, L.spots[r.spot].scale, tab, poly, f, out + i * MLP_OUT, p_lo, p_hi, g, L.shift,
+        resume_deferred<DenseSink, X>(v, acc, L.spots[r.spot].scale, tab, poly, f, out + i * MLP_OUT, p_lo, p_hi, g, L.shift,
                         L.range_scale, DenseSink{L.tally});
         acc.steps += v.nsteps;
     }
@@ -1304,12 +1373,13 @@ __global__ __launch_bounds__(256) void sur_resume_kernel(GeomDev g, FieldDev f, 
 
 // influence-matrix runs: the record's tag is its row within the epoch, which
 // selects the field, spot, scenario and the row's sparse slot
+template <bool X>
 __global__ __launch_bounds__(256) void sur_resume_csr_kernel(GeomDev g, QueueDev Q, const DeferRec *rec,
                                                              const float *out, unsigned long long n, float p_lo,
                                                              float p_hi) {
-    __shared__ float tab[TAB_FLOATS];
+    __shared__ float tab[X ? TAB_FLOATS : TAB_HI_FLOATS];
     __shared__ float2 poly[POLY_LDS];
-    for (int i = threadIdx.x; i < TAB_FLOATS / 4; i += blockDim.x)
+    for (int i = threadIdx.x; i < (X ? TAB_FLOATS : TAB_HI_FLOATS) / 4; i += blockDim.x)
         reinterpret_cast<float4 *>(tab)[i] = reinterpret_cast<const float4 *>(Q.tables)[i];
     for (int i = threadIdx.x; i < Q.n_poly_total; i += blockDim.x) poly[i] = Q.polys[i];
     __syncthreads();
@@ -1339,7 +1409,7 @@ __global__ __launch_bounds__(256) void sur_resume_csr_kernel(GeomDev g, QueueDev
         }
         Lane v;
         lane_from_record(v, r, Q.key0, Q.seed_hi ^ row.field_id, Q.physics, f.blk_zu);
-        resume_deferred(v, acc, Q.spots[row.spot_global].scale, tab, poly + Q.poly_off[row.field], f,
+        resume_deferred<SparseSink, X>(v, acc, Q.spots[row.spot_global].scale, tab, poly + Q.poly_off[row.field], f,
                         out + i * MLP_OUT, p_lo, p_hi, g, sc.shift, sc.range_scale, sink);
         acc.steps += v.nsteps;
     }
@@ -1392,13 +1462,16 @@ __global__ void dose_kernel(const long long *q, const double *s2, int B, GeomDev
 hipError_t launch_transport(const GeomDev &g, const FieldDev &f, const LaunchDev &L, int blocks,
                             int threads, hipStream_t s) {
     if (threads != 256 && threads != 512) threads = kThreads;
-    hipLaunchKernelGGL(transport_kernel, dim3(blocks), dim3(threads), 0, s, g, f, L);
+    // deterministic mode: the double-float instantiation
+    if (L.physics == 0) hipLaunchKernelGGL(transport_kernel<true>, dim3(blocks), dim3(threads), 0, s, g, f, L);
+    else hipLaunchKernelGGL(transport_kernel<false>, dim3(blocks), dim3(threads), 0, s, g, f, L);
     return hipGetLastError();
 }
 
 hipError_t launch_queue(const GeomDev &g, const QueueDev &Q, int blocks, int threads, hipStream_t s) {
     if (threads != 256 && threads != 512) threads = kThreads;
-    hipLaunchKernelGGL(queue_kernel, dim3(blocks), dim3(threads), 0, s, g, Q);
+    if (Q.physics == 0) hipLaunchKernelGGL(queue_kernel<true>, dim3(blocks), dim3(threads), 0, s, g, Q);
+    else hipLaunchKernelGGL(queue_kernel<false>, dim3(blocks), dim3(threads), 0, s, g, Q);
     return hipGetLastError();
 }
 
@@ -1459,14 +1532,20 @@ hipError_t launch_sur_features(const DeferRec *rec, int n, __bf16 *x, hipStream_
 hipError_t launch_sur_resume(const GeomDev &g, const FieldDev &f, const LaunchDev &L, const DeferRec *rec,
                              const float *out, unsigned long long n, float p_lo, float p_hi, hipStream_t s) {
     const int blocks = (int)std::max<unsigned long long>(1, std::min<unsigned long long>((n + 255) / 256, 4096));
-    hipLaunchKernelGGL(sur_resume_kernel, dim3(blocks), dim3(256), 0, s, g, f, L, rec, out, n, p_lo, p_hi);
+    if (L.physics == 0)
+        hipLaunchKernelGGL(sur_resume_kernel<true>, dim3(blocks), dim3(256), 0, s, g, f, L, rec, out, n, p_lo, p_hi);
+    else
+        hipLaunchKernelGGL(sur_resume_kernel<false>, dim3(blocks), dim3(256), 0, s, g, f, L, rec, out, n, p_lo, p_hi);
     return hipGetLastError();
 }
 
 hipError_t launch_sur_resume_csr(const GeomDev &g, const QueueDev &Q, const DeferRec *rec, const float *out,
                                  unsigned long long n, float p_lo, float p_hi, hipStream_t s) {
     const int blocks = (int)std::max<unsigned long long>(1, std::min<unsigned long long>((n + 255) / 256, 4096));
-    hipLaunchKernelGGL(sur_resume_csr_kernel, dim3(blocks), dim3(256), 0, s, g, Q, rec, out, n, p_lo, p_hi);
+    if (Q.physics == 0)
+        hipLaunchKernelGGL(sur_resume_csr_kernel<true>, dim3(blocks), dim3(256), 0, s, g, Q, rec, out, n, p_lo, p_hi);
+    else
+        hipLaunchKernelGGL(sur_resume_csr_kernel<false>, dim3(blocks), dim3(256), 0, s, g, Q, rec, out, n, p_lo, p_hi);
     return hipGetLastError();
 }
 
