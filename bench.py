@@ -33,6 +33,28 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 TARGET_U = 0.005
 
 
+PROFILE = os.path.join(ROOT, "profiles", "queue_kernel_head_im.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2307_01416_amd", "csrc", "vpmc_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per queue_kernel launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when
+    the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(PROFILE).read()
+        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    h = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    if not m or not h or h.group(1) != src:
+        return None
+    return float(m.group(1))
+
+
 def progress(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -276,7 +298,7 @@ def main():
                    "mean_histories_per_spot": float(H), "plan_dose_uncertainty": u, "nnz": nnz,
                    "csr_gb": nnz * 8 / 1e9, "graph": bool(a.graph), "launch_shape": shape_used},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": measured_traffic(),
                      "kernel": "queue_kernel", "avg_launch_ms": 1e3 * transport_s / max(1, launches),
                      "steps_per_s": steps_total / transport_s},
         "transport_fraction_of_wall": transport_s / dt,
