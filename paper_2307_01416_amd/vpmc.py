@@ -359,6 +359,10 @@ class Engine:
         import torch
         self.torch = torch
         self.device = device
+        # torch's runtime first: its tensors and streams are the ones passed in
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible to torch; the VP engine needs an MI355X GPU")
+        torch.cuda.set_device(device)
         self.ctx = vpmc_create(device)
         self._geom = None
 
