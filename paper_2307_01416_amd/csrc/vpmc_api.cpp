@@ -2,6 +2,8 @@
 // device buffers, fixed-point scaling, batch loop and the C ABI of
 // include/vpmc.h.
 #include <math.h>
+
+#include <cmath>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -46,8 +48,54 @@ struct FieldState {
     bool set = false;
     FieldDev dev{};
     std::vector<float2> poly;
-    DevBuf poly_buf;
+    DevBuf poly_buf, sdf_buf;
 };
+
+// Signed distance (FP64, + inside) from the cell centres of a raster over
+// the polygon's bounding box widened by `margin` to the polygon boundary;
+// the side follows the same half-open crossing-number rule as the kernels.
+struct Raster {
+    double x0, y0, h;
+    int nx, ny;
+    std::vector<float> d;
+};
+
+Raster polygon_raster(const std::vector<float2> &poly, double margin) {
+    double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+    for (const float2 &p : poly) {
+        xmin = std::min(xmin, (double)p.x); xmax = std::max(xmax, (double)p.x);
+        ymin = std::min(ymin, (double)p.y); ymax = std::max(ymax, (double)p.y);
+    }
+    Raster r;
+    const double ext = std::max(xmax - xmin, ymax - ymin) + 2.0 * margin;
+    r.h = std::max(0.25, ext / 512.0);
+    r.x0 = xmin - margin;
+    r.y0 = ymin - margin;
+    r.nx = (int)std::ceil((xmax - xmin + 2.0 * margin) / r.h);
+    r.ny = (int)std::ceil((ymax - ymin + 2.0 * margin) / r.h);
+    r.d.resize((size_t)r.nx * r.ny);
+    const int nv = (int)poly.size();
+    for (int j = 0; j < r.ny; ++j)
+        for (int i = 0; i < r.nx; ++i) {
+            const double x = r.x0 + (i + 0.5) * r.h, y = r.y0 + (j + 0.5) * r.h;
+            bool in = false;
+            double best = 1e300;
+            for (int a = nv - 1, b = 0; b < nv; a = b++) {
+                const double ax = poly[a].x, ay = poly[a].y, bx = poly[b].x, by = poly[b].y;
+                if ((ay > y) != (by > y)) {
+                    const double xc = ax + (y - ay) * (bx - ax) / (by - ay);
+                    if (x < xc) in = !in;
+                }
+                const double ex = bx - ax, ey = by - ay, l2 = ex * ex + ey * ey;
+                double t = l2 > 0.0 ? ((x - ax) * ex + (y - ay) * ey) / l2 : 0.0;
+                t = std::min(std::max(t, 0.0), 1.0);
+                const double dx = x - ax - t * ex, dy = y - ay - t * ey;
+                best = std::min(best, dx * dx + dy * dy);
+            }
+            r.d[(size_t)j * r.nx + i] = (float)(in ? std::sqrt(best) : -std::sqrt(best));
+        }
+    return r;
+}
 
 }  // namespace
 
@@ -876,7 +924,10 @@ void vpmc_destroy(vpmc_ctx *c) {
         (void)hipDeviceSynchronize();
         if (c->d_tables) (void)hipFree(c->d_tables);
         release(c->hu_buf);
-        for (auto &f : c->fields) release(f.poly_buf);
+        for (auto &f : c->fields) {
+            release(f.poly_buf);
+            release(f.sdf_buf);
+        }
         for (DevBuf *b : {&c->tallies, &c->qbatch, &c->s2, &c->ledger, &c->spots, &c->offsets,
                           &c->stage_dose, &c->stage_sigma, &c->stats, &c->slot_grid, &c->slot_mark, &c->slot_cnt,
                           &c->slot_coff, &c->slot_rowcnt, &c->rows, &c->chunk_off, &c->heads, &c->row_off, &c->row_nnz, &c->used,
@@ -989,12 +1040,29 @@ int vpmc_set_aperture(vpmc_ctx *c, int field_id, const vpmc_beam *beam, const fl
         d.rs_t = (float)rs_t;
         d.rs_tl = (float)(rs_t - (double)d.rs_t);
     }
+    Raster ras{};
+    if (poly.size() >= 3) {
+        ras = polygon_raster(poly, kSdfMargin);
+        d.sdf_x0 = (float)ras.x0;
+        d.sdf_y0 = (float)ras.y0;
+        d.sdf_ih = (float)(1.0 / ras.h);
+        // farthest point of a cell from its centre, plus room for FP32 rounding
+        d.sdf_r = (float)(ras.h * 0.70710678118654752 + 1e-3);
+        d.sdf_far = (float)(kSdfMargin - 1e-3);
+        d.sdf_nx = ras.nx;
+        d.sdf_ny = ras.ny;
+    }
     if (c->device >= 0 && !poly.empty()) {
         HIP_TRY(hipSetDevice(c->device));
         if ((rc = ensure(c, f.poly_buf, poly.size() * sizeof(float2), 0))) return rc;
         HIP_TRY(hipMemcpy(f.poly_buf.ptr, poly.data(), poly.size() * sizeof(float2), hipMemcpyHostToDevice));
+        if (!ras.d.empty()) {
+            if ((rc = ensure(c, f.sdf_buf, ras.d.size() * sizeof(float), 0))) return rc;
+            HIP_TRY(hipMemcpy(f.sdf_buf.ptr, ras.d.data(), ras.d.size() * sizeof(float), hipMemcpyHostToDevice));
+        }
     }
     d.poly = (const float2 *)f.poly_buf.ptr;
+    d.sdf = ras.d.empty() ? nullptr : (const float *)f.sdf_buf.ptr;
     f.dev = d;
     f.poly = std::move(poly);
     f.set = true;

@@ -52,6 +52,7 @@ constexpr float NUC_SIGMA_RAD = 0.15f;     // deflection of the leading secondar
 constexpr float EDGE_PUSH_MM = 1e-4f;      // push across an aperture edge in the BEV plane (FP32)
 constexpr int MAX_STEPS = 1000000;         // safety bound on steps per VP
 constexpr int MAX_BLOCK_ITER = 10000;      // bound on crossing-number tests per block traversal
+constexpr double kSdfMargin = 8.0;         // mm of aperture distance raster beyond the polygon's box
 constexpr double MEV_TO_J = 1.602176634e-13;
 
 enum { L_GRID = 0, L_RS = 1, L_BLOCK = 2, L_ESCAPED = 3, L_NUC = 4, NLEDGER = 6 };
@@ -68,6 +69,11 @@ struct FieldDev {
     float iso[3], ex[3], ey[3], ez[3];
     int has_block, nv;
     const float2 *poly;
+    // signed distance raster of the polygon (+ inside the opening), cell size
+    // 1/sdf_ih, for conservative bounds that skip the exact edge loops
+    const float *sdf;
+    float sdf_x0, sdf_y0, sdf_ih, sdf_r, sdf_far;
+    int sdf_nx, sdf_ny;
     float blk_zu, blk_zd, blk_rho, blk_t, blk_tl;
     int has_rs;
     float rs_zu, rs_zd, rs_r2, rs_rho, rs_rhol, rs_t, rs_tl;   // *_l: low parts of the FP64 values

@@ -420,6 +420,27 @@ __device__ __forceinline__ bool in_polygon(const float2 *poly, int nv, float x, 
     return c;
 }
 
+// Conservative distance from (x, y) to the aperture polygon's boundary, read
+// from the field's distance raster: the stored distance at the cell centre
+// less the farthest a point of the cell can be from it (distances are
+// 1-Lipschitz).  Returns 0 when the point may lie near the boundary (the
+// exact edge loops then decide) and sets `inside` when the bound is > 0.
+__device__ __forceinline__ float sdf_bound(const FieldDev &f, float x, float y, bool &inside) {
+    inside = false;
+    if (!f.sdf || !(x == x) || !(y == y)) return 0.0f;
+    const float fx = (x - f.sdf_x0) * f.sdf_ih, fy = (y - f.sdf_y0) * f.sdf_ih;
+    if (!(fx >= 0.0f && fy >= 0.0f && fx < (float)f.sdf_nx && fy < (float)f.sdf_ny)) return f.sdf_far;
+    const float d = f.sdf[(int)fy * f.sdf_nx + (int)fx];
+    inside = d > 0.0f;
+    return fmaxf(fabsf(d) - f.sdf_r, 0.0f);
+}
+
+// true when a BEV ray of lateral speed `lat` cannot reach the boundary within
+// path length t, with room for the FP32 rounding of the exact edge distance
+__device__ __forceinline__ bool no_edge_within(float lb, float lat, float t) {
+    return lb > 0.0f && lat * t < lb * (1.0f - 1e-5f) - 1e-4f;
+}
+
 // path length along (u, v) until the BEV ray from (x, y) meets an edge
 __device__ __forceinline__ float edge_distance(const float2 *poly, int nv, float x, float y, float u,
                                                float v) {
@@ -501,15 +522,28 @@ __device__ int slab_transport(Lane &v, Acc &acc, float scale, const float *tab, 
 // (straight transport, no random numbers) or brass (brass tables).
 template <bool X>
 __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab, const float2 *poly,
-                               int nv, float rho_b, float zu, float zd, DF thick) {
+                               int nv, float rho_b, float zu, float zd, DF thick, const FieldDev &f_sdf) {
     v.pz = 0.0f;
     v.pzlo = 0.0f;
     for (int it = 0; it < MAX_BLOCK_ITER; ++it) {
         bool down;
         const DF tpp = plane_distance<X>(v, thick, down);
         const float tp = tpp.h;
-        const bool open = nv >= 3 && in_polygon(poly, nv, v.px, v.py);
-        const float te = nv >= 3 ? edge_distance(poly, nv, v.px, v.py, v.dx, v.dy) : INFINITY;
+        bool open = false;
+        float te = INFINITY;
+        if (nv >= 3) {
+            // far from every edge for the whole path to the exit plane: the
+            // side is known and the exact edge distance exceeds tp, so the
+            // decisions below are those of the exact loops
+            bool inside;
+            const float lb = sdf_bound(f_sdf, v.px, v.py, inside);
+            if (no_edge_within(lb, sqrtf(v.dx * v.dx + v.dy * v.dy), tp)) {
+                open = inside;
+            } else {
+                open = in_polygon(poly, nv, v.px, v.py);
+                te = edge_distance(poly, nv, v.px, v.py, v.dx, v.dy);
+            }
+        }
         if (open) {
             if (tp <= te) {
                 v.px = fmaf(tp, v.dx, v.px);
@@ -598,14 +632,24 @@ __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const 
         const float t = (f.blk_zu - v.pz) / v.dz;
         const float qx = fmaf(t, v.dx, v.px), qy = fmaf(t, v.dy, v.py);
         const int nv = f.nv;
-        if (nv >= 3 && in_polygon(poly, nv, qx, qy)) {
-            const float te = edge_distance(poly, nv, qx, qy, v.dx, v.dy);
+        bool open = false, through = false;
+        if (nv >= 3) {
             const float tx = f.blk_t / v.dz;
-            if (te >= tx) {
-                tmin = (f.blk_zd - v.pz) / v.dz;
-                return BL_PATIENT;
+            bool inside;
+            const float lb = sdf_bound(f, qx, qy, inside);
+            if (no_edge_within(lb, sqrtf(v.dx * v.dx + v.dy * v.dy), tx)) {
+                open = inside;
+                through = inside;
+            } else {
+                open = in_polygon(poly, nv, qx, qy);
+                through = open && edge_distance(poly, nv, qx, qy, v.dx, v.dy) >= tx;
             }
-        } else if (sur && sur->enabled) {
+        }
+        if (through) {
+            tmin = (f.blk_zd - v.pz) / v.dz;
+            return BL_PATIENT;
+        }
+        if (!open && sur && sur->enabled) {
             // enters through brass: far enough from the opening's edge, the
             // learned surrogate takes over the traversal (queued for it)
             const float de = nv >= 3 ? dist_to_polygon(poly, nv, qx, qy) : 1000.0f;
@@ -636,7 +680,7 @@ __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const 
         v.px = qx;
         v.py = qy;
         v.pz = f.blk_zu;
-        if (block_transport<X>(v, acc, scale, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl}) !=
+        if (block_transport<X>(v, acc, scale, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl}, f) !=
             EX_DOWN)
             return BL_STOP;
         tmin = 0.0f;
@@ -681,10 +725,20 @@ __device__ __forceinline__ void clamp_pair(float &h, float &l, float sp) {
     else if (h > sp || (h == sp && l > 0.0f)) { h = sp; l = 0.0f; }
 }
 
-template <class Sink, bool X>
-__device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const GeomDev &g,
-                        const FieldDev &f, const float *shift, float range_scale, const Sink &sink,
-                        float tmin) {
+// position of a VP inside the CT grid between steps
+struct PState {
+    int idx[3];
+    uint32_t vox;   // linear index of voxel idx
+    int hu;         // its CT number (CT geometry)
+};
+
+// Entry into the CT grid: beam frame -> CT frame with the scenario shift,
+// ray-box intersection from the last exit plane (tmin), voxel-local
+// coordinates.  Returns false when the VP misses the grid (its energy goes
+// to the escaped ledger).
+template <bool X>
+__device__ bool patient_enter(Lane &v, Acc &acc, float scale, const GeomDev &g, const FieldDev &f,
+                              const float *shift, float tmin, PState &ps) {
     float p[3], d[3];
     {
         const float bx = v.px, by = v.py, bz = v.pz;
@@ -705,7 +759,7 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
         if (d[k] == 0.0f) {
             if (p[k] < g.lo[k] || p[k] >= hi[k]) {
                 ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
-                return;
+                return false;
             }
             continue;
         }
@@ -717,7 +771,7 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
     const float t0 = fmaxf(tnear, tmin);
     if (!(tfar > t0)) {
         ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
-        return;
+        return false;
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) p[k] = fmaf(t0, d[k], p[k]);
@@ -747,9 +801,28 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
         v.pxlo = v.pylo = v.pzlo = 0.0f;
     }
     v.dx = d[0]; v.dy = d[1]; v.dz = d[2];
-    uint32_t vox = (uint32_t)idx[0] + (uint32_t)g.nx * ((uint32_t)idx[1] + (uint32_t)g.ny * (uint32_t)idx[2]);
-    int hu = g.kind == 1 ? (int)g.hu[vox] : 0;
-    for (int it = 0; it < MAX_STEPS; ++it) {
+    ps.idx[0] = idx[0];
+    ps.idx[1] = idx[1];
+    ps.idx[2] = idx[2];
+    ps.vox = (uint32_t)idx[0] + (uint32_t)g.nx * ((uint32_t)idx[1] + (uint32_t)g.ny * (uint32_t)idx[2]);
+    ps.hu = g.kind == 1 ? (int)g.hu[ps.vox] : 0;
+    return true;
+}
+
+// One condensed-history step of a VP inside the CT grid; false once its
+// transport has ended (stopped, or left the grid: then the escaped ledger).
+template <class Sink, bool X>
+__device__ bool patient_step(Lane &v, Acc &acc, float scale, const float *tab, const GeomDev &g, float range_scale,
+                             const Sink &sink, PState &ps) {
+    if (v.nsteps >= (uint32_t)MAX_STEPS) {
+        ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
+        return false;
+    }
+    const int n[3] = {g.nx, g.ny, g.nz};
+    int *idx = ps.idx;
+    uint32_t &vox = ps.vox;
+    int &hu = ps.hu;
+    {
         int m = MAT_WATER;
         DF rho = {1.0f, 0.0f};
         if (g.kind == 1) rho = hu_density<X>(hu, m);
@@ -799,7 +872,7 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
         if (qd != 0) sink.add(vox, qd);
         acc.led[L_GRID] += qd;
         ledger_add(acc, L_NUC, esc, scale);
-        if (st == ST_STOP) return;
+        if (st == ST_STOP) return false;
         if (st == ST_GEO) {
             bool out = false;
 #pragma unroll
@@ -811,7 +884,7 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
             }
             if (out) {
                 ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
-                return;
+                return false;
             }
             // near face of the next voxel, exactly
             const float face_next = sgn > 0 ? 0.0f : (ax == 0 ? g.sp[0] : ax == 1 ? g.sp[1] : g.sp[2]);
@@ -825,7 +898,17 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
         clamp_pair(v.py, v.pylo, g.sp[1]);
         clamp_pair(v.pz, v.pzlo, g.sp[2]);
     }
-    ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
+    return true;
+}
+
+template <class Sink, bool X>
+__device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const GeomDev &g,
+                        const FieldDev &f, const float *shift, float range_scale, const Sink &sink,
+                        float tmin) {
+    PState ps;
+    if (!patient_enter<X>(v, acc, scale, g, f, shift, tmin, ps)) return;
+    while (patient_step<Sink, X>(v, acc, scale, tab, g, range_scale, sink, ps)) {
+    }
 }
 
 // ------------------------------------------------------------ source
@@ -926,7 +1009,6 @@ __global__ __launch_bounds__(512, X ? 3 : 4) void queue_kernel(GeomDev g, QueueD
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
-    unsigned long long st_steps = 0, st_hist = 0;
     for (;;) {
         unsigned long long item = 0;
         if (lane == 0) item = atomicAdd(Q.head, 1ull);
@@ -966,22 +1048,21 @@ __global__ __launch_bounds__(512, X ? 3 : 4) void queue_kernel(GeomDev g, QueueD
             acc.steps += v.nsteps;
             acc.hist += 1;
         }
-        st_steps += acc.steps;
-        st_hist += acc.hist;
 #pragma unroll
         for (int k = 0; k < NLEDGER; ++k) {
             long long x = acc.led[k];
             for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
             if (lane == 0 && x != 0) atomicAdd(Q.ledger + (size_t)row.scen * NLEDGER + k, (unsigned long long)x);
         }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        st_steps += __shfl_xor(st_steps, o, 64);
-        st_hist += __shfl_xor(st_hist, o, 64);
-    }
-    if (lane == 0 && st_hist != 0) {
-        atomicAdd(Q.stats + 0, st_steps);
-        atomicAdd(Q.stats + 1, st_hist);
+        unsigned long long sx = acc.steps, hx = acc.hist;
+        for (int o = 32; o > 0; o >>= 1) {
+            sx += __shfl_xor(sx, o, 64);
+            hx += __shfl_xor(hx, o, 64);
+        }
+        if (lane == 0 && hx != 0) {
+            atomicAdd(Q.stats + 0, sx);
+            atomicAdd(Q.stats + 1, hx);
+        }
     }
 }
 
@@ -1217,7 +1298,7 @@ __global__ __launch_bounds__(256) void surrogate_sample_kernel(FieldDev f, const
 #pragma unroll
         for (int k = 0; k < NLEDGER; ++k) acc.led[k] = 0;
         const int ex =
-            block_transport<false>(v, acc, 1.0f, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl});
+            block_transport<false>(v, acc, 1.0f, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl}, f);
         if (ex != EX_DOWN) {
             to[i] = 0.0f;
             continue;
@@ -1261,7 +1342,7 @@ __device__ void resume_deferred(Lane &v, Acc &acc, float scale, const float *tab
     const float ptrans = 1.0f / (1.0f + __expf(-o[0]));
     bool go = true;
     if (!(ptrans < p_lo || ptrans > p_hi)) {
-        go = block_transport<X>(v, acc, scale, tab, poly, f.nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl}) ==
+        go = block_transport<X>(v, acc, scale, tab, poly, f.nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl}, f) ==
              EX_DOWN;
     } else {
         v.E += v.Elo;
