@@ -134,7 +134,7 @@ struct vpmc_ctx {
     bool mlp_ready = false;
     int mlp_step = 0;
     int mlp_batch_cap = 0;
-    DevBuf sur_rec, sur_cnt;
+    DevBuf sur_rec, sur_cnt, sur_out;
     float sur_dfb = 3.0f, sur_plo = 0.02f, sur_phi = 0.98f;
 };
 
@@ -431,7 +431,6 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     // block with the plain transport)
     const bool sur_on = (o->flags & VPMC_SURROGATE) != 0;
     unsigned long long sur_cap = 0, deferred = 0;
-    MlpBuffers mb{};
     if (sur_on) {
         for (int e = 0; e < E; ++e) {
             unsigned long long h = 0;
@@ -440,8 +439,8 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
         }
         sur_cap = std::max(1ull, std::min(sur_cap, kSurMaxRecords));
         if ((rc = ensure(c, c->sur_rec, sur_cap * sizeof(DeferRec), cap))) return rc;
+        if ((rc = ensure(c, c->sur_out, sur_cap * MLP_OUT * sizeof(float), cap))) return rc;
         if ((rc = ensure(c, c->sur_cnt, sizeof(unsigned long long), cap))) return rc;
-        if ((rc = mlp_buffers(c, MLP_MAX_BATCH, &mb))) return rc;
     }
 
     QueueDev Q{};
@@ -590,12 +589,11 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
                 const unsigned long long nq = std::min(cnt, sur_cap);
                 deferred += nq;
                 const DeferRec *rec = (const DeferRec *)c->sur_rec.ptr;
-                for (unsigned long long s0 = 0; s0 < nq; s0 += MLP_MAX_BATCH) {
-                    const int m = (int)std::min<unsigned long long>(MLP_MAX_BATCH, nq - s0);
-                    HIP_TRY(launch_sur_features(rec + s0, m, mb.x, st));
-                    HIP_TRY(mlp_forward(mb, m, st));
-                    HIP_TRY(launch_sur_resume_csr(c->geom, Qe, rec + s0, mb.out, (unsigned long long)m, c->sur_plo,
-                                                  c->sur_phi, st));
+                float *sout = (float *)c->sur_out.ptr;
+                if (nq) {
+                    HIP_TRY(mlp_infer(nullptr, rec, (int)nq, (const __bf16 *)c->mlp_wb.ptr, (const float *)c->mlp_w.ptr,
+                                      sout, st));
+                    HIP_TRY(launch_sur_resume_csr(c->geom, Qe, rec, sout, nq, c->sur_plo, c->sur_phi, st));
                 }
             }
             HIP_TRY(hipEventRecord(c->events[3], st));
@@ -802,16 +800,15 @@ int vpmc_surrogate_forward(vpmc_ctx *c, const float *x, int n, float *out) {
     if (rc) return rc;
     if (!x || !out || n < 0) return fail(VPMC_E_ARG, "bad forward arguments");
     if (n == 0) return VPMC_OK;
-    MlpBuffers b;
-    const int cap = std::min(n, MLP_MAX_BATCH);
-    if ((rc = mlp_buffers(c, cap, &b))) return rc;
-    if ((rc = ensure(c, c->mlp_io, (size_t)cap * MLP_IN * 4, 0))) return rc;
+    // fused inference in chunks of up to 1M samples
+    const int cap = std::min(n, 1 << 20);
+    if ((rc = ensure(c, c->mlp_io, (size_t)cap * (MLP_IN + MLP_OUT) * 4, 0))) return rc;
+    float *dx = (float *)c->mlp_io.ptr, *dout = dx + (size_t)cap * MLP_IN;
     for (int s0 = 0; s0 < n; s0 += cap) {
         const int m = std::min(cap, n - s0);
-        HIP_TRY(hipMemcpy(c->mlp_io.ptr, x + (size_t)s0 * MLP_IN, (size_t)m * MLP_IN * 4, hipMemcpyHostToDevice));
-        HIP_TRY(mlp_to_bf16((const float *)c->mlp_io.ptr, b.x, (size_t)m * MLP_IN, nullptr));
-        HIP_TRY(mlp_forward(b, m, nullptr));
-        HIP_TRY(hipMemcpy(out + (size_t)s0 * MLP_OUT, b.out, (size_t)m * MLP_OUT * 4, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(dx, x + (size_t)s0 * MLP_IN, (size_t)m * MLP_IN * 4, hipMemcpyHostToDevice));
+        HIP_TRY(mlp_infer(dx, nullptr, m, (const __bf16 *)c->mlp_wb.ptr, (const float *)c->mlp_w.ptr, dout, nullptr));
+        HIP_TRY(hipMemcpy(out + (size_t)s0 * MLP_OUT, dout, (size_t)m * MLP_OUT * 4, hipMemcpyDeviceToHost));
     }
     return VPMC_OK;
 }
@@ -934,7 +931,7 @@ void vpmc_destroy(vpmc_ctx *c) {
                           &c->flags, &c->fields_tab, &c->poly_off, &c->polys, &c->scen_tab, &c->csr_col,
                           &c->csr_q, &c->mlp_w, &c->mlp_wb, &c->mlp_m, &c->mlp_v, &c->mlp_g, &c->mlp_act,
                           &c->mlp_io, &c->mlp_dx, &c->mlp_dy, &c->mlp_dt, &c->mlp_idx, &c->sur_rec,
-                          &c->sur_cnt})
+                          &c->sur_cnt, &c->sur_out})
             release(*b);
         for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -1136,14 +1133,13 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
     const FieldDev &fd = c->fields[field_id].dev;
     const bool sur_on = use_sur && fd.has_block;
     unsigned long long sur_cap = 0;
-    MlpBuffers mb{};
     if (sur_on) {
         unsigned long long per_batch = 0;
         for (int i = 0; i < n_spots; ++i) per_batch += (spots[i].n_histories + B - 1) / B;
         sur_cap = std::max(1ull, std::min(per_batch, kSurMaxRecords));
         if ((rc = ensure(c, c->sur_rec, sur_cap * sizeof(DeferRec), cap))) return rc;
+        if ((rc = ensure(c, c->sur_out, sur_cap * MLP_OUT * sizeof(float), cap))) return rc;
         if ((rc = ensure(c, c->sur_cnt, sizeof(unsigned long long), cap))) return rc;
-        if ((rc = mlp_buffers(c, MLP_MAX_BATCH, &mb))) return rc;
     }
 
     // spots and per-batch work offsets
@@ -1229,12 +1225,11 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
                 const unsigned long long nq = std::min(cnt, sur_cap);
                 deferred += nq;
                 const DeferRec *rec = (const DeferRec *)c->sur_rec.ptr;
-                for (unsigned long long s0 = 0; s0 < nq; s0 += MLP_MAX_BATCH) {
-                    const int m = (int)std::min<unsigned long long>(MLP_MAX_BATCH, nq - s0);
-                    HIP_TRY(launch_sur_features(rec + s0, m, mb.x, st));
-                    HIP_TRY(mlp_forward(mb, m, st));
-                    HIP_TRY(launch_sur_resume(c->geom, fd, L, rec + s0, mb.out, (unsigned long long)m, c->sur_plo,
-                                              c->sur_phi, st));
+                float *sout = (float *)c->sur_out.ptr;
+                if (nq) {
+                    HIP_TRY(mlp_infer(nullptr, rec, (int)nq, (const __bf16 *)c->mlp_wb.ptr, (const float *)c->mlp_w.ptr,
+                                      sout, st));
+                    HIP_TRY(launch_sur_resume(c->geom, fd, L, rec, sout, nq, c->sur_plo, c->sur_phi, st));
                 }
             }
             HIP_TRY(hipEventRecord(c->events[3 + 2 * n_launch], st));

@@ -193,7 +193,6 @@ struct MlpBuffers {
     float *loss;         // [n] per-sample loss
 };
 
-hipError_t launch_sur_features(const DeferRec *rec, int n, __bf16 *x, hipStream_t s);
 hipError_t launch_sur_resume(const GeomDev &g, const FieldDev &f, const LaunchDev &L, const DeferRec *rec,
                              const float *out, unsigned long long n, float p_lo, float p_hi, hipStream_t s);
 hipError_t launch_sur_resume_csr(const GeomDev &g, const QueueDev &Q, const DeferRec *rec, const float *out,
@@ -204,6 +203,10 @@ int mlp_param_count();
 int mlp_param_offset(int layer);
 int mlp_dim(int i);
 hipError_t mlp_forward(const MlpBuffers &b, int n, hipStream_t s);
+// fused inference of n samples: inputs x [n][8] FP32, or (rec != NULL) the
+// features of deferred-VP records; outputs out [n][29] FP32
+hipError_t mlp_infer(const float *x, const DeferRec *rec, int n, const __bf16 *wb, const float *wf, float *out,
+                     hipStream_t s);
 hipError_t mlp_loss_grad(const MlpBuffers &b, const float *y, const float *trans, int n, float *grad, float *loss,
                          hipStream_t s);
 hipError_t mlp_gather(const float *x, const int *idx, int n, int cols, __bf16 *xb, float *xf, hipStream_t s);

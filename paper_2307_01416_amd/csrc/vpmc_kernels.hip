@@ -172,16 +172,6 @@ __device__ __forceinline__ void rotate_dir(Lane &v, float ax, float ay) {
 
 
 
-// (pz, pzlo) += dz with an error-free two-sum
-__device__ __forceinline__ void add_depth(Lane &v, float dz) {
-    const float s = v.pz + dz;
-    const float bb = s - v.pz;
-    const float err = (v.pz - (s - bb)) + (dz - bb);
-    const float lo = v.pzlo + err;
-    const float t = s + lo;
-    v.pzlo = lo - (t - s);
-    v.pz = t;
-}
 
 enum { ST_STOP = 0, ST_GEO = 1, ST_INNER = 2 };
 
@@ -1314,21 +1304,6 @@ __global__ __launch_bounds__(256) void surrogate_sample_kernel(FieldDev f, const
     }
 }
 
-// network inputs of deferred VPs (same encoding as the training data)
-__global__ void sur_features_kernel(const DeferRec *rec, int n, __bf16 *x) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const DeferRec r = rec[i];
-        __bf16 *xr = x + (size_t)i * 8;
-        xr[0] = (__bf16)(r.x / 20.0f);
-        xr[1] = (__bf16)(r.y / 20.0f);
-        xr[2] = (__bf16)(r.u / 0.05f);
-        xr[3] = (__bf16)(r.v / 0.05f);
-        xr[4] = (__bf16)((r.E + r.Elo - 150.0f) / 50.0f);
-        xr[5] = (__bf16)(fminf(r.d_edge, 100.0f) / 10.0f);
-        xr[6] = (__bf16)(r.thick / 30.0f);
-        xr[7] = (__bf16)0.0f;
-    }
-}
 
 // Resume one deferred VP: where the network is confident the traversal is
 // sampled from it (transmission, then one mixture component and its
@@ -1604,11 +1579,6 @@ hipError_t launch_csr_values(const int32_t *col, const long long *qv, size_t n, 
     return hipGetLastError();
 }
 
-hipError_t launch_sur_features(const DeferRec *rec, int n, __bf16 *x, hipStream_t s) {
-    const int blocks = std::max(1, std::min((n + 255) / 256, 4096));
-    hipLaunchKernelGGL(sur_features_kernel, dim3(blocks), dim3(256), 0, s, rec, n, x);
-    return hipGetLastError();
-}
 
 hipError_t launch_sur_resume(const GeomDev &g, const FieldDev &f, const LaunchDev &L, const DeferRec *rec,
                              const float *out, unsigned long long n, float p_lo, float p_hi, hipStream_t s) {

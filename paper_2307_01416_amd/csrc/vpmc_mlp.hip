@@ -84,6 +84,126 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const __bf16 *__restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference: one workgroup (4 waves) carries 64 samples through all
+// five layers.  The activations stay in LDS (two BF16 buffers of 64 x 256,
+// rows padded to 264 to spread the banks); each wave computes 64 output
+// columns of a hidden layer as 2 x 2 tiles of v_mfma_f32_32x32x16_bf16, its B
+// fragments (eight consecutive K of one output unit, W[out][in] row-major)
+// read straight from the L2-resident BF16 weights.  The K order and the
+// instruction are those of gemm_bf16_kernel, so the outputs equal the
+// layer-by-layer forward pass bit for bit.  REC: the inputs are computed from
+// the deferred-VP records (same encoding as the training data) instead of
+// read as FP32 rows of 8.
+constexpr int kInfRows = 64;
+constexpr int kInfLd = 264;
+
+template <bool REC>
+__global__ __launch_bounds__(256) void mlp_infer_kernel(const float *__restrict__ x, const DeferRec *__restrict__ rec,
+                                                        int n, const __bf16 *__restrict__ wb,
+                                                        const float *__restrict__ wf, float *__restrict__ out) {
+    __shared__ __attribute__((aligned(16))) __bf16 H[2][kInfRows][kInfLd];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int row0 = blockIdx.x * kInfRows;
+    const __bf16 zero = (__bf16)0.0f;
+    if (t < kInfRows) {
+        float in[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const int r = row0 + t;
+        if (r < n) {
+            if (REC) {
+                const DeferRec q = rec[r];
+                in[0] = q.x / 20.0f;
+                in[1] = q.y / 20.0f;
+                in[2] = q.u / 0.05f;
+                in[3] = q.v / 0.05f;
+                in[4] = (q.E + q.Elo - 150.0f) / 50.0f;
+                in[5] = fminf(q.d_edge, 100.0f) / 10.0f;
+                in[6] = q.thick / 30.0f;
+                in[7] = 0.0f;   // brass
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) in[j] = x[(size_t)r * 8 + j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            H[0][t][j] = (__bf16)in[j];
+            H[0][t][8 + j] = zero;
+        }
+    }
+    __syncthreads();
+    int off = 0;   // parameter offset of the layer
+#pragma unroll 1
+    for (int l = 0; l < MLP_LAYERS; ++l) {
+        const int ni = l == 0 ? MLP_IN : MLP_HIDDEN;
+        const int no = l == MLP_LAYERS - 1 ? MLP_OUT : MLP_HIDDEN;
+        const int K = l == 0 ? 16 : MLP_HIDDEN;
+        const __bf16 *W = wb + off;
+        const float *bias = wf + off + no * ni;
+        const bool last = l == MLP_LAYERS - 1;
+        // hidden layers: wave w owns columns 64w .. 64w+63 (2 x 2 tiles);
+        // output layer: waves 0 and 1 each own one 32 x 32 tile (rows 32w)
+        const int ntile = last ? 1 : 2, mtile = last ? 1 : 2;
+        const int n0 = last ? 0 : 64 * w, m0 = last ? 32 * w : 0;
+        if (!last || w < 2) {
+            f32x16 acc[2][2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
+            const __bf16(*in)[kInfLd] = H[l & 1];
+            const int kb = 8 * (lane >> 5);
+            for (int k0 = 0; k0 < K; k0 += 16) {
+                bf16x8 af[2], bfr[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+                    if (a < mtile) af[a] = *reinterpret_cast<const bf16x8 *>(&in[m0 + 32 * a + (lane & 31)][k0 + kb]);
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    if (b >= ntile) continue;
+                    const int col = n0 + 32 * b + (lane & 31);
+                    const int k = k0 + kb;
+                    if (col < no && k < ni) {
+                        bfr[b] = *reinterpret_cast<const bf16x8 *>(W + (size_t)col * ni + k);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) bfr[b][j] = zero;
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        if (a < mtile && b < ntile)
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+            }
+            __bf16(*ob)[kInfLd] = H[(l + 1) & 1];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    if (a >= mtile || b >= ntile) continue;
+                    const int col = n0 + 32 * b + (lane & 31);
+                    const float bc = col < no ? bias[col] : 0.0f;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int r = m0 + 32 * a + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+                        const float z = acc[a][b][i] + bc;
+                        if (!last) {
+                            ob[r][col] = (__bf16)silu_f(z);
+                        } else if (col < no && row0 + r < n) {
+                            out[(size_t)(row0 + r) * MLP_OUT + col] = z;
+                        }
+                    }
+                }
+        }
+        off += no * ni + no;
+        __syncthreads();
+    }
+}
+
 __global__ void to_bf16_kernel(const float *__restrict__ x, __bf16 *__restrict__ y, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         y[i] = (__bf16)x[i];
@@ -300,6 +420,15 @@ hipError_t mlp_loss_grad(const MlpBuffers &b, const float *y, const float *trans
         dcur_b = dzb;
     }
     return hipSuccess;
+}
+
+hipError_t mlp_infer(const float *x, const DeferRec *rec, int n, const __bf16 *wb, const float *wf, float *out,
+                     hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const dim3 grid((n + kInfRows - 1) / kInfRows), block(256);
+    if (rec) hipLaunchKernelGGL(mlp_infer_kernel<true>, grid, block, 0, s, x, rec, n, wb, wf, out);
+    else hipLaunchKernelGGL(mlp_infer_kernel<false>, grid, block, 0, s, x, rec, n, wb, wf, out);
+    return hipGetLastError();
 }
 
 hipError_t mlp_gather(const float *x, const int *idx, int n, int cols, __bf16 *xb, float *xf, hipStream_t s) {
