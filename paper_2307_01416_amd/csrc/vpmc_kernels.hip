@@ -1469,10 +1469,25 @@ __global__ __launch_bounds__(256) void sur_resume_csr_kernel(GeomDev g, QueueDev
                         out + i * MLP_OUT, p_lo, p_hi, g, sc.shift, sc.range_scale, sink);
         acc.steps += v.nsteps;
     }
-    if (cur_scen >= 0)
-        for (int j = 0; j < NLEDGER; ++j)
-            if (acc.led[j] != 0) atomicAdd(Q.ledger + (size_t)cur_scen * NLEDGER + j, (unsigned long long)acc.led[j]);
-    // every lane of the wave is back here: the step count reduces per wave
+    // every lane of the wave is back here: the ledgers reduce per wave and
+    // scenario (an epoch's records span one or two scenarios), one atomic per
+    // group instead of one per lane
+    bool pending = cur_scen >= 0;
+    for (;;) {
+        const unsigned long long m = __ballot(pending);
+        if (!m) break;
+        const int leader = __ffsll((long long)m) - 1;
+        const int sc = __shfl(cur_scen, leader, 64);
+        const bool mine = pending && cur_scen == sc;
+#pragma unroll
+        for (int j = 0; j < NLEDGER; ++j) {
+            long long x = mine ? acc.led[j] : 0ll;
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+            if ((int)(threadIdx.x & 63) == leader && x != 0)
+                atomicAdd(Q.ledger + (size_t)sc * NLEDGER + j, (unsigned long long)x);
+        }
+        if (mine) pending = false;
+    }
     unsigned long long st = acc.steps;
     for (int o = 32; o > 0; o >>= 1) st += __shfl_xor(st, o, 64);
     if ((threadIdx.x & 63) == 0 && st != 0) atomicAdd(Q.stats + 0, st);
