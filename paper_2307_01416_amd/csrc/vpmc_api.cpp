@@ -682,8 +682,10 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
 // carve the activation buffers of a batch of up to `cap` samples
 int mlp_buffers(vpmc_ctx *c, int cap, MlpBuffers *b) {
     const size_t H = MLP_HIDDEN;
-    const size_t bytes = (size_t)cap * (MLP_IN * 2 + 4 * H * 2 + 4 * H * 4 + MLP_OUT * 4 * 2 + MLP_OUT * 2 +
-                                        H * 4 * 3 + H * 2 * 2 + 4) + 32 * 256;   // 17 carvings, each rounded up to 256 B
+    const size_t bytes = (size_t)cap * (MLP_IN * 2 + 4 * H * 2 + 4 * H * 4 + MLP_OUT * 4 * 2 + MLP_OUT_LD * 2 +
+                                        H * 2 * 2 + 4) +
+                         (size_t)kMlpSplit * H * H * 4 + ((size_t)cap / 32 + 1) * H * 4 +
+                         32 * 256;   // 17 carvings, each rounded up to 256 B
     if (c->mlp_batch_cap < cap) {
         int rc = ensure(c, c->mlp_act, bytes, 0);
         if (rc) return rc;
@@ -699,12 +701,11 @@ int mlp_buffers(vpmc_ctx *c, int cap, MlpBuffers *b) {
     for (int i = 0; i < 4; ++i) b->z[i] = (float *)take((size_t)cap * H * 4);
     b->out = (float *)take((size_t)cap * MLP_OUT * 4);
     b->dout = (float *)take((size_t)cap * MLP_OUT * 4);
-    b->dout_b = (__bf16 *)take((size_t)cap * MLP_OUT * 2);
-    b->dh = (float *)take((size_t)cap * H * 4);
-    b->dz_a = (float *)take((size_t)cap * H * 4);
-    b->dz_b = (float *)take((size_t)cap * H * 4);
+    b->dout_b = (__bf16 *)take((size_t)cap * MLP_OUT_LD * 2);
     b->dzb_a = (__bf16 *)take((size_t)cap * H * 2);
     b->dzb_b = (__bf16 *)take((size_t)cap * H * 2);
+    b->wpart = (float *)take((size_t)kMlpSplit * H * H * 4);
+    b->bpart = (float *)take(((size_t)cap / 32 + 1) * H * 4);
     b->loss = (float *)take((size_t)cap * 4);
     if (p > end) return fail(VPMC_E_OOM, "surrogate activation buffer too small");
     return VPMC_OK;
@@ -822,16 +823,18 @@ int vpmc_surrogate_loss_grad(vpmc_ctx *c, const float *x, const float *y, const 
     MlpBuffers b;
     if ((rc = mlp_buffers(c, n, &b))) return rc;
     if ((rc = ensure(c, c->mlp_io, (size_t)n * (MLP_IN + 4) * 4 + 64, 0))) return rc;
-    float *dx = (float *)c->mlp_io.ptr, *dy = dx + (size_t)n * MLP_IN, *dt = dy + (size_t)n * 3, *dl = dt + n;
+    double *dl = (double *)c->mlp_io.ptr;
+    float *dx = (float *)(dl + 2), *dy = dx + (size_t)n * MLP_IN, *dt = dy + (size_t)n * 3;
+    HIP_TRY(hipMemset(dl, 0, sizeof(double)));
     HIP_TRY(hipMemcpy(dx, x, (size_t)n * MLP_IN * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(dy, y, (size_t)n * 3 * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(dt, trans, (size_t)n * 4, hipMemcpyHostToDevice));
     HIP_TRY(mlp_to_bf16(dx, b.x, (size_t)n * MLP_IN, nullptr));
     HIP_TRY(mlp_loss_grad(b, dy, dt, n, (float *)c->mlp_g.ptr, dl, nullptr));
-    float lsum = 0.0f;
-    HIP_TRY(hipMemcpy(&lsum, dl, 4, hipMemcpyDeviceToHost));
+    double lmean = 0.0;
+    HIP_TRY(hipMemcpy(&lmean, dl, sizeof(double), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(grad, c->mlp_g.ptr, (size_t)mlp_param_count() * 4, hipMemcpyDeviceToHost));
-    if (loss) *loss = (double)lsum / n;
+    if (loss) *loss = lmean;
     return VPMC_OK;
 }
 
@@ -850,7 +853,8 @@ int vpmc_surrogate_train(vpmc_ctx *c, const float *x, const float *y, const floa
     HIP_TRY(hipMemcpy(c->mlp_dx.ptr, x, (size_t)n * MLP_IN * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->mlp_dy.ptr, y, (size_t)n * 3 * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->mlp_dt.ptr, trans, (size_t)n * 4, hipMemcpyHostToDevice));
-    float *by = (float *)c->mlp_io.ptr, *bt = by + (size_t)batch * 3, *bl = bt + batch;
+    double *bl = (double *)c->mlp_io.ptr;   // sum over the epoch's batches of the batch-mean loss
+    float *by = (float *)(bl + 2), *bt = by + (size_t)batch * 3;
     std::vector<int> perm(n);
     uint64_t st = seed ^ 0x9E3779B97F4A7C15ull;
     const int np = mlp_param_count();
@@ -862,7 +866,7 @@ int vpmc_surrogate_train(vpmc_ctx *c, const float *x, const float *y, const floa
             std::swap(perm[i], perm[j]);
         }
         HIP_TRY(hipMemcpy(c->mlp_idx.ptr, perm.data(), (size_t)n * 4, hipMemcpyHostToDevice));
-        double lsum = 0.0;
+        HIP_TRY(hipMemsetAsync(bl, 0, sizeof(double), nullptr));
         int nb = 0;
         for (int s0 = 0; s0 + batch <= n; s0 += batch, ++nb) {
             const int *idx = (const int *)c->mlp_idx.ptr + s0;
@@ -872,10 +876,9 @@ int vpmc_surrogate_train(vpmc_ctx *c, const float *x, const float *y, const floa
             HIP_TRY(mlp_loss_grad(b, by, bt, batch, (float *)c->mlp_g.ptr, bl, nullptr));
             HIP_TRY(mlp_adam((float *)c->mlp_w.ptr, (const float *)c->mlp_g.ptr, (float *)c->mlp_m.ptr,
                              (float *)c->mlp_v.ptr, (__bf16 *)c->mlp_wb.ptr, np, lr, ++c->mlp_step, nullptr));
-            float l = 0.0f;
-            HIP_TRY(hipMemcpy(&l, bl, 4, hipMemcpyDeviceToHost));
-            lsum += l / batch;
         }
+        double lsum = 0.0;
+        HIP_TRY(hipMemcpy(&lsum, bl, sizeof(double), hipMemcpyDeviceToHost));
         if (loss_per_epoch) loss_per_epoch[ep] = nb ? (float)(lsum / nb) : 0.0f;
     }
     return VPMC_OK;

@@ -175,6 +175,8 @@ constexpr int MLP_LAYERS = 5;
 constexpr int MLP_IN = 8;
 constexpr int MLP_OUT = 29;
 constexpr int MLP_HIDDEN = 256;
+constexpr int MLP_OUT_LD = 32;   // row pitch of the BF16 output gradient
+constexpr int kMlpSplit = 16;    // K split of the weight-gradient products
 constexpr int MLP_MAX_BATCH = 16384;
 constexpr unsigned long long kSurMaxRecords = 1ull << 22;   // surrogate queue (64 B each)
 
@@ -186,10 +188,10 @@ struct MlpBuffers {
     float *z[4];         // [n][256] hidden pre-activations
     float *out;          // [n][29]
     float *dout;         // [n][29] d loss / d out (batch mean)
-    __bf16 *dout_b;
-    float *dh;           // [n][256]
-    float *dz_a, *dz_b;  // [n][256]
-    __bf16 *dzb_a, *dzb_b;
+    __bf16 *dout_b;      // [n][MLP_OUT_LD], zero padded
+    __bf16 *dzb_a, *dzb_b;  // [n][256] d loss / d Z of a hidden layer
+    float *wpart;        // [kMlpSplit][256 * 256] split-K partial weight gradients
+    float *bpart;        // [(n + 31) / 32][256] 32-row partial bias gradients
     float *loss;         // [n] per-sample loss
 };
 
@@ -207,8 +209,10 @@ hipError_t mlp_forward(const MlpBuffers &b, int n, hipStream_t s);
 // features of deferred-VP records; outputs out [n][29] FP32
 hipError_t mlp_infer(const float *x, const DeferRec *rec, int n, const __bf16 *wb, const float *wf, float *out,
                      hipStream_t s);
-hipError_t mlp_loss_grad(const MlpBuffers &b, const float *y, const float *trans, int n, float *grad, float *loss,
-                         hipStream_t s);
+// forward + backward of n samples: gradient of the batch-mean loss into
+// grad; *loss_acc += the batch-mean loss
+hipError_t mlp_loss_grad(const MlpBuffers &b, const float *y, const float *trans, int n, float *grad,
+                         double *loss_acc, hipStream_t s);
 hipError_t mlp_gather(const float *x, const int *idx, int n, int cols, __bf16 *xb, float *xf, hipStream_t s);
 hipError_t mlp_to_bf16(const float *x, __bf16 *y, size_t n, hipStream_t s);
 hipError_t mlp_adam(float *p, const float *g, float *m, float *v, __bf16 *pb, int np, float lr, int step,

@@ -20,67 +20,140 @@ __device__ __forceinline__ float dsilu_f(float z) {
     return s * (1.0f + z * (1.0f - s));
 }
 
-// C[m][n] = sum_k A(m,k) B(k,n) + bias[n], A(m,k) = AT ? A[k*lda+m] : A[m*lda+k],
-// B(k,n) = BT ? B[n*ldb+k] : B[k*ldb+n].  C (FP32) and/or Cb (BF16 of the
-// activation, SiLU when ACT) are written.  Workgroup tile 64x64, four waves
-// each own a 32x32 block computed with v_mfma_f32_32x32x16_bf16; K advances
-// 16 at a time through LDS (B stored transposed so each lane's eight K values
-// are contiguous).  Tails in M, N, K are zero-filled / masked.
-template <bool AT, bool BT, bool ACT>
+// C[m][n] = sum_k A(m,k) B(k,n) over one K range, A(m,k) = AT ? A[k*lda+m] :
+// A[m*lda+k], B(k,n) = BT ? B[n*ldb+k] : B[k*ldb+n].  Workgroup tile 64x64,
+// four waves each own a 32x32 block computed with v_mfma_f32_32x32x16_bf16,
+// K advancing 64 per LDS stage (next stage's 16-byte global loads in flight
+// in registers during the current stage's MFMAs).  The operand whose
+// contiguous dimension is K is copied to LDS as is; the other is transposed
+// on the way in, so each lane's eight K values are contiguous in LDS.  Loads
+// are 8 elements wide: pitches and pointers are multiples of 8 elements and
+// the contiguous dimension of each operand is readable up to the next
+// multiple of 8 (elements past M or N only reach masked outputs; elements
+// past K are zeroed).  blockIdx.z selects the K range [z*kchunk, ...) for a
+// split-K product; its partial goes to C + z*czs.
+//   EPI_F32:   C = acc (+ bias[n])                                   (FP32)
+//   EPI_SILU:  C = z = acc + bias[n], Cb = bf16(silu(z))             (forward)
+//   EPI_DSILU: d = acc * silu'(aux[m*ldc+n]), Cb = bf16(d), and the sum of d
+//              over each 32-row block into C[(m/32)*ldc + n]          (backward)
+// For a given element the k16 MFMAs run in ascending K order into one
+// accumulator, as in the fused inference kernel below.
+enum { EPI_F32 = 0, EPI_SILU = 1, EPI_DSILU = 2 };
+constexpr int kGT = 64, kGK = 64, kGLd = kGK + 8;
+
+template <bool AT>
+__device__ __forceinline__ void gemm_fetch(const __bf16 *__restrict__ P, int ld, int rows, int r0, int k0, int kend,
+                                           int t, uint4 (&r)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = t + 256 * h, outer = c >> 3, inner = (c & 7) * 8;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (!AT) {   // rows of the tile, K contiguous
+            const int row = r0 + outer, k = k0 + inner;
+            if (row < rows && k < kend) {
+                v = *(const uint4 *)(P + (size_t)row * ld + k);
+                if (k + 8 > kend) {   // zero the elements past K
+                    unsigned int w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        if (k + j >= kend) w[j >> 1] &= (j & 1) ? 0x0000FFFFu : 0xFFFF0000u;
+                    v = make_uint4(w[0], w[1], w[2], w[3]);
+                }
+            }
+        } else {     // K rows, tile rows contiguous
+            const int k = k0 + outer, row = r0 + inner;
+            if (k < kend && row < rows) v = *(const uint4 *)(P + (size_t)k * ld + row);
+        }
+        r[h] = v;
+    }
+}
+
+template <bool AT>
+__device__ __forceinline__ void gemm_stash(unsigned short *L, int t, const uint4 (&r)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = t + 256 * h, outer = c >> 3, inner = (c & 7) * 8;
+        if (!AT) {
+            *(uint4 *)(L + outer * kGLd + inner) = r[h];
+        } else {
+            const unsigned int w[4] = {r[h].x, r[h].y, r[h].z, r[h].w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                L[(inner + j) * kGLd + outer] = (unsigned short)(w[j >> 1] >> (16 * (j & 1)));
+        }
+    }
+}
+
+template <bool AT, bool BT, int EPI>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(const __bf16 *__restrict__ A, int lda,
                                                         const __bf16 *__restrict__ B, int ldb,
-                                                        const float *__restrict__ bias, float *C, int ldc,
-                                                        __bf16 *Cb, int ldcb, int M, int N, int K) {
-    __shared__ __attribute__((aligned(16))) __bf16 As[64][24];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs[64][24];
+                                                        const float *__restrict__ bias, const float *__restrict__ aux,
+                                                        float *C, int ldc, size_t czs, __bf16 *Cb, int ldcb, int M,
+                                                        int N, int K, int kchunk) {
+    __shared__ __attribute__((aligned(16))) unsigned short As[kGT * kGLd];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[kGT * kGLd];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int m0 = blockIdx.y * kGT, n0 = blockIdx.x * kGT;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
     f32x16 acc;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
-    const __bf16 zero = (__bf16)0.0f;
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        {
-            const int r = t >> 2, kk = (t & 3) * 4, m = m0 + r;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = k0 + kk + j;
-                __bf16 val = zero;
-                if (m < M && k < K) val = AT ? A[(size_t)k * lda + m] : A[(size_t)m * lda + k];
-                As[r][kk + j] = val;
-            }
-        }
-        {
-            const int c = t >> 2, kk = (t & 3) * 4, n = n0 + c;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = k0 + kk + j;
-                __bf16 val = zero;
-                if (n < N && k < K) val = BT ? B[(size_t)n * ldb + k] : B[(size_t)k * ldb + n];
-                Bs[c][kk + j] = val;
-            }
-        }
+    uint4 ra[2], rb[2];
+    gemm_fetch<AT>(A, lda, M, m0, kbeg, kend, t, ra);
+    gemm_fetch<!BT>(B, ldb, N, n0, kbeg, kend, t, rb);
+    const int kb = 8 * (lane >> 5);
+    for (int k0 = kbeg; k0 < kend; k0 += kGK) {
+        gemm_stash<AT>(As, t, ra);
+        gemm_stash<!BT>(Bs, t, rb);
         __syncthreads();
-        bf16x8 a, b;
-        const int kb = 8 * (lane >> 5);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            a[j] = As[wr + (lane & 31)][kb + j];
-            b[j] = Bs[wc + (lane & 31)][kb + j];
+        if (k0 + kGK < kend) {
+            gemm_fetch<AT>(A, lda, M, m0, k0 + kGK, kend, t, ra);
+            gemm_fetch<!BT>(B, ldb, N, n0, k0 + kGK, kend, t, rb);
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+#pragma unroll
+        for (int kk = 0; kk < kGK / 16; ++kk) {
+            if (k0 + 16 * kk >= kend) break;
+            const uint4 av = *(const uint4 *)(As + (wr + (lane & 31)) * kGLd + 16 * kk + kb);
+            const uint4 bv = *(const uint4 *)(Bs + (wc + (lane & 31)) * kGLd + 16 * kk + kb);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
+                                                          __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+        }
         __syncthreads();
     }
     const int n = n0 + wc + (lane & 31);
+    float csum = 0.0f;
+    C += (size_t)blockIdx.z * czs;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int m = m0 + wr + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
         if (m < M && n < N) {
-            const float z = acc[i] + (bias ? bias[n] : 0.0f);
-            if (C) C[(size_t)m * ldc + n] = z;
-            if (Cb) Cb[(size_t)m * ldcb + n] = (__bf16)(ACT ? silu_f(z) : z);
+            if (EPI == EPI_F32) {
+                C[(size_t)m * ldc + n] = acc[i] + (bias ? bias[n] : 0.0f);
+            } else if (EPI == EPI_SILU) {
+                const float z = acc[i] + bias[n];
+                C[(size_t)m * ldc + n] = z;
+                Cb[(size_t)m * ldcb + n] = (__bf16)silu_f(z);
+            } else {
+                const float d = acc[i] * dsilu_f(aux[(size_t)m * ldc + n]);
+                Cb[(size_t)m * ldcb + n] = (__bf16)d;
+                csum += d;
+            }
         }
+    }
+    if (EPI == EPI_DSILU) {
+        csum += __shfl_xor(csum, 32, 64);
+        const int mb = (m0 + wr) >> 5;
+        if (lane < 32 && n < N && m0 + wr < M) C[(size_t)mb * ldc + n] = csum;
+    }
+}
+
+// out[i] = sum over p < parts of in[p*stride + i], in order of p
+__global__ void sum_parts_kernel(const float *__restrict__ in, int parts, size_t stride, size_t n, float *out) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int p = 0; p < parts; ++p) s += in[(size_t)p * stride + i];
+        out[i] = s;
     }
 }
 
@@ -221,7 +294,8 @@ __global__ void gather_rows_kernel(const float *__restrict__ x, const int *__res
 }
 
 // Per-sample loss and its gradient with respect to the 29 outputs (scaled
-// by 1/n for the batch mean), written as FP32 and BF16.
+// by 1/n for the batch mean), written as FP32 [n][29] and as BF16 rows of
+// MLP_OUT_LD with zero padding.
 __global__ void loss_head_kernel(const float *__restrict__ out, const float *__restrict__ y,
                                  const float *__restrict__ trans, int n, float inv_n, float *dout,
                                  __bf16 *dout_b, float *loss) {
@@ -277,19 +351,11 @@ __global__ void loss_head_kernel(const float *__restrict__ out, const float *__r
 #pragma unroll
     for (int j = 0; j < 29; ++j) {
         dout[(size_t)s * 29 + j] = g[j] * inv_n;
-        dout_b[(size_t)s * 29 + j] = (__bf16)(g[j] * inv_n);
+        dout_b[(size_t)s * MLP_OUT_LD + j] = (__bf16)(g[j] * inv_n);
     }
+#pragma unroll
+    for (int j = 29; j < MLP_OUT_LD; ++j) dout_b[(size_t)s * MLP_OUT_LD + j] = (__bf16)0.0f;
     loss[s] = L;
-}
-
-// dZ = dH * silu'(Z), FP32 and BF16 copies
-__global__ void silu_back_kernel(const float *__restrict__ dh, const float *__restrict__ z, float *dz,
-                                 __bf16 *dz_b, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const float v = dh[i] * dsilu_f(z[i]);
-        dz[i] = v;
-        dz_b[i] = (__bf16)v;
-    }
 }
 
 // bias gradient: column sums of dZ [n x cols]
@@ -322,7 +388,8 @@ __global__ void adam_kernel(float *p, const float *__restrict__ g, float *m, flo
     }
 }
 
-__global__ void reduce_sum_kernel(const float *__restrict__ x, int n, float *out) {
+// *out += (sum of x[0..n)) * scale, in FP64
+__global__ void reduce_sum_kernel(const float *__restrict__ x, int n, double scale, double *out) {
     __shared__ float red[256];
     float s = 0.0f;
     for (int i = threadIdx.x; i < n; i += blockDim.x) s += x[i];
@@ -332,7 +399,7 @@ __global__ void reduce_sum_kernel(const float *__restrict__ x, int n, float *out
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = red[0];
+    if (threadIdx.x == 0) *out += (double)red[0] * scale;
 }
 
 int grid_for(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 4096); }
@@ -356,17 +423,34 @@ int mlp_param_offset(int layer) {
 
 int mlp_dim(int i) { return kDims[i]; }
 
-hipError_t mlp_gemm(bool at, bool bt, bool act, const __bf16 *A, int lda, const __bf16 *B, int ldb,
-                    const float *bias, float *C, int ldc, __bf16 *Cb, int ldcb, int M, int N, int K, hipStream_t s) {
-    dim3 grid((N + 63) / 64, (M + 63) / 64), block(256);
-#define VPMC_GEMM(AT_, BT_, ACT_) \
-    hipLaunchKernelGGL((gemm_bf16_kernel<AT_, BT_, ACT_>), grid, block, 0, s, A, lda, B, ldb, bias, C, ldc, Cb, ldcb, M, N, K)
-    if (!at && bt && act) VPMC_GEMM(false, true, true);
-    else if (!at && bt && !act) VPMC_GEMM(false, true, false);
-    else if (!at && !bt) VPMC_GEMM(false, false, false);
-    else if (at && !bt) VPMC_GEMM(true, false, false);
+// C = A.B over the whole K range.  With `part` (room for kMlpSplit products
+// of M x N) and a product too small to fill the chip, K is split over up to
+// kMlpSplit workgroup layers whose partials are then summed in order.
+static hipError_t mlp_gemm(bool at, bool bt, int epi, const __bf16 *A, int lda, const __bf16 *B, int ldb,
+                           const float *bias, const float *aux, float *C, int ldc, __bf16 *Cb, int ldcb, int M, int N,
+                           int K, float *part, hipStream_t s) {
+    const int tiles = ((N + kGT - 1) / kGT) * ((M + kGT - 1) / kGT);
+    int split = 1;
+    if (part && epi == EPI_F32 && !bias && ldc == N && K >= 4 * kGK)
+        split = std::max(1, std::min({kMlpSplit, 256 / tiles, K / (2 * kGK)}));
+    const int kchunk = split > 1 ? ((K + split - 1) / split + kGK - 1) / kGK * kGK : K;
+    split = (K + kchunk - 1) / kchunk;
+    float *dst = split > 1 ? part : C;
+    const int ldd = split > 1 ? N : ldc;
+    const size_t czs = (size_t)M * N;
+    dim3 grid((N + kGT - 1) / kGT, (M + kGT - 1) / kGT, split), block(256);
+#define VPMC_GEMM(AT_, BT_, E_)                                                                                   \
+    hipLaunchKernelGGL((gemm_bf16_kernel<AT_, BT_, E_>), grid, block, 0, s, A, lda, B, ldb, bias, aux, dst, ldd, \
+                       czs, Cb, ldcb, M, N, K, kchunk)
+    if (!at && bt && epi == EPI_SILU) VPMC_GEMM(false, true, EPI_SILU);
+    else if (!at && bt && epi == EPI_F32) VPMC_GEMM(false, true, EPI_F32);
+    else if (!at && !bt && epi == EPI_DSILU) VPMC_GEMM(false, false, EPI_DSILU);
+    else if (at && !bt && epi == EPI_F32) VPMC_GEMM(true, false, EPI_F32);
     else return hipErrorInvalidValue;
 #undef VPMC_GEMM
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || split == 1) return e;
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(grid_for(czs)), dim3(256), 0, s, part, split, czs, czs, C);
     return hipGetLastError();
 }
 
@@ -379,45 +463,47 @@ hipError_t mlp_forward(const MlpBuffers &b, int n, hipStream_t s) {
         const __bf16 *W = b.wb + mlp_param_offset(l);
         const float *bias = b.w + mlp_param_offset(l) + no * ni;
         const bool last = l == MLP_LAYERS - 1;
-        e = mlp_gemm(false, true, !last, in, ni, W, ni, bias, last ? b.out : b.z[l], no, last ? nullptr : b.h[l], no,
-                     n, no, ni, s);
+        e = mlp_gemm(false, true, last ? EPI_F32 : EPI_SILU, in, ni, W, ni, bias, nullptr, last ? b.out : b.z[l], no,
+                     last ? nullptr : b.h[l], no, n, no, ni, nullptr, s);
     }
     return e;
 }
 
-hipError_t mlp_loss_grad(const MlpBuffers &b, const float *y, const float *trans, int n, float *grad, float *loss,
-                         hipStream_t s) {
+hipError_t mlp_loss_grad(const MlpBuffers &b, const float *y, const float *trans, int n, float *grad,
+                         double *loss_acc, hipStream_t s) {
     hipError_t e = mlp_forward(b, n, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(loss_head_kernel, dim3((n + 255) / 256), dim3(256), 0, s, b.out, y, trans, n, 1.0f / n,
                        b.dout, b.dout_b, b.loss);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(256), 0, s, b.loss, n, loss);
+    hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(256), 0, s, b.loss, n, 1.0 / n, loss_acc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // backward through the layers; dZ of the current layer in (dcur FP32, dcur_b BF16)
-    const float *dcur = b.dout;
-    const __bf16 *dcur_b = b.dout_b;
+    // backward through the layers; dZ of the current layer in BF16 (dcur, row
+    // pitch ldd) and its bias gradient from FP32 values
+    const __bf16 *dcur = b.dout_b;
+    int ldd = MLP_OUT_LD;
     for (int l = MLP_LAYERS - 1; l >= 0; --l) {
         const int ni = kDims[l], no = kDims[l + 1];
         const __bf16 *in = l == 0 ? b.x : b.h[l - 1];
         float *gW = grad + mlp_param_offset(l), *gb = gW + no * ni;
         // dW = dZ^T . H_in   (M = no, N = ni, K = n)
-        if ((e = mlp_gemm(true, false, false, dcur_b, no, in, ni, nullptr, gW, ni, nullptr, 0, no, ni, n, s)) != hipSuccess)
+        if ((e = mlp_gemm(true, false, EPI_F32, dcur, ldd, in, ni, nullptr, nullptr, gW, ni, nullptr, 0, no, ni, n,
+                          b.wpart, s)) != hipSuccess)
             return e;
-        hipLaunchKernelGGL(colsum_kernel, dim3(no), dim3(256), 0, s, dcur, n, no, gb);
+        if (l == MLP_LAYERS - 1)   // output layer: column sums of the FP32 dOUT
+            hipLaunchKernelGGL(colsum_kernel, dim3(no), dim3(256), 0, s, b.dout, n, no, gb);
+        else                       // 32-row partial sums left by the dZ epilogue
+            hipLaunchKernelGGL(colsum_kernel, dim3(no), dim3(256), 0, s, b.bpart, (n + 31) / 32, no, gb);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (l == 0) break;
-        // dH_in = dZ . W   (M = n, N = ni, K = no), then dZ_in = dH_in * silu'(Z_in)
+        // dZ_in = (dZ . W) * silu'(Z_in)   (M = n, N = ni, K = no)
         const __bf16 *W = b.wb + mlp_param_offset(l);
-        if ((e = mlp_gemm(false, false, false, dcur_b, no, W, ni, nullptr, b.dh, ni, nullptr, 0, n, ni, no, s)) != hipSuccess)
-            return e;
-        float *dz = (l & 1) ? b.dz_a : b.dz_b;
         __bf16 *dzb = (l & 1) ? b.dzb_a : b.dzb_b;
-        hipLaunchKernelGGL(silu_back_kernel, dim3(grid_for((size_t)n * ni)), dim3(256), 0, s, b.dh, b.z[l - 1], dz, dzb,
-                           (size_t)n * ni);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        dcur = dz;
-        dcur_b = dzb;
+        if ((e = mlp_gemm(false, false, EPI_DSILU, dcur, ldd, W, ni, nullptr, b.z[l - 1], b.bpart, ni, dzb, ni, n,
+                          ni, no, nullptr, s)) != hipSuccess)
+            return e;
+        dcur = dzb;
+        ldd = ni;
     }
     return hipSuccess;
 }

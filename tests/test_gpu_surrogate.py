@@ -52,11 +52,12 @@ def test_forward_matches_oracle(ctx, orc):
     assert _rel(out, ref) <= 2e-2 and _cos(out.ravel(), ref.ravel()) > 0.999
 
 
-def test_gradient_matches_oracle(ctx, orc):
+@pytest.mark.parametrize("n", [1000, 4096])   # ragged tiles and K split; the training batch
+def test_gradient_matches_oracle(ctx, orc, n):
     from paper_2307_01416_amd import vpmc as V
     p = orc.mlp_init(5) * 0.5
     V.vpmc_surrogate_set_weights(ctx, p)
-    x, y, t = _data(1000, seed=1)
+    x, y, t = _data(n, seed=1)
     lg, gg = V.vpmc_surrogate_loss_grad(ctx, x, y, t)
     lo, go = orc.mlp_loss_grad(p, x, y, t)
     say(f"  loss gpu {lg:.6f} oracle {lo:.6f}; grad rel L2 {_rel(gg, go):.3e} cosine {_cos(gg, go):.6f}")
