@@ -145,7 +145,9 @@ typedef struct {
     unsigned flags;         /* VPMC_DEVICE_PTRS */
     void *hip_stream;       /* hipStream_t or NULL (default stream) */
     size_t max_device_bytes;/* 0 = no cap; scratch above the cap -> VPMC_E_OOM */
-    int block_threads;      /* 0 = tuned default; else 256 or 512 */
+    int block_threads;      /* 0 = tuned default; else 256 or 512, for CSR output also 768 or 1024
+                               (the CSR queue runs at most 1024 threads in physics mode, 768 in
+                               straight mode, and its LDS tile shrinks with the workgroup) */
     int grid_blocks;        /* 0 = tuned default */
     int hist_per_lane;      /* CSR work-queue chunk = 64 * hist_per_lane histories; 0 = default 4 */
     int max_slots;          /* CSR rows resident at once (<= 1024); 0 = sized from memory */
@@ -192,9 +194,10 @@ int vpmc_run_batched(vpmc_ctx *ctx, const int *field_ids, const vpmc_spot *const
  * transport time per history, writes it into *best (a copy of *base with
  * hist_per_lane, grid_blocks and block_threads filled) and remembers it for
  * later runs on this context whose opts leave them at 0.  Candidates (CSR):
- * hist_per_lane in {4,8,16,32} x (workgroups, threads) in {(4 CUs, 256),
- * (8 CUs, 256), (2 CUs, 512), (4 CUs, 512)}; (dense): {4,8,16,32} x CUs x 256
- * threads of work per launch in workgroups of 256 or 512 threads. */
+ * hist_per_lane in {1,2,4,8} x workgroups of 1024 or 512 threads (768 or 512
+ * in straight mode), as many as fill every CU at its full wave occupancy;
+ * (dense): {4,8,16,32} x CUs x 256 threads of work per launch in workgroups of
+ * 256 or 512 threads. */
 int vpmc_autotune(vpmc_ctx *ctx, int field_id, const vpmc_spot *spots, int n_spots,
                   const vpmc_scenario *scen, const vpmc_opts *base, uint64_t sample_histories,
                   vpmc_opts *best);

@@ -116,7 +116,7 @@ struct vpmc_ctx {
     vpmc_stats last_stats{};
     std::vector<hipEvent_t> events;
     // influence-matrix builder
-    DevBuf slot_grid, slot_mark, slot_cnt, slot_coff, slot_rowcnt;
+    DevBuf slot_grid, slot_mark, slot_cnt, slot_coff, slot_rowcnt, q_stage, q_rownext;
     int n_slots = 0;
     size_t slot_nvox = 0;
     bool slots_dirty = false;
@@ -299,6 +299,66 @@ int grow_keep(vpmc_ctx *c, DevBuf &b, size_t keep_bytes, size_t bytes, size_t ca
     return VPMC_OK;
 }
 
+// LDS tile box of a row (voxel indices, x fastest): the voxels along the
+// spot's central ray from its CT entry to 1.5 x its CSDA range in water + 10 mm,
+// widened laterally by the largest half-width (<= 15 mm, 0.5 mm steps) that
+// keeps the box within cap voxels.  No box (tn = 0) when the ray misses the
+// grid or no width fits.
+static void tile_box(const FieldDev &f, const SpotDev &sp, const ScenDev &sc, const GeomDev &g, int cap, int lo[3],
+                     int n[3]) {
+    lo[0] = lo[1] = lo[2] = 0;
+    n[0] = n[1] = n[2] = 0;
+    if (cap <= 0) return;
+    const int gn[3] = {g.nx, g.ny, g.nz};
+    double p0[3], d[3], glo[3], ghi[3];
+    for (int k = 0; k < 3; ++k) {
+        p0[k] = (double)f.iso[k] + sp.x * (double)f.ex[k] + sp.y * (double)f.ey[k] - (double)sc.shift[k];
+        d[k] = f.ez[k];
+        glo[k] = g.lo[k];
+        ghi[k] = g.lo[k] + gn[k] * (double)g.sp[k];
+    }
+    double tn = -1e30, tf = 1e30;
+    for (int k = 0; k < 3; ++k) {
+        if (std::fabs(d[k]) < 1e-12) {
+            if (p0[k] < glo[k] || p0[k] >= ghi[k]) return;
+            continue;
+        }
+        const double t1 = (glo[k] - p0[k]) / d[k], t2 = (ghi[k] - p0[k]) / d[k];
+        tn = std::max(tn, std::min(t1, t2));
+        tf = std::min(tf, std::max(t1, t2));
+    }
+    if (!(tf > tn)) return;
+    const double reach = 1.5 * 10.0 * range_host(MAT_WATER, std::min((double)sp.e0, E_HI)) + 10.0;
+    const double t1 = std::min(tf, tn + reach);
+    int mn[3], mx[3], a = 0;
+    for (int k = 0; k < 3; ++k) {
+        auto cell = [&](double t) {
+            const int i = (int)std::floor((p0[k] + t * d[k] - glo[k]) / g.sp[k]);
+            return std::min(std::max(i, 0), gn[k] - 1);
+        };
+        mn[k] = std::min(cell(tn), cell(t1));
+        mx[k] = std::max(cell(tn), cell(t1));
+        if (std::fabs(d[k]) > std::fabs(d[a])) a = k;
+    }
+    for (double h = 15.0; h >= 0.0; h -= 0.5) {
+        int l[3], w[3];
+        size_t vol = 1;
+        for (int k = 0; k < 3; ++k) {
+            const int hk = k == a ? 0 : (int)std::floor(h / g.sp[k]);
+            l[k] = std::max(0, mn[k] - hk);
+            w[k] = std::min(gn[k] - 1, mx[k] + hk) - l[k] + 1;
+            vol *= (size_t)w[k];
+        }
+        if (vol <= (size_t)cap) {
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = l[k];
+                n[k] = w[k];
+            }
+            return;
+        }
+    }
+}
+
 int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario *scen, int n_scen, const vpmc_opts *o,
             int k, float *dose_gy, double *ledger_mev, int64_t *row_ptr) {
     const size_t nvox = c->nvox;
@@ -355,6 +415,30 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
         for (int q = 0; q < 3; ++q) stab[i].shift[q] = scen[i].shift_mm[q];
         stab[i].range_scale = scen[i].range_scale;
     }
+
+    // launch shape of the work queue and the LDS tile it leaves per workgroup
+    int dev_cus = 256;
+    size_t lds_wg = 64 * 1024;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+            dev_cus = prop.multiProcessorCount;
+            lds_wg = prop.sharedMemPerBlock;
+        }
+    }
+    const int q_threads = queue_threads(o->physics,
+                                        o->block_threads ? o->block_threads
+                                                         : (c->tuned_csr_threads ? c->tuned_csr_threads : 1024));
+    const int q_blocks = o->grid_blocks ? o->grid_blocks
+                         : (c->tuned_csr_blocks ? c->tuned_csr_blocks
+                                                : std::max(1, dev_cus * (o->physics == 0 ? 12 : 16) / (q_threads / 64)));
+    int tile_cap = queue_tile_cap(o->physics, q_threads);
+    {
+        const size_t stat = (o->physics == 0 ? TAB_FLOATS : TAB_HI_FLOATS) * 4 + POLY_LDS * 8 + 256;
+        tile_cap = (int)std::min<size_t>((size_t)tile_cap, lds_wg > stat ? (lds_wg - stat) / 8 : 0);
+    }
+    for (RowDev &r : rows)
+        tile_box(ftab[r.field], sd[r.spot_global], stab[r.scen], c->geom, tile_cap, r.tlo, r.tn);
 
     // slots: dense int64 grid + touched-block bytes per resident row
     const size_t nblk = (nvox + 31) / 32, nchunk = (nblk + 255) / 256;
@@ -470,14 +554,11 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     Q.stats = (unsigned long long *)c->stats.ptr;
     Q.tables = c->d_tables;
 
-    int dev_cus = 256;
-    {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) dev_cus = prop.multiProcessorCount;
-    }
-    const int q_threads = o->block_threads ? o->block_threads : (c->tuned_csr_threads ? c->tuned_csr_threads : 256);
-    const int q_blocks = o->grid_blocks ? o->grid_blocks
-                         : (c->tuned_csr_blocks ? c->tuned_csr_blocks : dev_cus * 4);   // 16 waves per CU
+    if ((rc = ensure(c, c->q_stage, queue_stage_floats(q_blocks, q_threads, hpl) * sizeof(float), cap))) return rc;
+    if ((rc = ensure(c, c->q_rownext, (size_t)std::max(R, 1) * 8, cap))) return rc;
+    Q.stage = (float *)c->q_stage.ptr;
+    Q.refill_min = kRefillMin;
+    Q.tile_cap = tile_cap;
     while (c->events.size() < 4) {
         hipEvent_t ev;
         HIP_TRY(hipEventCreate(&ev));
@@ -488,6 +569,7 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
         HIP_TRY(launch_fill_u64((unsigned long long *)c->ledger.ptr, (size_t)n_scen * NLEDGER, 0ull, st));
         HIP_TRY(launch_fill_u64((unsigned long long *)c->stats.ptr, 2, 0ull, st));
         HIP_TRY(launch_fill_u64((unsigned long long *)c->heads.ptr, (size_t)std::max(1, E), 0ull, st));
+        HIP_TRY(launch_fill_u64((unsigned long long *)c->q_rownext.ptr, (size_t)std::max(1, R), 0ull, st));
         HIP_TRY(launch_fill_u64((unsigned long long *)c->used.ptr, 1, 0ull, st));
         HIP_TRY(launch_fill_u64((unsigned long long *)c->flags.ptr, 1, 0ull, st));
         return VPMC_OK;
@@ -499,6 +581,7 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
         Qe.chunk_off = (const unsigned long long *)c->chunk_off.ptr + ep_choff[e];
         Qe.n_chunks = ep_chunks[e];
         Qe.head = (unsigned long long *)c->heads.ptr + e;
+        Qe.row_next = (unsigned long long *)c->q_rownext.ptr + Qe.row_begin;
         return Qe;
     };
     // compaction passes of one epoch (count per chunk, scan per row; emit)
@@ -930,7 +1013,7 @@ void vpmc_destroy(vpmc_ctx *c) {
         }
         for (DevBuf *b : {&c->tallies, &c->qbatch, &c->s2, &c->ledger, &c->spots, &c->offsets,
                           &c->stage_dose, &c->stage_sigma, &c->stats, &c->slot_grid, &c->slot_mark, &c->slot_cnt,
-                          &c->slot_coff, &c->slot_rowcnt, &c->rows, &c->chunk_off, &c->heads, &c->row_off, &c->row_nnz, &c->used,
+                          &c->slot_coff, &c->slot_rowcnt, &c->q_stage, &c->q_rownext, &c->rows, &c->chunk_off, &c->heads, &c->row_off, &c->row_nnz, &c->used,
                           &c->flags, &c->fields_tab, &c->poly_off, &c->polys, &c->scen_tab, &c->csr_col,
                           &c->csr_q, &c->mlp_w, &c->mlp_wb, &c->mlp_m, &c->mlp_v, &c->mlp_g, &c->mlp_act,
                           &c->mlp_io, &c->mlp_dx, &c->mlp_dy, &c->mlp_dt, &c->mlp_idx, &c->sur_rec,
@@ -1083,8 +1166,9 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
     if ((rc = validate_scen(scen, n_scen))) return rc;
     if (o->physics & ~VPMC_PHYS_ALL) return fail(VPMC_E_ARG, "unknown physics bits");
     if (o->n_batches < 0 || o->n_batches > 1024) return fail(VPMC_E_ARG, "n_batches outside [0, 1024]");
-    if (o->block_threads && o->block_threads != 256 && o->block_threads != 512)
-        return fail(VPMC_E_ARG, "block_threads must be 0, 256 or 512");
+    if (o->block_threads && o->block_threads != 256 && o->block_threads != 512 &&
+        !(o->output == VPMC_OUT_CSR && (o->block_threads == 768 || o->block_threads == 1024)))
+        return fail(VPMC_E_ARG, "block_threads must be 0, 256 or 512 (768 or 1024 also for CSR output)");
     if (o->grid_blocks < 0) return fail(VPMC_E_ARG, "grid_blocks < 0");
     if (o->hist_per_lane < 0 || o->hist_per_lane > 4096) return fail(VPMC_E_ARG, "hist_per_lane outside [0, 4096]");
     if (o->max_slots < 0) return fail(VPMC_E_ARG, "max_slots < 0");
@@ -1313,8 +1397,9 @@ int vpmc_run_batched(vpmc_ctx *c, const int *field_ids, const vpmc_spot *const *
     if ((o->flags & VPMC_SURROGATE) && !c->mlp_ready) return fail(VPMC_E_STATE, "VPMC_SURROGATE needs surrogate weights");
     if (o->hist_per_lane < 0 || o->hist_per_lane > 4096) return fail(VPMC_E_ARG, "hist_per_lane outside [0, 4096]");
     if (o->max_slots < 0 || o->grid_blocks < 0) return fail(VPMC_E_ARG, "negative tuning value");
-    if (o->block_threads && o->block_threads != 256 && o->block_threads != 512)
-        return fail(VPMC_E_ARG, "block_threads must be 0, 256 or 512");
+    if (o->block_threads && o->block_threads != 256 && o->block_threads != 512 &&
+        o->block_threads != 768 && o->block_threads != 1024)
+        return fail(VPMC_E_ARG, "block_threads must be 0, 256, 512, 768 or 1024");
     int k = 0;
     if ((rc = pick_k(o, T, &k))) return rc;
     if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
@@ -1345,9 +1430,13 @@ int vpmc_autotune(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spots
     struct Cand { int hpl, blocks, threads; };
     std::vector<Cand> cand;
     if (csr) {
-        for (int h : {4, 8, 16, 32})
-            for (auto bt : {std::make_pair(4, 256), std::make_pair(8, 256), std::make_pair(2, 512), std::make_pair(4, 512)})
-                cand.push_back({h, bt.first * cus, bt.second});
+        // one resident set of workgroups: 16 waves per CU (12 in double-float mode)
+        const int waves_cu = base->physics == 0 ? 12 : 16;
+        for (int h : {1, 2, 4, 8})
+            for (int t : {1024, 512}) {
+                const int tt = queue_threads(base->physics, t);
+                cand.push_back({h, std::max(1, cus * waves_cu / (tt / 64)), tt});
+            }
     } else {
         for (int m : {4, 8, 16, 32})
             for (int t : {256, 512}) cand.push_back({0, m * cus * 256 / t, t});

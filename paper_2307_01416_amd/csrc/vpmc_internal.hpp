@@ -134,6 +134,7 @@ struct RowDev {
     uint32_t spot_global; // index into the flattened spot table
     int scen;
     uint32_t n_hist;
+    int tlo[3], tn[3];    // LDS tile box of the row in voxel indices (tn = 0: none)
 };
 
 struct ScenDev {
@@ -146,8 +147,12 @@ struct QueueDev {
     const unsigned long long *chunk_off;  // [n_rows + 1] chunk prefix of this epoch's rows
     int row_begin, n_rows;
     unsigned long long n_chunks;
-    unsigned long long *head;             // work-queue counter of this epoch
+    unsigned long long *head;             // fresh-row counter of this epoch
+    unsigned long long *row_next;         // [n_rows] chunk counter per row of this epoch
+    int tile_cap;                         // int64 entries of the workgroup's LDS tile
     int hist_per_lane;                    // one chunk = 64 * hist_per_lane histories
+    int refill_min;                       // idle lanes that trigger a refill in the patient loop
+    float *stage;                         // [waves of the launch][64 * min(hist_per_lane, kStageHpl)] staged VPs (64 B)
     const FieldDev *fields;
     const int *poly_off;                  // per field: offset into polys
     const float2 *polys;
@@ -166,7 +171,20 @@ struct QueueDev {
     SurDev sur;                           // surrogate queue (enabled = 0: off)
 };
 
+// staging floats the queue kernel needs for a launch shape (per wave up to
+// 64 * kStageHpl VPs of 16 words)
+constexpr size_t kStageFields = 16;
+constexpr int kStageHpl = 32;
+constexpr int kRefillMin = 8;   // idle lanes that trigger a refill of the patient loop
+inline size_t queue_stage_floats(int blocks, int threads, int hist_per_lane) {
+    const size_t hps = (size_t)(hist_per_lane < kStageHpl ? hist_per_lane : kStageHpl);
+    return (size_t)blocks * (size_t)((threads + 63) / 64) * kStageFields * 64 * hps;
+}
 hipError_t launch_queue(const GeomDev &g, const QueueDev &Q, int blocks, int threads, hipStream_t s);
+// workgroup size the queue kernel runs with for a requested size, and the
+// LDS tile entries that leave the CU its full wave occupancy
+int queue_threads(unsigned physics, int threads);
+int queue_tile_cap(unsigned physics, int threads);
 
 // ------------------------------------------------------- aperture surrogate
 // MLP 8 -> 256 -> 256 -> 256 -> 256 -> 29, parameters layer by layer as

@@ -374,7 +374,7 @@ __device__ __forceinline__ void ledger_add(Acc &a, int j, float e, float scale) 
 // dense tally: one 64-bit atomic per deposit
 struct DenseSink {
     unsigned long long *tally;
-    __device__ __forceinline__ void add(uint32_t v, long long q) const {
+    __device__ __forceinline__ void add(uint32_t v, const int *, long long q) const {
         atomicAdd(tally + v, (unsigned long long)q);
     }
 };
@@ -388,9 +388,37 @@ struct DenseSink {
 struct SparseSink {
     unsigned long long *grid;
     uint8_t *mark;
-    __device__ __forceinline__ void add(uint32_t v, long long q) const {
+    __device__ __forceinline__ void add(uint32_t v, const int *, long long q) const {
+        put(v, q);
+    }
+    __device__ __forceinline__ void put(uint32_t v, long long q) const {
         atomicAdd(grid + v, (unsigned long long)q);
         __hip_atomic_store(mark + (v >> 5), (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+};
+
+// Row tile of the influence-matrix builder: a dense int64 box of the CT grid
+// in LDS around the spot's central ray, shared by the waves of a workgroup
+// that work on the same row.  Deposits inside the box are LDS atomics, the
+// others go to the row's slot grid; the box is added into the slot grid once
+// when its last user leaves.  On this GPU the int64 tally atomics to device
+// memory are performed on the memory side, beyond the XCD's L2, and their
+// rate bounds the step loop; the tile takes most of them off that path.
+struct TileSink {
+    long long *tile;     // nullptr: this batch does not use the tile
+    int lo0, lo1, lo2;
+    uint32_t n0, n1, n2;
+    SparseSink gs;
+    __device__ __forceinline__ void add(uint32_t v, const int *idx, long long q) const {
+        if (tile) {
+            const uint32_t u0 = (uint32_t)(idx[0] - lo0), u1 = (uint32_t)(idx[1] - lo1), u2 = (uint32_t)(idx[2] - lo2);
+            if (u0 < n0 && u1 < n1 && u2 < n2) {
+                atomicAdd(reinterpret_cast<unsigned long long *>(tile) + (u0 + n0 * (u1 + n1 * u2)),
+                          (unsigned long long)q);
+                return;
+            }
+        }
+        gs.put(v, q);
     }
 };
 
@@ -859,7 +887,7 @@ __device__ bool patient_step(Lane &v, Acc &acc, float scale, const float *tab, c
         float dep, esc;
         const int st = phys_step<false, X>(v, tab, m, rho_loss, rho.h, dg, dep, esc);
         const long long qd = to_fixed(dep, scale);
-        if (qd != 0) sink.add(vox, qd);
+        if (qd != 0) sink.add(vox, idx, qd);
         acc.led[L_GRID] += qd;
         ledger_add(acc, L_NUC, esc, scale);
         if (st == ST_STOP) return false;
@@ -983,60 +1011,279 @@ __global__ __launch_bounds__(512) void transport_kernel(GeomDev g, FieldDev f, L
 }
 
 // ------------------------------------------------------------ CSR mode
-// Work-queue transport: each wavefront takes one chunk (64 * hist_per_lane
-// histories of one row) at a time from the epoch's atomic counter, so rows
-// of uneven energy and history count balance across the chip.  Every wave
-// exits once the counter passes the number of chunks.
-// at most 512 threads per workgroup; physics mode keeps 4 waves per SIMD
-// (<= 128 VGPRs), the double-float mode needs about 160 VGPRs (3 waves)
+// A VP staged at its entry into the CT grid (64 B, four 16-byte words):
+// voxel-local position, direction in the CT frame, energy pair, Philox block
+// counter, history, step count, voxel (linear, per axis) and its CT number.
+struct alignas(16) StagedVP {
+    float px, py, pz, dx;
+    float dy, dz, E, Elo;
+    uint32_t nblk, hist, nsteps, vox;
+    int i0, i1, i2, hu;
+};
+static_assert(sizeof(StagedVP) == 4 * kStageFields, "staging record");
+
+constexpr uint32_t kRowNone = 0xFFFFFFFFu;   // workgroup row word: no row yet
+constexpr uint32_t kRowPick = 0xFFFFFFFDu;   // a wave is picking the next row
+constexpr uint32_t kRowEnd = 0xFFFFFFFEu;    // no work left in the epoch
+constexpr uint32_t kTileBusy = 0xFFFFFFFFu;  // tile users field while it is added out
+
+__device__ __forceinline__ unsigned long long rd_lds64(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Adds the tile of row rl (epoch-local) into its slot grid and clears it; one wave.
+__device__ void tile_flush(long long *tile, const RowDev &row, const QueueDev &Q, const GeomDev &g, uint32_t rl,
+                           int lane) {
+    const uint32_t n0 = (uint32_t)row.tn[0], n1 = (uint32_t)row.tn[1], n2 = (uint32_t)row.tn[2];
+    const SparseSink gs{Q.grid + (size_t)rl * Q.gstride, Q.mark + (size_t)rl * Q.mstride};
+    uint32_t e = 0;
+    for (uint32_t u2 = 0; u2 < n2; ++u2)
+        for (uint32_t u1 = 0; u1 < n1; ++u1, e += n0)
+            for (uint32_t u0 = (uint32_t)lane; u0 < n0; u0 += 64) {
+                const long long q = tile[e + u0];
+                if (q != 0) {
+                    tile[e + u0] = 0;
+                    gs.put((uint32_t)(row.tlo[0] + (int)u0) +
+                               (uint32_t)g.nx * ((uint32_t)(row.tlo[1] + (int)u1) + (uint32_t)g.ny * (uint32_t)(row.tlo[2] + (int)u2)),
+                           q);
+                }
+            }
+}
+
+// Influence-matrix transport of an epoch's rows.  Each row has a chunk
+// counter (chunk = 64 * hist_per_lane histories); a workgroup works on one
+// current row at a time, its waves drawing chunks of it, and when the row is
+// exhausted one wave picks the next: a fresh row from the epoch's row head,
+// else (work stealing) any row with chunks left, else the end.  The
+// workgroup's LDS tile holds one row's box at a time (RowDev::tlo/tn): a
+// wave joins it for a chunk of that row, and the last wave to leave adds
+// it into the slot grid; chunks of another row go straight to the slot
+// grid.  Per chunk, in stage fills of up to 64 * kStageHpl histories:
+// phase 1 runs source, beam line and CT entry with the lanes in lock step
+// and stages the VPs that enter the grid (compacted with a ballot); phase 2
+// is the patient step loop, where a lane whose VP has ended takes the next
+// staged VP as soon as refill_min lanes are idle (or all remaining VPs fit).
+// Each history's arithmetic and random stream are those of a lane running it
+// alone, and the tallies are integer sums: the result does not depend on
+// the schedule.  The only waits between waves are for the wave that is
+// replacing the current row, which does so without waiting on anyone.
 template <bool X>
-__global__ __launch_bounds__(512, X ? 3 : 4) void queue_kernel(GeomDev g, QueueDev Q) {
+// Physics mode: up to 1024 threads (16 waves at <= 128 VGPRs, one workgroup
+// per CU with a ~120 KiB tile); double-float mode: up to 768 (12 waves at
+// <= 168 VGPRs).
+__global__ __launch_bounds__(X ? 768 : 1024) void queue_kernel(GeomDev g, QueueDev Q) {
     __shared__ float tab[X ? TAB_FLOATS : TAB_HI_FLOATS];
     __shared__ float2 poly[POLY_LDS];
+    __shared__ unsigned long long s_row;    // current row (high word; kRowNone while replaced)
+    __shared__ unsigned long long s_tile;   // (row of the tile << 32) | users, kTileBusy while flushed
+    extern __shared__ __attribute__((aligned(16))) long long tile[];   // Q.tile_cap int64
     for (int i = threadIdx.x; i < (X ? TAB_FLOATS : TAB_HI_FLOATS) / 4; i += blockDim.x)
         reinterpret_cast<float4 *>(tab)[i] = reinterpret_cast<const float4 *>(Q.tables)[i];
     for (int i = threadIdx.x; i < Q.n_poly_total; i += blockDim.x) poly[i] = Q.polys[i];
+    for (int i = threadIdx.x; i < Q.tile_cap; i += blockDim.x) tile[i] = 0;
+    if (threadIdx.x == 0) {
+        s_row = (unsigned long long)kRowNone << 32;
+        s_tile = (unsigned long long)kRowNone << 32;
+    }
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int hps = min(Q.hist_per_lane, kStageHpl);   // histories per lane per stage fill
+    StagedVP *const stg = reinterpret_cast<StagedVP *>(Q.stage) +
+                          ((size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (size_t)(hps * 64);
+    const unsigned long long chunk_h = 64ull * (unsigned long long)Q.hist_per_lane;
     for (;;) {
-        unsigned long long item = 0;
-        if (lane == 0) item = atomicAdd(Q.head, 1ull);
-        // all lanes are active here: lane 0 is the first lane, so the item
-        // (and everything derived from it) is wave-uniform in scalar registers
-        const uint32_t ilo = __builtin_amdgcn_readfirstlane((uint32_t)item);
-        const uint32_t ihi = __builtin_amdgcn_readfirstlane((uint32_t)(item >> 32));
-        item = ((unsigned long long)ihi << 32) | ilo;
-        if (item >= Q.n_chunks) break;
-        const int rl = find_spot(Q.chunk_off, Q.n_rows, item);
-        const unsigned long long j = item - Q.chunk_off[rl];
+        // ---- the workgroup's current row, and a chunk of it
+        const uint32_t cur = __builtin_amdgcn_readfirstlane((uint32_t)(rd_lds64(&s_row) >> 32));
+        if (cur == kRowEnd) break;
+        if (cur == kRowPick) {   // another wave is picking the next row (it waits on nobody)
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        unsigned long long cj = ~0ull;
+        uint32_t nch = 0;
+        if (cur != kRowNone) {
+            nch = (uint32_t)((Q.rows[Q.row_begin + cur].n_hist + chunk_h - 1) / chunk_h);
+            if (lane == 0) cj = atomicAdd(Q.row_next + cur, 1ull);
+            cj = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(cj >> 32)) << 32) |
+                 __builtin_amdgcn_readfirstlane((uint32_t)cj);
+        }
+        if (cj >= nch) {
+            // no row yet, or this one is exhausted: the one wave that swaps
+            // the row word from cur to kRowPick picks the next row
+            bool mine = false;
+            if (lane == 0) {
+                unsigned long long w = (unsigned long long)cur << 32;
+                mine = __hip_atomic_compare_exchange_strong(&s_row, &w, (unsigned long long)kRowPick << 32,
+                                                            __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            if (__builtin_amdgcn_readfirstlane((uint32_t)mine) != 0u) {
+                // a fresh row from the epoch's head, else the first row with
+                // chunks left (64 rows per probe), else the end
+                unsigned long long f = 0;
+                if (lane == 0) f = atomicAdd(Q.head, 1ull);
+                f = __builtin_amdgcn_readfirstlane((uint32_t)f);   // < 2^32 rows
+                uint32_t nr = kRowEnd;
+                if (f < (unsigned long long)Q.n_rows) {
+                    nr = (uint32_t)f;
+                } else {
+                    for (int r0 = 0; r0 < Q.n_rows; r0 += 64) {
+                        const int r = r0 + lane;
+                        bool left = false;
+                        if (r < Q.n_rows) {
+                            const unsigned long long nc = (Q.rows[Q.row_begin + r].n_hist + chunk_h - 1) / chunk_h;
+                            left = __hip_atomic_load(Q.row_next + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nc;
+                        }
+                        const unsigned long long m = __ballot(left);
+                        if (m) {
+                            nr = (uint32_t)(r0 + __ffsll((long long)m) - 1);
+                            break;
+                        }
+                    }
+                }
+                if (lane == 0)
+                    __hip_atomic_store(&s_row, (unsigned long long)nr << 32, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            continue;
+        }
+        const uint32_t rl = cur;
+        const unsigned long long j = cj;
         const RowDev row = Q.rows[Q.row_begin + rl];
-        const FieldDev f = Q.fields[row.field];
         const SpotDev sp = Q.spots[row.spot_global];
         const ScenDev sc = Q.scen[row.scen];
-        const SparseSink sink{Q.grid + (size_t)rl * Q.gstride, Q.mark + (size_t)rl * Q.mstride};
-        const float2 *fpoly = poly + Q.poly_off[row.field];
+        const SparseSink gsink{Q.grid + (size_t)rl * Q.gstride, Q.mark + (size_t)rl * Q.mstride};
+        // ---- join the tile for this chunk if it holds this row (or is free)
+        bool joined = false;
+        const uint32_t tn = (uint32_t)row.tn[0] * (uint32_t)row.tn[1] * (uint32_t)row.tn[2];
+        if (tn != 0u && tn <= (uint32_t)Q.tile_cap) {
+            if (lane == 0) {
+                for (;;) {
+                    unsigned long long t = rd_lds64(&s_tile);
+                    const uint32_t tr = (uint32_t)(t >> 32), us = (uint32_t)t;
+                    unsigned long long want;
+                    if (us == kTileBusy) break;
+                    if (tr == rl) want = t + 1ull;
+                    else if (us == 0u) want = ((unsigned long long)rl << 32) | 1ull;   // free (and clear): take it
+                    else break;
+                    if (__hip_atomic_compare_exchange_strong(&s_tile, &t, want, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                        joined = true;
+                        break;
+                    }
+                }
+            }
+            joined = __builtin_amdgcn_readfirstlane((uint32_t)joined) != 0u;
+        }
+        const TileSink sink{joined ? tile : nullptr, row.tlo[0], row.tlo[1], row.tlo[2],
+                            (uint32_t)row.tn[0], (uint32_t)row.tn[1], (uint32_t)row.tn[2], gsink};
         Acc acc;
 #pragma unroll
         for (int k = 0; k < NLEDGER; ++k) acc.led[k] = 0;
         acc.steps = acc.hist = 0;
-        for (int t = 0; t < Q.hist_per_lane; ++t) {
-            const unsigned long long h = (j * (unsigned long long)Q.hist_per_lane + t) * 64ull + lane;
-            if (h >= row.n_hist) break;
-            Lane v;
-            v.k0 = Q.key0;
-            v.k1 = Q.seed_hi ^ row.field_id;
-            v.spot = row.spot;
-            v.hist = (uint32_t)h;
-            v.nblk = 0;
-            v.nsteps = 0;
-            v.physics = Q.physics;
-            source(v, sp);
-            float tmin;
-            if (beamline<X>(v, acc, sp.scale, tab, fpoly, f, tmin, &Q.sur, (uint32_t)rl) == BL_PATIENT)
-                patient<SparseSink, X>(v, acc, sp.scale, tab, g, f, sc.shift, sc.range_scale, sink, tmin);
-            acc.steps += v.nsteps;
-            acc.hist += 1;
+        Lane v;
+        v.k0 = Q.key0;
+        v.k1 = Q.seed_hi ^ row.field_id;
+        v.spot = row.spot;
+        v.physics = Q.physics;
+        for (int t0 = 0; t0 < Q.hist_per_lane; t0 += hps) {
+            if ((j * (unsigned long long)Q.hist_per_lane + t0) * 64ull >= row.n_hist) break;
+            // phase 1
+            uint32_t nst = 0;
+            {
+                const FieldDev &f = Q.fields[row.field];
+                const float2 *fpoly = poly + Q.poly_off[row.field];
+                for (int t = t0; t < min(Q.hist_per_lane, t0 + hps); ++t) {
+                    const unsigned long long h0 = (j * (unsigned long long)Q.hist_per_lane + t) * 64ull;
+                    if (h0 >= row.n_hist) break;
+                    const unsigned long long h = h0 + lane;
+                    bool in = false;
+                    PState ps;
+                    if (h < row.n_hist) {
+                        v.hist = (uint32_t)h;
+                        v.nblk = 0;
+                        v.nsteps = 0;
+                        source(v, sp);
+                        float tmin;
+                        in = beamline<X>(v, acc, sp.scale, tab, fpoly, f, tmin, &Q.sur, (uint32_t)rl) == BL_PATIENT &&
+                             patient_enter<X>(v, acc, sp.scale, g, f, sc.shift, tmin, ps);
+                        if (!in) acc.steps += v.nsteps;
+                        acc.hist += 1;
+                    }
+                    const unsigned long long rb = __ballot(in);
+                    if (in) {
+                        StagedVP r;
+                        r.px = v.px; r.py = v.py; r.pz = v.pz; r.dx = v.dx;
+                        r.dy = v.dy; r.dz = v.dz; r.E = v.E; r.Elo = v.Elo;
+                        r.nblk = v.nblk; r.hist = v.hist; r.nsteps = v.nsteps; r.vox = ps.vox;
+                        r.i0 = ps.idx[0]; r.i1 = ps.idx[1]; r.i2 = ps.idx[2]; r.hu = ps.hu;
+                        stg[nst + (uint32_t)__popcll(rb & below)] = r;
+                    }
+                    nst += (uint32_t)__popcll(rb);
+                }
+            }
+            // the staged entries are read back by other lanes of this wave
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            // phase 2
+            uint32_t next = 0;
+            bool active = false;
+            PState ps;
+            for (;;) {
+                const unsigned long long idle = __ballot(!active);
+                const uint32_t nidle = (uint32_t)__popcll(idle);
+                if (next < nst && nidle >= min((uint32_t)Q.refill_min, nst - next)) {
+                    if (!active) {
+                        const uint32_t k = next + (uint32_t)__popcll(idle & below);
+                        if (k < nst) {
+                            const StagedVP r = stg[k];
+                            v.px = r.px; v.py = r.py; v.pz = r.pz; v.dx = r.dx;
+                            v.dy = r.dy; v.dz = r.dz; v.E = r.E; v.Elo = r.Elo;
+                            v.pxlo = v.pylo = v.pzlo = 0.0f;
+                            v.nblk = r.nblk; v.hist = r.hist; v.nsteps = r.nsteps;
+                            ps.vox = r.vox;
+                            ps.idx[0] = r.i0; ps.idx[1] = r.i1; ps.idx[2] = r.i2;
+                            ps.hu = r.hu;
+                            active = true;
+                        }
+                    }
+                    next = min(nst, next + nidle);
+                } else if (nidle == 64u) {
+                    break;
+                }
+                if (active) {
+                    active = patient_step<TileSink, X>(v, acc, sp.scale, tab, g, sc.range_scale, sink, ps);
+                    if (!active) acc.steps += v.nsteps;
+                }
+            }
+        }
+        // ---- leave the tile; the last user adds it out and frees it
+        if (joined) {
+            bool flusher = false;
+            if (lane == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                for (;;) {
+                    unsigned long long t = rd_lds64(&s_tile);
+                    const bool last = (uint32_t)t == 1u;
+                    const unsigned long long want = last ? (((unsigned long long)rl << 32) | kTileBusy) : t - 1ull;
+                    if (__hip_atomic_compare_exchange_strong(&s_tile, &t, want, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                        flusher = last;
+                        break;
+                    }
+                }
+            }
+            flusher = __builtin_amdgcn_readfirstlane((uint32_t)flusher) != 0u;
+            if (flusher) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                tile_flush(tile, row, Q, g, rl, lane);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                if (lane == 0)
+                    __hip_atomic_store(&s_tile, (unsigned long long)rl << 32, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
         }
 #pragma unroll
         for (int k = 0; k < NLEDGER; ++k) {
@@ -1539,10 +1786,28 @@ hipError_t launch_transport(const GeomDev &g, const FieldDev &f, const LaunchDev
     return hipGetLastError();
 }
 
+int queue_threads(unsigned physics, int threads) {
+    const int cap = physics == 0 ? 768 : 1024;
+    if (threads != 256 && threads != 512 && threads != 768 && threads != 1024) threads = cap;
+    return std::min(threads, cap);
+}
+
+// LDS per CU (160 KiB) shared by the workgroups that give the CU its target
+// waves (16 in physics mode, 12 in double-float mode), less the static tables
+int queue_tile_cap(unsigned physics, int threads) {
+    threads = queue_threads(physics, threads);
+    const int waves_cu = physics == 0 ? 12 : 16;
+    const int wgs = std::max(1, waves_cu / (threads / 64));
+    const int stat = (physics == 0 ? TAB_FLOATS : TAB_HI_FLOATS) * 4 + POLY_LDS * 8 + 256;
+    const int per_wg = 160 * 1024 / wgs - stat;
+    return std::max(0, per_wg / 8);
+}
+
 hipError_t launch_queue(const GeomDev &g, const QueueDev &Q, int blocks, int threads, hipStream_t s) {
-    if (threads != 256 && threads != 512) threads = kThreads;
-    if (Q.physics == 0) hipLaunchKernelGGL(queue_kernel<true>, dim3(blocks), dim3(threads), 0, s, g, Q);
-    else hipLaunchKernelGGL(queue_kernel<false>, dim3(blocks), dim3(threads), 0, s, g, Q);
+    threads = queue_threads(Q.physics, threads);
+    const size_t tile_bytes = (size_t)Q.tile_cap * sizeof(long long);
+    if (Q.physics == 0) hipLaunchKernelGGL(queue_kernel<true>, dim3(blocks), dim3(threads), tile_bytes, s, g, Q);
+    else hipLaunchKernelGGL(queue_kernel<false>, dim3(blocks), dim3(threads), tile_bytes, s, g, Q);
     return hipGetLastError();
 }
 
