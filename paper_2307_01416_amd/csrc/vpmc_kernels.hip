@@ -28,9 +28,9 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        // full 64-bit products (one v_mad_u64_u32 each)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
     }
     return c;
 }
@@ -106,9 +106,13 @@ __device__ __forceinline__ uint4 draw(Lane &v) {
     return w;
 }
 
+// Sampling arithmetic of the physics steps uses the hardware square root
+// (about 1 ulp); the straight-mode bookkeeping never calls it.
+__device__ __forceinline__ float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // step normals: hardware sin/cos take the angle in turns
 __device__ __forceinline__ void box_muller_fast(uint32_t a, uint32_t b, float &z1, float &z2) {
-    const float r = sqrtf(-2.0f * __logf(unit_open(a)));
+    const float r = sqrt_hw(-2.0f * __logf(unit_open(a)));
     const float t = unit_open(b);
     z1 = r * __builtin_amdgcn_cosf(t);
     z2 = r * __builtin_amdgcn_sinf(t);
@@ -131,12 +135,40 @@ struct NodePos {
     float f;
 };
 
-__device__ __forceinline__ NodePos node_pos(const float *tab, float E) {
-    const int i = seg_of(tab, E);
-    // interpolation weight of the physics tables: an approximate reciprocal
-    // of the node spacing is ample here
+// position of an energy E < E_i+1 known to lie at or below segment i (the
+// search walks down from i to the unique segment with E_j <= E < E_j+1)
+__device__ __forceinline__ NodePos node_pos_below(const float *tab, float E, int i) {
+    while (i > 0 && E < tab[TAB_E + i]) --i;
     const float f = (E - tab[TAB_E + i]) * __builtin_amdgcn_rcpf(tab[TAB_DWH + i]);
     return {i, fminf(fmaxf(f, 0.0f), 1.0f)};
+}
+
+// Standard normal quantile of u in (0, 1), z = sqrt(2) erfinv(2u - 1), for
+// the straggling draw: erfinv(t)/t as degree-8 polynomials in w - 2.5 (w < 5)
+// and sqrt(w) - 3 (w >= 5), w = -log(1 - t^2) = -log(4u(1 - u)); weighted
+// least-squares fits to the FP64 function (gen_quantile.py), largest
+// relative error 2.7e-7 over the uniform grid u = (k + 1/2) 2^-23.
+__device__ __forceinline__ float normal_quantile(float u) {
+    const float t = 2.0f * u - 1.0f;
+    const float w = -__logf(4.0f * u * (1.0f - u));
+    const float s1 = w - 2.5f, s2 = sqrt_hw(w) - 3.0f;
+    float a = 2.798955610e-08f, b = -2.393541571e-04f;
+    a = fmaf(a, s1, 3.430734327e-07f);  b = fmaf(b, s2, 1.079666834e-04f);
+    a = fmaf(a, s1, -3.522236486e-06f); b = fmaf(b, s2, 1.402476381e-03f);
+    a = fmaf(a, s1, -4.389634286e-06f); b = fmaf(b, s2, -3.678024843e-03f);
+    a = fmaf(a, s1, 2.185773789e-04f);  b = fmaf(b, s2, 5.716959691e-03f);
+    a = fmaf(a, s1, -1.253729840e-03f); b = fmaf(b, s2, -7.622124629e-03f);
+    a = fmaf(a, s1, -4.177678720e-03f); b = fmaf(b, s2, 9.441883054e-03f);
+    a = fmaf(a, s1, 2.466407436e-01f);  b = fmaf(b, s2, 1.001674163e+00f);
+    a = fmaf(a, s1, 1.501409417e+00f);  b = fmaf(b, s2, 2.832976859e+00f);
+    return 1.41421356237f * (w < 5.0f ? a : b) * t;
+}
+
+// 1 - exp(-x) for x >= 0 (nuclear removal over a step): the series to x^5
+// below 1/8 (truncation below x^6/720), else through exp
+__device__ __forceinline__ float one_minus_exp_neg(float x) {
+    const float s = x * (1.0f - x * (0.5f - x * (0.16666667f - x * (0.041666668f - x * 0.0083333338f))));
+    return x < 0.125f ? s : 1.0f - __expf(-x);
 }
 
 __device__ __forceinline__ float node_lerp(const float *y, NodePos p) {
@@ -152,7 +184,7 @@ __device__ __forceinline__ float node_lerp(const float *y, NodePos p) {
 __device__ __forceinline__ void rotate_dir(Lane &v, float ax, float ay) {
     const float th2 = ax * ax + ay * ay;
     if (th2 == 0.0f) return;
-    const float th = sqrtf(th2);
+    const float th = sqrt_hw(th2);
     const float sg = copysignf(1.0f, v.dz);
     const float a = -__builtin_amdgcn_rcpf(sg + v.dz);
     const float b = v.dx * v.dy * a;
@@ -316,12 +348,12 @@ __device__ int phys_step(Lane &v, const float *tab, int m, DF rho_loss, float rh
     NodePos pb{0, 0.0f};
     if (v.physics) {
         w = draw(v);
-        pb = node_pos(tab, Ebar);
+        pb = node_pos_below(tab, Ebar, i);
     }
     if (v.physics & PH_STRAGGLE) {
         const float var = r.h * node_lerp(tm + T_W2 * NE, pb);
-        const float z = 1.41421356237f * erfinvf(2.0f * unit_open(w.z) - 1.0f);
-        dE = A::add(dE, {-(sqrtf(var) * z), 0.0f});
+        const float z = normal_quantile(unit_open(w.z));
+        dE = A::add(dE, {-(sqrt_hw(var) * z), 0.0f});
         const float tot = v.E + v.Elo;
         if (!(dE.h + dE.l > 0.0f)) dE = {0.0f, 0.0f};
         else if (dE.h + dE.l > tot) dE = {v.E, v.Elo};
@@ -329,7 +361,7 @@ __device__ int phys_step(Lane &v, const float *tab, int m, DF rho_loss, float rh
     dep = dE.h + dE.l;
     sub_energy<X>(v, dE);
     if (v.physics & PH_MCS) {
-        const float th0 = sqrtf(rho * s.h * node_lerp(tm + T_T * NE, pb));
+        const float th0 = sqrt_hw(rho * s.h * node_lerp(tm + T_T * NE, pb));
         float z1, z2;
         box_muller_fast(w.x, w.y, z1, z2);
         const DF h = {0.5f * s.h, 0.5f * s.l};
@@ -340,7 +372,7 @@ __device__ int phys_step(Lane &v, const float *tab, int m, DF rho_loss, float rh
         move<Slab, X>(v, s);
     }
     if (v.physics & PH_NUCLEAR) {
-        const float P = -expm1f(-rho * s.h * node_lerp(tm + T_SN * NE, pb));
+        const float P = one_minus_exp_neg(rho * s.h * node_lerp(tm + T_SN * NE, pb));
         if (unit_open(w.w) < P) {
             const uint4 w2 = draw(v);
             const float E1 = v.E + v.Elo;
@@ -889,7 +921,7 @@ __device__ bool patient_step(Lane &v, Acc &acc, float scale, const float *tab, c
         const long long qd = to_fixed(dep, scale);
         if (qd != 0) sink.add(vox, idx, qd);
         acc.led[L_GRID] += qd;
-        ledger_add(acc, L_NUC, esc, scale);
+        if (esc != 0.0f) ledger_add(acc, L_NUC, esc, scale);
         if (st == ST_STOP) return false;
         if (st == ST_GEO) {
             bool out = false;
