@@ -300,7 +300,8 @@ int grow_keep(vpmc_ctx *c, DevBuf &b, size_t keep_bytes, size_t bytes, size_t ca
 }
 
 // LDS tile box of a row (voxel indices, x fastest): the voxels along the
-// spot's central ray from its CT entry to 1.5 x its CSDA range in water + 10 mm,
+// spot's central ray from its CT entry to 1.15 x its CSDA range in water
+// (less the range shifter) + 10 mm,
 // widened laterally by the largest half-width (<= 15 mm, 0.5 mm steps) that
 // keeps the box within cap voxels.  No box (tn = 0) when the ray misses the
 // grid or no width fits.
@@ -328,7 +329,11 @@ static void tile_box(const FieldDev &f, const SpotDev &sp, const ScenDev &sc, co
         tf = std::min(tf, std::max(t1, t2));
     }
     if (!(tf > tn)) return;
-    const double reach = 1.5 * 10.0 * range_host(MAT_WATER, std::min((double)sp.e0, E_HI)) + 10.0;
+    // water range left after the range shifter (its water-equivalent
+    // thickness taken low, 0.95 x rho x t), with 15 % and 10 mm to spare
+    double rw = 10.0 * range_host(MAT_WATER, std::min((double)sp.e0, E_HI));
+    if (f.has_rs) rw -= 0.95 * (double)f.rs_rho * (double)f.rs_t;
+    const double reach = 1.15 * std::max(rw, 0.0) + 10.0;
     const double t1 = std::min(tf, tn + reach);
     int mn[3], mx[3], a = 0;
     for (int k = 0; k < 3; ++k) {
