@@ -1336,48 +1336,63 @@ __global__ __launch_bounds__(X ? 768 : 1024) void queue_kernel(GeomDev g, QueueD
 }
 
 // ---- compaction of an epoch's rows into CSR (three passes per epoch)
-// A chunk is 256 touched-block bytes (8192 voxels) of one row.  The marked
-// blocks of a chunk are listed in ascending order in LDS; then 32 lanes read
-// one block's 32 slot values (coalesced 256 B) at a time.
+// A chunk is 256 touched-block bytes (8192 voxels) of one row, handled by
+// one wave: lane l reads mark bytes 4l..4l+3 as one word (the mark stride is
+// a multiple of 256, so the word stays inside the row's marks), the marked
+// blocks are listed in ascending order in the wave's LDS, and then the two
+// half-waves read two blocks' 32 slot values (coalesced 256 B each) at a
+// time.  The waves of the launch stride over the epoch's (row, chunk) pairs,
+// consecutive waves on consecutive chunks; a chunk without marks costs one
+// load and a ballot.
 
-// lists the marked blocks of this workgroup's chunk; returns their count
-__device__ __forceinline__ int marked_blocks(const uint8_t *mark, size_t nblk, size_t b0, int *list, int *wsum) {
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const size_t b = b0 + t;
-    const bool m = b < nblk && mark[b] != 0;
-    const unsigned long long bal = __ballot(m);
-    const int pre = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0) wsum[w] = __popcll(bal);
-    __syncthreads();
-    int base = 0, tot = 0;
-    for (int k = 0; k < 4; ++k) {
-        base += k < w ? wsum[k] : 0;
-        tot += wsum[k];
+// lists the marked blocks of a chunk (offsets 0..255) in ascending order;
+// returns their count
+__device__ __forceinline__ int chunk_blocks(uint32_t wv, int lane, int *list) {
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c += ((wv >> (8 * k)) & 0xFFu) != 0u;
+    int pre = c;   // inclusive prefix over the lanes
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(pre, o, 64);
+        if (lane >= o) pre += y;
     }
-    if (m) list[base + pre] = (int)(b - b0);
-    __syncthreads();
+    const int tot = __shfl(pre, 63, 64);
+    int at = pre - c;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (((wv >> (8 * k)) & 0xFFu) != 0u) list[at++] = 4 * lane + k;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     return tot;
 }
 
 // pass 1: non-zero count of every (row, chunk)
 __global__ __launch_bounds__(256) void csr_count_kernel(QueueDev Q, unsigned int *cnt) {
-    __shared__ int list[256];
-    __shared__ int wsum[4];
-    __shared__ unsigned int red[4];
-    const int row = blockIdx.y, chunk = blockIdx.x, t = threadIdx.x;
-    const size_t b0 = (size_t)chunk * 256;
-    const uint8_t *mark = Q.mark + (size_t)row * Q.mstride;
-    const unsigned long long *grid = Q.grid + (size_t)row * Q.gstride;
-    const int nm = marked_blocks(mark, Q.nblk, b0, list, wsum);
-    unsigned int c = 0;
-    for (int p = 0; p * 8 < nm; ++p) {
-        const int idx = p * 8 + (t >> 5);
-        if (idx < nm) c += grid[(b0 + list[idx]) * 32 + (t & 31)] != 0ull;
+    __shared__ int lists[4][256];
+    const int lane = threadIdx.x & 63, wv_id = threadIdx.x >> 6;
+    int *list = lists[wv_id];
+    const size_t npair = (size_t)Q.n_rows * Q.nchunk;
+    const size_t nwave = (size_t)gridDim.x * 4;
+    for (size_t pair = (size_t)blockIdx.x * 4 + wv_id; pair < npair; pair += nwave) {
+        const size_t row = pair / Q.nchunk, chunk = pair - row * Q.nchunk;
+        const size_t b0 = chunk * 256;
+        const uint8_t *mark = Q.mark + row * Q.mstride;
+        const uint32_t w = *reinterpret_cast<const uint32_t *>(mark + b0 + 4 * lane);
+        unsigned int c = 0;
+        if (__ballot(w != 0u) != 0ull) {
+            const unsigned long long *grid = Q.grid + row * Q.gstride;
+            const int nm = chunk_blocks(w, lane, list);
+            for (int p = 0; 2 * p < nm; ++p) {
+                const int idx = 2 * p + (lane >> 5);
+                if (idx < nm) c += grid[(b0 + list[idx]) * 32 + (lane & 31)] != 0ull;
+            }
+            for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+            __builtin_amdgcn_wave_barrier();   // list reused by the next chunk
+        }
+        if (lane == 0) cnt[pair] = c;
     }
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-    if ((t & 63) == 0) red[t >> 6] = c;
-    __syncthreads();
-    if (t == 0) cnt[(size_t)row * Q.nchunk + chunk] = red[0] + red[1] + red[2] + red[3];
 }
 
 // pass 2: per row, exclusive prefix of its chunk counts and the row total
@@ -1445,44 +1460,40 @@ __global__ __launch_bounds__(256) void csr_emit_kernel(QueueDev Q, const unsigne
                                                        const unsigned long long *row_nnz, int32_t *col,
                                                        long long *qv, unsigned long long capacity,
                                                        unsigned int *flags) {
-    __shared__ int list[256];
-    __shared__ int wsum[4];
-    __shared__ unsigned int wz[4];
-    const int row = blockIdx.y, chunk = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const size_t b0 = (size_t)chunk * 256;
-    uint8_t *mark = Q.mark + (size_t)row * Q.mstride;
-    unsigned long long *grid = Q.grid + (size_t)row * Q.gstride;
-    const int nm = marked_blocks(mark, Q.nblk, b0, list, wsum);
-    if (nm == 0) return;
-    const size_t ci = (size_t)row * Q.nchunk + chunk;
-    const unsigned long long rb = row_off[Q.row_begin + row];
-    const bool write = rb + row_nnz[Q.row_begin + row] <= capacity;
-    unsigned long long pos = rb + coff[ci];
-    for (int p = 0; p * 8 < nm; ++p) {
-        const int idx = p * 8 + (t >> 5);
-        const size_t v = idx < nm ? (b0 + list[idx]) * 32 + (t & 31) : 0;
-        const unsigned long long q = idx < nm ? grid[v] : 0ull;
-        const unsigned long long bal = __ballot(q != 0ull);
-        if (lane == 0) wz[w] = __popcll(bal);
-        __syncthreads();
-        unsigned long long wb = 0, tot = 0;
-        for (int k = 0; k < 4; ++k) {
-            wb += k < w ? wz[k] : 0u;
-            tot += wz[k];
-        }
-        if (q != 0ull) {
-            const unsigned long long at = pos + wb + __popcll(bal & ((1ull << lane) - 1ull));
-            if (write) {
+    __shared__ int lists[4][256];
+    const int lane = threadIdx.x & 63, wv_id = threadIdx.x >> 6;
+    int *list = lists[wv_id];
+    const size_t npair = (size_t)Q.n_rows * Q.nchunk;
+    const size_t nwave = (size_t)gridDim.x * 4;
+    for (size_t pair = (size_t)blockIdx.x * 4 + wv_id; pair < npair; pair += nwave) {
+        const size_t row = pair / Q.nchunk, chunk = pair - row * Q.nchunk;
+        const size_t b0 = chunk * 256;
+        uint8_t *mark = Q.mark + row * Q.mstride;
+        const uint32_t w = *reinterpret_cast<const uint32_t *>(mark + b0 + 4 * lane);
+        if (__ballot(w != 0u) == 0ull) continue;
+        unsigned long long *grid = Q.grid + row * Q.gstride;
+        const int nm = chunk_blocks(w, lane, list);
+        const unsigned long long rb = row_off[Q.row_begin + row];
+        const bool write = rb + row_nnz[Q.row_begin + row] <= capacity;
+        const unsigned long long p0 = rb + coff[pair];
+        unsigned long long pos = p0;
+        for (int p = 0; 2 * p < nm; ++p) {
+            const int idx = 2 * p + (lane >> 5);
+            const size_t v = idx < nm ? (b0 + list[idx]) * 32 + (lane & 31) : 0;
+            const unsigned long long q = idx < nm ? grid[v] : 0ull;
+            const unsigned long long bal = __ballot(q != 0ull);
+            if (q != 0ull && write) {
+                const unsigned long long at = pos + __popcll(bal & ((1ull << lane) - 1ull));
                 col[at] = (int32_t)v;
                 qv[at] = (long long)q;
             }
+            if (idx < nm) grid[v] = 0ull;
+            pos += __popcll(bal);
         }
-        if (idx < nm) grid[v] = 0ull;
-        pos += tot;
-        __syncthreads();
+        if (w != 0u) *reinterpret_cast<uint32_t *>(mark + b0 + 4 * lane) = 0u;
+        if (lane == 0 && pos - p0 != cnt[pair]) atomicOr(flags, 2u);
+        __builtin_amdgcn_wave_barrier();   // list reused by the next chunk
     }
-    if (t < nm) mark[b0 + list[t]] = 0;
-    if (t == 0 && pos - rb - coff[ci] != cnt[ci]) atomicOr(flags, 2u);
 }
 
 __global__ void fill_u64_kernel(unsigned long long *p, size_t n, unsigned long long v) {
@@ -1843,8 +1854,15 @@ hipError_t launch_queue(const GeomDev &g, const QueueDev &Q, int blocks, int thr
     return hipGetLastError();
 }
 
+// workgroups (4 waves each) of the compaction passes: one wave per (row,
+// chunk) pair up to 4096 workgroups, the waves striding over the rest
+static unsigned csr_pass_blocks(const QueueDev &Q) {
+    const size_t npair = (size_t)Q.n_rows * Q.nchunk;
+    return (unsigned)std::max<size_t>(1, std::min<size_t>((npair + 3) / 4, 4096));
+}
+
 hipError_t launch_csr_count(const QueueDev &Q, unsigned int *cnt, hipStream_t s) {
-    hipLaunchKernelGGL(csr_count_kernel, dim3((unsigned)Q.nchunk, Q.n_rows), dim3(256), 0, s, Q, cnt);
+    hipLaunchKernelGGL(csr_count_kernel, dim3(csr_pass_blocks(Q)), dim3(256), 0, s, Q, cnt);
     return hipGetLastError();
 }
 
@@ -1865,7 +1883,7 @@ hipError_t launch_csr_offsets(const unsigned int *nnz, int n_rows, int row_begin
 hipError_t launch_csr_emit(const QueueDev &Q, const unsigned int *cnt, const unsigned int *coff,
                            const unsigned long long *row_off, const unsigned long long *row_nnz, int32_t *col,
                            long long *qv, unsigned long long capacity, unsigned int *flags, hipStream_t s) {
-    hipLaunchKernelGGL(csr_emit_kernel, dim3((unsigned)Q.nchunk, Q.n_rows), dim3(256), 0, s, Q, cnt, coff, row_off,
+    hipLaunchKernelGGL(csr_emit_kernel, dim3(csr_pass_blocks(Q)), dim3(256), 0, s, Q, cnt, coff, row_off,
                        row_nnz, col, qv, capacity, flags);
     return hipGetLastError();
 }
