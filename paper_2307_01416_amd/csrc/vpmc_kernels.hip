@@ -1266,25 +1266,29 @@ __global__ __launch_bounds__(X ? 768 : 1024) void queue_kernel(GeomDev g, QueueD
             for (;;) {
                 const unsigned long long idle = __ballot(!active);
                 const uint32_t nidle = (uint32_t)__popcll(idle);
-                if (next < nst && nidle >= min((uint32_t)Q.refill_min, nst - next)) {
-                    if (!active) {
-                        const uint32_t k = next + (uint32_t)__popcll(idle & below);
-                        if (k < nst) {
-                            const StagedVP r = stg[k];
-                            v.px = r.px; v.py = r.py; v.pz = r.pz; v.dx = r.dx;
-                            v.dy = r.dy; v.dz = r.dz; v.E = r.E; v.Elo = r.Elo;
-                            v.pxlo = v.pylo = v.pzlo = 0.0f;
-                            v.nblk = r.nblk; v.hist = r.hist; v.nsteps = r.nsteps;
-                            ps.vox = r.vox;
-                            ps.idx[0] = r.i0; ps.idx[1] = r.i1; ps.idx[2] = r.i2;
-                            ps.hu = r.hu;
-                            active = true;
-                        }
-                    }
-                    next = min(nst, next + nidle);
-                } else if (nidle == 64u) {
-                    break;
+                const bool refill = next < nst && nidle >= min((uint32_t)Q.refill_min, nst - next);
+                if (!refill && nidle == 64u) break;
+                const uint32_t k = next + (uint32_t)__popcll(idle & below);
+                if (refill && !active && k < nst) {
+                    // word by word (single-word loads are not merged into
+                    // 4-register tuples, so each field can land in the
+                    // register the loop carries it in)
+                    const uint32_t *rw = reinterpret_cast<const uint32_t *>(stg + k);
+                    auto ld = [&](int i) {
+                        return __hip_atomic_load(rw + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    };
+                    v.px = __uint_as_float(ld(0)); v.py = __uint_as_float(ld(1));
+                    v.pz = __uint_as_float(ld(2)); v.dx = __uint_as_float(ld(3));
+                    v.dy = __uint_as_float(ld(4)); v.dz = __uint_as_float(ld(5));
+                    v.E = __uint_as_float(ld(6)); v.Elo = __uint_as_float(ld(7));
+                    v.pxlo = v.pylo = v.pzlo = 0.0f;
+                    v.nblk = ld(8); v.hist = ld(9); v.nsteps = ld(10);
+                    ps.vox = ld(11);
+                    ps.idx[0] = (int)ld(12); ps.idx[1] = (int)ld(13); ps.idx[2] = (int)ld(14);
+                    ps.hu = (int)ld(15);
+                    active = true;
                 }
+                if (refill) next = min(nst, next + nidle);
                 if (active) {
                     active = patient_step<TileSink, X>(v, acc, sp.scale, tab, g, sc.range_scale, sink, ps);
                     if (!active) acc.steps += v.nsteps;
