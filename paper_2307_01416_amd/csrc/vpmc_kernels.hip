@@ -184,15 +184,23 @@ __device__ __forceinline__ float node_lerp(const float *y, NodePos p) {
 __device__ __forceinline__ void rotate_dir(Lane &v, float ax, float ay) {
     const float th2 = ax * ax + ay * ay;
     if (th2 == 0.0f) return;
-    const float th = sqrt_hw(th2);
     const float sg = copysignf(1.0f, v.dz);
     const float a = -__builtin_amdgcn_rcpf(sg + v.dz);
     const float b = v.dx * v.dy * a;
     const float e1x = 1.0f + sg * v.dx * v.dx * a, e1y = sg * b, e1z = -sg * v.dx;
     const float e2x = b, e2y = sg + v.dy * v.dy * a, e2z = -v.dy;
-    float sn, c;
-    __sincosf(th, &sn, &c);
-    const float k = sn * __builtin_amdgcn_rcpf(th);
+    // cos(th) and sin(th)/th: series in th^2 below th^2 = 0.01 (multiple
+    // scattering per step; truncation below 3e-10), else from sin and cos
+    float c, k;
+    if (th2 < 0.01f) {
+        c = 1.0f - th2 * (0.5f - th2 * (0.041666668f - th2 * 0.0013888889f));
+        k = 1.0f - th2 * (0.16666667f - th2 * (0.0083333338f - th2 * 0.00019841270f));
+    } else {
+        const float th = sqrt_hw(th2);
+        float sn;
+        __sincosf(th, &sn, &c);
+        k = sn * __builtin_amdgcn_rcpf(th);
+    }
     float nx = c * v.dx + k * (ax * e1x + ay * e2x);
     float ny = c * v.dy + k * (ax * e1y + ay * e2y);
     float nz = c * v.dz + k * (ax * e1z + ay * e2z);
