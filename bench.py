@@ -320,6 +320,19 @@ def main():
                          "EPYC 7543 + 4x A100",
         "device": torch.cuda.get_device_name(0),
     }
+    # roof time of the transport: the method's one tally atomic per step at
+    # the measured atomic rate (pencil-beam address pattern, own kernel) or
+    # its VALU work at the chip's rate, whichever is longer
+    rate = V.vpmc_atomic_rate(eng.ctx, case.geometry.shape, 1 << 28)
+    t_launch = transport_s / max(1, launches)
+    t_atomic = steps_total / max(1, launches) / rate
+    t_valu = ALG_OPS_PER_STEP * steps_total / max(1, launches) / VALU_PEAK_OPS
+    out["roof_time"] = {"atomic_rate_per_s": rate, "atomics_per_launch": steps_total / max(1, launches),
+                        "t_atomic_ms": 1e3 * t_atomic, "t_valu_ms": 1e3 * t_valu,
+                        "t_roof_ms": 1e3 * max(t_atomic, t_valu), "t_launch_ms": 1e3 * t_launch,
+                        "frac": max(t_atomic, t_valu) / t_launch}
+    progress(f"atomic rate {rate:.3e}/s: roof {1e3 * max(t_atomic, t_valu):.2f} ms per launch "
+             f"(atomics {1e3 * t_atomic:.2f}, VALU {1e3 * t_valu:.2f}) vs {1e3 * t_launch:.2f} ms measured")
     if not a.no_surrogate:
         out["surrogate"] = surrogate_comparison(eng, case, I, V, np, a, shape, dt / a.steps,
                                                 steps_total / a.steps)

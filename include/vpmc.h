@@ -282,6 +282,17 @@ int vpmc_last_stats(const vpmc_ctx *ctx, vpmc_stats *out);
  * removal.  Writes n <= 256 values; returns the node count. */
 int vpmc_table_host(int material, int which, double *out, int n);
 
+/* Measurement support for the roofline of the transport (the atomic-rate
+ * bound of the deposit tally): times n_atomics non-returning int64 atomic
+ * adds into a zeroed nx*ny*nz grid on the context's device, issued as tracks
+ * of 100 consecutive voxels along x at Gaussian lateral offsets (sigma 4
+ * voxels) around 64 spot axes, the deposit pattern of a lateral pencil beam,
+ * after one untimed warm-up pass; writes atomics per second.  Allocates and
+ * frees its grid (8 bytes per voxel).  Errors: VPMC_E_ARG (grid below 16^3 or
+ * >= 2^31 voxels, n_atomics outside [1024, 2^40], NULL pointers),
+ * VPMC_E_STATE (validation-only context), VPMC_E_DEVICE (HIP failure). */
+int vpmc_atomic_rate(vpmc_ctx *ctx, int nx, int ny, int nz, uint64_t n_atomics, double *atomics_per_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1030,6 +1030,39 @@ void vpmc_destroy(vpmc_ctx *c) {
     delete c;
 }
 
+int vpmc_atomic_rate(vpmc_ctx *c, int nx, int ny, int nz, uint64_t n_atomics, double *atomics_per_s) {
+    if (!c || !atomics_per_s) return fail(VPMC_E_ARG, "ctx and atomics_per_s are required");
+    if (nx < 16 || ny < 16 || nz < 16 || (size_t)nx * ny * nz >= ((size_t)1 << 31))
+        return fail(VPMC_E_ARG, "grid must be at least 16^3 and below 2^31 voxels");
+    if (n_atomics < 1024 || n_atomics > ((uint64_t)1 << 40)) return fail(VPMC_E_ARG, "n_atomics outside [1024, 2^40]");
+    if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
+    HIP_TRY(hipSetDevice(c->device));
+    const size_t nvox = (size_t)nx * ny * nz;
+    unsigned long long *grid = nullptr;
+    HIP_TRY(hipMalloc(&grid, nvox * 8));
+    const int len = 100;   // voxels per track (~ steps per history of the head case)
+    const unsigned long long tracks = (n_atomics + len - 1) / len;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipMemset(grid, 0, nvox * 8);
+    // one warm-up pass, then the timed pass
+    if (e == hipSuccess) e = launch_atomic_rate(grid, nx, ny, nz, std::min<unsigned long long>(tracks, 1 << 20), len,
+                                                4.0f, 1u, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+    if (e == hipSuccess) e = launch_atomic_rate(grid, nx, ny, nz, tracks, len, 4.0f, 2u, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(grid);
+    HIP_TRY(e);
+    *atomics_per_s = ms > 0.0f ? (double)tracks * len / (ms * 1e-3) : 0.0;
+    return VPMC_OK;
+}
+
 int vpmc_table_host(int material, int which, double *out, int n) {
     if (material < 0 || material >= NMAT || which < 0 || which > 4 || !out || n < 0)
         return fail(VPMC_E_ARG, "bad table request");

@@ -245,6 +245,8 @@ hipError_t launch_csr_emit(const QueueDev &Q, const unsigned int *cnt, const uns
                            const unsigned long long *row_off, const unsigned long long *row_nnz, int32_t *col,
                            long long *qv, unsigned long long capacity, unsigned int *flags, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_atomic_rate(unsigned long long *grid, int nx, int ny, int nz, unsigned long long n_tracks, int len,
+                              float sigma, uint32_t seed, hipStream_t s);
 hipError_t launch_csr_scatter(const int32_t *col, const long long *qv, unsigned long long begin,
                               unsigned long long end, unsigned long long *dense, hipStream_t s);
 hipError_t launch_csr_values(const int32_t *col, const long long *qv, size_t n, const GeomDev &g,

@@ -1508,6 +1508,40 @@ __global__ __launch_bounds__(256) void csr_emit_kernel(QueueDev Q, const unsigne
     }
 }
 
+// Rate of non-returning int64 atomic adds to device memory with the address
+// pattern of the transport's deposits: each lane walks a track of `len`
+// consecutive voxels along x (the beam axis of a lateral field) from a
+// random depth, at a lateral (y, z) offset drawn around one of 64 spot axes
+// with a Gaussian of sigma voxels (sum of 4 uniforms), so that hot spots
+// form where tracks overlap.  Work: n_tracks x len atomics.
+__global__ __launch_bounds__(256) void atomic_rate_kernel(unsigned long long *grid, int nx, int ny, int nz,
+                                                          unsigned long long n_tracks, int len, float sigma,
+                                                          uint32_t seed) {
+    for (unsigned long long t = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; t < n_tracks;
+         t += (unsigned long long)gridDim.x * blockDim.x) {
+        uint32_t x = (uint32_t)t * 0x9E3779B9u ^ seed;
+        auto next = [&]() {   // xorshift32
+            x ^= x << 13; x ^= x >> 17; x ^= x << 5;
+            return x;
+        };
+        next(); next();
+        const uint32_t spot = (uint32_t)(t >> 12) & 63u;   // neighbouring tracks share a spot
+        const float cy = 0.25f * ny + 0.5f * ny * (float)((spot * 2654435761u) >> 16 & 0xFFFFu) / 65536.0f;
+        const float cz = 0.25f * nz + 0.5f * nz * (float)((spot * 2246822519u) >> 16 & 0xFFFFu) / 65536.0f;
+        float gy = 0.0f, gz = 0.0f;
+        for (int k = 0; k < 4; ++k) {
+            gy += (float)(next() >> 8) * 0x1p-24f;
+            gz += (float)(next() >> 8) * 0x1p-24f;
+        }
+        // sum of 4 U(0,1): mean 2, variance 1/3
+        const int y = min(max((int)(cy + (gy - 2.0f) * 1.7320508f * sigma), 0), ny - 1);
+        const int z = min(max((int)(cz + (gz - 2.0f) * 1.7320508f * 0.5f * sigma), 0), nz - 1);
+        const int x0 = (int)(next() % (uint32_t)max(nx - len, 1));
+        unsigned long long *row = grid + (size_t)nx * ((size_t)y + (size_t)ny * (size_t)z);
+        for (int i = 0; i < len && x0 + i < nx; ++i) atomicAdd(row + x0 + i, 1ull);
+    }
+}
+
 __global__ void fill_u64_kernel(unsigned long long *p, size_t n, unsigned long long v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -1897,6 +1931,12 @@ hipError_t launch_csr_emit(const QueueDev &Q, const unsigned int *cnt, const uns
                            long long *qv, unsigned long long capacity, unsigned int *flags, hipStream_t s) {
     hipLaunchKernelGGL(csr_emit_kernel, dim3(csr_pass_blocks(Q)), dim3(256), 0, s, Q, cnt, coff, row_off,
                        row_nnz, col, qv, capacity, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_atomic_rate(unsigned long long *grid, int nx, int ny, int nz, unsigned long long n_tracks, int len,
+                              float sigma, uint32_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(atomic_rate_kernel, dim3(4096), dim3(256), 0, s, grid, nx, ny, nz, n_tracks, len, sigma, seed);
     return hipGetLastError();
 }
 

@@ -109,6 +109,7 @@ def load() -> C.CDLL:
         "vpmc_surrogate_forward": (i, [vp, vp, i, vp]),
         "vpmc_surrogate_loss_grad": (i, [vp, vp, vp, vp, i, vp, C.POINTER(C.c_double)]),
         "vpmc_surrogate_train": (i, [vp, vp, vp, vp, i, i, i, C.c_float, C.c_uint64, vp]),
+        "vpmc_atomic_rate": (i, [vp, i, i, i, C.c_uint64, f64p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -152,6 +153,15 @@ def vpmc_create(device: int = 0) -> C.c_void_p:
 
 def vpmc_destroy(ctx) -> None:
     load().vpmc_destroy(ctx)
+
+
+def vpmc_atomic_rate(ctx, shape=(256, 256, 160), n_atomics: int = 1 << 28) -> float:
+    """Non-returning int64 atomic adds per second on the context's device,
+    pencil-beam track pattern over a grid of the given (nx, ny, nz)."""
+    out = C.c_double(0.0)
+    nx, ny, nz = shape
+    _check(load().vpmc_atomic_rate(ctx, nx, ny, nz, int(n_atomics), C.byref(out)), ctx)
+    return out.value
 
 
 def vpmc_table_host(material: int, which: int) -> np.ndarray:

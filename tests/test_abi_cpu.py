@@ -123,3 +123,11 @@ def test_surrogate_config_validation(vctx):
     assert _rc(V.vpmc_surrogate_config, vctx, 3.0, 0.1, 1.5) == V.E_ARG
     # forward/sample need a device and weights
     assert _rc(V.vpmc_surrogate_forward, vctx, np.zeros((4, 8), np.float32)) == V.E_STATE
+
+
+def test_atomic_rate_validation(vctx):
+    # arguments are checked before the device is needed
+    assert _rc(V.vpmc_atomic_rate, vctx, (8, 256, 160), 1 << 20) == V.E_ARG
+    assert _rc(V.vpmc_atomic_rate, vctx, (256, 256, 160), 100) == V.E_ARG
+    assert _rc(V.vpmc_atomic_rate, vctx, (4096, 4096, 4096), 1 << 20) == V.E_ARG
+    assert _rc(V.vpmc_atomic_rate, vctx, (256, 256, 160), 1 << 20) == V.E_STATE

@@ -148,3 +148,17 @@ def test_head_three_fields_rows_sum_to_dense(eng):
             assert np.all(np.diff(cc) > 0)
             np.add.at(acc, cc, qq)
         assert dense.any() and np.array_equal(acc, dense)
+
+
+@pytest.mark.gpu
+def test_atomic_rate_microbenchmark():
+    """The roofline's atomic-rate probe runs on the device and reports a
+    plausible rate for the head grid's shape (int64 adds per second)."""
+    from paper_2307_01416_amd import vpmc as V
+    c = V.vpmc_create(0)
+    try:
+        r = V.vpmc_atomic_rate(c, (256, 256, 160), 1 << 22)
+    finally:
+        V.vpmc_destroy(c)
+    print(f"  int64 atomic adds: {r:.3e} per second")
+    assert 1e8 < r < 1e13
