@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--sur-samples", type=int, default=3_000_000)
     ap.add_argument("--sur-epochs", type=int, default=6)
     ap.add_argument("--shape", default="", help="HPL,BLOCKS,THREADS: fixed work-queue launch shape (no autotune)")
+    ap.add_argument("--oracle-suite", action="store_true",
+                    help="time the oracle beside the GPU on config 1 and two config-2 cases (not the bench line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="before the workload, run three plain 256 MiB device copies (HBM counter calibration)")
     return ap.parse_args()
@@ -212,8 +214,56 @@ def cpu_baseline(case, seconds, np):
                       f"({n} VPs, full physics, {dt:.1f} s on {cpu})"}
 
 
+def oracle_suite(np):
+    """The oracle beside the GPU on the small workloads: config 1 in full,
+    two config-2 cases in full (all host threads), and single-thread rates
+    on bounded samples; one JSON line per case."""
+    import oracle
+    from paper_2307_01416_amd import inputs as I
+    from paper_2307_01416_amd import vpmc as V
+    import torch
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    eng = V.Engine(0)
+    cases = [("config1 water 100 MeV", I.config1(100_000)),
+             ("config2 10 mm opening + RS", I.config2(10.0, True)),
+             ("config2 40 mm opening, no RS", I.config2(40.0, False))]
+    for name, c in cases:
+        n = int(np.sum(c.fields[0].spots["n_histories"]))
+        eng.load_case(c)
+        eng.run_dose(c, 0, n_batches=0, sigma=False)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eng.run_dose(c, 0, n_batches=0, sigma=False)
+        torch.cuda.synchronize()
+        t_gpu = time.perf_counter() - t0
+        progress(f"{name}: GPU {n} VPs in {t_gpu:.3f} s; oracle on {threads} threads ...")
+        t0 = time.perf_counter()
+        oracle.run_tally(c, threads=threads)
+        t_all = time.perf_counter() - t0
+        # single thread on a sample sized for about 4 s (ideal scaling assumed)
+        sub = I.Field(beam=c.fields[0].beam, spots=c.fields[0].spots.copy(), polygon=c.fields[0].polygon,
+                      block=c.fields[0].block, rs=c.fields[0].rs)
+        frac = min(1.0, 4.0 / max(t_all * threads, 1e-3))
+        sub.spots["n_histories"] = np.maximum(1, (sub.spots["n_histories"] * frac).astype(np.uint32))
+        probe = I.Case("probe", c.geometry, [sub], c.scenarios, seed=c.seed, physics=c.physics)
+        n1 = int(np.sum(sub.spots["n_histories"]))
+        t0 = time.perf_counter()
+        oracle.run_tally(probe, threads=1)
+        t_one = time.perf_counter() - t0
+        print(json.dumps({"case": name, "histories": n, "gpu_s": t_gpu, "gpu_histories_per_s": n / t_gpu,
+                          "oracle_threads": threads, "oracle_s": t_all, "oracle_histories_per_s": n / t_all,
+                          "oracle_1thread_sample": n1, "oracle_1thread_s": t_one,
+                          "oracle_1thread_histories_per_s": n1 / t_one,
+                          "gpu_over_oracle": (n / t_gpu) / (n / t_all)}), flush=True)
+    eng.close()
+
+
 def main():
     a = parse()
+    if a.oracle_suite:
+        import numpy as np
+        oracle_suite(np)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path is not built",
               file=sys.stderr)
