@@ -45,6 +45,8 @@ PINS = {
     "hu_lookup": "breakpoints of the piecewise-linear calibration",
     "absolute_dosimetry": "parity unpinned (no measurement or comparison system available)",
     "mlp": "gradients vs central finite differences; mixture NLL vs scipy for one component",
+    "let": "entrance LET_d = NIST PSTAR stopping power; per-voxel LET_d = exact CSDA energy loss / path in "
+           "straight water (closed form); rises with depth",
 }
 
 
@@ -96,7 +98,7 @@ def lib():
             ("orc_philox4x32_10", None, [vp, vp, vp]),
             ("orc_uniform", d, [C.c_uint32]), ("orc_normal_quantile", d, [d]),
             ("orc_in_polygon", i, [vp, i, d, d]), ("orc_edge_distance", d, [vp, i, d, d, d, d]),
-            ("orc_run", i64, [vp, vp, vp, i, i, vp, vp, vp, vp, i]),
+            ("orc_run", i64, [vp, vp, vp, i, i, vp, vp, vp, vp, i, vp]),
             ("orc_trace_history", None, [vp, vp, vp, i, i64, vp, vp, vp, vp, vp]),
             ("orc_slab_exit", None, [i, d, d, d, i, C.c_uint64, i64, vp, i]),
             ("orc_fixed_point_k", i, [d]), ("orc_rs_thickness", d, [d]),
@@ -269,8 +271,42 @@ def run_tally(case, field_index: int = 0, scenario_index: int = 0, k: Optional[i
     led = np.zeros(6, np.int64)
     s0, s1 = (0, P.n_spots) if spots is None else spots
     lib().orc_run(C.byref(P.geom), C.byref(P.field), C.cast(P.spots, C.c_void_p), s0, s1,
-                  C.byref(P.scen), C.byref(o), _ptr(q), _ptr(led), threads)
+                  C.byref(P.scen), C.byref(o), _ptr(q), _ptr(led), threads, None)
     return q.reshape(nz, ny, nx), led, k
+
+
+LET_SHIFT = 8
+
+
+def run_let(case, field_index: int = 0, scenario_index: int = 0, k: Optional[int] = None, spots=None,
+            threads: int = 0, physics: Optional[int] = None, seed: Optional[int] = None):
+    """Dose tally and dose-averaged-LET numerator of one field/scenario (NEXT-3):
+    (q int64[nz,ny,nx], qL int64[nz,ny,nx], k); LET_d = qL * 2^LET_SHIFT / q in
+    keV/um, where each step's LET is its mean CSDA stopping power."""
+    P = _Prepared(case, field_index, scenario_index)
+    if k is None:
+        k = fixed_point_k(case)
+    o = _Opts()
+    o.seed = case.seed if seed is None else seed
+    o.field_id = field_index
+    o.physics = case.physics if physics is None else physics
+    o.k = k
+    o.batch = 0
+    o.n_batches = 1
+    nx, ny, nz = case.geometry.shape
+    q = np.zeros(nx * ny * nz, np.int64)
+    qL = np.zeros(nx * ny * nz, np.int64)
+    led = np.zeros(6, np.int64)
+    s0, s1 = (0, P.n_spots) if spots is None else spots
+    lib().orc_run(C.byref(P.geom), C.byref(P.field), C.cast(P.spots, C.c_void_p), s0, s1,
+                  C.byref(P.scen), C.byref(o), _ptr(q), _ptr(led), threads, _ptr(qL))
+    return q.reshape(nz, ny, nx), qL.reshape(nz, ny, nx), k
+
+
+def let_d(q, qL):
+    """Dose-averaged LET in keV/um from the two tallies (0 where no dose)."""
+    q = np.asarray(q, np.float64)
+    return np.where(q > 0, np.asarray(qL, np.float64) * 2.0 ** LET_SHIFT / np.where(q > 0, q, 1.0), 0.0)
 
 
 def trace_history(case, spot_index: int, h: int, field_index: int = 0, scenario_index: int = 0,

@@ -59,6 +59,7 @@
 #define EDGE_PUSH_MM 1e-6        /* push across an aperture edge, in the aperture plane (R5) */
 #define MAX_ITER 1000000         /* safety bound on steps per VP */
 #define MAX_BLOCK_ITER 10000     /* safety bound on crossing-number tests per block traversal */
+#define LET_SHIFT 8              /* LET numerator in units of 2^(8-k) MeV keV/um (LET <= 256 keV/um) */
 
 enum { M_WATER = 0, M_AIR = 1, M_PMMA = 2, M_BRASS = 3, M_BONE = 4, NMAT = 5 };
 enum { L_GRID = 0, L_RS = 1, L_BLOCK = 2, L_ESCAPED = 3, L_NUC = 4, L_SPARE = 5, NLEDGER = 6 };
@@ -370,12 +371,16 @@ typedef struct {
 typedef struct {
     int64_t *q;                 /* [nvox] or NULL */
     double scale;               /* w_s / N_s * 2^k */
+    int64_t *qL;                /* [nvox] LET numerator or NULL */
     int64_t led_q[NLEDGER];     /* per-thread fixed-point ledgers */
     double *grid_fp;            /* trace: FP64 per-voxel deposits or NULL */
     double led_fp[NLEDGER];     /* trace: FP64 ledgers */
 } sink_t;
 
-static void sink_grid(sink_t *s, int64_t v, double e)
+/* deposit e (MeV) in voxel v by a step of LET `let` (MeV/mm = keV/um): the
+ * dose tally and, when asked for, the numerator of the dose-averaged LET,
+ * rne(e * let * w/N * 2^(k - LET_SHIFT)) */
+static void sink_grid(sink_t *s, int64_t v, double e, double let)
 {
     if (e == 0.0) return;
     s->led_fp[L_GRID] += e;
@@ -383,6 +388,10 @@ static void sink_grid(sink_t *s, int64_t v, double e)
     int64_t q = llrint(e * s->scale);
     s->led_q[L_GRID] += q;
     if (s->q && q) __atomic_fetch_add(&s->q[v], q, __ATOMIC_RELAXED);
+    if (s->qL) {
+        int64_t qL = llrint(e * let * ldexp(s->scale, -LET_SHIFT));
+        if (qL) __atomic_fetch_add(&s->qL[v], qL, __ATOMIC_RELAXED);
+    }
 }
 
 static void sink_ledger(sink_t *s, int j, double e)
@@ -427,14 +436,23 @@ enum { ST_STOP = 0, ST_GEO = 1, ST_INNER = 2 };
  *   dg:       distance (mm) to the region's geometric limit along d
  * On return *dep is the energy left in this region, *esc the nuclear-escaped
  * energy; the VP has moved (hinge scheme) and E is updated. */
+/* One condensed-history step.  *let: the step's linear energy transfer
+ * (MeV/mm = keV/um), the mean CSDA stopping power over the step, dE_csda / s;
+ * for a VP that stops, its energy over its residual path, E / (R / rho); at
+ * the cut-off, the CSDA relation's slope on its first segment (NEXT-3 LET
+ * tally: dose-averaged LET = sum(dep * let) / sum(dep) per voxel). */
 static int phys_step(vp_t *vp, int m, double rho_loss, double rho, double dg,
-                     double *dep, double *esc)
+                     double *dep, double *esc, double *let)
 {
-    *dep = 0.0; *esc = 0.0;
+    *dep = 0.0; *esc = 0.0; *let = 0.0;
     vp->n_steps++;
-    if (vp->E <= E_LO) { *dep = vp->E; vp->E = 0.0; return ST_STOP; }
+    if (vp->E <= E_LO) {
+        *let = rho_loss / 10.0 * (g_E[1] - g_E[0]) / (g_R[m][1] - g_R[m][0]);
+        *dep = vp->E; vp->E = 0.0; return ST_STOP;
+    }
     double R = orc_range(m, vp->E);
     if (rho_loss * dg / 10.0 >= R) {           /* stops inside: range-out */
+        *let = vp->E * rho_loss / (10.0 * R);
         *dep = vp->E; vp->E = 0.0; return ST_STOP;
     }
     double smax = 10.0 * STEP_FRACTION * R / rho_loss;   /* mm */
@@ -443,6 +461,7 @@ static int phys_step(vp_t *vp, int m, double rho_loss, double rho, double dg,
     double E = vp->E;
     double E1 = orc_energy_of_range(m, R - rho_loss * s / 10.0);   /* CSDA */
     double Ebar = 0.5 * (E + E1);
+    if (s > 0.0) *let = (E - E1) / s;
     double u[4] = {0.5, 0.5, 0.5, 1.0};
     if (vp->physics) draw_block(vp, u);
     if (vp->physics & PH_STRAGGLE) {
@@ -547,7 +566,8 @@ static int slab_transport(vp_t *vp, sink_t *sk, int m, double rho, double zu, do
         double tp = plane_distance(vp, zu, zd, &down);
         if (tp < 0.0) tp = 0.0;
         double dep, esc;
-        int st = phys_step(vp, m, rho, rho, tp, &dep, &esc);
+        double let;
+        int st = phys_step(vp, m, rho, rho, tp, &dep, &esc, &let);
         sink_ledger(sk, ledger, dep);
         sink_ledger(sk, L_NUC, esc);
         if (st == ST_STOP) return EX_GONE;
@@ -589,7 +609,8 @@ static int block_transport(vp_t *vp, sink_t *sk, const orc_field *f, double zu, 
         }
         double dg = te < tp ? te : tp;
         double dep, esc;
-        int st = phys_step(vp, M_BRASS, f->blk_rho, f->blk_rho, dg, &dep, &esc);
+        double let;
+        int st = phys_step(vp, M_BRASS, f->blk_rho, f->blk_rho, dg, &dep, &esc, &let);
         sink_ledger(sk, L_BLOCK, dep);
         sink_ledger(sk, L_NUC, esc);
         if (st == ST_STOP) return EX_GONE;
@@ -708,9 +729,9 @@ static void patient(vp_t *vp, sink_t *sk, const orc_geom *g, const orc_field *f,
             if (t < 0.0) t = 0.0;
             if (t < dg) { dg = t; ax = k; sgn = up ? 1 : -1; bnd = b; }
         }
-        double dep, esc;
-        int st = phys_step(vp, m, rho_loss, rho, dg, &dep, &esc);
-        sink_grid(sk, v, dep);
+        double dep, esc, let;
+        int st = phys_step(vp, m, rho_loss, rho, dg, &dep, &esc, &let);
+        sink_grid(sk, v, dep, let);
         sink_ledger(sk, L_NUC, esc);
         if (st == ST_STOP) return;
         if (st == ST_GEO) {
@@ -767,9 +788,11 @@ static void one_history(const orc_geom *g, const orc_field *f, const orc_spot *s
 
 /* Run all histories h of spots [s_begin, s_end) in the requested batch.
  * q[nvox] receives int64 fixed-point deposits rne(dE * w_s/N_s * 2^k);
- * led[6] the same for the ledgers.  Returns the number of histories run. */
+ * led[6] the same for the ledgers; qL[nvox] (optional) the LET numerator
+ * rne(dE * LET * w_s/N_s * 2^(k - LET_SHIFT)).  Returns the number of
+ * histories run. */
 int64_t orc_run(const orc_geom *g, const orc_field *f, const orc_spot *spots, int s_begin, int s_end,
-                const orc_scen *sc, const orc_opts *o, int64_t *q, int64_t *led, int nthreads)
+                const orc_scen *sc, const orc_opts *o, int64_t *q, int64_t *led, int nthreads, int64_t *qL)
 {
     orc_init();
     int B = o->n_batches > 1 ? o->n_batches : 1;
@@ -788,6 +811,7 @@ int64_t orc_run(const orc_geom *g, const orc_field *f, const orc_spot *spots, in
             sink_t sk;
             memset(&sk, 0, sizeof sk);
             sk.q = q;
+            sk.qL = qL;
             sk.scale = scale;
             vp_t vp;
 #ifdef _OPENMP
