@@ -62,6 +62,8 @@ extern "C" {
 #define VPMC_SURROGATE 4u   /* VPs entering the brass far from the opening's edge cross it
                                by the learned surrogate (weights must be set; dense and
                                eager CSR runs, not with VPMC_GRAPH) */
+#define VPMC_LET 8u         /* dense dose: also tally the numerator of the dose-averaged LET
+                               (vpmc_last_let); rejected with CSR output */
 
 #define VPMC_MAX_FIELDS 64
 #define VPMC_MAX_VERTICES 1024
@@ -281,6 +283,17 @@ int vpmc_last_stats(const vpmc_ctx *ctx, vpmc_stats *out);
  * nodes, 1 CSDA range, 2 straggling variance, 3 scattering power, 4 nuclear
  * removal.  Writes n <= 256 values; returns the node count. */
 int vpmc_table_host(int material, int which, double *out, int n);
+
+/* Dose-averaged LET (an addition to the paper's dose engine, whose TPS uses
+ * LET clinically, Discussion): after a dense vpmc_run_spots with VPMC_LET,
+ * copies scenario scen_index's int64 numerator sum(dep * LET) * w/N *
+ * 2^(k - shift) into ql_out[nvox] (host, or device with VPMC_DEVICE_PTRS)
+ * and writes shift (8).  Each step's LET is its mean CSDA stopping power in
+ * keV/um (dE_csda over the step length; a VP that stops: E rho / R over its
+ * residual range), so LET_d = ql * 2^shift / q with q from vpmc_last_tally.
+ * Errors: VPMC_E_ARG (no output, bad index or flags), VPMC_E_STATE (the last
+ * dense run did not tally LET), VPMC_E_DEVICE. */
+int vpmc_last_let(vpmc_ctx *ctx, int scen_index, int64_t *ql_out, int *shift_out, unsigned flags);
 
 /* Measurement support for the roofline of the transport (the atomic-rate
  * bound of the deposit tally): times n_atomics non-returning int64 atomic

@@ -109,7 +109,8 @@ struct vpmc_ctx {
     size_t nvox = 0;
     FieldState fields[VPMC_MAX_FIELDS];
     // scratch (grow-only)
-    DevBuf tallies, qbatch, s2, ledger, spots, offsets, stage_dose, stage_sigma, stats;
+    DevBuf tallies, qbatch, s2, ledger, spots, offsets, stage_dose, stage_sigma, stats, let_tallies;
+    bool last_let = false;   // the last dense run tallied the LET numerator
     size_t bytes = 0;
     // last run
     int last_k = 0, last_nscen = 0;
@@ -736,6 +737,7 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
         for (size_t i = 0; i < led.size(); ++i) ledger_mev[i] = ldexp((double)led[i], -k);
     // plan dose per scenario from its rows (contiguous in row order)
     c->last_nscen = 0;
+    c->last_let = false;
     if (dose_gy) {
         if ((rc = ensure(c, c->tallies, (size_t)n_scen * nvox * 8, cap))) return rc;
         if (!dev_out && (rc = ensure(c, c->stage_dose, nvox * sizeof(float), cap))) return rc;
@@ -1016,7 +1018,7 @@ void vpmc_destroy(vpmc_ctx *c) {
             release(f.poly_buf);
             release(f.sdf_buf);
         }
-        for (DevBuf *b : {&c->tallies, &c->qbatch, &c->s2, &c->ledger, &c->spots, &c->offsets,
+        for (DevBuf *b : {&c->tallies, &c->let_tallies, &c->qbatch, &c->s2, &c->ledger, &c->spots, &c->offsets,
                           &c->stage_dose, &c->stage_sigma, &c->stats, &c->slot_grid, &c->slot_mark, &c->slot_cnt,
                           &c->slot_coff, &c->slot_rowcnt, &c->q_stage, &c->q_rownext, &c->rows, &c->chunk_off, &c->heads, &c->row_off, &c->row_nnz, &c->used,
                           &c->flags, &c->fields_tab, &c->poly_off, &c->polys, &c->scen_tab, &c->csr_col,
@@ -1210,7 +1212,10 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
     if (o->grid_blocks < 0) return fail(VPMC_E_ARG, "grid_blocks < 0");
     if (o->hist_per_lane < 0 || o->hist_per_lane > 4096) return fail(VPMC_E_ARG, "hist_per_lane outside [0, 4096]");
     if (o->max_slots < 0) return fail(VPMC_E_ARG, "max_slots < 0");
-    if (o->flags & ~(VPMC_DEVICE_PTRS | VPMC_GRAPH | VPMC_SURROGATE)) return fail(VPMC_E_ARG, "unknown flags");
+    if (o->flags & ~(VPMC_DEVICE_PTRS | VPMC_GRAPH | VPMC_SURROGATE | VPMC_LET))
+        return fail(VPMC_E_ARG, "unknown flags");
+    if ((o->flags & VPMC_LET) && o->output != VPMC_OUT_DOSE)
+        return fail(VPMC_E_ARG, "VPMC_LET is a dense-dose option");
     const bool use_sur = (o->flags & VPMC_SURROGATE) != 0;
     if (use_sur) {
         if (o->flags & VPMC_GRAPH) return fail(VPMC_E_ARG, "VPMC_SURROGATE cannot be combined with VPMC_GRAPH");
@@ -1241,6 +1246,9 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
     hipStream_t st = (hipStream_t)o->hip_stream;
     HIP_TRY(hipSetDevice(c->device));
     if ((rc = ensure(c, c->tallies, (size_t)n_scen * nvox * sizeof(long long), cap))) return rc;
+    const bool want_let = (o->flags & VPMC_LET) != 0;
+    if (want_let && (rc = ensure(c, c->let_tallies, (size_t)n_scen * nvox * sizeof(long long), cap))) return rc;
+    c->last_let = false;
     if (B > 1) {
         if ((rc = ensure(c, c->qbatch, nvox * sizeof(unsigned long long), cap))) return rc;
         if ((rc = ensure(c, c->s2, nvox * sizeof(double), cap))) return rc;
@@ -1306,6 +1314,9 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
     for (int sc = 0; sc < n_scen; ++sc) {
         long long *tally = (long long *)c->tallies.ptr + (size_t)sc * nvox;
         HIP_TRY(hipMemsetAsync(tally, 0, nvox * sizeof(long long), st));
+        unsigned long long *let_tally =
+            want_let ? (unsigned long long *)c->let_tallies.ptr + (size_t)sc * nvox : nullptr;
+        if (let_tally) HIP_TRY(hipMemsetAsync(let_tally, 0, nvox * sizeof(long long), st));
         if (B > 1) HIP_TRY(hipMemsetAsync(c->s2.ptr, 0, nvox * sizeof(double), st));
         if (B > 1) HIP_TRY(hipMemsetAsync(c->qbatch.ptr, 0, nvox * sizeof(unsigned long long), st));
         for (int b = 0; b < B; ++b) {
@@ -1325,6 +1336,7 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
             for (int q = 0; q < 3; ++q) L.shift[q] = scen[sc].shift_mm[q];
             L.range_scale = scen[sc].range_scale;
             L.tally = B > 1 ? (unsigned long long *)c->qbatch.ptr : (unsigned long long *)tally;
+            L.let_tally = let_tally;   // every batch adds to the scenario's numerator
             L.ledger = (unsigned long long *)c->ledger.ptr + (size_t)sc * NLEDGER;
             L.tables = c->d_tables;
             L.stats = (unsigned long long *)c->stats.ptr;
@@ -1394,6 +1406,7 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
     if (ledger_mev)
         for (size_t i = 0; i < led.size(); ++i) ledger_mev[i] = ldexp((double)led[i], -k);
     c->last_k = k;
+    c->last_let = want_let;
     c->last_nscen = n_scen;
     return VPMC_OK;
 }
@@ -1544,6 +1557,22 @@ int vpmc_copy_csr(vpmc_ctx *c, int32_t *col, float *val, int64_t *q_raw) {
                                   ldexp(MEV_TO_J, -c->last_k), dst, nullptr));
         HIP_TRY(hipDeviceSynchronize());
         if (!dev) HIP_TRY(hipMemcpy(val, dst, n * 4, hipMemcpyDeviceToHost));
+    }
+    return VPMC_OK;
+}
+
+int vpmc_last_let(vpmc_ctx *c, int scen_index, int64_t *ql_out, int *shift_out, unsigned flags) {
+    if (!c) return fail(VPMC_E_ARG, "ctx is NULL");
+    if (!ql_out && !shift_out) return fail(VPMC_E_ARG, "no output");
+    if (flags & ~VPMC_DEVICE_PTRS) return fail(VPMC_E_ARG, "unknown flags");
+    if (c->last_nscen == 0 || !c->last_let) return fail(VPMC_E_STATE, "the last dense run did not tally LET");
+    if (scen_index < 0 || scen_index >= c->last_nscen) return fail(VPMC_E_ARG, "scenario index out of range");
+    if (shift_out) *shift_out = kLetShift;
+    if (ql_out) {
+        HIP_TRY(hipSetDevice(c->device));
+        HIP_TRY(hipMemcpy(ql_out, (long long *)c->let_tallies.ptr + (size_t)scen_index * c->nvox,
+                          c->nvox * sizeof(long long),
+                          (flags & VPMC_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
     }
     return VPMC_OK;
 }

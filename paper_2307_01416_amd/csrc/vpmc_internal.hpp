@@ -112,6 +112,7 @@ struct LaunchDev {
     float shift[3];
     float range_scale;
     unsigned long long *tally;            // int64 fixed point, two's complement
+    unsigned long long *let_tally;        // dose-averaged LET numerator (same layout) or null
     unsigned long long *ledger;           // [NLEDGER]
     unsigned long long *stats;            // [2]: steps, histories
     const float *tables;                  // TAB_FLOATS
@@ -119,6 +120,7 @@ struct LaunchDev {
 };
 
 constexpr int POLY_LDS = 1024;  // == VPMC_MAX_VERTICES
+constexpr int kLetShift = 8;    // LET numerator scale 2^(k - 8): LET <= 256 keV/um keeps it within the dose bound
 
 // ------------------------------------------- influence-matrix (CSR) mode
 // One row = (scenario, field, spot).  Rows are processed in epochs of at

@@ -315,19 +315,25 @@ __device__ __forceinline__ DF csda_loss(const float *tab, const float *tm, const
 // rho scattering and nuclear removal.  dg: distance to the region boundary.
 // Energy, residual range, path and density are pairs (double-float); the
 // decisions (range-out, step length) and the physics sampling use FP32.
+// let: the step's LET in MeV/mm (= keV/um) for the dose-averaged LET tally:
+// the mean CSDA stopping power over the step (dE_csda / s); for a VP that
+// stops, its energy over its residual path (E rho / R); at the cut-off, the
+// slope of the CSDA relation's first segment times the density.
 template <bool Slab, bool X>
 __device__ int phys_step(Lane &v, const float *tab, int m, DF rho_loss, float rho, DF dg, float &dep,
-                         float &esc) {
+                         float &esc, float &let) {
     using A = Ar<X>;
     dep = 0.0f;
     esc = 0.0f;
+    let = 0.0f;
     v.nsteps++;
+    const float *tm = tab + TAB_MAT0 + m * TAB_PER_MAT;
     if (v.E + v.Elo <= kELo) {
+        let = rho_loss.h * tm[T_SH * NE];
         dep = v.E + v.Elo;
         v.E = v.Elo = 0.0f;
         return ST_STOP;
     }
-    const float *tm = tab + TAB_MAT0 + m * TAB_PER_MAT;
     const float *tl = tab + TAB_LMAT0 + m * TAB_PER_LMAT;
     int i = seg_of(tab, v.E);
     // E - E_i: the high parts subtract exactly (same binade), the low parts add
@@ -342,6 +348,7 @@ __device__ int phys_step(Lane &v, const float *tab, int m, DF rho_loss, float rh
     const DF rem = A::div(x, S);
     const float R = tm[T_R * NE + i] + rem.h;
     if (rho_loss.h * dg.h >= R) {
+        let = (v.E + v.Elo) * rho_loss.h * __builtin_amdgcn_rcpf(R);
         dep = v.E + v.Elo;
         v.E = v.Elo = 0.0f;
         return ST_STOP;
@@ -351,6 +358,7 @@ __device__ int phys_step(Lane &v, const float *tab, int m, DF rho_loss, float rh
     const DF s = geo ? dg : DF{smax, 0.0f};
     const DF r = A::mul(rho_loss, s);   // density x mm (the tables' unit)
     DF dE = csda_loss<X>(tab, tm, tl, i, x, rem, r);
+    if (s.h > 0.0f) let = (dE.h + dE.l) / (s.h + s.l);
     const float Ebar = v.E - 0.5f * dE.h;
     uint4 w = make_uint4(0u, 0u, 0u, 0xFFFFFFFFu);
     NodePos pb{0, 0.0f};
@@ -414,6 +422,11 @@ __device__ __forceinline__ void ledger_add(Acc &a, int j, float e, float scale) 
 // dense tally: one 64-bit atomic per deposit
 struct DenseSink {
     unsigned long long *tally;
+    unsigned long long *let = nullptr;   // dose-averaged LET numerator, or none
+    static constexpr bool kLet = true;
+    __device__ __forceinline__ void add_let(uint32_t v, long long q) const {
+        atomicAdd(let + v, (unsigned long long)q);
+    }
     __device__ __forceinline__ void add(uint32_t v, const int *, long long q) const {
         atomicAdd(tally + v, (unsigned long long)q);
     }
@@ -428,6 +441,9 @@ struct DenseSink {
 struct SparseSink {
     unsigned long long *grid;
     uint8_t *mark;
+    static constexpr bool kLet = false;
+    unsigned long long *let = nullptr;
+    __device__ __forceinline__ void add_let(uint32_t, long long) const {}
     __device__ __forceinline__ void add(uint32_t v, const int *, long long q) const {
         put(v, q);
     }
@@ -449,6 +465,9 @@ struct TileSink {
     int lo0, lo1, lo2;
     uint32_t n0, n1, n2;
     SparseSink gs;
+    unsigned long long *let = nullptr;   // (no LET tally in influence matrices)
+    static constexpr bool kLet = false;
+    __device__ __forceinline__ void add_let(uint32_t, long long) const {}
     __device__ __forceinline__ void add(uint32_t v, const int *idx, long long q) const {
         if (tile) {
             const uint32_t u0 = (uint32_t)(idx[0] - lo0), u1 = (uint32_t)(idx[1] - lo1), u2 = (uint32_t)(idx[2] - lo2);
@@ -558,7 +577,8 @@ __device__ int slab_transport(Lane &v, Acc &acc, float scale, const float *tab, 
         bool down;
         const DF tp = plane_distance<X>(v, thick, down);
         float dep, esc;
-        const int st = phys_step<true, X>(v, tab, m, rho, rho.h, tp, dep, esc);
+        float let;
+        const int st = phys_step<true, X>(v, tab, m, rho, rho.h, tp, dep, esc, let);
         ledger_add(acc, ledger, dep, scale);
         ledger_add(acc, L_NUC, esc, scale);
         if (st == ST_STOP) return EX_GONE;
@@ -618,7 +638,8 @@ __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab,
         }
         const DF dg = te < tp ? DF{te, 0.0f} : tpp;
         float dep, esc;
-        const int st = phys_step<true, X>(v, tab, MAT_BRASS, {rho_b, 0.0f}, rho_b, dg, dep, esc);
+        float let;
+        const int st = phys_step<true, X>(v, tab, MAT_BRASS, {rho_b, 0.0f}, rho_b, dg, dep, esc, let);
         ledger_add(acc, L_BLOCK, dep, scale);
         ledger_add(acc, L_NUC, esc, scale);
         if (st == ST_STOP) return EX_GONE;
@@ -924,10 +945,17 @@ __device__ bool patient_step(Lane &v, Acc &acc, float scale, const float *tab, c
                 if (g.kind == 1) hu_next = (int)g.hu[nvox];
             }
         }
-        float dep, esc;
-        const int st = phys_step<false, X>(v, tab, m, rho_loss, rho.h, dg, dep, esc);
+        float dep, esc, let;
+        const int st = phys_step<false, X>(v, tab, m, rho_loss, rho.h, dg, dep, esc, let);
         const long long qd = to_fixed(dep, scale);
         if (qd != 0) sink.add(vox, idx, qd);
+        if constexpr (Sink::kLet) {
+            if (sink.let != nullptr) {
+                // numerator of the dose-averaged LET: rne(dep * LET * w/N * 2^(k - kLetShift))
+                const long long ql = to_fixed(dep * let, scale * (1.0f / (float)(1 << kLetShift)));
+                if (ql != 0) sink.add_let(vox, ql);
+            }
+        }
         acc.led[L_GRID] += qd;
         if (esc != 0.0f) ledger_add(acc, L_NUC, esc, scale);
         if (st == ST_STOP) return false;
@@ -1028,7 +1056,8 @@ __global__ __launch_bounds__(512) void transport_kernel(GeomDev g, FieldDev f, L
         source(v, sp);
         float tmin;
         if (beamline<X>(v, acc, sp.scale, tab, poly, f, tmin, &L.sur) == BL_PATIENT)
-            patient<DenseSink, X>(v, acc, sp.scale, tab, g, f, L.shift, L.range_scale, DenseSink{L.tally}, tmin);
+            patient<DenseSink, X>(v, acc, sp.scale, tab, g, f, L.shift, L.range_scale, DenseSink{L.tally, L.let_tally},
+                                  tmin);
         acc.steps += v.nsteps;
         acc.hist += 1;
     }
@@ -1757,7 +1786,7 @@ __global__ __launch_bounds__(256) void sur_resume_kernel(GeomDev g, FieldDev f, 
         Lane v;
         lane_from_record(v, r, L.key0, L.key1, L.physics, f.blk_zu);
         resume_deferred<DenseSink, X>(v, acc, L.spots[r.spot].scale, tab, poly, f, out + i * MLP_OUT, p_lo, p_hi, g, L.shift,
-                        L.range_scale, DenseSink{L.tally});
+                        L.range_scale, DenseSink{L.tally, L.let_tally});
         acc.steps += v.nsteps;
     }
     flush_ledger_steps(acc, L.ledger, L.stats);

@@ -29,6 +29,7 @@ OUT_DOSE, OUT_CSR = 0, 1
 DEVICE_PTRS = 1
 GRAPH = 2
 SURROGATE = 4
+LET = 8
 NLEDGER = 6
 
 
@@ -97,6 +98,7 @@ def load() -> C.CDLL:
         "vpmc_run_spots": (i, [vp, i, vp, i, vp, i, vp, vp, vp, vp, vp]),
         "vpmc_copy_csr": (i, [vp, vp, vp, vp]),
         "vpmc_last_tally": (i, [vp, i, vp, C.POINTER(C.c_int), u]),
+        "vpmc_last_let": (i, [vp, i, vp, C.POINTER(C.c_int), u]),
         "vpmc_table_host": (i, [i, i, vp, i]),
         "vpmc_last_stats": (i, [vp, vp]),
         "vpmc_run_batched": (i, [vp, vp, vp, vp, i, vp, i, vp, vp, vp, vp]),
@@ -277,6 +279,13 @@ def vpmc_last_tally_k(ctx) -> int:
     return k.value
 
 
+def vpmc_last_let(ctx, scen_index: int, ql_out=None, flags: int = 0) -> int:
+    """Copy the last dense run's LET numerator of one scenario; returns its shift."""
+    sh = C.c_int(0)
+    _check(load().vpmc_last_let(ctx, scen_index, _ptr(ql_out), C.byref(sh), flags), ctx)
+    return sh.value
+
+
 def vpmc_last_tally(ctx, scen_index: int, q_out=None, flags: int = 0) -> int:
     k = C.c_int(0)
     _check(load().vpmc_last_tally(ctx, scen_index, _ptr(q_out), C.byref(k), flags), ctx)
@@ -399,11 +408,12 @@ class Engine:
 
     def run_dose(self, case: I.Case, field_index: int = 0, scenarios=None, n_batches: Optional[int] = None,
                  sigma: bool = True, physics: Optional[int] = None, seed: Optional[int] = None,
-                 fixed_point_bits: int = 0, grid_blocks: int = 0, surrogate: bool = False):
+                 fixed_point_bits: int = 0, grid_blocks: int = 0, surrogate: bool = False, let: bool = False):
         """Dense dose of one field for the given scenario list.  Returns
         (dose[n_scen, nz, ny, nx], sigma or None, ledger_mev[n_scen, 6]) with
         dose/sigma as torch float32 tensors on the GPU.  surrogate: deep
-        brass entries cross the block by the learned surrogate."""
+        brass entries cross the block by the learned surrogate.  let: also
+        tally the dose-averaged LET numerator (last_let)."""
         torch = self.torch
         scen = case.scenarios if scenarios is None else scenarios
         B = case.n_batches if n_batches is None else n_batches
@@ -416,7 +426,8 @@ class Engine:
         opts = make_opts(seed=case.seed if seed is None else seed,
                          physics=case.physics if physics is None else physics,
                          n_batches=B if (sigma and B >= 2) else 0, fixed_point_bits=fixed_point_bits,
-                         flags=DEVICE_PTRS | (SURROGATE if surrogate else 0), stream=self.stream_ptr(),
+                         flags=DEVICE_PTRS | (SURROGATE if surrogate else 0) | (LET if let else 0),
+                         stream=self.stream_ptr(),
                          grid_blocks=grid_blocks)
         vpmc_run_spots(self.ctx, field_index, spot_array(spots), len(spots), scenario_array(scen), len(scen),
                        opts, dose, sig, led)
@@ -513,6 +524,15 @@ class Engine:
         vpmc_surrogate_set_weights(self.ctx, surrogate_init(seed))
         return vpmc_surrogate_train(self.ctx, np.concatenate(xs), np.concatenate(ys), np.concatenate(ts), epochs,
                                     batch, lr, seed)
+
+    def last_let(self, scen_index: int = 0):
+        """(numerator int64[nz, ny, nx] on the GPU, shift) of the last dense
+        run with let=True; LET_d = numerator * 2^shift / last_tally q."""
+        torch = self.torch
+        ql = torch.empty(self._geom.nvox, dtype=torch.int64, device=torch.device("cuda", self.device))
+        sh = vpmc_last_let(self.ctx, scen_index, ql, DEVICE_PTRS)
+        nx, ny, nz = self._geom.shape
+        return ql.reshape(nz, ny, nx), sh
 
     def last_tally(self, scen_index: int = 0):
         torch = self.torch

@@ -131,3 +131,15 @@ def test_atomic_rate_validation(vctx):
     assert _rc(V.vpmc_atomic_rate, vctx, (256, 256, 160), 100) == V.E_ARG
     assert _rc(V.vpmc_atomic_rate, vctx, (4096, 4096, 4096), 1 << 20) == V.E_ARG
     assert _rc(V.vpmc_atomic_rate, vctx, (256, 256, 160), 1 << 20) == V.E_STATE
+
+
+def test_let_validation(vctx):
+    # no dense run yet (and a validation-only context)
+    assert _rc(V.vpmc_last_let, vctx, 0, np.zeros(8, np.int64)) == V.E_STATE
+    assert V.load().vpmc_last_let(vctx, 0, None, None, 0) == V.E_ARG
+    # LET is a dense-dose option
+    spots = V.spot_array(I.make_spots([(0.0, 0.0)], 100.0, 3.0, 10))
+    scen = V.scenario_array([I.Scenario()])
+    opts = V.make_opts(output=V.OUT_CSR, flags=V.LET)
+    rp = np.zeros(2, np.int64)
+    assert _rc(V.vpmc_run_spots, vctx, 0, spots, 1, scen, 1, opts, None, None, None, rp) in (V.E_ARG, V.E_STATE)
