@@ -306,6 +306,56 @@ int vpmc_last_let(vpmc_ctx *ctx, int scen_index, int64_t *ql_out, int *shift_out
  * VPMC_E_STATE (validation-only context), VPMC_E_DEVICE (HIP failure). */
 int vpmc_atomic_rate(vpmc_ctx *ctx, int nx, int ny, int nz, uint64_t n_atomics, double *atomics_per_s);
 
+/* ---------------------------------------------------------------------------
+ * Robust spot-weight optimisation on influence matrices (the plan optimiser
+ * that consumes the matrices of the 13 robust scenarios, Methods E; the
+ * paper's own optimiser belongs to its planning system, this one is the
+ * library's).  Objective, averaged over the n_scen scenarios s:
+ *   F(x) = 1/S sum_s [ w_target sum_{v in T} (D_s(v) - d_presc)^2
+ *                      + w_oar sum_{v in O} max(0, D_s(v) - d_max)^2 ],
+ *   D_s = A_s^T x, x >= 0: one weight per spot shared by all scenarios,
+ * A_s[j, v] = the CSR row of (scenario s, spot j) = dose in voxel v per unit
+ * weight.  Solver: projected FISTA with the fixed step 1/L, L = 1.05 x the
+ * largest eigenvalue of 2/S sum_s A_s M A_s^T (M = w_target on T plus w_oar
+ * on O) from n_power power iterations started at the all-ones vector; if
+ * that eigenvalue is 0 the step is the projection alone.  Each dose sweep
+ * sums in int64 fixed point and each gradient in FP64 in a fixed order, so
+ * reruns give identical bits.  Every iteration reads the CSR twice
+ * (HBM-bound sparse products).
+ * ------------------------------------------------------------------------- */
+#define VPMC_OPT_REUSE 16u  /* keep the segment index of the previous call: row_ptr, col and val
+                               must be unchanged (same dims, same row_ptr contents checked) */
+
+typedef struct {
+    double d_presc;     /* target prescription, Gy (finite) */
+    double w_target;    /* weight of the target term (>= 0) */
+    double d_max;       /* organ-at-risk maximum dose, Gy (finite) */
+    double w_oar;       /* weight of the organ term (>= 0) */
+    int iters;          /* FISTA iterations, 0 .. 100000 */
+    int n_power;        /* power iterations for L, 1 .. 1000 */
+    int row_stride;     /* CSR row of (s, j) = s*row_stride + row_offset + j; 0 = n_spots.  A field's */
+    int row_offset;     /*   spots inside rows of vpmc_run_batched: stride = all spots, offset = field's */
+    unsigned flags;     /* VPMC_DEVICE_PTRS, VPMC_OPT_REUSE */
+    void *hip_stream;   /* hipStream_t or NULL */
+} vpmc_opt_params;
+
+/* row_ptr [n_scen*row_stride + 1] non-decreasing int64 offsets (the whole
+ * layout, as vpmc_run_batched writes it), col [row_ptr[n_scen*row_stride]]
+ * voxel indices in [0, nvox), val [same] finite FP32, roi [nvox] bit 0 target,
+ * bit 1 organ at risk (both allowed), x [n_spots] starting weights in, final
+ * weights out (FP64), obj_hist [iters + 1] (optional) F at each FISTA
+ * extrapolation point y_0 .. y_{iters-1} then F at the final x, step_L
+ * (optional, always host) the L used, dose_gy [n_scen][nvox] (optional) D_s at
+ * the final x.  Pointer kind of every array per p->flags.  Scratch: about
+ * 4 B x n_scen x nvox + 16 B per segment (a row's run inside one 4096-voxel
+ * chunk) + 40 B per spot and scenario, kept for VPMC_OPT_REUSE.  Errors:
+ * VPMC_E_ARG (dims, parameters, flags, row_ptr decreasing, a column out of
+ * range or a value not finite), VPMC_E_STATE (validation-only context;
+ * VPMC_OPT_REUSE without a matching index), VPMC_E_OOM, VPMC_E_DEVICE. */
+int vpmc_optimize(vpmc_ctx *ctx, const int64_t *row_ptr, const int32_t *col, const float *val, int n_scen,
+                  int n_spots, int nvox, const uint8_t *roi, const vpmc_opt_params *p, double *x, double *obj_hist,
+                  double *step_L, float *dose_gy);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,7 +13,9 @@ s.  Gradient: 2/S sum_s A_s r_s with r_s = wT (D_s - dp) on T + wO max(0,
 D_s - dmax) on O.  Solver: FISTA (Beck and Teboulle 2009) with the
 projection onto x >= 0 and the fixed step 1/L, L = 1.05 x the largest
 eigenvalue of 2/S sum_s A_s M A_s^T (M = wT on T + wO on O) from n_power
-power iterations started at the all-ones vector."""
+power iterations started at the all-ones vector.  Reading for the
+degenerate case (no curvature: all of M A_s^T vanishes): the eigenvalue is
+0, the power vector stays as it is and each step is the projection alone."""
 from __future__ import annotations
 
 import numpy as np
@@ -47,13 +49,16 @@ def lipschitz(A, tmask, omask, wT, wO, n_power=20):
         for As in A:
             y += As @ (m * (As.T @ z))
         y *= 2.0 / S
-        lam = float(np.linalg.norm(y) / np.linalg.norm(z))
-        z = y / np.linalg.norm(y)
+        ny_ = float(np.linalg.norm(y))
+        lam = ny_ / float(np.linalg.norm(z))
+        if ny_ > 0.0:
+            z = y / ny_
     return 1.05 * lam
 
 
 def fista(A, x0, tmask, omask, dp, wT, dmax, wO, iters, n_power=20):
-    """Returns (x, objective at each iterate's extrapolated point, L)."""
+    """Returns (x, objective at each extrapolated point y_k then at the final
+    x [iters + 1], L)."""
     L = lipschitz(A, tmask, omask, wT, wO, n_power)
     x = np.maximum(np.asarray(x0, np.float64), 0.0)
     y = x.copy()
@@ -62,8 +67,24 @@ def fista(A, x0, tmask, omask, dp, wT, dmax, wO, iters, n_power=20):
     for _ in range(iters):
         F, g = objective_grad(A, y, tmask, omask, dp, wT, dmax, wO)
         hist.append(F)
-        xn = np.maximum(0.0, y - g / L)
+        xn = np.maximum(0.0, y - g / L if L > 0.0 else y)
         tn = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))
         y = xn + ((t - 1.0) / tn) * (xn - x)
         x, t = xn, tn
+    hist.append(objective_grad(A, x, tmask, omask, dp, wT, dmax, wO)[0])
     return x, np.array(hist), L
+
+
+def matrices_from_csr(row_ptr, col, val, n_scen, n_spots, nvox, row_stride=0, row_offset=0):
+    """Scenario matrices A_s [n_spots, nvox] (FP64) from CSR rows
+    s*row_stride + row_offset + j."""
+    import scipy.sparse as sp
+    stride = row_stride or n_spots
+    A = []
+    for s in range(n_scen):
+        r0 = s * stride + row_offset
+        rp = np.asarray(row_ptr[r0: r0 + n_spots + 1], np.int64)
+        lo, hi = int(rp[0]), int(rp[-1])
+        A.append(sp.csr_matrix((np.asarray(val[lo:hi], np.float64), np.asarray(col[lo:hi], np.int64), rp - lo),
+                               shape=(n_spots, nvox)))
+    return A

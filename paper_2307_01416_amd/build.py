@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libvpmc.so")
-SOURCES = ["csrc/vpmc_kernels.hip", "csrc/vpmc_mlp.hip", "csrc/vpmc_api.cpp", "csrc/tables.cpp"]
+SOURCES = ["csrc/vpmc_kernels.hip", "csrc/vpmc_mlp.hip", "csrc/vpmc_opt.hip", "csrc/vpmc_api.cpp", "csrc/tables.cpp"]
 ARCH = os.environ.get("VPMC_OFFLOAD_ARCH", "gfx950")
 
 

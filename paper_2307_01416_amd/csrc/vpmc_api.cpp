@@ -136,6 +136,13 @@ struct vpmc_ctx {
     int mlp_step = 0;
     int mlp_batch_cap = 0;
     DevBuf sur_rec, sur_cnt, sur_out;
+    // spot-weight optimiser: segment index (kept for VPMC_OPT_REUSE) and work buffers
+    DevBuf opt_rp, opt_col, opt_val, opt_roi, opt_amax, opt_cnt, opt_off, opt_seg, opt_resid, opt_fpart,
+        opt_gpart, opt_vec, opt_scal, opt_err, opt_hist, opt_dose;
+    bool opt_valid = false;
+    int opt_dims[5] = {0, 0, 0, 0, 0};   // n_scen, n_spots, row_stride, row_offset, nvox
+    std::vector<int64_t> opt_rp_host;
+    const void *opt_col_src = nullptr, *opt_val_src = nullptr;
     float sur_dfb = 3.0f, sur_plo = 0.02f, sur_phi = 0.98f;
 };
 
@@ -1024,7 +1031,9 @@ void vpmc_destroy(vpmc_ctx *c) {
                           &c->flags, &c->fields_tab, &c->poly_off, &c->polys, &c->scen_tab, &c->csr_col,
                           &c->csr_q, &c->mlp_w, &c->mlp_wb, &c->mlp_m, &c->mlp_v, &c->mlp_g, &c->mlp_act,
                           &c->mlp_io, &c->mlp_dx, &c->mlp_dy, &c->mlp_dt, &c->mlp_idx, &c->sur_rec,
-                          &c->sur_cnt, &c->sur_out})
+                          &c->sur_cnt, &c->sur_out, &c->opt_rp, &c->opt_col, &c->opt_val, &c->opt_roi, &c->opt_amax,
+                          &c->opt_cnt, &c->opt_off, &c->opt_seg, &c->opt_resid, &c->opt_fpart, &c->opt_gpart,
+                          &c->opt_vec, &c->opt_scal, &c->opt_err, &c->opt_hist, &c->opt_dose})
             release(*b);
         for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -1597,3 +1606,176 @@ int vpmc_last_tally(vpmc_ctx *c, int scen_index, int64_t *q_out, int *k_out, uns
 }
 
 }  // extern "C"
+
+int vpmc_optimize(vpmc_ctx *c, const int64_t *row_ptr, const int32_t *col, const float *val, int n_scen,
+                  int n_spots, int nvox, const uint8_t *roi, const vpmc_opt_params *p, double *x, double *obj_hist,
+                  double *step_L, float *dose_gy) {
+    if (!c || !p) return fail(VPMC_E_ARG, "ctx and params are required");
+    if (!row_ptr || !roi || !x) return fail(VPMC_E_ARG, "row_ptr, roi and x are required");
+    if (n_scen < 1 || n_spots < 1 || nvox < 1) return fail(VPMC_E_ARG, "n_scen, n_spots and nvox must be >= 1");
+    if (p->flags & ~(VPMC_DEVICE_PTRS | VPMC_OPT_REUSE)) return fail(VPMC_E_ARG, "unknown flags");
+    if (!std::isfinite(p->d_presc) || !std::isfinite(p->d_max) || !std::isfinite(p->w_target) ||
+        !std::isfinite(p->w_oar) || p->w_target < 0.0 || p->w_oar < 0.0)
+        return fail(VPMC_E_ARG, "d_presc and d_max must be finite, the weights finite and >= 0");
+    if (p->iters < 0 || p->iters > 100000) return fail(VPMC_E_ARG, "iters outside [0, 100000]");
+    if (p->n_power < 1 || p->n_power > 1000) return fail(VPMC_E_ARG, "n_power outside [1, 1000]");
+    const int stride = p->row_stride ? p->row_stride : n_spots;
+    if (p->row_offset < 0 || stride < 1 || (long long)p->row_offset + n_spots > stride)
+        return fail(VPMC_E_ARG, "need 0 <= row_offset and row_offset + n_spots <= row_stride");
+    const long long n_layout = (long long)n_scen * stride;
+    const long long n_rows = (long long)n_scen * n_spots;
+    if (n_layout >= (1ll << 31) || n_rows * 64 >= (1ll << 31)) return fail(VPMC_E_ARG, "too many rows");
+    const bool dev = (p->flags & VPMC_DEVICE_PTRS) != 0;
+    const bool reuse = (p->flags & VPMC_OPT_REUSE) != 0;
+    // host copy of the row pointer for validation (host arrays are checked
+    // here, before the device is touched)
+    std::vector<int64_t> rp((size_t)n_layout + 1);
+    if (!dev) {
+        memcpy(rp.data(), row_ptr, rp.size() * sizeof(int64_t));
+    } else {
+        if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
+        HIP_TRY(hipSetDevice(c->device));
+        HIP_TRY(hipMemcpy(rp.data(), row_ptr, rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+    }
+    if (rp[0] < 0) return fail(VPMC_E_ARG, "row_ptr[0] < 0");
+    for (size_t r = 0; r + 1 < rp.size(); ++r)
+        if (rp[r + 1] < rp[r]) return fail(VPMC_E_ARG, "row_ptr decreases at row %zu", r);
+    const long long nnz = rp.back();
+    if (nnz > 0 && (!col || !val)) return fail(VPMC_E_ARG, "col and val are required");
+    if (!dev) {
+        for (long long i = 0; i < nnz; ++i) {
+            if ((unsigned)col[i] >= (unsigned)nvox) return fail(VPMC_E_ARG, "column %lld out of range", i);
+            if (!std::isfinite(val[i])) return fail(VPMC_E_ARG, "value %lld not finite", i);
+        }
+    }
+    if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)p->hip_stream;
+    const int nchunks = (int)((nvox + (long long)kOptChunk - 1) / kOptChunk);
+    const size_t nlist = (size_t)n_scen * nchunks;
+    const int dims[5] = {n_scen, n_spots, stride, p->row_offset, nvox};
+    const bool same = c->opt_valid && memcmp(dims, c->opt_dims, sizeof dims) == 0 && c->opt_rp_host == rp &&
+                      (!dev || (c->opt_col_src == col && c->opt_val_src == val));
+    if (reuse && !same) return fail(VPMC_E_STATE, "VPMC_OPT_REUSE without a matching segment index");
+    int rc;
+    // CSR on the device: the library's own row pointer (validated), caller's or copied arrays
+    if ((rc = ensure(c, c->opt_rp, rp.size() * 8, 0))) return rc;
+    const int32_t *d_col = col;
+    const float *d_val = val;
+    const uint8_t *d_roi = roi;
+    if (!dev) {
+        if ((rc = ensure(c, c->opt_col, (size_t)std::max(nnz, 1ll) * 4, 0))) return rc;
+        if ((rc = ensure(c, c->opt_val, (size_t)std::max(nnz, 1ll) * 4, 0))) return rc;
+        if ((rc = ensure(c, c->opt_roi, (size_t)nvox, 0))) return rc;
+        if (!reuse) {
+            HIP_TRY(hipMemcpyAsync(c->opt_col.ptr, col, (size_t)nnz * 4, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(c->opt_val.ptr, val, (size_t)nnz * 4, hipMemcpyHostToDevice, st));
+        }
+        HIP_TRY(hipMemcpyAsync(c->opt_roi.ptr, roi, (size_t)nvox, hipMemcpyHostToDevice, st));
+        d_col = (const int32_t *)c->opt_col.ptr;
+        d_val = (const float *)c->opt_val.ptr;
+        d_roi = (const uint8_t *)c->opt_roi.ptr;
+    }
+    if ((rc = ensure(c, c->opt_amax, (size_t)n_rows * 4, 0))) return rc;
+    if ((rc = ensure(c, c->opt_cnt, nlist * 4, 0))) return rc;
+    if ((rc = ensure(c, c->opt_off, (nlist + 1) * 8, 0))) return rc;
+    if ((rc = ensure(c, c->opt_resid, (size_t)n_scen * nvox * 4, 0))) return rc;
+    if ((rc = ensure(c, c->opt_fpart, nlist * 8, 0))) return rc;
+    if ((rc = ensure(c, c->opt_gpart, (size_t)n_rows * 8, 0))) return rc;
+    if ((rc = ensure(c, c->opt_vec, (size_t)n_spots * 4 * 8, 0))) return rc;
+    if ((rc = ensure(c, c->opt_scal, ((size_t)2 * n_scen + 2) * 8, 0))) return rc;
+    if ((rc = ensure(c, c->opt_err, 4, 0))) return rc;
+    if ((rc = ensure(c, c->opt_hist, ((size_t)p->iters + 1) * 8, 0))) return rc;
+    OptDev O{};
+    O.row_ptr = (const long long *)c->opt_rp.ptr;
+    O.col = d_col;
+    O.val = d_val;
+    O.roi = d_roi;
+    O.n_scen = n_scen;
+    O.n_spots = n_spots;
+    O.row_stride = stride;
+    O.row_offset = p->row_offset;
+    O.nvox = nvox;
+    O.nchunks = nchunks;
+    O.d_presc = p->d_presc;
+    O.w_target = p->w_target;
+    O.d_max = p->d_max;
+    O.w_oar = p->w_oar;
+    O.amax = (float *)c->opt_amax.ptr;
+    O.resid = (float *)c->opt_resid.ptr;
+    O.fpart = (double *)c->opt_fpart.ptr;
+    O.gpart = (double *)c->opt_gpart.ptr;
+    double *vec = (double *)c->opt_vec.ptr;
+    O.x = vec;
+    O.y = vec + n_spots;
+    O.z = vec + 2 * (size_t)n_spots;
+    O.gvec = vec + 3 * (size_t)n_spots;
+    O.scale = (double *)c->opt_scal.ptr;
+    O.scal = O.scale + 2 * (size_t)n_scen;
+    O.seg_off = (const unsigned long long *)c->opt_off.ptr;
+    if (!reuse) {
+        c->opt_valid = false;
+        HIP_TRY(hipMemcpyAsync(c->opt_rp.ptr, rp.data(), rp.size() * 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemsetAsync(c->opt_cnt.ptr, 0, nlist * 4, st));
+        HIP_TRY(hipMemsetAsync(c->opt_err.ptr, 0, 4, st));
+        HIP_TRY(opt_build_count(O, (unsigned *)c->opt_cnt.ptr, (unsigned *)c->opt_err.ptr, st));
+        unsigned err = 0;
+        HIP_TRY(hipMemcpyAsync(&err, c->opt_err.ptr, 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (err & 1u) return fail(VPMC_E_ARG, "a column index is outside [0, nvox)");
+        if (err & 2u) return fail(VPMC_E_ARG, "a value is not finite");
+        HIP_TRY(opt_build_scan((unsigned *)c->opt_cnt.ptr, (unsigned long long *)c->opt_off.ptr, nlist, st));
+        unsigned long long n_seg = 0;
+        HIP_TRY(hipMemcpyAsync(&n_seg, (unsigned long long *)c->opt_off.ptr + nlist, 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if ((rc = ensure(c, c->opt_seg, (size_t)std::max(n_seg, 1ull) * sizeof(OptSeg), 0))) return rc;
+        O.seg = (const OptSeg *)c->opt_seg.ptr;
+        HIP_TRY(opt_build_emit(O, (const unsigned long long *)c->opt_off.ptr, (unsigned *)c->opt_cnt.ptr,
+                               (OptSeg *)c->opt_seg.ptr, n_seg, st));
+        memcpy(c->opt_dims, dims, sizeof dims);
+        c->opt_rp_host.swap(rp);
+        c->opt_col_src = dev ? (const void *)col : nullptr;
+        c->opt_val_src = dev ? (const void *)val : nullptr;
+        c->opt_valid = true;
+    }
+    O.seg = (const OptSeg *)c->opt_seg.ptr;
+    HIP_TRY(hipMemcpyAsync(O.x, x, (size_t)n_spots * 8, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    double *hist = (double *)c->opt_hist.ptr;
+    HIP_TRY(opt_update(O, kOptPowerInit, 0.0, 0, hist, st));
+    for (int k = 0; k < p->n_power; ++k) {
+        HIP_TRY(opt_forward(O, O.z, 1, nullptr, st));
+        HIP_TRY(opt_gradient(O, st));
+        HIP_TRY(opt_update(O, kOptPower, 0.0, 0, hist, st));
+    }
+    HIP_TRY(opt_update(O, kOptFistaInit, 0.0, 0, hist, st));
+    double t = 1.0;
+    for (int it = 0; it < p->iters; ++it) {
+        HIP_TRY(opt_forward(O, O.y, 0, nullptr, st));
+        HIP_TRY(opt_gradient(O, st));
+        const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+        HIP_TRY(opt_update(O, kOptFista, (t - 1.0) / tn, it, hist, st));
+        t = tn;
+    }
+    HIP_TRY(opt_update(O, kOptFinalPrep, 0.0, 0, hist, st));
+    float *dose_dev = nullptr;
+    if (dose_gy) {
+        if (dev) {
+            dose_dev = dose_gy;
+        } else {
+            if ((rc = ensure(c, c->opt_dose, (size_t)n_scen * nvox * 4, 0))) return rc;
+            dose_dev = (float *)c->opt_dose.ptr;
+        }
+    }
+    HIP_TRY(opt_forward(O, O.x, 2, dose_dev, st));
+    HIP_TRY(opt_update(O, kOptFinal, 0.0, p->iters, hist, st));
+    const hipMemcpyKind out_kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIP_TRY(hipMemcpyAsync(x, O.x, (size_t)n_spots * 8, out_kind, st));
+    if (obj_hist) HIP_TRY(hipMemcpyAsync(obj_hist, hist, ((size_t)p->iters + 1) * 8, out_kind, st));
+    if (dose_gy && !dev)
+        HIP_TRY(hipMemcpyAsync(dose_gy, dose_dev, (size_t)n_scen * nvox * 4, hipMemcpyDeviceToHost, st));
+    double L = 0.0;
+    HIP_TRY(hipMemcpyAsync(&L, O.scal + kOptL, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (step_L) *step_L = L;
+    return VPMC_OK;
+}

@@ -436,3 +436,65 @@ def surrogate_training_entries(n: int, seed: int = 0, polygon: Optional[np.ndarr
     ang = rng.normal(0.0, 0.02, size=(n, 2))
     e = rng.uniform(71.0, 229.0, size=n)
     return xy, ang, e
+
+
+@dataclasses.dataclass
+class OptProblem:
+    """Influence matrices in CSR (rows (scenario, spot), ascending voxel
+    columns, FP32 Gy per unit weight) with target / organ masks, as the
+    spot-weight optimiser consumes them."""
+    shape: tuple            # (nx, ny, nz), x fastest
+    n_scen: int
+    n_spots: int
+    row_ptr: np.ndarray     # int64 [n_scen * n_spots + 1]
+    col: np.ndarray         # int32
+    val: np.ndarray         # float32
+    roi: np.ndarray         # uint8 [nvox]: bit 0 target, bit 1 organ at risk
+
+    @property
+    def nvox(self) -> int:
+        return int(np.prod(self.shape))
+
+
+def opt_problem(seed: int = 0, shape=(40, 36, 20), n_spots: int = 48, n_scen: int = 3,
+                empty_rows: int = 2) -> OptProblem:
+    """Pencil-beam-like synthetic matrices: each spot covers the voxels of a
+    lateral square (half width 2-5 voxels) around its axis along +x, from the
+    entrance to a random depth; values fall off laterally and rise towards the
+    end of the range; each scenario moves the spot axes by up to 1 voxel.  A
+    few rows are empty.  The target is a box in the middle of the grid, the
+    organ at risk a slab beside it (a few voxels in both)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    jc = rng.uniform(ny * 0.3, ny * 0.7, n_spots)
+    kc = rng.uniform(nz * 0.3, nz * 0.7, n_spots)
+    hw = rng.integers(2, 6, n_spots)
+    depth = rng.integers(nx // 3, nx, n_spots)
+    empty = set(rng.choice(n_spots, size=min(empty_rows, n_spots), replace=False).tolist())
+    rows_col, rows_val = [], []
+    for s in range(n_scen):
+        dj, dk = rng.uniform(-1.0, 1.0, 2) if s else (0.0, 0.0)
+        for j in range(n_spots):
+            if j in empty:
+                rows_col.append(np.zeros(0, np.int32))
+                rows_val.append(np.zeros(0, np.float32))
+                continue
+            c0, c1 = jc[j] + dj, kc[j] + dk
+            js = np.arange(max(0, int(c0) - hw[j]), min(ny, int(c0) + hw[j] + 1))
+            ks = np.arange(max(0, int(c1) - hw[j]), min(nz, int(c1) + hw[j] + 1))
+            i = np.arange(0, depth[j])
+            K, J, I = np.meshgrid(ks, js, i, indexing="ij")
+            lat = np.exp(-((J - c0) ** 2 + (K - c1) ** 2) / (2.0 * (0.5 * hw[j]) ** 2))
+            dep = 0.3 + 0.7 * (I / max(1, depth[j] - 1)) ** 4
+            v = 1e-3 * lat * dep * rng.uniform(0.9, 1.1, I.shape)
+            idx = (K * ny + J) * nx + I
+            order = np.argsort(idx.ravel(), kind="stable")
+            rows_col.append(idx.ravel()[order].astype(np.int32))
+            rows_val.append(v.ravel()[order].astype(np.float32))
+    lens = np.array([len(c) for c in rows_col], np.int64)
+    row_ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    roi = np.zeros((nz, ny, nx), np.uint8)
+    roi[nz // 2 - 3: nz // 2 + 3, ny // 2 - 4: ny // 2 + 4, nx // 2 - 5: nx // 2 + 5] |= 1
+    roi[nz // 2 - 3: nz // 2 + 3, ny // 2 + 3: ny // 2 + 8, :] |= 2
+    return OptProblem(tuple(shape), n_scen, n_spots, row_ptr, np.concatenate(rows_col).astype(np.int32),
+                      np.concatenate(rows_val).astype(np.float32), roi.ravel())

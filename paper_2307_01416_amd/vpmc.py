@@ -30,6 +30,7 @@ DEVICE_PTRS = 1
 GRAPH = 2
 SURROGATE = 4
 LET = 8
+OPT_REUSE = 16
 NLEDGER = 6
 
 
@@ -68,6 +69,12 @@ class vpmc_opts(C.Structure):
                 ("hip_stream", C.c_void_p), ("max_device_bytes", C.c_size_t),
                 ("block_threads", C.c_int), ("grid_blocks", C.c_int), ("hist_per_lane", C.c_int),
                 ("max_slots", C.c_int)]
+
+
+class vpmc_opt_params(C.Structure):
+    _fields_ = [("d_presc", C.c_double), ("w_target", C.c_double), ("d_max", C.c_double),
+                ("w_oar", C.c_double), ("iters", C.c_int), ("n_power", C.c_int), ("row_stride", C.c_int),
+                ("row_offset", C.c_int), ("flags", C.c_uint), ("hip_stream", C.c_void_p)]
 
 
 class vpmc_stats(C.Structure):
@@ -112,6 +119,7 @@ def load() -> C.CDLL:
         "vpmc_surrogate_loss_grad": (i, [vp, vp, vp, vp, i, vp, C.POINTER(C.c_double)]),
         "vpmc_surrogate_train": (i, [vp, vp, vp, vp, i, i, i, C.c_float, C.c_uint64, vp]),
         "vpmc_atomic_rate": (i, [vp, i, i, i, C.c_uint64, f64p]),
+        "vpmc_optimize": (i, [vp, vp, vp, vp, i, i, i, vp, vp, vp, vp, f64p, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -290,6 +298,24 @@ def vpmc_last_tally(ctx, scen_index: int, q_out=None, flags: int = 0) -> int:
     k = C.c_int(0)
     _check(load().vpmc_last_tally(ctx, scen_index, _ptr(q_out), C.byref(k), flags), ctx)
     return k.value
+
+
+def vpmc_optimize(ctx, row_ptr, col, val, n_scen: int, n_spots: int, nvox: int, roi, x, *, d_presc: float,
+                  w_target: float, d_max: float, w_oar: float, iters: int, n_power: int = 20,
+                  row_stride: int = 0, row_offset: int = 0, flags: int = 0, stream=None, obj_hist=None,
+                  dose=None) -> float:
+    """Spot weights by projected FISTA on the scenario influence matrices; x
+    (FP64, n_spots) holds the start and receives the result, obj_hist
+    (iters + 1) and dose (n_scen x nvox FP32) are optional outputs.  Arrays
+    are numpy (host) or torch CUDA tensors with flags |= DEVICE_PTRS.
+    Returns the step constant L."""
+    p = vpmc_opt_params(d_presc=float(d_presc), w_target=float(w_target), d_max=float(d_max),
+                        w_oar=float(w_oar), iters=int(iters), n_power=int(n_power), row_stride=int(row_stride),
+                        row_offset=int(row_offset), flags=int(flags), hip_stream=stream)
+    L = C.c_double(0.0)
+    _check(load().vpmc_optimize(ctx, _ptr(row_ptr), _ptr(col), _ptr(val), int(n_scen), int(n_spots), int(nvox),
+                                _ptr(roi), C.byref(p), _ptr(x), _ptr(obj_hist), C.byref(L), _ptr(dose)), ctx)
+    return L.value
 
 
 def vpmc_last_stats(ctx) -> dict:

@@ -143,3 +143,37 @@ def test_let_validation(vctx):
     opts = V.make_opts(output=V.OUT_CSR, flags=V.LET)
     rp = np.zeros(2, np.int64)
     assert _rc(V.vpmc_run_spots, vctx, 0, spots, 1, scen, 1, opts, None, None, None, rp) in (V.E_ARG, V.E_STATE)
+
+
+def test_optimize_validation(vctx):
+    from paper_2307_01416_amd import inputs as I
+    P = I.opt_problem(seed=1, shape=(12, 10, 8), n_spots=6, n_scen=2)
+    kw = dict(d_presc=1.0, w_target=1.0, d_max=0.5, w_oar=1.0, iters=3)
+
+    def call(rp=P.row_ptr, col=P.col, val=P.val, n_scen=2, n_spots=6, nvox=P.nvox, **over):
+        args = dict(kw)
+        args.update(over)
+        try:
+            V.vpmc_optimize(vctx, rp, col, val, n_scen, n_spots, nvox, P.roi, np.zeros(n_spots), **args)
+        except V.VpmcError as e:
+            return e.code
+        return 0
+
+    assert call(n_scen=0) == V.E_ARG
+    assert call(nvox=0) == V.E_ARG
+    assert call(iters=-1) == V.E_ARG
+    assert call(n_power=0) == V.E_ARG
+    assert call(w_oar=-1.0) == V.E_ARG
+    assert call(d_presc=float("nan")) == V.E_ARG
+    assert call(flags=64) == V.E_ARG
+    assert call(row_stride=6, row_offset=1) == V.E_ARG          # offset + n_spots > stride
+    bad = P.row_ptr.copy()
+    bad[3] = bad[2] - 1
+    assert call(rp=bad) == V.E_ARG                              # decreasing row pointer
+    col = P.col.copy()
+    col[5] = P.nvox
+    assert call(col=col) == V.E_ARG                             # column out of range
+    val = P.val.copy()
+    val[7] = np.inf
+    assert call(val=val) == V.E_ARG                             # value not finite
+    assert call() == V.E_STATE                                  # well-formed: reaches the device step

@@ -1,0 +1,163 @@
+"""Spot-weight optimiser (NEXT-1: robust optimisation on the scenario
+influence matrices, Methods E) on the GPU against the FP64 oracle, through
+the C ABI, on seeded synthetic pencil-beam-like matrices (several 4096-voxel
+chunks with a ragged last chunk, empty rows, 3 and 13 scenarios).
+
+Tolerance: the dose sweep is exact to 2^-60 of its bound (int64 fixed point),
+but the residual handed to the gradient sweep is FP32 (relative 2^-24 per
+voxel), so each gradient carries a relative error of order 1e-7 of
+sum |a r|; FISTA's momentum carries such errors forward over the iterations.
+The objective history and the weights are compared at 1e-5 relative (weights
+to 1e-5 of the largest weight), the step constant at 1e-6.  Integer-exact
+properties (reruns, the index reused, a field's rows addressed inside the
+whole layout, host against device pointers) are compared bit for bit."""
+import numpy as np
+import pytest
+
+from oracle import optimize as OO
+from paper_2307_01416_amd import inputs as I
+from test_gpu_parity import say
+
+pytestmark = pytest.mark.gpu
+
+PAR = dict(d_presc=2.0, w_target=1.0, d_max=0.8, w_oar=4.0)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2307_01416_amd import vpmc as V
+    c = V.vpmc_create(0)
+    yield c
+    V.vpmc_destroy(c)
+
+
+def x_start(P):
+    return np.full(P.n_spots, 50.0)
+
+
+def gpu(ctx, P, x0, iters, n_power=30, flags=0, dose=False, n_spots=None, row_stride=0, row_offset=0,
+        rp=None, col=None, val=None, **par):
+    from paper_2307_01416_amd import vpmc as V
+    n = P.n_spots if n_spots is None else n_spots
+    x = np.array(x0, np.float64)
+    hist = np.zeros(iters + 1)
+    d = np.zeros((P.n_scen, P.nvox), np.float32) if dose else None
+    kw = dict(PAR)
+    kw.update(par)
+    L = V.vpmc_optimize(ctx, P.row_ptr if rp is None else rp, P.col if col is None else col,
+                        P.val if val is None else val, P.n_scen, n, P.nvox, P.roi, x, iters=iters, n_power=n_power,
+                        row_stride=row_stride, row_offset=row_offset, flags=flags, obj_hist=hist, dose=d, **kw)
+    return x, hist, L, d
+
+
+def orc(P, x0, iters, n_power=30, **par):
+    kw = dict(PAR)
+    kw.update(par)
+    A = OO.matrices_from_csr(P.row_ptr, P.col, P.val, P.n_scen, P.n_spots, P.nvox)
+    tm, om = (P.roi & 1) > 0, (P.roi & 2) > 0
+    x, hist, L = OO.fista(A, x0, tm, om, kw["d_presc"], kw["w_target"], kw["d_max"], kw["w_oar"], iters, n_power)
+    return x, hist, L, A
+
+
+def check(xg, hg, Lg, xo, ho, Lo):
+    assert Lg == pytest.approx(Lo, rel=1e-6)
+    np.testing.assert_allclose(hg, ho, rtol=1e-5)
+    np.testing.assert_allclose(xg, xo, rtol=0, atol=1e-5 * np.abs(xo).max())
+
+
+def test_parity_small(ctx):
+    P = I.opt_problem(seed=0)
+    say(f"optimiser parity: nvox {P.nvox}, nnz {P.row_ptr[-1]}, rows {P.n_scen}x{P.n_spots}")
+    assert P.nvox % 4096 and P.nvox > 4 * 4096   # several chunks and a ragged last one
+    x0 = x_start(P)
+    xg, hg, Lg, dg = gpu(ctx, P, x0, 150, dose=True)
+    xo, ho, Lo, A = orc(P, x0, 150)
+    check(xg, hg, Lg, xo, ho, Lo)
+    assert ho[-1] < 0.2 * ho[0]          # the optimisation did something
+    for s in range(P.n_scen):
+        do = A[s].T @ xo
+        np.testing.assert_allclose(dg[s], do, rtol=0, atol=1e-5 * do.max())
+
+
+def test_reruns_reuse_and_host_device_identical(ctx):
+    import torch
+    from paper_2307_01416_amd import vpmc as V
+    P = I.opt_problem(seed=1, n_scen=2)
+    x0 = x_start(P)
+    a = gpu(ctx, P, x0, 40)
+    b = gpu(ctx, P, x0, 40)
+    c = gpu(ctx, P, x0, 40, flags=V.OPT_REUSE)
+    for r in (b, c):
+        assert np.array_equal(a[0], r[0]) and np.array_equal(a[1], r[1]) and a[2] == r[2]
+    # trial-and-error: new objective parameters on the reused index
+    d = gpu(ctx, P, x0, 40, flags=V.OPT_REUSE, d_max=0.5)
+    e = gpu(ctx, P, x0, 40, d_max=0.5)
+    assert np.array_equal(d[0], e[0]) and np.array_equal(d[1], e[1])
+    # device pointers
+    dev = torch.device("cuda", 0)
+    t = lambda arr: torch.from_numpy(arr).to(dev)
+    xd = t(np.array(x0))
+    hd = torch.zeros(41, dtype=torch.float64, device=dev)
+    Ld = V.vpmc_optimize(ctx, t(P.row_ptr), t(P.col), t(P.val), P.n_scen, P.n_spots, P.nvox, t(P.roi), xd,
+                         iters=40, n_power=30, flags=V.DEVICE_PTRS, obj_hist=hd, **PAR)
+    assert np.array_equal(xd.cpu().numpy(), a[0]) and np.array_equal(hd.cpu().numpy(), a[1]) and Ld == a[2]
+    # the index of another problem does not match
+    Q = I.opt_problem(seed=2, n_scen=2)
+    with pytest.raises(V.VpmcError) as ex:
+        gpu(ctx, Q, x_start(Q), 5, flags=V.OPT_REUSE)
+    assert ex.value.code == V.E_STATE
+
+
+def test_field_rows_inside_the_whole_layout(ctx):
+    """Spots 5..11 of 12 (one field) addressed with row_stride/row_offset give
+    the same bits as the extracted sub-matrix."""
+    P = I.opt_problem(seed=3, n_spots=12, n_scen=3)
+    off, n = 5, 7
+    rows = [s * 12 + off + j for s in range(3) for j in range(n)]
+    lens = np.diff(P.row_ptr)[rows]
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = np.concatenate([P.col[P.row_ptr[r]:P.row_ptr[r + 1]] for r in rows]).astype(np.int32)
+    val = np.concatenate([P.val[P.row_ptr[r]:P.row_ptr[r + 1]] for r in rows]).astype(np.float32)
+    x0 = np.full(n, 30.0)
+    a = gpu(ctx, P, x0, 30, n_spots=n, row_stride=12, row_offset=off)
+    b = gpu(ctx, P, x0, 30, n_spots=n, rp=rp, col=col, val=val)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+
+
+def test_degenerate_cases(ctx):
+    from paper_2307_01416_amd import vpmc as V
+    P = I.opt_problem(seed=5, shape=(20, 16, 12), n_spots=8, n_scen=2)
+    # no entries at all: L = 0, the start is only projected, F constant
+    E = I.OptProblem(P.shape, 2, 8, np.zeros(17, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32), P.roi)
+    x0 = np.linspace(-3.0, 3.0, 8)
+    xg, hg, Lg, _ = gpu(ctx, E, x0, 4)
+    xo, ho, Lo, _ = orc(E, x0, 4)
+    assert Lg == 0.0 and Lo == 0.0
+    assert np.array_equal(xg, np.maximum(x0, 0.0)) and np.array_equal(xo, xg)
+    np.testing.assert_allclose(hg, ho, rtol=1e-12)
+    # no iterations: the objective at the projected start
+    xg, hg, Lg, _ = gpu(ctx, P, x0, 0)
+    xo, ho, Lo, _ = orc(P, x0, 0)
+    assert hg.shape == (1,) and np.array_equal(xg, np.maximum(x0, 0.0))
+    np.testing.assert_allclose(hg, ho, rtol=1e-6)
+    # a device column out of range is caught by the index pass
+    import torch
+    dev = torch.device("cuda", 0)
+    col = P.col.copy()
+    col[len(col) // 2] = P.nvox + 7
+    t = lambda arr: torch.from_numpy(arr).to(dev)
+    with pytest.raises(V.VpmcError) as ex:
+        V.vpmc_optimize(ctx, t(P.row_ptr), t(col), t(P.val), 2, 8, P.nvox, t(P.roi),
+                        torch.zeros(8, dtype=torch.float64, device=dev), iters=2, flags=V.DEVICE_PTRS, **PAR)
+    assert ex.value.code == V.E_ARG
+
+
+def test_parity_13_scenarios_many_chunks(ctx):
+    P = I.opt_problem(seed=7, shape=(128, 96, 48), n_spots=240, n_scen=13)
+    say(f"optimiser parity: nvox {P.nvox}, nnz {P.row_ptr[-1]}, rows {P.n_scen}x{P.n_spots}")
+    x0 = x_start(P)
+    xg, hg, Lg, _ = gpu(ctx, P, x0, 60, n_power=20)
+    xo, ho, Lo, _ = orc(P, x0, 60, n_power=20)
+    check(xg, hg, Lg, xo, ho, Lo)

@@ -55,6 +55,30 @@ def test_fista_reaches_the_nnls_optimum():
     x_star, _ = nnls(M, b)
     F_star = np.sum((M @ x_star - b) ** 2) / len(A)
     x, hist, L = O.fista(A, np.ones(A[0].shape[0]), tm, om, dp, 1.0, 0.0, 0.0, iters=3000)
+    assert hist[-1] == pytest.approx(O.objective_grad(A, x, tm, om, dp, 1.0, 0.0, 0.0)[0], rel=1e-15)
     F_end = O.objective_grad(A, x, tm, om, dp, 1.0, 0.0, 0.0)[0]
     assert F_end == pytest.approx(F_star, rel=1e-6)
     assert np.allclose(x, x_star, rtol=1e-3, atol=1e-3 * x_star.max())
+
+
+def test_no_curvature_leaves_the_projected_start():
+    """Empty structures: the eigenvalue is 0 and every step only projects."""
+    A, _, _ = _problem(seed=2)
+    n = A[0].shape[0]
+    z = np.zeros(A[0].shape[1], bool)
+    x0 = np.linspace(-1.0, 1.0, n)
+    x, hist, L = O.fista(A, x0, z, z, 1.0, 1.0, 0.5, 1.0, iters=5)
+    assert L == 0.0
+    assert np.array_equal(x, np.maximum(x0, 0.0))
+    assert np.all(hist == 0.0)
+
+
+def test_matrices_from_csr_layout():
+    """A field's rows inside the (scenario, field, spot) layout."""
+    from paper_2307_01416_amd import inputs as I
+    P = I.opt_problem(seed=4, n_spots=10, n_scen=2)
+    # the 10 spots as two fields of 4 and 6: field 1 = offset 4, stride 10
+    A = O.matrices_from_csr(P.row_ptr, P.col, P.val, 2, 6, P.nvox, row_stride=10, row_offset=4)
+    full = O.matrices_from_csr(P.row_ptr, P.col, P.val, 2, 10, P.nvox)
+    for s in range(2):
+        assert (A[s] != full[s][4:]).nnz == 0
