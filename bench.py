@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 ALG_OPS_PER_STEP = 255.0
 # gfx950: 256 CUs x 64 FP32 lanes per clock x 2.4 GHz, single-issue VALU
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
+HBM_PEAK = 8.0e12   # MI355X HBM3E, bytes/s
 TARGET_U = 0.005
 
 
@@ -75,6 +76,8 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate comparison")
     ap.add_argument("--sur-samples", type=int, default=3_000_000)
     ap.add_argument("--sur-epochs", type=int, default=6)
+    ap.add_argument("--no-optimize", action="store_true", help="skip the spot-weight optimiser measurement")
+    ap.add_argument("--opt-iters", type=int, default=80)
     ap.add_argument("--shape", default="", help="HPL,BLOCKS,THREADS: fixed work-queue launch shape (no autotune)")
     ap.add_argument("--oracle-suite", action="store_true",
                     help="time the oracle beside the GPU on config 1 and two config-2 cases (not the bench line)")
@@ -179,6 +182,70 @@ def surrogate_comparison(eng, case, I, V, np, a, shape, plain_s, plain_steps):
             "plan_dose_3sigma_fraction": frac, "plan_dose_gamma_1pct_1mm": rate,
             "plan_dose_gamma_plain_vs_plain": floor, "plan_dose_mean_ratio": ratio, "plan_dose_histories_x": 4,
             "steps_ratio": st["steps"] / max(1, plain_steps)}
+
+
+def optimizer_measure(eng, case, I, V, np, torch, a, shape):
+    """Robust spot-weight optimisation on the head case's 13-scenario
+    influence matrices (device CSR): index build, then the time per FISTA
+    iteration from two calls on the reused index (difference of
+    a.opt_iters and a.opt_iters // 4 iterations), HBM-bound roofline of an
+    iteration (the entries in structure voxels read twice, the structure
+    voxels' residual written and read once and their mask read once per
+    scenario)."""
+    rp, col, val, _, _ = eng.run_csr(case, device_out=True, **shape)
+    dev = col.device
+    n_scen = len(case.scenarios)
+    n_spots = sum(len(fl.spots) for fl in case.fields)
+    nvox = case.geometry.nvox
+    nnz = int(col.numel())
+    roi = torch.from_numpy(I.head_structures(case, a.target_cc)).to(dev)
+    par = dict(d_presc=2.0, w_target=1.0, d_max=1.0, w_oar=1.0)
+    x = torch.ones(n_spots, dtype=torch.float64, device=dev)
+    dose = torch.empty((n_scen, nvox), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    V.vpmc_optimize(eng.ctx, rp, col, val, n_scen, n_spots, nvox, roi, x, iters=0, n_power=1,
+                    flags=V.DEVICE_PTRS, stream=eng.stream_ptr(), dose=dose, **par)
+    t_first = time.perf_counter() - t0
+    tmask = (roi & 1) > 0
+    scale = par["d_presc"] / float(dose[:, tmask].mean())
+    runs = {}
+    for iters in (a.opt_iters // 4, a.opt_iters):
+        x = torch.full((n_spots,), scale, dtype=torch.float64, device=dev)
+        hist = torch.zeros(iters + 1, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = V.vpmc_optimize(eng.ctx, rp, col, val, n_scen, n_spots, nvox, roi, x, iters=iters, n_power=20,
+                            flags=V.DEVICE_PTRS | V.OPT_REUSE, stream=eng.stream_ptr(), obj_hist=hist,
+                            dose=dose, **par)
+        runs[iters] = (time.perf_counter() - t0, hist.cpu().numpy(), L)
+        progress(f"optimiser: {iters} iterations in {runs[iters][0]:.3f} s")
+    i1, i2 = a.opt_iters // 4, a.opt_iters
+    t_it = (runs[i2][0] - runs[i1][0]) / (i2 - i1)
+    hist = runs[i2][1]
+    dt = dose[:, tmask]
+    do = dose[:, (roi & 2) > 0]
+    # entries in structure voxels (the iterations' working set) and the
+    # structure voxels: each entry is read twice per iteration (dose and
+    # gradient sweeps), each structure voxel's residual written and read once
+    # per scenario, its mask byte read once per scenario
+    n_roi_entries = int(sum(int((roi[col[i:i + (1 << 28)].long()] != 0).sum())
+                            for i in range(0, nnz, 1 << 28)))
+    n_roi_vox = int((roi != 0).sum())
+    alg = 16.0 * n_roi_entries + n_scen * n_roi_vox * (4.0 + 4.0 + 1.0)
+    del rp, col, val
+    return {"what": "robust spot-weight optimisation (projected FISTA, 13 scenarios, target + organ-at-risk "
+                    "quadratic penalties) on the device-resident influence matrices",
+            "n_spots": n_spots, "nnz": nnz, "structure_entries": n_roi_entries, "structure_voxels": n_roi_vox,
+            "index_build_and_first_call_s": t_first,
+            "iters": i2, "s_total": runs[i2][0], "ms_per_iteration": 1e3 * t_it, "step_L": runs[i2][2],
+            "objective_first": float(hist[0]), "objective_final": float(hist[-1]),
+            "target_mean_dose_gy_per_scenario_min_max": [float(dt.mean(1).min()), float(dt.mean(1).max())],
+            "oar_max_dose_gy_worst_scenario": float(do.max()),
+            "roofline": {"bound": "hbm", "achieved": alg / t_it / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                         "frac": alg / t_it / HBM_PEAK, "traffic": None,
+                         "kernel": "opt_forward_kernel + opt_grad_kernel (one iteration)",
+                         "alg_bytes_per_iteration": alg}}
 
 
 def cpu_baseline(case, seconds, np):
@@ -386,6 +453,8 @@ def main():
     if not a.no_surrogate:
         out["surrogate"] = surrogate_comparison(eng, case, I, V, np, a, shape, dt / a.steps,
                                                 steps_total / a.steps)
+    if not a.no_optimize:
+        out["optimizer"] = optimizer_measure(eng, case, I, V, np, torch, a, shape)
     if not a.no_cpu_baseline:
         progress("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(case, a.cpu_seconds, np)

@@ -320,8 +320,11 @@ int vpmc_atomic_rate(vpmc_ctx *ctx, int nx, int ny, int nz, uint64_t n_atomics, 
  * on O) from n_power power iterations started at the all-ones vector; if
  * that eigenvalue is 0 the step is the projection alone.  Each dose sweep
  * sums in int64 fixed point and each gradient in FP64 in a fixed order, so
- * reruns give identical bits.  Every iteration reads the CSR twice
- * (HBM-bound sparse products).
+ * reruns give identical bits.  The objective and its gradient involve only
+ * voxels with a structure bit, so the iterations use only the rows' entries
+ * in those voxels (restricted once per index build) and read each of them
+ * twice (a copy bucketed by voxel chunk for the dose, a compacted CSR for the
+ * gradient): HBM-bound.  The optional dose output sweeps the whole rows.
  * ------------------------------------------------------------------------- */
 #define VPMC_OPT_REUSE 16u  /* keep the segment index of the previous call: row_ptr, col and val
                                must be unchanged (same dims, same row_ptr contents checked) */
@@ -346,9 +349,11 @@ typedef struct {
  * weights out (FP64), obj_hist [iters + 1] (optional) F at each FISTA
  * extrapolation point y_0 .. y_{iters-1} then F at the final x, step_L
  * (optional, always host) the L used, dose_gy [n_scen][nvox] (optional) D_s at
- * the final x.  Pointer kind of every array per p->flags.  Scratch: about
- * 4 B x n_scen x nvox + 16 B per segment (a row's run inside one 4096-voxel
- * chunk) + 40 B per spot and scenario, kept for VPMC_OPT_REUSE.  Errors:
+ * the final x.  Pointer kind of every array per p->flags.  n_spots <= 2^20.
+ * Scratch, kept for VPMC_OPT_REUSE: 16 B per entry in a structure voxel,
+ * with dose_gy also 8 B per entry of the used rows (a bucketed copy of the
+ * whole rows), plus about 4 B x n_scen x nvox and 32 B per spot and scenario.
+ * VPMC_OPT_REUSE also requires identical structure masks (checked).  Errors:
  * VPMC_E_ARG (dims, parameters, flags, row_ptr decreasing, a column out of
  * range or a value not finite), VPMC_E_STATE (validation-only context;
  * VPMC_OPT_REUSE without a matching index), VPMC_E_OOM, VPMC_E_DEVICE. */

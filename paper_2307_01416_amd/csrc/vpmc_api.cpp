@@ -136,12 +136,20 @@ struct vpmc_ctx {
     int mlp_step = 0;
     int mlp_batch_cap = 0;
     DevBuf sur_rec, sur_cnt, sur_out;
-    // spot-weight optimiser: segment index (kept for VPMC_OPT_REUSE) and work buffers
-    DevBuf opt_rp, opt_col, opt_val, opt_roi, opt_amax, opt_cnt, opt_off, opt_seg, opt_resid, opt_fpart,
-        opt_gpart, opt_vec, opt_scal, opt_err, opt_hist, opt_dose;
+    // spot-weight optimiser: structure-restricted rows, bucketed copies and
+    // gradient pieces (kept for VPMC_OPT_REUSE), work buffers
+    struct OptBuckets {
+        DevBuf off, key, val, work;
+        long long n_work = 0;
+        bool valid = false;
+    } opt_broi, opt_bfull;
+    DevBuf opt_rp, opt_col, opt_val, opt_roi, opt_amax, opt_cnt, opt_rcnt, opt_crp, opt_ccol, opt_cval, opt_piece,
+        opt_poff, opt_resid, opt_fpart, opt_gpart, opt_vec, opt_scal, opt_err, opt_hist, opt_dose;
+    long long opt_npieces = 0;
     bool opt_valid = false;
     int opt_dims[5] = {0, 0, 0, 0, 0};   // n_scen, n_spots, row_stride, row_offset, nvox
     std::vector<int64_t> opt_rp_host;
+    std::vector<uint8_t> opt_roi_host;
     const void *opt_col_src = nullptr, *opt_val_src = nullptr;
     float sur_dfb = 3.0f, sur_plo = 0.02f, sur_phi = 0.98f;
 };
@@ -1032,8 +1040,11 @@ void vpmc_destroy(vpmc_ctx *c) {
                           &c->csr_q, &c->mlp_w, &c->mlp_wb, &c->mlp_m, &c->mlp_v, &c->mlp_g, &c->mlp_act,
                           &c->mlp_io, &c->mlp_dx, &c->mlp_dy, &c->mlp_dt, &c->mlp_idx, &c->sur_rec,
                           &c->sur_cnt, &c->sur_out, &c->opt_rp, &c->opt_col, &c->opt_val, &c->opt_roi, &c->opt_amax,
-                          &c->opt_cnt, &c->opt_off, &c->opt_seg, &c->opt_resid, &c->opt_fpart, &c->opt_gpart,
-                          &c->opt_vec, &c->opt_scal, &c->opt_err, &c->opt_hist, &c->opt_dose})
+                          &c->opt_cnt, &c->opt_rcnt, &c->opt_crp, &c->opt_ccol, &c->opt_cval, &c->opt_piece,
+                          &c->opt_poff, &c->opt_resid, &c->opt_fpart, &c->opt_gpart, &c->opt_vec, &c->opt_scal,
+                          &c->opt_err, &c->opt_hist, &c->opt_dose, &c->opt_broi.off, &c->opt_broi.key,
+                          &c->opt_broi.val, &c->opt_broi.work, &c->opt_bfull.off, &c->opt_bfull.key,
+                          &c->opt_bfull.val, &c->opt_bfull.work})
             release(*b);
         for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -1625,6 +1636,7 @@ int vpmc_optimize(vpmc_ctx *c, const int64_t *row_ptr, const int32_t *col, const
     const long long n_layout = (long long)n_scen * stride;
     const long long n_rows = (long long)n_scen * n_spots;
     if (n_layout >= (1ll << 31) || n_rows * 64 >= (1ll << 31)) return fail(VPMC_E_ARG, "too many rows");
+    if (n_spots > (1 << 20)) return fail(VPMC_E_ARG, "n_spots above 2^20");
     const bool dev = (p->flags & VPMC_DEVICE_PTRS) != 0;
     const bool reuse = (p->flags & VPMC_OPT_REUSE) != 0;
     // host copy of the row pointer for validation (host arrays are checked
@@ -1656,7 +1668,11 @@ int vpmc_optimize(vpmc_ctx *c, const int64_t *row_ptr, const int32_t *col, const
     const int dims[5] = {n_scen, n_spots, stride, p->row_offset, nvox};
     const bool same = c->opt_valid && memcmp(dims, c->opt_dims, sizeof dims) == 0 && c->opt_rp_host == rp &&
                       (!dev || (c->opt_col_src == col && c->opt_val_src == val));
-    if (reuse && !same) return fail(VPMC_E_STATE, "VPMC_OPT_REUSE without a matching segment index");
+    // structure masks on the host (chunks that hold structure voxels; reuse check)
+    std::vector<uint8_t> roi_h((size_t)nvox);
+    HIP_TRY(hipMemcpy(roi_h.data(), roi, (size_t)nvox, dev ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+    if (reuse && (!same || roi_h != c->opt_roi_host))
+        return fail(VPMC_E_STATE, "VPMC_OPT_REUSE without a matching index (rows, columns or structures changed)");
     int rc;
     // CSR on the device: the library's own row pointer (validated), caller's or copied arrays
     if ((rc = ensure(c, c->opt_rp, rp.size() * 8, 0))) return rc;
@@ -1677,68 +1693,157 @@ int vpmc_optimize(vpmc_ctx *c, const int64_t *row_ptr, const int32_t *col, const
         d_roi = (const uint8_t *)c->opt_roi.ptr;
     }
     if ((rc = ensure(c, c->opt_amax, (size_t)n_rows * 4, 0))) return rc;
-    if ((rc = ensure(c, c->opt_cnt, nlist * 4, 0))) return rc;
-    if ((rc = ensure(c, c->opt_off, (nlist + 1) * 8, 0))) return rc;
+    if ((rc = ensure(c, c->opt_cnt, nlist * 8, 0))) return rc;
+    if ((rc = ensure(c, c->opt_rcnt, (size_t)n_rows * 8, 0))) return rc;
+    if ((rc = ensure(c, c->opt_crp, ((size_t)n_rows + 1) * 8, 0))) return rc;
+    if ((rc = ensure(c, c->opt_poff, ((size_t)n_rows + 1) * 8, 0))) return rc;
     if ((rc = ensure(c, c->opt_resid, (size_t)n_scen * nvox * 4, 0))) return rc;
     if ((rc = ensure(c, c->opt_fpart, nlist * 8, 0))) return rc;
-    if ((rc = ensure(c, c->opt_gpart, (size_t)n_rows * 8, 0))) return rc;
     if ((rc = ensure(c, c->opt_vec, (size_t)n_spots * 4 * 8, 0))) return rc;
     if ((rc = ensure(c, c->opt_scal, ((size_t)2 * n_scen + 2) * 8, 0))) return rc;
     if ((rc = ensure(c, c->opt_err, 4, 0))) return rc;
     if ((rc = ensure(c, c->opt_hist, ((size_t)p->iters + 1) * 8, 0))) return rc;
-    OptDev O{};
-    O.row_ptr = (const long long *)c->opt_rp.ptr;
-    O.col = d_col;
-    O.val = d_val;
-    O.roi = d_roi;
-    O.n_scen = n_scen;
-    O.n_spots = n_spots;
-    O.row_stride = stride;
-    O.row_offset = p->row_offset;
-    O.nvox = nvox;
-    O.nchunks = nchunks;
-    O.d_presc = p->d_presc;
-    O.w_target = p->w_target;
-    O.d_max = p->d_max;
-    O.w_oar = p->w_oar;
-    O.amax = (float *)c->opt_amax.ptr;
-    O.resid = (float *)c->opt_resid.ptr;
-    O.fpart = (double *)c->opt_fpart.ptr;
-    O.gpart = (double *)c->opt_gpart.ptr;
+    // the whole layout (validation, bound of every row, dose output) ...
+    OptDev F{};
+    F.row_ptr = (const long long *)c->opt_rp.ptr;
+    F.col = d_col;
+    F.val = d_val;
+    F.roi = d_roi;
+    F.n_scen = n_scen;
+    F.n_spots = n_spots;
+    F.row_stride = stride;
+    F.row_offset = p->row_offset;
+    F.nvox = nvox;
+    F.nchunks = nchunks;
+    F.d_presc = p->d_presc;
+    F.w_target = p->w_target;
+    F.d_max = p->d_max;
+    F.w_oar = p->w_oar;
+    F.amax = (float *)c->opt_amax.ptr;
+    F.resid = (float *)c->opt_resid.ptr;
+    F.fpart = (double *)c->opt_fpart.ptr;
     double *vec = (double *)c->opt_vec.ptr;
-    O.x = vec;
-    O.y = vec + n_spots;
-    O.z = vec + 2 * (size_t)n_spots;
-    O.gvec = vec + 3 * (size_t)n_spots;
-    O.scale = (double *)c->opt_scal.ptr;
-    O.scal = O.scale + 2 * (size_t)n_scen;
-    O.seg_off = (const unsigned long long *)c->opt_off.ptr;
+    F.x = vec;
+    F.y = vec + n_spots;
+    F.z = vec + 2 * (size_t)n_spots;
+    F.gvec = vec + 3 * (size_t)n_spots;
+    F.scale = (double *)c->opt_scal.ptr;
+    F.scal = F.scale + 2 * (size_t)n_scen;
+    F.piece_off = (const long long *)c->opt_poff.ptr;
+    // ... and its rows restricted to the structure voxels (the iterations)
+    OptDev O = F;
+    O.row_ptr = (const long long *)c->opt_crp.ptr;
+    O.row_stride = n_spots;
+    O.row_offset = 0;
+    auto set_buckets = [](OptDev &D, const vpmc_ctx::OptBuckets &B) {
+        D.boff = (const unsigned long long *)B.off.ptr;
+        D.bkey = (const uint32_t *)B.key.ptr;
+        D.bval = (const float *)B.val.ptr;
+        D.work = (const uint32_t *)B.work.ptr;
+        D.n_work = B.n_work;
+    };
+    // bucketed copy of the rows of D: lists (scenario, chunk) over the chunks
+    // with keep[chunk] (all when keep is empty), heaviest first in the work list
+    auto build_buckets = [&](OptDev &D, vpmc_ctx::OptBuckets &B, const std::vector<char> &keep,
+                             long long expect) -> int {
+        B.valid = false;
+        int rc2;
+        if ((rc2 = ensure(c, B.off, (nlist + 1) * 8, 0))) return rc2;
+        if ((rc2 = ensure(c, B.work, std::max<size_t>(nlist, 1) * 4, 0))) return rc2;
+        HIP_TRY(hipMemsetAsync(c->opt_cnt.ptr, 0, nlist * 8, st));
+        HIP_TRY(hipMemsetAsync(c->opt_err.ptr, 0, 4, st));
+        HIP_TRY(opt_build_count(D, (unsigned long long *)c->opt_cnt.ptr, (unsigned *)c->opt_err.ptr, st));
+        HIP_TRY(opt_build_scan((unsigned long long *)c->opt_cnt.ptr, (unsigned long long *)B.off.ptr, nlist, st));
+        std::vector<unsigned long long> boff(nlist + 1);
+        HIP_TRY(hipMemcpyAsync(boff.data(), B.off.ptr, (nlist + 1) * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if ((long long)boff[nlist] != expect)
+            return fail(VPMC_E_DEVICE, "entry count %llu of the chunk lists differs from the rows' %lld", boff[nlist],
+                        expect);
+        std::vector<uint32_t> work;
+        for (size_t k = 0; k < nlist; ++k)
+            if (keep.empty() || keep[k % (size_t)nchunks]) work.push_back((uint32_t)k);
+        std::stable_sort(work.begin(), work.end(), [&](uint32_t a, uint32_t b) {
+            return boff[a + 1] - boff[a] > boff[b + 1] - boff[b];
+        });
+        if (!work.empty())
+            HIP_TRY(hipMemcpyAsync(B.work.ptr, work.data(), work.size() * 4, hipMemcpyHostToDevice, st));
+        if ((rc2 = ensure(c, B.key, (size_t)std::max(expect, 1ll) * 4, 0))) return rc2;
+        if ((rc2 = ensure(c, B.val, (size_t)std::max(expect, 1ll) * 4, 0))) return rc2;
+        HIP_TRY(opt_build_emit(D, B.off.ptr ? (const unsigned long long *)B.off.ptr : nullptr,
+                               (unsigned long long *)c->opt_cnt.ptr, (uint32_t *)B.key.ptr, (float *)B.val.ptr, st));
+        HIP_TRY(hipStreamSynchronize(st));   // the host vectors outlive the copies
+        B.n_work = (long long)work.size();
+        B.valid = true;
+        return VPMC_OK;
+    };
     if (!reuse) {
         c->opt_valid = false;
+        c->opt_bfull.valid = false;
         HIP_TRY(hipMemcpyAsync(c->opt_rp.ptr, rp.data(), rp.size() * 8, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemsetAsync(c->opt_cnt.ptr, 0, nlist * 4, st));
         HIP_TRY(hipMemsetAsync(c->opt_err.ptr, 0, 4, st));
-        HIP_TRY(opt_build_count(O, (unsigned *)c->opt_cnt.ptr, (unsigned *)c->opt_err.ptr, st));
+        HIP_TRY(opt_roi_count(F, (unsigned long long *)c->opt_rcnt.ptr, (unsigned *)c->opt_err.ptr, st));
+        std::vector<unsigned long long> rcnt((size_t)n_rows);
         unsigned err = 0;
+        HIP_TRY(hipMemcpyAsync(rcnt.data(), c->opt_rcnt.ptr, (size_t)n_rows * 8, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(&err, c->opt_err.ptr, 4, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if (err & 1u) return fail(VPMC_E_ARG, "a column index is outside [0, nvox)");
         if (err & 2u) return fail(VPMC_E_ARG, "a value is not finite");
-        HIP_TRY(opt_build_scan((unsigned *)c->opt_cnt.ptr, (unsigned long long *)c->opt_off.ptr, nlist, st));
-        unsigned long long n_seg = 0;
-        HIP_TRY(hipMemcpyAsync(&n_seg, (unsigned long long *)c->opt_off.ptr + nlist, 8, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        if ((rc = ensure(c, c->opt_seg, (size_t)std::max(n_seg, 1ull) * sizeof(OptSeg), 0))) return rc;
-        O.seg = (const OptSeg *)c->opt_seg.ptr;
-        HIP_TRY(opt_build_emit(O, (const unsigned long long *)c->opt_off.ptr, (unsigned *)c->opt_cnt.ptr,
-                               (OptSeg *)c->opt_seg.ptr, n_seg, st));
+        // structure-restricted CSR and its gradient pieces of at most kOptPiece entries
+        std::vector<long long> crp((size_t)n_rows + 1), poff((size_t)n_rows + 1);
+        std::vector<OptPiece> pieces;
+        crp[0] = 0;
+        for (long long r = 0; r < n_rows; ++r) {
+            crp[(size_t)r + 1] = crp[(size_t)r] + (long long)rcnt[(size_t)r];
+            poff[(size_t)r] = (long long)pieces.size();
+            for (long long q = crp[(size_t)r]; q < crp[(size_t)r + 1]; q += kOptPiece)
+                pieces.push_back(OptPiece{q, (int)std::min<long long>(kOptPiece, crp[(size_t)r + 1] - q), (int)r});
+        }
+        poff[(size_t)n_rows] = (long long)pieces.size();
+        const long long kept = crp[(size_t)n_rows];
+        if ((rc = ensure(c, c->opt_ccol, (size_t)std::max(kept, 1ll) * 4, 0))) return rc;
+        if ((rc = ensure(c, c->opt_cval, (size_t)std::max(kept, 1ll) * 4, 0))) return rc;
+        if ((rc = ensure(c, c->opt_piece, std::max<size_t>(pieces.size(), 1) * sizeof(OptPiece), 0))) return rc;
+        if ((rc = ensure(c, c->opt_gpart, std::max<size_t>(pieces.size(), 1) * 8, 0))) return rc;
+        HIP_TRY(hipMemcpyAsync(c->opt_crp.ptr, crp.data(), crp.size() * 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(c->opt_poff.ptr, poff.data(), poff.size() * 8, hipMemcpyHostToDevice, st));
+        if (!pieces.empty())
+            HIP_TRY(hipMemcpyAsync(c->opt_piece.ptr, pieces.data(), pieces.size() * sizeof(OptPiece),
+                                   hipMemcpyHostToDevice, st));
+        HIP_TRY(opt_roi_copy(F, (const long long *)c->opt_crp.ptr, (int32_t *)c->opt_ccol.ptr,
+                             (float *)c->opt_cval.ptr, st));
+        c->opt_npieces = (long long)pieces.size();
+        O.col = (const int32_t *)c->opt_ccol.ptr;
+        O.val = (const float *)c->opt_cval.ptr;
+        std::vector<char> keep((size_t)nchunks, 0);
+        for (int v = 0; v < nvox; ++v)
+            if (roi_h[(size_t)v]) keep[(size_t)(v / kOptChunk)] = 1;
+        if ((rc = build_buckets(O, c->opt_broi, keep, kept))) return rc;
         memcpy(c->opt_dims, dims, sizeof dims);
         c->opt_rp_host.swap(rp);
+        c->opt_roi_host.swap(roi_h);
         c->opt_col_src = dev ? (const void *)col : nullptr;
         c->opt_val_src = dev ? (const void *)val : nullptr;
         c->opt_valid = true;
     }
-    O.seg = (const OptSeg *)c->opt_seg.ptr;
+    O.col = (const int32_t *)c->opt_ccol.ptr;
+    O.val = (const float *)c->opt_cval.ptr;
+    O.piece = (const OptPiece *)c->opt_piece.ptr;
+    O.n_pieces = c->opt_npieces;
+    O.gpart = (double *)c->opt_gpart.ptr;
+    F.piece = O.piece;
+    F.n_pieces = O.n_pieces;
+    F.gpart = O.gpart;
+    set_buckets(O, c->opt_broi);
+    if (dose_gy && !c->opt_bfull.valid) {
+        long long used = 0;
+        for (long long r = 0; r < n_rows; ++r) {
+            const long long crow = (r / n_spots) * stride + p->row_offset + r % n_spots;
+            used += c->opt_rp_host[(size_t)crow + 1] - c->opt_rp_host[(size_t)crow];
+        }
+        if ((rc = build_buckets(F, c->opt_bfull, std::vector<char>(), used))) return rc;
+    }
     HIP_TRY(hipMemcpyAsync(O.x, x, (size_t)n_spots * 8, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
     double *hist = (double *)c->opt_hist.ptr;
     HIP_TRY(opt_update(O, kOptPowerInit, 0.0, 0, hist, st));
@@ -1766,8 +1871,15 @@ int vpmc_optimize(vpmc_ctx *c, const int64_t *row_ptr, const int32_t *col, const
             dose_dev = (float *)c->opt_dose.ptr;
         }
     }
-    HIP_TRY(opt_forward(O, O.x, 2, dose_dev, st));
-    HIP_TRY(opt_update(O, kOptFinal, 0.0, p->iters, hist, st));
+    if (dose_dev) {
+        // the dose everywhere: the whole rows (objective from the same dose)
+        set_buckets(F, c->opt_bfull);
+        HIP_TRY(opt_forward(F, F.x, 2, dose_dev, st));
+        HIP_TRY(opt_update(F, kOptFinal, 0.0, p->iters, hist, st));
+    } else {
+        HIP_TRY(opt_forward(O, O.x, 0, nullptr, st));
+        HIP_TRY(opt_update(O, kOptFinal, 0.0, p->iters, hist, st));
+    }
     const hipMemcpyKind out_kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     HIP_TRY(hipMemcpyAsync(x, O.x, (size_t)n_spots * 8, out_kind, st));
     if (obj_hist) HIP_TRY(hipMemcpyAsync(obj_hist, hist, ((size_t)p->iters + 1) * 8, out_kind, st));

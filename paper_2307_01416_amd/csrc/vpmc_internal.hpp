@@ -255,39 +255,55 @@ hipError_t launch_csr_values(const int32_t *col, const long long *qv, size_t n, 
                              double mev_scale, float *val, hipStream_t s);
 
 // ------------------------------------------------- spot-weight optimiser
-constexpr int kOptChunk = 4096;   // voxels per forward workgroup (int64 LDS sums, 32 KB)
+#ifndef VPMC_OPT_CHUNK_BITS
+#define VPMC_OPT_CHUNK_BITS 9
+#endif
+constexpr int kOptChunkBits = VPMC_OPT_CHUNK_BITS;
+constexpr int kOptChunk = 1 << kOptChunkBits;   // voxels per forward workgroup (int64 LDS sums)
 enum { kOptPowerInit = 0, kOptPower = 1, kOptFistaInit = 2, kOptFista = 3, kOptFinalPrep = 4, kOptFinal = 5 };
 enum { kOptLam = 0, kOptL = 1 };   // device scalars
 
-// a maximal run of one row's entries inside one voxel chunk
-struct OptSeg {
+constexpr int kOptPiece = 4096;   // entries per gradient wavefront
+
+// at most kOptPiece consecutive entries of one row
+struct OptPiece {
     long long begin;   // first entry (CSR index)
     int len;
-    int spot;          // j of the row (scenario s, spot j)
+    int row;           // compact row s * n_spots + j
 };
 
 struct OptDev {
     const long long *row_ptr;       // CSR row pointer, row of (s, j) = s*row_stride + row_offset + j
-    const int32_t *col;             // ascending voxel indices per row
+    const int32_t *col;             // voxel indices per row
     const float *val;               // Gy per unit spot weight
     const uint8_t *roi;             // [nvox] bit 0 target, bit 1 organ at risk
     int n_scen, n_spots, row_stride, row_offset, nvox, nchunks;
     double d_presc, w_target, d_max, w_oar;
-    const OptSeg *seg;              // segments grouped by (scenario, chunk)
-    const unsigned long long *seg_off;  // [n_scen * nchunks + 1]
+    // chunk-bucketed copy of the entries: list (s, chunk) holds entries
+    // boff[list] .. boff[list + 1], key = spot << kOptChunkBits | voxel - chunk base
+    const unsigned long long *boff; // [n_scen * nchunks + 1]
+    const uint32_t *bkey;
+    const float *bval;
+    const uint32_t *work;           // [n_work] lists to sweep, in decreasing entry count
+    long long n_work;
+    const OptPiece *piece;          // gradient pieces, row-major
+    long long n_pieces;
+    const long long *piece_off;     // [n_scen * n_spots + 1] first piece of each compact row
     float *amax;                    // [n_scen * n_spots] largest |a| of each row
     float *resid;                   // [n_scen][nvox] residual of the last forward sweep
-    double *fpart;                  // [n_scen * nchunks] objective partials
-    double *gpart;                  // [n_scen * n_spots] row products A_s[j,:] r_s
+    double *fpart;                  // [n_work] objective partials
+    double *gpart;                  // [n_pieces] piece products with the residual
     double *x, *y, *z, *gvec;       // [n_spots]
     double *scale;                  // [2 * n_scen] 2^m, 2^-m of the next forward sweep
     double *scal;                   // device scalars (kOptLam, kOptL)
 };
 
-hipError_t opt_build_count(const OptDev &O, unsigned *cnt, unsigned *err, hipStream_t st);
-hipError_t opt_build_scan(unsigned *cnt, unsigned long long *off, size_t n, hipStream_t st);
-hipError_t opt_build_emit(const OptDev &O, const unsigned long long *off, unsigned *cur, OptSeg *seg,
-                          unsigned long long cap, hipStream_t st);
+hipError_t opt_build_count(const OptDev &O, unsigned long long *cnt, unsigned *err, hipStream_t st);
+hipError_t opt_roi_count(const OptDev &O, unsigned long long *rcnt, unsigned *err, hipStream_t st);
+hipError_t opt_roi_copy(const OptDev &O, const long long *rptr, int32_t *ccol, float *cval, hipStream_t st);
+hipError_t opt_build_scan(unsigned long long *cnt, unsigned long long *off, size_t n, hipStream_t st);
+hipError_t opt_build_emit(const OptDev &O, const unsigned long long *off, unsigned long long *cur, uint32_t *bkey,
+                          float *bval, hipStream_t st);
 hipError_t opt_forward(const OptDev &O, const double *w, int mode, float *dose_out, hipStream_t st);
 hipError_t opt_gradient(const OptDev &O, hipStream_t st);
 hipError_t opt_update(const OptDev &O, int mode, double beta, int it, double *hist, hipStream_t st);

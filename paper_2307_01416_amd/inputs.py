@@ -498,3 +498,24 @@ def opt_problem(seed: int = 0, shape=(40, 36, 20), n_spots: int = 48, n_scen: in
     roi[nz // 2 - 3: nz // 2 + 3, ny // 2 + 3: ny // 2 + 8, :] |= 2
     return OptProblem(tuple(shape), n_scen, n_spots, row_ptr, np.concatenate(rows_col).astype(np.int32),
                       np.concatenate(rows_val).astype(np.float32), roi.ravel())
+
+
+def head_structures(case: Case, target_cc: float = 8.0, oar_radius_mm: float = 8.0, gap_mm: float = 3.0):
+    """Structure masks of the synthetic head case for plan optimisation:
+    uint8 [nvox], bit 0 = the spherical target, bit 1 = a spherical organ at
+    risk of radius oar_radius_mm whose surface lies gap_mm from the target's,
+    on the line from the target centre towards the head centre."""
+    g = case.geometry
+    nx, ny, nz = g.shape
+    r = sphere_radius_mm(target_cc)
+    c = np.array(HEAD_TARGET_CENTRES.get(target_cc, (0.0, 0.0, 0.0)), np.float64)
+    u = -c / max(np.linalg.norm(c), 1e-9) if np.linalg.norm(c) > 0 else np.array([1.0, 0.0, 0.0])
+    co = c + u * (r + gap_mm + oar_radius_mm)
+    x = g.origin[0] + (np.arange(nx) + 0.5) * g.spacing[0]
+    y = g.origin[1] + (np.arange(ny) + 0.5) * g.spacing[1]
+    z = g.origin[2] + (np.arange(nz) + 0.5) * g.spacing[2]
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    roi = np.zeros((nz, ny, nx), np.uint8)
+    roi[(X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2 <= r * r] |= 1
+    roi[(X - co[0]) ** 2 + (Y - co[1]) ** 2 + (Z - co[2]) ** 2 <= oar_radius_mm ** 2] |= 2
+    return roi.ravel()

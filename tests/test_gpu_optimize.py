@@ -1,7 +1,10 @@
 """Spot-weight optimiser (NEXT-1: robust optimisation on the scenario
 influence matrices, Methods E) on the GPU against the FP64 oracle, through
-the C ABI, on seeded synthetic pencil-beam-like matrices (several 4096-voxel
+the C ABI, on seeded synthetic pencil-beam-like matrices (many 512-voxel
 chunks with a ragged last chunk, empty rows, 3 and 13 scenarios).
+
+Each iteration sweeps only the entries in structure voxels (the objective
+and its gradient vanish elsewhere); the dose output sweeps whole rows.
 
 Tolerance: the dose sweep is exact to 2^-60 of its bound (int64 fixed point),
 but the residual handed to the gradient sweep is FP32 (relative 2^-24 per
@@ -70,7 +73,7 @@ def check(xg, hg, Lg, xo, ho, Lo):
 def test_parity_small(ctx):
     P = I.opt_problem(seed=0)
     say(f"optimiser parity: nvox {P.nvox}, nnz {P.row_ptr[-1]}, rows {P.n_scen}x{P.n_spots}")
-    assert P.nvox % 4096 and P.nvox > 4 * 4096   # several chunks and a ragged last one
+    assert P.nvox % 512 and P.nvox > 4 * 512   # several chunks and a ragged last one
     x0 = x_start(P)
     xg, hg, Lg, dg = gpu(ctx, P, x0, 150, dose=True)
     xo, ho, Lo, A = orc(P, x0, 150)
@@ -103,6 +106,16 @@ def test_reruns_reuse_and_host_device_identical(ctx):
     Ld = V.vpmc_optimize(ctx, t(P.row_ptr), t(P.col), t(P.val), P.n_scen, P.n_spots, P.nvox, t(P.roi), xd,
                          iters=40, n_power=30, flags=V.DEVICE_PTRS, obj_hist=hd, **PAR)
     assert np.array_equal(xd.cpu().numpy(), a[0]) and np.array_equal(hd.cpu().numpy(), a[1]) and Ld == a[2]
+    # the dose output on the reused index (whole rows bucketed on demand):
+    # same iterates; the final objective summed over other chunk lists
+    f = gpu(ctx, P, x0, 40, flags=V.OPT_REUSE, dose=True)
+    assert np.array_equal(f[0], a[0]) and np.array_equal(f[1][:-1], a[1][:-1])
+    assert f[1][-1] == pytest.approx(a[1][-1], rel=1e-12)
+    # other structures do not match the index
+    P2 = I.OptProblem(P.shape, P.n_scen, P.n_spots, P.row_ptr, P.col, P.val, (P.roi & 1).astype(np.uint8))
+    with pytest.raises(V.VpmcError) as ex:
+        gpu(ctx, P2, x0, 5, flags=V.OPT_REUSE)
+    assert ex.value.code == V.E_STATE
     # the index of another problem does not match
     Q = I.opt_problem(seed=2, n_scen=2)
     with pytest.raises(V.VpmcError) as ex:
