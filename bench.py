@@ -38,18 +38,23 @@ PROFILE = os.path.join(ROOT, "profiles", "queue_kernel_head_im.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2307_01416_amd", "csrc", "vpmc_kernels.hip")
 
 
-def measured_traffic():
-    """HBM bytes per queue_kernel launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when
-    the kernel source has changed since the counters were taken."""
+OPT_PROFILE = os.path.join(ROOT, "profiles", "optimizer_head_im.md")
+OPT_SRC = os.path.join(ROOT, "paper_2307_01416_amd", "csrc", "vpmc_opt.hip")
+
+
+def measured_traffic(profile=PROFILE, src_path=KERNEL_SRC, key="traffic_bytes_per_launch"):
+    """HBM bytes per launch of queue_kernel (or per optimiser iteration) from a
+    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated
+    on a plain copy), or None when the kernel source has changed since the
+    counters were taken."""
     import hashlib
     import re
     try:
-        text = open(PROFILE).read()
-        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        text = open(profile).read()
+        src = hashlib.sha256(open(src_path, "rb").read()).hexdigest()
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    m = re.search(key + r":\s*([0-9.eE+]+)", text)
     h = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
     if not m or not h or h.group(1) != src:
         return None
@@ -243,7 +248,8 @@ def optimizer_measure(eng, case, I, V, np, torch, a, shape):
             "target_mean_dose_gy_per_scenario_min_max": [float(dt.mean(1).min()), float(dt.mean(1).max())],
             "oar_max_dose_gy_worst_scenario": float(do.max()),
             "roofline": {"bound": "hbm", "achieved": alg / t_it / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                         "frac": alg / t_it / HBM_PEAK, "traffic": None,
+                         "frac": alg / t_it / HBM_PEAK,
+                         "traffic": measured_traffic(OPT_PROFILE, OPT_SRC, "traffic_bytes_per_iteration"),
                          "kernel": "opt_forward_kernel + opt_grad_kernel (one iteration)",
                          "alg_bytes_per_iteration": alg}}
 
