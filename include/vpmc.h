@@ -100,7 +100,8 @@ typedef struct {
 
 /* Aperture block (Methods B): brass slab of the given thickness and
  * density whose downstream face lies downstream_mm upstream of the
- * beam-frame origin plane; non-divergent opening (Methods D). */
+ * beam-frame origin plane; non-divergent opening (Methods D) unless
+ * vpmc_set_divergence gives a focus. */
 typedef struct {
     float thickness_mm, density_gcc, downstream_mm;
 } vpmc_block;
@@ -122,6 +123,22 @@ typedef struct {
  * vertices but not 0, zero area, self-intersection, > VPMC_MAX_VERTICES). */
 int vpmc_set_aperture(vpmc_ctx *ctx, int field_id, const vpmc_beam *beam, const float *xy_mm,
                       int n_vertices, const vpmc_block *block, const vpmc_rs *rs);
+
+/* Divergence of field `field_id` (the divergent block is the paper's next
+ * step, Discussion; this library's addition, not the paper's validated
+ * geometry).  vsad_mm > 0: every VP's ray passes through a virtual source
+ * vsad_mm upstream of the beam-frame origin plane (a spot's position is then
+ * its central ray's crossing of that plane); 0: parallel beam.
+ * focus_mm > 0: divergent block, every wall is the plane through the point
+ * focus_mm upstream of the origin plane and an edge of the polygon, which
+ * then describes the opening on the block's downstream face (at depth z the
+ * opening is the polygon scaled by (z + focus) / (focus - downstream_mm)); 0:
+ * non-divergent block.  VPs entering a divergent block are never handed to
+ * the learned surrogate.  vpmc_set_aperture resets both to 0.  Errors:
+ * VPMC_E_STATE (field not set), VPMC_E_ARG (negative or non-finite values,
+ * a virtual source not upstream of every beam-line component, a focus without
+ * a block or not upstream of the block). */
+int vpmc_set_divergence(vpmc_ctx *ctx, int field_id, float vsad_mm, float focus_mm);
 
 /* One pencil-beam spot (Methods D.1/D.2): position at the beam-frame origin
  * plane, energy, Gaussian in-air sigma, optional Gaussian energy spread,

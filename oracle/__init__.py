@@ -60,7 +60,7 @@ class _Field(C.Structure):
                 ("ez", C.c_double * 3), ("has_block", C.c_int), ("nv", C.c_int),
                 ("poly", C.c_void_p), ("blk_t", C.c_double), ("blk_rho", C.c_double),
                 ("blk_d", C.c_double), ("has_rs", C.c_int), ("rs_t", C.c_double),
-                ("rs_diam", C.c_double), ("rs_d", C.c_double)]
+                ("rs_diam", C.c_double), ("rs_d", C.c_double), ("vsad", C.c_double), ("focus", C.c_double)]
 
 
 class _Spot(C.Structure):
@@ -105,6 +105,8 @@ def lib():
             ("orc_mev_to_joule", d, []),
             ("orc_polygon_distance", d, [vp, i, d, d]),
             ("orc_block_traverse", None, [vp, vp, i64, C.c_uint64, i, i, vp, i]),
+            ("orc_block_trace", None, [vp, vp, vp, d, i, C.c_uint64, vp]),
+            ("orc_edge_distance_div", d, [vp, i, vp, vp, d, d]),
             ("mlp_num_params", i, []), ("mlp_forward", None, [vp, vp, i, vp]),
             ("mlp_loss_grad", d, [vp, vp, vp, vp, i, vp]),
             ("mlp_adam_step", None, [vp, vp, vp, vp, i, i, d, d, d, d]),
@@ -206,12 +208,14 @@ class _Prepared:
         self.field.ex = (C.c_double * 3)(*b.ex)
         self.field.ey = (C.c_double * 3)(*b.ey)
         self.field.ez = (C.c_double * 3)(*b.ez)
+        self.field.vsad = f.vsad_mm
         self.poly = None
         if f.block is not None:
             self.field.has_block = 1
             self.field.blk_t = f.block.thickness_mm
             self.field.blk_rho = f.block.density_gcc
             self.field.blk_d = f.block.downstream_mm
+            self.field.focus = f.block.focus_mm
             if f.polygon is not None and len(f.polygon) > 0:
                 self.poly = np.ascontiguousarray(f.polygon, np.float64)
                 self.field.nv = self.poly.shape[0]
@@ -448,6 +452,17 @@ def block_traverse(case, entries: np.ndarray, seed: int = 0, field_index: int = 
     out = np.zeros((e.shape[0], 8), np.float64)
     lib().orc_block_traverse(C.byref(P.field), _ptr(e), e.shape[0], seed, field_index,
                              case.physics if physics is None else physics, _ptr(out), threads)
+    return out
+
+
+def block_trace(case, p, d, energy: float, physics: int = 0, seed: int = 0, field_index: int = 0) -> np.ndarray:
+    """One VP through the field's block from p (x, y on the upstream face)
+    along d: [left downstream, E, x, y, z, path length in brass]."""
+    P = _Prepared(case, field_index, 0)
+    pp = np.ascontiguousarray(p, np.float64)
+    dd = np.ascontiguousarray(d, np.float64)
+    out = np.zeros(6, np.float64)
+    lib().orc_block_trace(C.byref(P.field), _ptr(pp), _ptr(dd), float(energy), int(physics), int(seed), _ptr(out))
     return out
 
 

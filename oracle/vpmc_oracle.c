@@ -338,6 +338,9 @@ typedef struct {
     double blk_t, blk_rho, blk_d;         /* thickness, density, downstream face to origin */
     int has_rs;
     double rs_t, rs_diam, rs_d;           /* physical thickness, diameter, downstream face */
+    double vsad;                          /* virtual source upstream of the origin plane (0: parallel beam) */
+    double focus;                         /* focus of the block's walls upstream of the origin plane
+                                             (0: non-divergent block) */
 } orc_field;
 
 typedef struct {
@@ -365,6 +368,7 @@ typedef struct {
     uint32_t spot, hist, nblk;
     int physics;
     int n_nuc, n_steps;
+    double brass_path;        /* path length inside brass (test support) */
 } vp_t;
 
 /* tally sink: either fixed-point atomics (run) or FP64 sums (trace) */
@@ -517,6 +521,43 @@ int orc_in_polygon(const double *poly, int nv, double x, double y)
     return c;
 }
 
+/* Divergent block (the paper's next step, Discussion): every wall is the
+ * plane through the focus and an edge of the polygon, which is given on the
+ * downstream face; at depth z the opening is the polygon scaled by
+ * s(z) = (z + focus) / (focus - blk_d).  A non-divergent block has s = 1. */
+static double blk_scale(const orc_field *f, double z)
+{
+    return f->focus > 0.0 ? (z + f->focus) / (f->focus - f->blk_d) : 1.0;
+}
+
+static double blk_kw(const orc_field *f, double w)
+{
+    return f->focus > 0.0 ? w / (f->focus - f->blk_d) : 0.0;
+}
+
+/* path length along d until the ray from p meets a wall: for the edge (a, b)
+ * the point p + t d lies on the wall when p_xy + t d_xy = s(t) (a + lam (b - a))
+ * with s(t) = s0 + t kw and 0 <= lam <= 1, which is linear in t (INFINITY if
+ * it never does).  s0 = 1, kw = 0 is the non-divergent block, where this is
+ * the ray-segment intersection of the beam's-eye-view projection. */
+double orc_edge_distance_div(const double *poly, int nv, const double p[3], const double d[3], double s0, double kw)
+{
+    double best = INFINITY;
+    for (int i = 0, j = nv - 1; i < nv; j = i++) {
+        double ax = poly[2 * j], ay = poly[2 * j + 1];
+        double ex = poly[2 * i] - ax, ey = poly[2 * i + 1] - ay;
+        double ux = d[0] - kw * ax, uy = d[1] - kw * ay;
+        double den = ux * ey - uy * ex;
+        if (den == 0.0) continue;
+        double wx = s0 * ax - p[0], wy = s0 * ay - p[1];
+        double t = (wx * ey - wy * ex) / den;
+        double mu = (wx * uy - wy * ux) / den;
+        double st = s0 + t * kw;
+        if (t > 0.0 && st > 0.0 && mu >= 0.0 && mu <= st && t < best) best = t;
+    }
+    return best;
+}
+
 /* path length along the 3D direction d until the BEV projection of the ray
  * from (x, y) meets an edge of the polygon (INFINITY if never) */
 double orc_edge_distance(const double *poly, int nv, double x, double y, double u, double v)
@@ -549,9 +590,12 @@ enum { EX_DOWN = 0, EX_GONE = 1 };
 /* Move the VP's projected (BEV) position EDGE_PUSH_MM further along its
  * projected direction, so that the next crossing-number test sees it on the
  * far side of the edge it has just reached; its depth is unchanged (R5). */
-static void edge_push(vp_t *vp)
+static void edge_push(vp_t *vp, const orc_field *f)
 {
-    double u = vp->d[0], v = vp->d[1], n = sqrt(u * u + v * v);
+    /* in a divergent block the crossing direction is that of the scaled
+     * position p_xy / s(z): d_xy - kw p_xy / s */
+    double s = blk_scale(f, vp->p[2]), kw = blk_kw(f, vp->d[2]);
+    double u = vp->d[0] - kw * (vp->p[0] / s), v = vp->d[1] - kw * (vp->p[1] / s), n = sqrt(u * u + v * v);
     if (n > 0.0) {
         vp->p[0] += EDGE_PUSH_MM * u / n;
         vp->p[1] += EDGE_PUSH_MM * v / n;
@@ -592,9 +636,9 @@ static int block_transport(vp_t *vp, sink_t *sk, const orc_field *f, double zu, 
         int down;
         double tp = plane_distance(vp, zu, zd, &down);
         if (tp < 0.0) tp = 0.0;
-        int open = f->nv >= 3 && orc_in_polygon(f->poly, f->nv, vp->p[0], vp->p[1]);
-        double te = f->nv >= 3 ? orc_edge_distance(f->poly, f->nv, vp->p[0], vp->p[1], vp->d[0], vp->d[1])
-                               : INFINITY;
+        double s0 = blk_scale(f, vp->p[2]), kw = blk_kw(f, vp->d[2]);
+        int open = f->nv >= 3 && orc_in_polygon(f->poly, f->nv, vp->p[0] / s0, vp->p[1] / s0);
+        double te = f->nv >= 3 ? orc_edge_distance_div(f->poly, f->nv, vp->p, vp->d, s0, kw) : INFINITY;
         if (open) {
             if (tp <= te) {
                 for (int k = 0; k < 3; k++) vp->p[k] += tp * vp->d[k];
@@ -604,13 +648,16 @@ static int block_transport(vp_t *vp, sink_t *sk, const orc_field *f, double zu, 
                 return EX_GONE;
             }
             for (int k = 0; k < 3; k++) vp->p[k] += te * vp->d[k];
-            edge_push(vp);
+            edge_push(vp, f);
             continue;
         }
         double dg = te < tp ? te : tp;
         double dep, esc;
         double let;
+        double p0[3] = {vp->p[0], vp->p[1], vp->p[2]};
         int st = phys_step(vp, M_BRASS, f->blk_rho, f->blk_rho, dg, &dep, &esc, &let);
+        vp->brass_path += sqrt((vp->p[0] - p0[0]) * (vp->p[0] - p0[0]) + (vp->p[1] - p0[1]) * (vp->p[1] - p0[1]) +
+                               (vp->p[2] - p0[2]) * (vp->p[2] - p0[2]));
         sink_ledger(sk, L_BLOCK, dep);
         sink_ledger(sk, L_NUC, esc);
         if (st == ST_STOP) return EX_GONE;
@@ -620,7 +667,7 @@ static int block_transport(vp_t *vp, sink_t *sk, const orc_field *f, double zu, 
             sink_ledger(sk, L_ESCAPED, vp->E);
             return EX_GONE;
         }
-        if (st == ST_GEO) edge_push(vp);
+        if (st == ST_GEO) edge_push(vp, f);
         if (vp->p[2] >= zd) { vp->p[2] = zd; return EX_DOWN; }
         if (vp->p[2] <= zu) { vp->p[2] = zu; sink_ledger(sk, L_ESCAPED, vp->E); return EX_GONE; }
     }
@@ -654,9 +701,10 @@ static int beamline(vp_t *vp, sink_t *sk, const orc_field *f, double *tmin)
         double q[3];
         for (int k = 0; k < 3; k++) q[k] = vp->p[k] + t * vp->d[k];
         q[2] = zu;
-        int open = f->nv >= 3 && orc_in_polygon(f->poly, f->nv, q[0], q[1]);
+        double su = blk_scale(f, zu);
+        int open = f->nv >= 3 && orc_in_polygon(f->poly, f->nv, q[0] / su, q[1] / su);
         if (open) {
-            double te = orc_edge_distance(f->poly, f->nv, q[0], q[1], vp->d[0], vp->d[1]);
+            double te = orc_edge_distance_div(f->poly, f->nv, q, vp->d, su, blk_kw(f, vp->d[2]));
             double tx = (zd - zu) / vp->d[2];
             if (te >= tx) {                      /* straight through the opening */
                 *tmin = (zd - vp->p[2]) / vp->d[2];
@@ -748,10 +796,12 @@ static void patient(vp_t *vp, sink_t *sk, const orc_geom *g, const orc_field *f,
     sink_ledger(sk, L_ESCAPED, vp->E);
 }
 
-/* Source (Methods A, Introduction): parallel Gaussian pencil beam, spot sigma
- * from the spot list, monoenergetic unless an energy spread is given.  The VP
- * starts on its ray at the beam-frame origin plane, direction +z. */
-static void source(vp_t *vp, const orc_spot *sp)
+/* Source (Methods A, Introduction): Gaussian pencil beam, spot sigma from
+ * the spot list, monoenergetic unless an energy spread is given.  The VP
+ * starts on its ray at the beam-frame origin plane, direction +z, or with a
+ * virtual source vsad upstream of that plane (scanned beams diverge from it)
+ * along the line from the virtual source through its start point. */
+static void source(vp_t *vp, const orc_spot *sp, const orc_field *f)
 {
     double u[4], z1, z2;
     draw_block(vp, u);
@@ -760,6 +810,12 @@ static void source(vp_t *vp, const orc_spot *sp)
     vp->p[1] = sp->y + sp->sigma * z2;
     vp->p[2] = 0.0;
     vp->d[0] = 0.0; vp->d[1] = 0.0; vp->d[2] = 1.0;
+    if (f->vsad > 0.0) {
+        double n = sqrt(vp->p[0] * vp->p[0] + vp->p[1] * vp->p[1] + f->vsad * f->vsad);
+        vp->d[0] = vp->p[0] / n;
+        vp->d[1] = vp->p[1] / n;
+        vp->d[2] = f->vsad / n;
+    }
     vp->E = sp->e0;
     if (sp->esig > 0.0) {
         double e = sp->e0 + sp->esig * orc_normal_quantile(u[2]);
@@ -780,7 +836,7 @@ static void one_history(const orc_geom *g, const orc_field *f, const orc_spot *s
     vp->spot = (uint32_t)spot_index;
     vp->hist = (uint32_t)h;
     vp->physics = o->physics;
-    source(vp, sp);
+    source(vp, sp, f);
     double tmin;
     if (!beamline(vp, sk, f, &tmin)) return;
     patient(vp, sk, g, f, sc, tmin);
@@ -922,8 +978,9 @@ void orc_block_traverse(const orc_field *f, const double *entries, int64_t n, ui
         vp.d[0] = e[2]; vp.d[1] = e[3];
         vp.d[2] = sqrt(fmax(1.0 - e[2] * e[2] - e[3] * e[3], 0.0));
         vp.E = e[4];
-        o[7] = f->nv >= 3 ? orc_polygon_distance(f->poly, f->nv, e[0], e[1]) : 1000.0;
-        if (f->nv >= 3 && orc_in_polygon(f->poly, f->nv, e[0], e[1])) {
+        double su = blk_scale(f, zu);
+        o[7] = f->nv >= 3 ? su * orc_polygon_distance(f->poly, f->nv, e[0] / su, e[1] / su) : 1000.0;
+        if (f->nv >= 3 && orc_in_polygon(f->poly, f->nv, e[0] / su, e[1] / su)) {
             o[0] = -1.0;
             continue;
         }
@@ -952,3 +1009,26 @@ double orc_rs_thickness(double wet_mm)
 }
 
 double orc_mev_to_joule(void) { return MEV_TO_J; }
+
+/* One VP through the block from p (on its upstream face) along d with energy
+ * E: out = [1 if it left through the downstream face, E, x, y, z, path length
+ * inside brass].  Test support for the geometry of the block's walls. */
+void orc_block_trace(const orc_field *f, const double *p, const double *d, double E, int physics, uint64_t seed,
+                     double *out)
+{
+    orc_init();
+    double zu = -(f->blk_d + f->blk_t), zd = -f->blk_d;
+    vp_t vp;
+    sink_t sk;
+    memset(&vp, 0, sizeof vp);
+    memset(&sk, 0, sizeof sk);
+    vp.key[0] = (uint32_t)(seed & 0xffffffffu);
+    vp.key[1] = (uint32_t)(seed >> 32);
+    vp.physics = physics;
+    for (int k = 0; k < 3; k++) { vp.p[k] = p[k]; vp.d[k] = d[k]; }
+    vp.p[2] = zu;
+    vp.E = E;
+    int ex = block_transport(&vp, &sk, f, zu, zd);
+    out[0] = ex == EX_DOWN; out[1] = vp.E; out[2] = vp.p[0]; out[3] = vp.p[1]; out[4] = vp.p[2];
+    out[5] = vp.brass_path;
+}

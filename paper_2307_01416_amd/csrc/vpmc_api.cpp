@@ -1155,6 +1155,8 @@ int vpmc_set_aperture(vpmc_ctx *c, int field_id, const vpmc_beam *beam, const fl
     }
     FieldState &f = c->fields[field_id];
     FieldDev d{};
+    d.fs = 0.0f;    // non-divergent block, parallel beam (vpmc_set_divergence)
+    d.fc0 = 1.0f;
     for (int k = 0; k < 3; ++k) {
         d.iso[k] = beam->iso_mm[k];
         d.ex[k] = beam->ex[k];
@@ -1209,6 +1211,35 @@ int vpmc_set_aperture(vpmc_ctx *c, int field_id, const vpmc_beam *beam, const fl
     f.dev = d;
     f.poly = std::move(poly);
     f.set = true;
+    return VPMC_OK;
+}
+
+int vpmc_set_divergence(vpmc_ctx *c, int field_id, float vsad_mm, float focus_mm) {
+    if (!c) return fail(VPMC_E_ARG, "ctx is NULL");
+    if (field_id < 0 || field_id >= VPMC_MAX_FIELDS)
+        return fail(VPMC_E_ARG, "field_id %d outside [0, %d)", field_id, VPMC_MAX_FIELDS);
+    if (!c->fields[field_id].set) return fail(VPMC_E_STATE, "field %d has no aperture/beam set", field_id);
+    if (!(vsad_mm >= 0.0f && std::isfinite(vsad_mm)) || !(focus_mm >= 0.0f && std::isfinite(focus_mm)))
+        return fail(VPMC_E_ARG, "vsad_mm and focus_mm must be finite and >= 0");
+    FieldDev &d = c->fields[field_id].dev;
+    double up = 0.0;   // the upstream-most face of the beam-line components
+    if (d.has_block) up = std::max(up, -(double)d.blk_zu);
+    if (d.has_rs) up = std::max(up, -(double)d.rs_zu);
+    if (vsad_mm > 0.0f && (double)vsad_mm <= up)
+        return fail(VPMC_E_ARG, "the virtual source must lie upstream of the range shifter and the block");
+    if (focus_mm > 0.0f && !d.has_block) return fail(VPMC_E_ARG, "focus_mm needs an aperture block");
+    if (focus_mm > 0.0f && (double)focus_mm <= -(double)d.blk_zu)
+        return fail(VPMC_E_ARG, "the focus must lie upstream of the block's upstream face");
+    d.vsad = vsad_mm;
+    d.div = focus_mm > 0.0f ? 1 : 0;
+    if (d.div) {
+        const double fs = 1.0 / ((double)focus_mm + (double)d.blk_zd);   // 1 / (focus - downstream distance)
+        d.fs = (float)fs;
+        d.fc0 = (float)(((double)d.blk_zu + (double)focus_mm) * fs);
+    } else {
+        d.fs = 0.0f;
+        d.fc0 = 1.0f;
+    }
     return VPMC_OK;
 }
 

@@ -77,6 +77,12 @@ struct FieldDev {
     float blk_zu, blk_zd, blk_rho, blk_t, blk_tl;
     int has_rs;
     float rs_zu, rs_zd, rs_r2, rs_rho, rs_rhol, rs_t, rs_tl;   // *_l: low parts of the FP64 values
+    // virtual source vsad upstream of the origin plane (0: parallel beam);
+    // divergent block (div): the opening at block depth pz is the polygon
+    // scaled by pz * fs + fc0 (walls through the focus)
+    float vsad;
+    int div;
+    float fs, fc0;
 };
 
 struct SpotDev {

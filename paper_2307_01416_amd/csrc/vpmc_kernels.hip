@@ -518,25 +518,46 @@ __device__ __forceinline__ bool no_edge_within(float lb, float lat, float t) {
     return lb > 0.0f && lat * t < lb * (1.0f - 1e-5f) - 1e-4f;
 }
 
-// path length along (u, v) until the BEV ray from (x, y) meets an edge
-__device__ __forceinline__ float edge_distance(const float2 *poly, int nv, float x, float y, float u,
-                                               float v) {
+// Path length along the ray (x, y) + t (u, v) to the first wall of the block
+// (INFINITY if none).  Every wall is the plane through the focus and an edge
+// of the polygon: at opening scale s0 (s = s0 + t kw along the ray) the ray
+// meets the wall of edge (a, b) where p + t d = s (a + lam (b - a)), linear
+// in t.  A non-divergent block has s0 = 1, kw = 0: the beam's-eye-view
+// ray-segment intersection.
+__device__ __forceinline__ float edge_distance_div(const float2 *poly, int nv, float x, float y, float u,
+                                                   float v, float s0, float kw) {
     float best = INFINITY;
     float2 a = poly[nv - 1];
     for (int i = 0; i < nv; ++i) {
         const float2 b = poly[i];
         const float ex = b.x - a.x, ey = b.y - a.y;
-        const float den = u * ey - v * ex;
+        const float ux = u - kw * a.x, uy = v - kw * a.y;
+        const float den = ux * ey - uy * ex;
         if (den != 0.0f) {
-            const float wx = a.x - x, wy = a.y - y;
+            const float wx = s0 * a.x - x, wy = s0 * a.y - y;
             const float inv = 1.0f / den;
             const float t = (wx * ey - wy * ex) * inv;
-            const float lam = (wx * v - wy * u) * inv;
-            if (t > 0.0f && lam >= 0.0f && lam <= 1.0f) best = fminf(best, t);
+            const float mu = (wx * uy - wy * ux) * inv;
+            const float st = fmaf(t, kw, s0);
+            if (t > 0.0f && st > 0.0f && mu >= 0.0f && mu <= st) best = fminf(best, t);
         }
         a = b;
     }
     return best;
+}
+
+// edge push in the block: along the scaled position's direction of travel
+// d_xy - kw X, which crosses the wall just reached (d_xy for a non-divergent
+// block, where kw = 0)
+__device__ __forceinline__ void edge_push_blk(Lane &v, const FieldDev &f) {
+    const float isc = 1.0f / fmaf(v.pz, f.fs, f.fc0), kw = v.dz * f.fs;
+    const float cx = v.dx - kw * (v.px * isc), cy = v.dy - kw * (v.py * isc);
+    const float n2 = cx * cx + cy * cy;
+    if (n2 > 0.0f) {
+        const float k = EDGE_PUSH_MM * rsqrtf(n2);
+        v.px = fmaf(k, cx, v.px);
+        v.py = fmaf(k, cy, v.py);
+    }
 }
 
 // Inside a slab (range shifter or block) the depth is kept relative to the
@@ -551,17 +572,6 @@ __device__ __forceinline__ DF plane_distance(const Lane &v, DF thick, bool &down
     if (v.dz > 0.0f) t = A::div_f(A::sub(thick, A::pair(v.pz, v.pzlo)), v.dz);
     else if (v.dz < 0.0f) { down = false; t = A::div_f(A::pair(-v.pz, -v.pzlo), v.dz); }
     return t.h > 0.0f ? t : DF{0.0f, 0.0f};
-}
-
-// push the projected (beam's-eye-view) position EDGE_PUSH_MM further along
-// the projected direction, depth unchanged, across the edge just reached
-__device__ __forceinline__ void edge_push(Lane &v) {
-    const float n2 = v.dx * v.dx + v.dy * v.dy;
-    if (n2 > 0.0f) {
-        const float k = EDGE_PUSH_MM * rsqrtf(n2);
-        v.px = fmaf(k, v.dx, v.px);
-        v.py = fmaf(k, v.dy, v.py);
-    }
 }
 
 enum { EX_DOWN = 0, EX_GONE = 1 };
@@ -610,16 +620,24 @@ __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab,
         bool open = false;
         float te = INFINITY;
         if (nv >= 3) {
+            // opening scale at this depth (1 and kw = 0 for a non-divergent
+            // block, where (bx, by) = p_xy and every expression below is the plain
+            // beam's-eye-view one)
+            const float sc = fmaf(v.pz, f_sdf.fs, f_sdf.fc0), kw = v.dz * f_sdf.fs;
+            const float isc = 1.0f / sc;
+            const float bx = v.px * isc, by = v.py * isc;
+            const float cx = v.dx - kw * bx, cy = v.dy - kw * by;
             // far from every edge for the whole path to the exit plane: the
             // side is known and the exact edge distance exceeds tp, so the
-            // decisions below are those of the exact loops
+            // decisions below are those of the exact loops (the scaled
+            // position moves by at most tp |d_xy - kw (bx, by)| / min s)
             bool inside;
-            const float lb = sdf_bound(f_sdf, v.px, v.py, inside);
-            if (no_edge_within(lb, sqrtf(v.dx * v.dx + v.dy * v.dy), tp)) {
+            const float lb = sdf_bound(f_sdf, bx, by, inside);
+            if (no_edge_within(lb, sqrtf(cx * cx + cy * cy) / fminf(sc, fmaf(tp, kw, sc)), tp)) {
                 open = inside;
             } else {
-                open = in_polygon(poly, nv, v.px, v.py);
-                te = edge_distance(poly, nv, v.px, v.py, v.dx, v.dy);
+                open = in_polygon(poly, nv, bx, by);
+                te = edge_distance_div(poly, nv, v.px, v.py, v.dx, v.dy, sc, kw);
             }
         }
         if (open) {
@@ -633,7 +651,7 @@ __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab,
                 return EX_GONE;
             }
             move<true, X>(v, {te, 0.0f});
-            edge_push(v);
+            edge_push_blk(v, f_sdf);
             continue;
         }
         const DF dg = te < tp ? DF{te, 0.0f} : tpp;
@@ -650,7 +668,7 @@ __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab,
             ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
             return EX_GONE;
         }
-        if (st == ST_GEO) edge_push(v);
+        if (st == ST_GEO) edge_push_blk(v, f_sdf);
         if (v.pz >= thick.h) { v.pz = zd; v.pzlo = 0.0f; return EX_DOWN; }
         if (v.pz <= 0.0f) {
             v.pz = zu;
@@ -714,21 +732,26 @@ __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const 
         bool open = false, through = false;
         if (nv >= 3) {
             const float tx = f.blk_t / v.dz;
+            // opening scale on the upstream face (1, kw = 0: non-divergent)
+            const float sc = f.fc0, kw = v.dz * f.fs;
+            const float isc = 1.0f / sc;
+            const float bx = qx * isc, by = qy * isc;
+            const float cx = v.dx - kw * bx, cy = v.dy - kw * by;
             bool inside;
-            const float lb = sdf_bound(f, qx, qy, inside);
-            if (no_edge_within(lb, sqrtf(v.dx * v.dx + v.dy * v.dy), tx)) {
+            const float lb = sdf_bound(f, bx, by, inside);
+            if (no_edge_within(lb, sqrtf(cx * cx + cy * cy) / fminf(sc, fmaf(tx, kw, sc)), tx)) {
                 open = inside;
                 through = inside;
             } else {
-                open = in_polygon(poly, nv, qx, qy);
-                through = open && edge_distance(poly, nv, qx, qy, v.dx, v.dy) >= tx;
+                open = in_polygon(poly, nv, bx, by);
+                through = open && edge_distance_div(poly, nv, qx, qy, v.dx, v.dy, sc, kw) >= tx;
             }
         }
         if (through) {
             tmin = (f.blk_zd - v.pz) / v.dz;
             return BL_PATIENT;
         }
-        if (!open && sur && sur->enabled) {
+        if (!open && sur && sur->enabled && !f.div) {
             // enters through brass: far enough from the opening's edge, the
             // learned surrogate takes over the traversal (queued for it)
             const float de = nv >= 3 ? dist_to_polygon(poly, nv, qx, qy) : 1000.0f;
@@ -998,7 +1021,7 @@ __device__ void patient(Lane &v, Acc &acc, float scale, const float *tab, const 
 }
 
 // ------------------------------------------------------------ source
-__device__ void source(Lane &v, const SpotDev &sp) {
+__device__ void source(Lane &v, const SpotDev &sp, float vsad) {
     const uint4 w = draw(v);
     const float r = sqrtf(-2.0f * logf(unit_open(w.x)));
     float sn, c;
@@ -1009,6 +1032,13 @@ __device__ void source(Lane &v, const SpotDev &sp) {
     v.pzlo = 0.0f;
     v.pxlo = v.pylo = 0.0f;
     v.dx = 0.0f; v.dy = 0.0f; v.dz = 1.0f;
+    if (vsad > 0.0f) {
+        // along the line from the virtual source through the start point
+        const float inv = 1.0f / sqrtf(fmaf(v.px, v.px, fmaf(v.py, v.py, vsad * vsad)));
+        v.dx = v.px * inv;
+        v.dy = v.py * inv;
+        v.dz = vsad * inv;
+    }
     v.E = sp.e0;
     v.Elo = 0.0f;
     if (sp.esig > 0.0f) {
@@ -1053,7 +1083,7 @@ __global__ __launch_bounds__(512) void transport_kernel(GeomDev g, FieldDev f, L
         v.nblk = 0;
         v.nsteps = 0;
         v.physics = L.physics;
-        source(v, sp);
+        source(v, sp, f.vsad);
         float tmin;
         if (beamline<X>(v, acc, sp.scale, tab, poly, f, tmin, &L.sur) == BL_PATIENT)
             patient<DenseSink, X>(v, acc, sp.scale, tab, g, f, L.shift, L.range_scale, DenseSink{L.tally, L.let_tally},
@@ -1274,7 +1304,7 @@ __global__ __launch_bounds__(X ? 768 : 1024) void queue_kernel(GeomDev g, QueueD
                         v.hist = (uint32_t)h;
                         v.nblk = 0;
                         v.nsteps = 0;
-                        source(v, sp);
+                        source(v, sp, f.vsad);
                         float tmin;
                         in = beamline<X>(v, acc, sp.scale, tab, fpoly, f, tmin, &Q.sur, (uint32_t)rl) == BL_PATIENT &&
                              patient_enter<X>(v, acc, sp.scale, g, f, sc.shift, tmin, ps);

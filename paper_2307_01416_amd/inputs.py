@@ -100,10 +100,11 @@ class Block:
     thickness_mm: float = 30.0
     density_gcc: float = 8.5
     downstream_mm: float = 150.0   # downstream face to the beam-frame origin
+    focus_mm: float = 0.0          # walls focused this far upstream of the origin (0: non-divergent)
 
     def __post_init__(self):
-        self.thickness_mm, self.density_gcc, self.downstream_mm = f32s(
-            (self.thickness_mm, self.density_gcc, self.downstream_mm))
+        self.thickness_mm, self.density_gcc, self.downstream_mm, self.focus_mm = f32s(
+            (self.thickness_mm, self.density_gcc, self.downstream_mm, self.focus_mm))
 
 
 @dataclasses.dataclass
@@ -123,6 +124,7 @@ class Field:
     polygon: Optional[np.ndarray] = None    # float32 [n, 2] BEV, mm
     block: Optional[Block] = None           # None: no aperture block at all
     rs: Optional[RangeShifter] = None
+    vsad_mm: float = 0.0                    # virtual source upstream of the origin (0: parallel beam)
 
 
 @dataclasses.dataclass

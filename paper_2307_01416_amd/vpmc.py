@@ -102,6 +102,7 @@ def load() -> C.CDLL:
         "vpmc_version": (i, []),
         "vpmc_load_geometry": (i, [vp, i, vp, i, i, i, vp, vp, u]),
         "vpmc_set_aperture": (i, [vp, i, vp, vp, i, vp, vp]),
+        "vpmc_set_divergence": (i, [vp, i, C.c_float, C.c_float]),
         "vpmc_run_spots": (i, [vp, i, vp, i, vp, i, vp, vp, vp, vp, vp]),
         "vpmc_copy_csr": (i, [vp, vp, vp, vp]),
         "vpmc_last_tally": (i, [vp, i, vp, C.POINTER(C.c_int), u]),
@@ -215,6 +216,13 @@ def vpmc_set_aperture(ctx, field_id: int, field: I.Field) -> None:
     _check(load().vpmc_set_aperture(ctx, field_id, C.byref(beam), _ptr(poly), nv,
                                     C.byref(blk) if blk is not None else None,
                                     C.byref(rs) if rs is not None else None), ctx)
+    focus = field.block.focus_mm if field.block is not None else 0.0
+    if field.vsad_mm or focus:
+        vpmc_set_divergence(ctx, field_id, field.vsad_mm, focus)
+
+
+def vpmc_set_divergence(ctx, field_id: int, vsad_mm: float, focus_mm: float) -> None:
+    _check(load().vpmc_set_divergence(ctx, field_id, float(vsad_mm), float(focus_mm)), ctx)
 
 
 def spot_array(spots: np.ndarray):

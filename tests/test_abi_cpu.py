@@ -177,3 +177,21 @@ def test_optimize_validation(vctx):
     val[7] = np.inf
     assert call(val=val) == V.E_ARG                             # value not finite
     assert call() == V.E_STATE                                  # well-formed: reaches the device step
+
+
+def test_divergence_validation(vctx):
+    from paper_2307_01416_amd import inputs as I
+    L = V.load()
+    assert L.vpmc_set_divergence(vctx, 60, 2000.0, 0.0) == V.E_STATE      # field never set
+    c = I.config2(20.0, True, histories_per_case=1000, shape=(16, 16, 16))
+    V.vpmc_set_aperture(vctx, 0, c.fields[0])
+    assert L.vpmc_set_divergence(vctx, 0, -1.0, 0.0) == V.E_ARG
+    assert L.vpmc_set_divergence(vctx, 0, float("inf"), 0.0) == V.E_ARG
+    assert L.vpmc_set_divergence(vctx, 0, 100.0, 0.0) == V.E_ARG         # source inside the beam line
+    assert L.vpmc_set_divergence(vctx, 0, 0.0, 60.0) == V.E_ARG          # focus inside the block
+    assert L.vpmc_set_divergence(vctx, 0, 2000.0, 2000.0) == V.VPMC_OK
+    assert L.vpmc_set_divergence(vctx, 0, 0.0, 0.0) == V.VPMC_OK
+    f = I.Field(beam=c.fields[0].beam, spots=c.fields[0].spots)          # no block
+    V.vpmc_set_aperture(vctx, 1, f)
+    assert L.vpmc_set_divergence(vctx, 1, 0.0, 2000.0) == V.E_ARG        # focus without a block
+    assert L.vpmc_set_divergence(vctx, 1, 2000.0, 0.0) == V.VPMC_OK

@@ -1,0 +1,149 @@
+"""Pins of the divergent aperture block and the virtual source (NEXT-2: the
+divergent block the paper names as its next step, Discussion), no GPU.
+
+A divergent block's walls are the planes through the focus and the edges of
+the opening polygon (given on the downstream face).  Pins: rays through the
+focus never meet a wall (no brass inside the opening, the whole thickness
+outside); the brass path of rays that cross a wall equals the intersection
+with the wall plane computed here from plane geometry (square opening, so
+the walls are exact planes); a block focused very far away gives the
+non-divergent result; the virtual source makes a thin beam's dose follow the
+line from the source through the spot."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2307_01416_amd import inputs as I
+
+F = 2000.0        # focus upstream of the origin plane
+BLK_D, BLK_T = 150.0, 30.0
+ZU, ZD = -(BLK_D + BLK_T), -BLK_D
+A = 10.0          # square opening [-A, A]^2 on the downstream face
+
+
+def field(focus=F, polygon=None):
+    poly = np.array([[-A, -A], [A, -A], [A, A], [-A, A]], np.float32) if polygon is None else polygon
+    return I.Field(beam=I.beam_along_z((0.0, 0.0, 0.0)), spots=I.make_spots([[0.0, 0.0]], [150.0], [3.0], 1),
+                   polygon=poly, block=I.Block(BLK_T, 8.5, BLK_D, focus_mm=focus))
+
+
+def case(f):
+    g = I.water_geometry((8, 8, 8), (1.0, 1.0, 1.0))
+    return I.Case("div", g, [f], [I.Scenario()], physics=0)
+
+
+def s(z, focus=F):
+    return (z + focus) / (focus - BLK_D)
+
+
+def unit(v):
+    v = np.asarray(v, np.float64)
+    return v / np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("X", [(3.0, 2.0), (-9.0, 4.0), (9.9, -9.9)])
+def test_ray_through_focus_inside_never_meets_brass(X):
+    c = case(field())
+    q = np.array([X[0] * s(ZU), X[1] * s(ZU), ZU])
+    d = unit(q - np.array([0.0, 0.0, -F]))
+    out = O.block_trace(c, q, d, 150.0)
+    assert out[0] == 1.0 and out[5] == 0.0 and out[1] == 150.0
+    t = (ZD - ZU) / d[2]
+    np.testing.assert_allclose(out[2:4], q[:2] + t * d[:2], rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("X", [(10.1, 2.0), (-15.0, 0.0), (12.0, 12.0)])
+def test_ray_through_focus_outside_crosses_the_whole_thickness(X):
+    c = case(field())
+    q = np.array([X[0] * s(ZU), X[1] * s(ZU), ZU])
+    d = unit(q - np.array([0.0, 0.0, -F]))
+    out = O.block_trace(c, q, d, 200.0)
+    assert out[0] == 1.0
+    assert out[5] == pytest.approx(BLK_T / d[2], rel=1e-12)
+    assert out[1] < 200.0
+
+
+def wall_crossing(q, d, focus):
+    """Path length to the plane x = A s(z) (the right wall), or None."""
+    # x(t) = q0 + t d0 ; z(t) = q2 + t d2 ; A (z(t) + focus) / (focus - BLK_D) = x(t)
+    k = A / (focus - BLK_D) if focus > 0 else 0.0
+    c0 = A * (q[2] + focus) / (focus - BLK_D) if focus > 0 else A
+    den = d[0] - k * d[2]
+    return None if den == 0 else (c0 - q[0]) / den
+
+
+@pytest.mark.parametrize("focus", [F, 0.0])
+@pytest.mark.parametrize("inside", [True, False])
+def test_brass_path_of_a_ray_crossing_a_wall(focus, inside):
+    """Parallel-to-z and tilted rays crossing the right wall (x = A s(z)),
+    from the opening into brass and from brass into the opening."""
+    c = case(field(focus=focus))
+    su = s(ZU, focus) if focus > 0 else 1.0
+    if inside:        # starts inside near the wall, tilted outward: opening then brass
+        q = np.array([A * su - 0.5, 0.3, ZU])
+        d = unit([0.05, 0.0, 1.0])
+    else:             # starts in the brass beyond the wall, tilted inward: brass then opening
+        q = np.array([A * su + 0.5, -0.2, ZU])
+        d = unit([-0.05, 0.01, 1.0])
+    tw = wall_crossing(q, d, focus)
+    tp = (ZD - ZU) / d[2]
+    assert tw is not None and 0.0 < tw < tp
+    out = O.block_trace(c, q, d, 220.0)
+    expect = tp - tw if inside else tw
+    assert out[0] == 1.0
+    assert out[5] == pytest.approx(expect, abs=1e-5)   # the edge push is 1e-6 mm
+
+
+def test_parallel_ray_enters_the_widening_opening():
+    """A ray along z just outside the opening on the upstream face enters it
+    where A s(z) reaches its x (the opening widens downstream)."""
+    c = case(field())
+    x0 = A * s(ZU) + 0.05
+    out = O.block_trace(c, np.array([x0, 0.0, ZU]), np.array([0.0, 0.0, 1.0]), 220.0)
+    zstar = x0 / A * (F - BLK_D) - F
+    assert ZU < zstar < ZD
+    assert out[5] == pytest.approx(zstar - ZU, abs=1e-5)
+
+
+def test_edge_distance_reduces_to_the_projection_without_divergence():
+    poly = np.array([[-A, -A], [A, -A], [A, A], [-A, A]], np.float64)
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        p = np.array([rng.uniform(-15, 15), rng.uniform(-15, 15), ZU])
+        d = unit([rng.normal(0, 0.1), rng.normal(0, 0.1), 1.0])
+        a = O.lib().orc_edge_distance_div(O._ptr(poly), 4, O._ptr(p), O._ptr(d), 1.0, 0.0)
+        b = O.lib().orc_edge_distance(O._ptr(poly), 4, p[0], p[1], d[0], d[1])
+        assert a == b
+
+
+def test_far_focus_matches_the_non_divergent_block():
+    """Full transport through a 20 mm circular opening: a focus 1e9 mm away
+    gives the non-divergent dose (the walls tilt by < 1e-8 rad)."""
+    geom = I.water_geometry((40, 40, 60), (1.0, 1.0, 2.0))
+    spots = I.make_spots(I.square_grid_in_disk(10.0, 5.0), [140.0] * 13, [3.0] * 13, 500)
+    out = []
+    for focus in (0.0, 1e9):
+        f = I.Field(beam=I.beam_along_z((0.0, 0.0, -50.0)), spots=spots, polygon=I.circle_polygon(20.0, 64),
+                    block=I.Block(30.0, 8.5, 80.0, focus_mm=focus))
+        out.append(O.run_tally(I.Case("far", geom, [f], [I.Scenario()], physics=0))[0])
+    a, b = out
+    assert np.abs(a - b).sum() <= 1e-6 * np.abs(a).sum()
+
+
+def test_virtual_source_beam_follows_the_source_line():
+    """Straight transport of a thin spot at x0 with the virtual source 1 m
+    upstream: the dose centroid of every depth slice lies on the line from
+    the source through the spot (within the voxel's half width)."""
+    vsad, x0 = 1000.0, 20.0
+    geom = I.water_geometry((80, 20, 60), (1.0, 1.0, 2.0))   # x from 0 to 80
+    f = I.Field(beam=I.beam_along_z((0.0, 0.0, -60.0)), spots=I.make_spots([[x0, 0.0]], [150.0], [0.05], 200),
+                vsad_mm=vsad)
+    q = O.run_tally(I.Case("vsad", geom, [f], [I.Scenario()], physics=0))[0].reshape(60, 20, 80).astype(np.float64)
+    xc = geom.origin[0] + (np.arange(80) + 0.5) * geom.spacing[0]
+    for k in range(0, 50, 7):
+        sl = q[k].sum(axis=0)
+        if sl.sum() == 0:
+            continue
+        cen = (sl * xc).sum() / sl.sum()
+        zb = geom.origin[2] + (k + 0.5) * geom.spacing[2] - (-60.0)   # beam-frame depth of the slice centre
+        assert abs(cen - x0 * (zb + vsad) / vsad) <= 0.5 + 0.02 * geom.spacing[2], (k, cen)
