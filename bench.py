@@ -82,6 +82,10 @@ def parse():
     ap.add_argument("--sur-samples", type=int, default=3_000_000)
     ap.add_argument("--sur-epochs", type=int, default=6)
     ap.add_argument("--no-optimize", action="store_true", help="skip the spot-weight optimiser measurement")
+    ap.add_argument("--layer-apertures", action="store_true",
+                    help="energy-layer-specific apertures: one field per energy layer (30 fields)")
+    ap.add_argument("--divergent", type=float, default=0.0, metavar="MM",
+                    help="virtual source and block focus this far upstream of the isocentre (0: off)")
     ap.add_argument("--opt-iters", type=int, default=80)
     ap.add_argument("--shape", default="", help="HPL,BLOCKS,THREADS: fixed work-queue launch shape (no autotune)")
     ap.add_argument("--oracle-suite", action="store_true",
@@ -113,8 +117,8 @@ def plan_dose(eng, case, I, seed=None, surrogate=False, mult=1):
     import torch
     fields = case.fields
     if mult != 1:
-        fields = [I.Field(beam=f.beam, spots=f.spots.copy(), polygon=f.polygon, block=f.block, rs=f.rs)
-                  for f in case.fields]
+        fields = [I.Field(beam=f.beam, spots=f.spots.copy(), polygon=f.polygon, block=f.block, rs=f.rs,
+                          vsad_mm=f.vsad_mm) for f in case.fields]
         for f in fields:
             f.spots["n_histories"] = (f.spots["n_histories"].astype(np.uint64) * mult).astype(np.uint32)
     nom = I.Case("nominal", case.geometry, fields, [I.Scenario()], seed=case.seed, physics=case.physics,
@@ -350,7 +354,12 @@ def main():
         copy_calibration()
     progress("building the synthetic head case ...")
     H = a.histories_per_spot
-    case = I.config4(a.target_cc, int(H))
+    case = I.config4(a.target_cc, int(H), layer_apertures=a.layer_apertures,
+                     n_vertices=32 if a.layer_apertures else 128)
+    if a.divergent > 0.0:
+        for f in case.fields:
+            f.vsad_mm = a.divergent
+            f.block.focus_mm = a.divergent
     eng = V.Engine(0)
     eng.load_case(case)
 
@@ -430,7 +439,10 @@ def main():
         "s_per_13_scenario_im": dt / a.steps,
         "config": {"workload": f"synthetic head CT 256x256x160 @1x1x2 mm, {a.target_cc} cc target, 3 coplanar "
                                f"fields with brass aperture (+5 mm) and 45 mm WET PMMA range shifter, "
-                               f"13 robust scenarios, per-spot CSR influence matrices",
+                               f"13 robust scenarios, per-spot CSR influence matrices"
+                               + (", energy-layer-specific apertures (one field per layer)" if a.layer_apertures else "")
+                               + (f", virtual source and divergent block focused {a.divergent:.0f} mm upstream"
+                                  if a.divergent > 0.0 else ""),
                    "rows": n_rows, "histories_per_step": n_hist_step,
                    "mean_histories_per_spot": float(H), "plan_dose_uncertainty": u, "nnz": nnz,
                    "csr_gb": nnz * 8 / 1e9, "graph": bool(a.graph), "launch_shape": shape_used},

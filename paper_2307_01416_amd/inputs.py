@@ -367,11 +367,17 @@ HEAD_TARGET_CENTRES = {0.4: (20.0, 30.0, 10.0), 8.0: (-25.0, 20.0, 20.0), 43.0: 
 def config3(target_cc: float = 8.0, histories_per_spot: int = 10_000, physics: int = PHYS_ALL,
             seed: int = 0, gantries=(90.0, 180.0, 270.0), layer_spacing_mm: Optional[float] = None,
             uneven: bool = False, n_vertices: int = 128, geometry: Optional[Geometry] = None,
-            scenarios: Optional[Sequence[Scenario]] = None) -> Case:
+            scenarios: Optional[Sequence[Scenario]] = None, layer_apertures: bool = False) -> Case:
     """Synthetic head case: one spherical target, 3 coplanar fields, each with
     a brass aperture = BEV projection of the target + 5 mm and a 45 mm WET
     range shifter; spots on a 2.5 mm grid in layers whose cross-section
-    follows the target (+5 mm); energies from the 97-energy table."""
+    follows the target (+5 mm); energies from the 97-energy table.
+
+    layer_apertures: energy-layer-specific apertures (the paper's proposed
+    dynamic aperture, Discussion): every energy layer becomes a field of its
+    own (same beam, block and range shifter) whose opening is the target's
+    cross-section at that layer's depth + 5 mm (n_vertices-gon), i.e. the
+    layer's spot disk; fields are ordered gantry by gantry, layer by layer."""
     geom = geometry if geometry is not None else head_ct(seed)
     r = sphere_radius_mm(target_cc)
     centre = HEAD_TARGET_CENTRES.get(target_cc, (0.0, 0.0, 0.0))
@@ -405,6 +411,16 @@ def config3(target_cc: float = 8.0, histories_per_spot: int = 10_000, physics: i
             nh = np.full(e.size, histories_per_spot, dtype=np.uint32)
         spots = make_spots(xy, e, spot_sigma_mm(e), 1)
         spots["n_histories"] = nh
+        if layer_apertures:
+            k0 = 0
+            for xy_l in xy_all:
+                k1 = k0 + xy_l.shape[0]
+                rad = float(np.max(np.hypot(xy_l[:, 0], xy_l[:, 1]))) if xy_l.shape[0] else 5.0
+                fields.append(Field(beam=beam, spots=spots[k0:k1].copy(),
+                                    polygon=circle_polygon(2.0 * max(rad, 5.0), n_vertices),
+                                    block=Block(30.0, 8.5, 150.0), rs=RangeShifter(45.0, 61.0, 190.0)))
+                k0 = k1
+            continue
         poly = circle_polygon(2.0 * (r + 5.0), n_vertices)
         fields.append(Field(beam=beam, spots=spots, polygon=poly,
                             block=Block(30.0, 8.5, 150.0), rs=RangeShifter(45.0, 61.0, 190.0)))

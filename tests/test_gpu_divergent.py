@@ -1,5 +1,6 @@
-"""Divergent aperture block and virtual source (NEXT-2, the paper's next step
-in its Discussion) on the GPU against the FP64 oracle, through the C ABI.
+"""Divergent aperture block, virtual source and energy-layer-specific
+apertures (NEXT-2, the paper's next steps in its Discussion) on the GPU
+against the FP64 oracle, through the C ABI.
 
 Workload: config 2 geometry (water, 30 mm brass block 50 mm upstream of the
 surface, 20 mm circular opening, 45 mm WET range shifter) with the beam
@@ -94,3 +95,22 @@ def test_far_focus_and_far_source_match_the_parallel_geometry(eng):
     qa = a[0].astype(np.float64) * 2.0 ** -a[1]
     qb = b[0].astype(np.float64) * 2.0 ** -b[1]
     assert np.abs(qa - qb).sum() <= 1e-5 * qa.sum()
+
+
+def test_straight_parity_layer_aperture_head_ct(eng, orc):
+    """Energy-layer-specific apertures (one field per energy layer, opening =
+    the target's cross-section at the layer's depth + 5 mm): straight-mode
+    parity on the head CT for the layer with the smallest opening and for a
+    central one."""
+    from test_gpu_parity import assert_straight_parity
+    g = I.head_ct(0, shape=(128, 128, 80), spacing=(2.0, 2.0, 2.0))
+    c = I.config3(8.0, 400, physics=0, geometry=g, gantries=(90.0,), layer_apertures=True, n_vertices=32)
+    radii = [float(np.abs(f.polygon).max()) for f in c.fields]
+    for fi in (int(np.argmin(radii)), int(np.argmax(radii))):
+        sub = I.Case(f"layer{fi}", g, [c.fields[fi]], c.scenarios, physics=0)
+        f = sub.fields[0]
+        f.spots = f.spots[:: max(1, len(f.spots) // 24)]
+        say(f"case head layer aperture field {fi} radius {radii[fi]:.1f} spots={len(f.spots)}")
+        qg, kg, _, _, _ = gpu_q(eng, sub)
+        qo, _, ko = orc.run_tally(sub)
+        assert_straight_parity(qg, kg, qo, ko, ambiguous_mask(orc, sub))
