@@ -90,6 +90,9 @@ def parse():
     ap.add_argument("--shape", default="", help="HPL,BLOCKS,THREADS: fixed work-queue launch shape (no autotune)")
     ap.add_argument("--oracle-suite", action="store_true",
                     help="time the oracle beside the GPU on config 1 and two config-2 cases (not the bench line)")
+    ap.add_argument("--resolution-study", action="store_true",
+                    help="the head IM on 1x1x2, 1x1x1 and 2x2x2 mm grids and the coarse doses' gamma against "
+                         "1 mm (not the bench line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="before the workload, run three plain 256 MiB device copies (HBM counter calibration)")
     return ap.parse_args()
@@ -258,6 +261,84 @@ def optimizer_measure(eng, case, I, V, np, torch, a, shape):
                          "alg_bytes_per_iteration": alg}}
 
 
+def resolution_study(a, np):
+    """Dose-grid resolution (the paper's 2 mm vs 1 mm observation, Discussion;
+    IM memory, SURVEY's NEXT-4): the head case's spots, fields and scenarios
+    on CT grids of 1x1x2, 1x1x1 and 2x2x2 mm over the same 256x256x320 mm
+    volume, the same VPs per spot everywhere.  Per grid: seconds per
+    13-scenario IM (one warm-up, one timed), non-zeros, CSR bytes, U of the
+    uniform-weight plan dose; then the plan dose (4x the VPs) of the coarse
+    grids, read as constant over each coarse voxel and trilinear between the
+    coarse voxels' centres, against the 1 mm dose: global gamma 2 %/2 mm and
+    1 %/1 mm (10 % threshold) over the bounding box of the 10 % region, the
+    fraction of voxels within 2 % of the maximum in the high-dose (>= 50 %)
+    and 10-50 % regions, the high-dose mean ratio.  Prints one JSON line (not
+    the bench line)."""
+    import torch
+    from paper_2307_01416_amd import inputs as I
+    from paper_2307_01416_amd import vpmc as V
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gamma import gamma_pass_rate
+    base = I.config4(a.target_cc, int(a.histories_per_spot))
+    ext = (256.0, 256.0, 320.0)
+    grids = {"1x1x2": (1.0, 1.0, 2.0), "1x1x1": (1.0, 1.0, 1.0), "2x2x2": (2.0, 2.0, 2.0)}
+    eng = V.Engine(0)
+    out, doses = {}, {}
+    for name, sp in grids.items():
+        shape = tuple(int(round(e / h)) for e, h in zip(ext, sp))
+        case = I.Case(f"head_{name}", I.head_ct(0, shape=shape, spacing=sp), base.fields, base.scenarios,
+                      seed=base.seed, physics=base.physics)
+        eng.load_case(case)
+        for rep_ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rp, col, val, _, _ = eng.run_csr(case, device_out=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            nnz = int(col.numel())
+            del rp, col, val
+        u = plan_uncertainty(eng, case, I, V, np)
+        d, _ = plan_dose(eng, case, I, mult=4)
+        doses[name] = d.cpu().numpy().reshape(shape[::-1])
+        out[name] = {"shape": shape, "s_per_13_scenario_im": dt, "nnz": nnz, "csr_gb_int32_fp32": 8e-9 * nnz,
+                     "plan_dose_uncertainty": u}
+        progress(f"resolution {name}: {dt:.2f} s per IM, nnz {nnz}, U {u:.4f}")
+    eng.close()
+    ref = doses["1x1x1"]
+    m = np.argwhere(ref >= 0.1 * ref.max())
+    lo = np.maximum(m.min(0) - 3, 0)
+    hi = np.minimum(m.max(0) + 4, ref.shape)
+    box = tuple(slice(l, h) for l, h in zip(lo, hi))
+    from scipy.ndimage import map_coordinates
+    rb = ref[box]
+    hi_region = rb >= 0.5 * ref.max()
+    mid_region = (rb >= 0.1 * ref.max()) & ~hi_region
+    for name in ("1x1x2", "2x2x2"):
+        fx, fy, fz = (int(round(h)) for h in grids[name])
+        res = {}
+        # the coarse dose read as constant over each coarse voxel, and
+        # trilinear between the coarse voxels' centres
+        zz, yy, xx = np.meshgrid(*[np.arange(l, h) for l, h in zip(lo, hi)], indexing="ij")
+        cz, cy, cx = (zz + 0.5) / fz - 0.5, (yy + 0.5) / fy - 0.5, (xx + 0.5) / fx - 0.5
+        evs = {"constant": np.repeat(np.repeat(np.repeat(doses[name], fz, 0), fy, 1), fx, 2)[box],
+               "trilinear": map_coordinates(doses[name].astype(np.float64), [cz, cy, cx], order=1, mode="nearest")}
+        for how, ev in evs.items():
+            g22 = gamma_pass_rate(rb, ev, (1.0, 1.0, 1.0), 0.02, 2.0)
+            g11 = gamma_pass_rate(rb, ev, (1.0, 1.0, 1.0), 0.01, 1.0)
+            d = np.abs(ev - rb) / ref.max()
+            res[how] = {"gamma_2pct_2mm": g22, "gamma_1pct_1mm": g11,
+                        "within_2pct_of_max_high_dose": float((d[hi_region] <= 0.02).mean()),
+                        "within_2pct_of_max_10_50pct": float((d[mid_region] <= 0.02).mean()),
+                        "high_dose_mean_ratio": float(ev[hi_region].mean() / rb[hi_region].mean())}
+            progress(f"{name} ({how}) vs 1x1x1: gamma 2%/2mm {g22:.4f}, 1%/1mm {g11:.4f}, "
+                     f"|dD| <= 2% of max: high {res[how]['within_2pct_of_max_high_dose']:.4f} "
+                     f"10-50% {res[how]['within_2pct_of_max_10_50pct']:.4f}, "
+                     f"high-dose mean ratio {res[how]['high_dose_mean_ratio']:.4f}")
+        out[name]["vs_1mm"] = res
+    print(json.dumps({"study": "dose-grid resolution of the head IM", "histories_per_spot": a.histories_per_spot,
+                      "grids": out}), flush=True)
+
+
 def cpu_baseline(case, seconds, np):
     """The oracle on a bounded sample of the same workload: nominal scenario,
     first field, every 10th spot, the same VP count per spot, grown until
@@ -340,6 +421,10 @@ def main():
     if a.oracle_suite:
         import numpy as np
         oracle_suite(np)
+        return
+    if a.resolution_study:
+        import numpy as np
+        resolution_study(a, np)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path is not built",

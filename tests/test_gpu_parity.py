@@ -165,12 +165,14 @@ def test_straight_parity_water_aperture(eng, orc, opening, rs):
     np.testing.assert_allclose(lg[1:3], e_or[1:3], rtol=1e-5, atol=1e-9 * e_or.sum())
 
 
-def test_straight_parity_head_ct(eng, orc):
-    g = I.head_ct(0, shape=(128, 128, 80), spacing=(2.0, 2.0, 2.0))
+@pytest.mark.parametrize("grid", [((128, 128, 80), (2.0, 2.0, 2.0)), ((256, 256, 320), (1.0, 1.0, 1.0))])
+def test_straight_parity_head_ct(eng, orc, grid):
+    """Head CT at 2 mm and at 1 mm (the resolution study's finest grid)."""
+    g = I.head_ct(0, shape=grid[0], spacing=grid[1])
     c = I.config3(8.0, 400, physics=0, geometry=g, gantries=(90.0,))
     f = c.fields[0]
     f.spots = f.spots[:: max(1, len(f.spots) // 24)]
-    say(f"case head straight spots={len(f.spots)}")
+    say(f"case head straight grid={grid[1]} spots={len(f.spots)}")
     qg, kg, _, _, _ = gpu_q(eng, c)
     qo, _, ko = orc.run_tally(c)
     assert_straight_parity(qg, kg, qo, ko, ambiguous_mask(orc, c))
