@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--sur-samples", type=int, default=3_000_000)
     ap.add_argument("--sur-epochs", type=int, default=6)
     ap.add_argument("--no-optimize", action="store_true", help="skip the spot-weight optimiser measurement")
+    ap.add_argument("--dynamic-spacing", action="store_true",
+                    help="also merge the head IM into coarser cells away from the target (dynamic voxel spacing)")
     ap.add_argument("--layer-apertures", action="store_true",
                     help="energy-layer-specific apertures: one field per energy layer (30 fields)")
     ap.add_argument("--divergent", type=float, default=0.0, metavar="MM",
@@ -259,6 +261,37 @@ def optimizer_measure(eng, case, I, V, np, torch, a, shape):
                          "traffic": measured_traffic(OPT_PROFILE, OPT_SRC, "traffic_bytes_per_iteration"),
                          "kernel": "opt_forward_kernel + opt_grad_kernel (one iteration)",
                          "alg_bytes_per_iteration": alg}}
+
+
+def dynamic_spacing_measure(eng, case, I, V, np, torch, a, shape):
+    """Dynamic voxel spacing (coarser IM cells away from the target) of the
+    head IM: rows merged into cells of 1 (target), 2 (organ at risk) and 4 or
+    8 (elsewhere) voxels along x, on the device; cells, entries, time of the
+    merge (both passes, map checks included)."""
+    rp, col, val, _, _ = eng.run_csr(case, device_out=True, **shape)
+    k = V.vpmc_last_tally_k(eng.ctx)
+    nnz = int(col.numel())
+    del val
+    q = torch.empty(nnz, dtype=torch.int64, device=col.device)
+    V.vpmc_copy_csr(eng.ctx, None, None, q)
+    roi = I.head_structures(case, a.target_cc)
+    out = {"nnz_voxels": nnz}
+    for other in (4, 8):
+        cmap, n_cells = I.dynamic_spacing_map(case.geometry.shape, roi, target=1, oar=2, other=other)
+        cm = torch.from_numpy(cmap).to(col.device)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rpc, cell, qc, valc = V.vpmc_csr_cells(eng.ctx, rp, col, q, k, cm, n_cells, V.DEVICE_PTRS)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        n_out = int(cell.numel())
+        out[f"target1_oar2_other{other}"] = {"cells": n_cells, "entries": n_out, "entries_ratio": n_out / nnz,
+                                             "gb_int32_fp32": 8e-9 * n_out, "s_merge": dt}
+        progress(f"dynamic spacing (other {other}): {n_cells} cells, {n_out} entries ({n_out / nnz:.3f} of "
+                 f"{nnz}) in {dt:.3f} s")
+        del rpc, cell, qc, valc, cm
+    del rp, col, q
+    return out
 
 
 def resolution_study(a, np):
@@ -558,6 +591,8 @@ def main():
                                                 steps_total / a.steps)
     if not a.no_optimize:
         out["optimizer"] = optimizer_measure(eng, case, I, V, np, torch, a, shape)
+    if a.dynamic_spacing:
+        out["dynamic_spacing"] = dynamic_spacing_measure(eng, case, I, V, np, torch, a, shape)
     if not a.no_cpu_baseline:
         progress("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(case, a.cpu_seconds, np)

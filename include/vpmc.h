@@ -378,6 +378,27 @@ int vpmc_optimize(vpmc_ctx *ctx, const int64_t *row_ptr, const int32_t *col, con
                   int n_spots, int nvox, const uint8_t *roi, const vpmc_opt_params *p, double *x, double *obj_hist,
                   double *step_L, float *dose_gy);
 
+/* Dynamic voxel spacing of influence matrices (the planning system keeps
+ * organs at risk on coarser voxels to save IM memory, Methods C): merges the
+ * entries of every row into cells.  A cell is a run of consecutive voxels
+ * (linear index, x fastest): cell_of_voxel [nvox of the loaded geometry] must
+ * start at 0, grow by 0 or 1 from voxel to voxel and end at n_cells - 1.
+ * Input rows: row_ptr [n_rows + 1] non-decreasing, col ascending within a
+ * row, q the int64 fixed-point energies of exponent k (as vpmc_copy_csr's
+ * q_raw and vpmc_last_tally's k).  Output: row_ptr_out [n_rows + 1] (always
+ * written; rows start at 0), then, if any is given, cell_out (ascending cell
+ * ids), q_out (exact int64 sums of the cell's entries) and val_out (FP32 Gy
+ * per unit weight = the cell's energy over its mass, the mass-weighted mean
+ * of its voxels' doses; masses from the loaded geometry), each
+ * row_ptr_out[n_rows] long.  Pointer kind of every array per flags
+ * (VPMC_DEVICE_PTRS).  Errors: VPMC_E_ARG (dims, k outside [0, 62], a bad
+ * map, row_ptr decreasing, a column out of range or not ascending),
+ * VPMC_E_STATE (no geometry; validation-only context), VPMC_E_OOM,
+ * VPMC_E_DEVICE. */
+int vpmc_csr_cells(vpmc_ctx *ctx, const int64_t *row_ptr, int n_rows, const int32_t *col, const int64_t *q, int k,
+                   const int32_t *cell_of_voxel, int n_cells, int64_t *row_ptr_out, int32_t *cell_out,
+                   int64_t *q_out, float *val_out, unsigned flags);
+
 #ifdef __cplusplus
 }
 #endif

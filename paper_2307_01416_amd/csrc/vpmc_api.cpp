@@ -146,6 +146,8 @@ struct vpmc_ctx {
     DevBuf opt_rp, opt_col, opt_val, opt_roi, opt_amax, opt_cnt, opt_rcnt, opt_crp, opt_ccol, opt_cval, opt_piece,
         opt_poff, opt_resid, opt_fpart, opt_gpart, opt_vec, opt_scal, opt_err, opt_hist, opt_dose;
     long long opt_npieces = 0;
+    // dynamic voxel spacing (vpmc_csr_cells)
+    DevBuf cl_rp, cl_map, cl_start, cl_mass, cl_cnt, cl_out, cl_col, cl_q, cl_ocell, cl_oq, cl_oval;
     bool opt_valid = false;
     int opt_dims[5] = {0, 0, 0, 0, 0};   // n_scen, n_spots, row_stride, row_offset, nvox
     std::vector<int64_t> opt_rp_host;
@@ -1044,7 +1046,9 @@ void vpmc_destroy(vpmc_ctx *c) {
                           &c->opt_poff, &c->opt_resid, &c->opt_fpart, &c->opt_gpart, &c->opt_vec, &c->opt_scal,
                           &c->opt_err, &c->opt_hist, &c->opt_dose, &c->opt_broi.off, &c->opt_broi.key,
                           &c->opt_broi.val, &c->opt_broi.work, &c->opt_bfull.off, &c->opt_bfull.key,
-                          &c->opt_bfull.val, &c->opt_bfull.work})
+                          &c->opt_bfull.val, &c->opt_bfull.work, &c->cl_rp, &c->cl_map, &c->cl_start,
+                          &c->cl_mass, &c->cl_cnt, &c->cl_out, &c->cl_col, &c->cl_q, &c->cl_ocell, &c->cl_oq,
+                          &c->cl_oval})
             release(*b);
         for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -1920,5 +1924,114 @@ int vpmc_optimize(vpmc_ctx *c, const int64_t *row_ptr, const int32_t *col, const
     HIP_TRY(hipMemcpyAsync(&L, O.scal + kOptL, 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (step_L) *step_L = L;
+    return VPMC_OK;
+}
+
+int vpmc_csr_cells(vpmc_ctx *c, const int64_t *row_ptr, int n_rows, const int32_t *col, const int64_t *q, int k,
+                   const int32_t *cell_of_voxel, int n_cells, int64_t *row_ptr_out, int32_t *cell_out,
+                   int64_t *q_out, float *val_out, unsigned flags) {
+    if (!c) return fail(VPMC_E_ARG, "ctx is NULL");
+    if (!row_ptr || !cell_of_voxel || !row_ptr_out) return fail(VPMC_E_ARG, "row_ptr, cell_of_voxel and row_ptr_out are required");
+    if (n_rows < 0 || (long long)n_rows * 64 >= (1ll << 31)) return fail(VPMC_E_ARG, "n_rows outside [0, 2^25)");
+    if (k < 0 || k > 62) return fail(VPMC_E_ARG, "k outside [0, 62]");
+    if (n_cells < 1) return fail(VPMC_E_ARG, "n_cells must be >= 1");
+    if (flags & ~VPMC_DEVICE_PTRS) return fail(VPMC_E_ARG, "unknown flags");
+    if (!c->has_geom) return fail(VPMC_E_STATE, "no geometry loaded");
+    const bool dev = (flags & VPMC_DEVICE_PTRS) != 0;
+    const int nvox = (int)c->nvox;
+    std::vector<int64_t> rp((size_t)n_rows + 1);
+    std::vector<int32_t> cmap((size_t)nvox);
+    if (dev) {
+        if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
+        HIP_TRY(hipSetDevice(c->device));
+        HIP_TRY(hipMemcpy(rp.data(), row_ptr, rp.size() * 8, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(cmap.data(), cell_of_voxel, cmap.size() * 4, hipMemcpyDeviceToHost));
+    } else {
+        memcpy(rp.data(), row_ptr, rp.size() * 8);
+        memcpy(cmap.data(), cell_of_voxel, cmap.size() * 4);
+    }
+    if (rp[0] < 0) return fail(VPMC_E_ARG, "row_ptr[0] < 0");
+    for (size_t r = 0; r + 1 < rp.size(); ++r)
+        if (rp[r + 1] < rp[r]) return fail(VPMC_E_ARG, "row_ptr decreases at row %zu", r);
+    // cells: runs of consecutive voxels, numbered 0 .. n_cells-1 in order
+    if (cmap[0] != 0 || cmap[(size_t)nvox - 1] != n_cells - 1)
+        return fail(VPMC_E_ARG, "cell map must start at 0 and end at n_cells - 1");
+    std::vector<int32_t> cstart((size_t)n_cells + 1);
+    cstart[0] = 0;
+    for (int v = 1; v < nvox; ++v) {
+        const int d = cmap[(size_t)v] - cmap[(size_t)v - 1];
+        if (d != 0 && d != 1) return fail(VPMC_E_ARG, "cell map must grow by 0 or 1 from voxel to voxel (voxel %d)", v);
+        if (d == 1) cstart[(size_t)cmap[(size_t)v]] = v;
+    }
+    cstart[(size_t)n_cells] = nvox;
+    const long long nnz = rp[(size_t)n_rows] - rp[0];
+    if (nnz > 0 && (!col || !q)) return fail(VPMC_E_ARG, "col and q are required");
+    if (!dev && nnz > 0) {
+        for (long long i = rp[0]; i < rp[(size_t)n_rows]; ++i)
+            if ((unsigned)col[i] >= (unsigned)nvox) return fail(VPMC_E_ARG, "column %lld out of range", i);
+    }
+    if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
+    HIP_TRY(hipSetDevice(c->device));
+    int rc;
+    const size_t R = (size_t)n_rows;
+    if ((rc = ensure(c, c->cl_rp, (R + 1) * 8, 0))) return rc;
+    if ((rc = ensure(c, c->cl_map, (size_t)nvox * 4, 0))) return rc;
+    if ((rc = ensure(c, c->cl_start, ((size_t)n_cells + 1) * 4, 0))) return rc;
+    if ((rc = ensure(c, c->cl_mass, (size_t)n_cells * 8, 0))) return rc;
+    if ((rc = ensure(c, c->cl_cnt, std::max<size_t>(R, 1) * 8, 0))) return rc;
+    if ((rc = ensure(c, c->cl_out, (R + 1) * 8, 0))) return rc;
+    if ((rc = ensure(c, c->flags, 4, 0))) return rc;
+    HIP_TRY(hipMemcpy(c->cl_rp.ptr, rp.data(), rp.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->cl_map.ptr, cmap.data(), cmap.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->cl_start.ptr, cstart.data(), cstart.size() * 4, hipMemcpyHostToDevice));
+    const int32_t *d_col = col;
+    const long long *d_q = (const long long *)q;
+    if (!dev && nnz > 0) {
+        // host rows: the used range [rp[0], rp[n_rows]) is staged; offsets stay as given
+        if ((rc = ensure(c, c->cl_col, (size_t)rp[R] * 4, 0))) return rc;
+        if ((rc = ensure(c, c->cl_q, (size_t)rp[R] * 8, 0))) return rc;
+        HIP_TRY(hipMemcpy(c->cl_col.ptr, col, (size_t)rp[R] * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->cl_q.ptr, q, (size_t)rp[R] * 8, hipMemcpyHostToDevice));
+        d_col = (const int32_t *)c->cl_col.ptr;
+        d_q = (const long long *)c->cl_q.ptr;
+    }
+    HIP_TRY(hipMemset(c->flags.ptr, 0, 4));
+    HIP_TRY(launch_cell_count((const long long *)c->cl_rp.ptr, n_rows, d_col, (const int32_t *)c->cl_map.ptr, nvox,
+                              (unsigned long long *)c->cl_cnt.ptr, (unsigned *)c->flags.ptr, nullptr));
+    std::vector<unsigned long long> cnt(std::max<size_t>(R, 1));
+    unsigned err = 0;
+    if (R) HIP_TRY(hipMemcpy(cnt.data(), c->cl_cnt.ptr, R * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&err, c->flags.ptr, 4, hipMemcpyDeviceToHost));
+    if (err & 1u) return fail(VPMC_E_ARG, "a column index is outside [0, nvox)");
+    if (err & 2u) return fail(VPMC_E_ARG, "columns are not ascending within a row");
+    std::vector<int64_t> op(R + 1);
+    op[0] = 0;
+    for (size_t r = 0; r < R; ++r) op[r + 1] = op[r] + (int64_t)cnt[r];
+    HIP_TRY(hipMemcpy(row_ptr_out, op.data(), op.size() * 8, dev ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+    const long long nout = op[R];
+    if (!cell_out && !q_out && !val_out) return VPMC_OK;
+    HIP_TRY(hipMemcpy(c->cl_out.ptr, op.data(), op.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(launch_cell_mass(c->geom, (const int32_t *)c->cl_start.ptr, n_cells, (double *)c->cl_mass.ptr, nullptr));
+    int32_t *ocell = cell_out;
+    long long *oq = (long long *)q_out;
+    float *oval = val_out;
+    if (!dev) {
+        const size_t n1 = (size_t)std::max(nout, 1ll);
+        if (cell_out && (rc = ensure(c, c->cl_ocell, n1 * 4, 0))) return rc;
+        if (q_out && (rc = ensure(c, c->cl_oq, n1 * 8, 0))) return rc;
+        if (val_out && (rc = ensure(c, c->cl_oval, n1 * 4, 0))) return rc;
+        ocell = cell_out ? (int32_t *)c->cl_ocell.ptr : nullptr;
+        oq = q_out ? (long long *)c->cl_oq.ptr : nullptr;
+        oval = val_out ? (float *)c->cl_oval.ptr : nullptr;
+    }
+    HIP_TRY(launch_cell_emit((const long long *)c->cl_rp.ptr, n_rows, d_col, d_q, (const int32_t *)c->cl_map.ptr,
+                             (const long long *)c->cl_out.ptr, (const double *)c->cl_mass.ptr, ldexp(MEV_TO_J, -k),
+                             ocell, oq, oval, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    if (!dev && nout > 0) {
+        if (cell_out) HIP_TRY(hipMemcpy(cell_out, ocell, (size_t)nout * 4, hipMemcpyDeviceToHost));
+        if (q_out) HIP_TRY(hipMemcpy(q_out, oq, (size_t)nout * 8, hipMemcpyDeviceToHost));
+        if (val_out) HIP_TRY(hipMemcpy(val_out, oval, (size_t)nout * 4, hipMemcpyDeviceToHost));
+    }
     return VPMC_OK;
 }

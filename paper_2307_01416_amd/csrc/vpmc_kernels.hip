@@ -1624,6 +1624,121 @@ __global__ void csr_values_kernel(const int32_t *col, const long long *qv, size_
     }
 }
 
+// ------------------------------------------------------------ dynamic voxel spacing
+// Influence-matrix rows merged into cells (the planning system's coarser
+// voxels for organs at risk, Methods C): a cell is a run of consecutive
+// voxels given by a non-decreasing voxel -> cell map, cstart[c] its first
+// voxel.  Cell mass (kg) = the sum of its voxels' masses, in voxel order.
+__global__ void cell_mass_kernel(GeomDev g, const int32_t *cstart, int n_cells, double *mass) {
+    const double vol_kg = (double)g.sp[0] * (double)g.sp[1] * (double)g.sp[2] * 1e-6;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n_cells; c += gridDim.x * blockDim.x) {
+        double m = 0.0;
+        for (int v = cstart[c]; v < cstart[c + 1]; ++v) {
+            float rho = 1.0f;
+            int mm;
+            if (g.kind == 1) hu_material(g.hu[v], mm, rho);
+            m += (double)rho;
+        }
+        mass[c] = m * vol_kg;
+    }
+}
+
+// cells per row (wavefront per row); flags columns outside the grid (bit 1)
+// and columns not ascending within a row (bit 2)
+__global__ __launch_bounds__(256) void cell_count_kernel(const long long *rp, int n_rows, const int32_t *col,
+                                                         const int32_t *cmap, int nvox, unsigned long long *cnt,
+                                                         unsigned *err) {
+    const int r = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
+    if (r >= n_rows) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const long long b = rp[r], e = rp[r + 1];
+    int carry = -1, carry_col = -1;
+    unsigned long long n = 0;
+    for (long long i0 = b; i0 < e; i0 += 64) {
+        const long long i = i0 + lane;
+        const bool valid = i < e;
+        int c = -1, v = -1;
+        if (valid) {
+            v = col[i];
+            if ((unsigned)v >= (unsigned)nvox) atomicOr(err, 1u);
+            else c = cmap[v];
+        }
+        int pv = __shfl_up(v, 1);
+        int pc = __shfl_up(c, 1);
+        if (lane == 0) {
+            pv = carry_col;
+            pc = carry;
+        }
+        if (valid && i > b && v <= pv) atomicOr(err, 2u);
+        n += (unsigned long long)__popcll(__ballot(valid && c >= 0 && c != pc));
+        carry = __shfl(c, 63);
+        carry_col = __shfl(v, 63);
+    }
+    if (lane == 0) cnt[r] = n;
+}
+
+// merged rows: a wavefront per row, segmented sums of the int64 energies over
+// each run of one cell (exact), carried across 64-entry windows; the value is
+// the cell's energy over its mass
+__global__ __launch_bounds__(256) void cell_emit_kernel(const long long *rp, int n_rows, const int32_t *col,
+                                                        const long long *q, const int32_t *cmap,
+                                                        const long long *out_ptr, const double *mass,
+                                                        double mev_scale, int32_t *ocell, long long *oq,
+                                                        float *oval) {
+    const int r = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
+    if (r >= n_rows) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const long long b = rp[r], e = rp[r + 1];
+    const long long o0 = out_ptr[r], o1 = out_ptr[r + 1];
+    int carry_cell = -1;
+    long long carry_sum = 0, starts_before = 0;
+    for (long long i0 = b; i0 < e; i0 += 64) {
+        const long long i = i0 + lane;
+        const bool valid = i < e;
+        const int c = valid ? cmap[col[i]] : -1;
+        long long x = valid ? q[i] : 0;
+        int pc = __shfl_up(c, 1);
+        if (lane == 0) pc = carry_cell;
+        const bool start = valid && c != pc;
+        // the run left open at the end of the last window: continued by
+        // lane 0 (its sum carried in), or ended there (written now)
+        if (lane == 0 && valid && !start) x += carry_sum;
+        if (lane == 0 && start && carry_cell >= 0) {
+            const long long pos = o0 + starts_before - 1;
+            if (pos >= o0 && pos < o1) {
+                if (ocell) ocell[pos] = carry_cell;
+                if (oq) oq[pos] = carry_sum;
+                if (oval) oval[pos] = (float)((double)carry_sum * mev_scale / mass[carry_cell]);
+            }
+        }
+        long long sum = x;
+        int f = start ? 1 : 0;
+        for (int d = 1; d < 64; d <<= 1) {
+            const long long so = __shfl_up(sum, d);
+            const int fo = __shfl_up(f, d);
+            if (lane >= d && !f) sum += so;
+            if (lane >= d) f |= fo;
+        }
+        const unsigned long long m = __ballot(start);
+        const long long last = (e - i0 < 64 ? e - i0 : 64) - 1;
+        const bool next_start = __shfl_down(start ? 1 : 0, 1) != 0;
+        const bool final_window = i0 + 64 >= e;
+        const bool ends = valid && ((lane < last && next_start) || (lane == last && final_window));
+        if (ends) {
+            const long long idx = starts_before + (long long)__popcll(m & ((2ull << lane) - 1ull)) - 1;
+            const long long pos = o0 + idx;
+            if (pos >= o0 && pos < o1) {
+                if (ocell) ocell[pos] = c;
+                if (oq) oq[pos] = sum;
+                if (oval) oval[pos] = (float)((double)sum * mev_scale / mass[c]);
+            }
+        }
+        carry_cell = __shfl(c, 63);
+        carry_sum = __shfl(sum, 63);
+        starts_before += (long long)__popcll(m);
+    }
+}
+
 // ------------------------------------------------------------ surrogate data
 // Plain brass traversals for the surrogate's training data: each entry state
 // (x, y on the block's upstream face, direction cosines u, v, energy) crosses
@@ -2020,6 +2135,30 @@ hipError_t launch_csr_values(const int32_t *col, const long long *qv, size_t n, 
     return hipGetLastError();
 }
 
+
+hipError_t launch_cell_mass(const GeomDev &g, const int32_t *cstart, int n_cells, double *mass, hipStream_t s) {
+    const int blocks = std::max(1, std::min((n_cells + 255) / 256, 8192));
+    hipLaunchKernelGGL(cell_mass_kernel, dim3(blocks), dim3(256), 0, s, g, cstart, n_cells, mass);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_count(const long long *rp, int n_rows, const int32_t *col, const int32_t *cmap, int nvox,
+                             unsigned long long *cnt, unsigned *err, hipStream_t s) {
+    if (n_rows == 0) return hipSuccess;
+    const int blocks = (int)(((long long)n_rows * 64 + 255) / 256);
+    hipLaunchKernelGGL(cell_count_kernel, dim3(blocks), dim3(256), 0, s, rp, n_rows, col, cmap, nvox, cnt, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_emit(const long long *rp, int n_rows, const int32_t *col, const long long *q,
+                            const int32_t *cmap, const long long *out_ptr, const double *mass, double mev_scale,
+                            int32_t *ocell, long long *oq, float *oval, hipStream_t s) {
+    if (n_rows == 0) return hipSuccess;
+    const int blocks = (int)(((long long)n_rows * 64 + 255) / 256);
+    hipLaunchKernelGGL(cell_emit_kernel, dim3(blocks), dim3(256), 0, s, rp, n_rows, col, q, cmap, out_ptr, mass,
+                       mev_scale, ocell, oq, oval);
+    return hipGetLastError();
+}
 
 hipError_t launch_sur_resume(const GeomDev &g, const FieldDev &f, const LaunchDev &L, const DeferRec *rec,
                              const float *out, unsigned long long n, float p_lo, float p_hi, hipStream_t s) {

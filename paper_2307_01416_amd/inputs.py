@@ -537,3 +537,27 @@ def head_structures(case: Case, target_cc: float = 8.0, oar_radius_mm: float = 8
     roi[(X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2 <= r * r] |= 1
     roi[(X - co[0]) ** 2 + (Y - co[1]) ** 2 + (Z - co[2]) ** 2 <= oar_radius_mm ** 2] |= 2
     return roi.ravel()
+
+
+def dynamic_spacing_map(shape, roi: np.ndarray, target: int = 1, oar: int = 2, other: int = 4):
+    """Voxel -> cell map for dynamic voxel spacing of the influence matrices
+    along x (runs of consecutive voxels, never across an x row): target
+    voxels (roi bit 0) in runs of `target`, organ-at-risk voxels (bit 1) in
+    runs of `oar`, all others in runs of `other`; a run ends where the
+    voxels' class changes.  Returns (int32 map [nvox], number of cells)."""
+    nx, ny, nz = shape
+    cls = np.where((roi & 1) != 0, 0, np.where((roi & 2) != 0, 1, 2)).reshape(nz * ny, nx)
+    width = np.array([target, oar, other], np.int64)
+    # start of a new cell: first voxel of an x row, a class change, or the
+    # run of its class reaching its width
+    start = np.zeros((nz * ny, nx), bool)
+    start[:, 0] = True
+    start[:, 1:] = cls[:, 1:] != cls[:, :-1]
+    run = np.zeros(nz * ny, np.int64)
+    for i in range(nx):
+        run = np.where(start[:, i], 0, run + 1)
+        w = width[cls[:, i]]
+        hit = (run % w == 0) & ~start[:, i]
+        start[:, i] |= hit
+    cmap = np.cumsum(start.ravel()) - 1
+    return cmap.astype(np.int32), int(cmap[-1]) + 1

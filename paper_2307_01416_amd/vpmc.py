@@ -121,6 +121,7 @@ def load() -> C.CDLL:
         "vpmc_surrogate_train": (i, [vp, vp, vp, vp, i, i, i, C.c_float, C.c_uint64, vp]),
         "vpmc_atomic_rate": (i, [vp, i, i, i, C.c_uint64, f64p]),
         "vpmc_optimize": (i, [vp, vp, vp, vp, i, i, i, vp, vp, vp, vp, f64p, vp]),
+        "vpmc_csr_cells": (i, [vp, vp, i, vp, vp, i, vp, i, vp, vp, vp, vp, u]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -324,6 +325,31 @@ def vpmc_optimize(ctx, row_ptr, col, val, n_scen: int, n_spots: int, nvox: int, 
     _check(load().vpmc_optimize(ctx, _ptr(row_ptr), _ptr(col), _ptr(val), int(n_scen), int(n_spots), int(nvox),
                                 _ptr(roi), C.byref(p), _ptr(x), _ptr(obj_hist), C.byref(L), _ptr(dose)), ctx)
     return L.value
+
+
+def vpmc_csr_cells(ctx, row_ptr, col, q, k: int, cell_of_voxel, n_cells: int, flags: int = 0):
+    """Rows merged into cells (dynamic voxel spacing): (row_ptr, cell, q,
+    val) as numpy arrays, or torch CUDA tensors with flags |= DEVICE_PTRS."""
+    n_rows = len(row_ptr) - 1
+    L = load()
+    if flags & DEVICE_PTRS:
+        import torch
+        dev = row_ptr.device
+        rp_out = torch.empty(n_rows + 1, dtype=torch.int64, device=dev)
+    else:
+        rp_out = np.zeros(n_rows + 1, np.int64)
+    _check(L.vpmc_csr_cells(ctx, _ptr(row_ptr), n_rows, _ptr(col), _ptr(q), int(k), _ptr(cell_of_voxel),
+                            int(n_cells), _ptr(rp_out), None, None, None, flags), ctx)
+    nout = int(rp_out[-1])
+    if flags & DEVICE_PTRS:
+        cell = torch.empty(nout, dtype=torch.int32, device=dev)
+        qo = torch.empty(nout, dtype=torch.int64, device=dev)
+        val = torch.empty(nout, dtype=torch.float32, device=dev)
+    else:
+        cell, qo, val = np.zeros(nout, np.int32), np.zeros(nout, np.int64), np.zeros(nout, np.float32)
+    _check(L.vpmc_csr_cells(ctx, _ptr(row_ptr), n_rows, _ptr(col), _ptr(q), int(k), _ptr(cell_of_voxel),
+                            int(n_cells), _ptr(rp_out), _ptr(cell), _ptr(qo), _ptr(val), flags), ctx)
+    return rp_out, cell, qo, val
 
 
 def vpmc_last_stats(ctx) -> dict:

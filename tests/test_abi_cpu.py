@@ -195,3 +195,23 @@ def test_divergence_validation(vctx):
     V.vpmc_set_aperture(vctx, 1, f)
     assert L.vpmc_set_divergence(vctx, 1, 0.0, 2000.0) == V.E_ARG        # focus without a block
     assert L.vpmc_set_divergence(vctx, 1, 2000.0, 0.0) == V.VPMC_OK
+
+
+def test_csr_cells_validation(vctx):
+    """Argument checks before any device work (the map is checked against the
+    loaded geometry on the GPU, in tests/test_gpu_cells.py)."""
+    L = V.load()
+    rp = np.array([0, 2, 3], np.int64)
+    col = np.array([1, 5, 2], np.int32)
+    q = np.array([7, 8, 9], np.int64)
+    out = np.zeros(3, np.int64)
+    cmap = (np.arange(4096) // 2).astype(np.int32)
+    P = V._ptr
+    call = lambda rp_=rp, k=30, n=2048, flags=0: L.vpmc_csr_cells(vctx, P(rp_), 2, P(col), P(q), k, P(cmap), n,
+                                                                   P(out), None, None, None, flags)
+    assert call(k=63) == V.E_ARG
+    assert call(k=-1) == V.E_ARG
+    assert call(n=0) == V.E_ARG
+    assert call(flags=8) == V.E_ARG
+    assert call(rp_=None) == V.E_ARG
+    assert call() == V.E_STATE            # no geometry (a validation-only context has none)
