@@ -569,6 +569,9 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     Q.key0 = (uint32_t)(o->seed & 0xffffffffu);
     Q.seed_hi = (uint32_t)(o->seed >> 32);
     Q.physics = o->physics;
+    Q.div = 0;
+    for (const FieldDev &fd : ftab)
+        if (fd.div || fd.vsad > 0.0f) Q.div = 1;
     Q.grid = (unsigned long long *)c->slot_grid.ptr;
     Q.mark = (uint8_t *)c->slot_mark.ptr;
     Q.nvox = nvox; Q.nblk = nblk; Q.nchunk = nchunk;

@@ -169,6 +169,7 @@ struct QueueDev {
     const ScenDev *scen;
     uint32_t key0, seed_hi;
     unsigned physics;
+    int div;                              // some field is divergent (virtual source or divergent block)
     unsigned long long *grid;             // [slots][gstride] int64 tallies
     uint8_t *mark;                        // [slots][mstride] touched-block bytes (32 voxels each)
     size_t nvox, nblk, nchunk;            // blocks = ceil(nvox/32), chunks = ceil(blocks/256)

@@ -518,6 +518,28 @@ __device__ __forceinline__ bool no_edge_within(float lb, float lat, float t) {
     return lb > 0.0f && lat * t < lb * (1.0f - 1e-5f) - 1e-4f;
 }
 
+// path length along (u, v) until the beam's-eye-view ray from (x, y) meets an
+// edge (a non-divergent block)
+__device__ __forceinline__ float edge_distance(const float2 *poly, int nv, float x, float y, float u,
+                                               float v) {
+    float best = INFINITY;
+    float2 a = poly[nv - 1];
+    for (int i = 0; i < nv; ++i) {
+        const float2 b = poly[i];
+        const float ex = b.x - a.x, ey = b.y - a.y;
+        const float den = u * ey - v * ex;
+        if (den != 0.0f) {
+            const float wx = a.x - x, wy = a.y - y;
+            const float inv = 1.0f / den;
+            const float t = (wx * ey - wy * ex) * inv;
+            const float lam = (wx * v - wy * u) * inv;
+            if (t > 0.0f && lam >= 0.0f && lam <= 1.0f) best = fminf(best, t);
+        }
+        a = b;
+    }
+    return best;
+}
+
 // Path length along the ray (x, y) + t (u, v) to the first wall of the block
 // (INFINITY if none).  Every wall is the plane through the focus and an edge
 // of the polygon: at opening scale s0 (s = s0 + t kw along the ray) the ray
@@ -544,6 +566,17 @@ __device__ __forceinline__ float edge_distance_div(const float2 *poly, int nv, f
         a = b;
     }
     return best;
+}
+
+// push the projected position EDGE_PUSH_MM further along the projected
+// direction, depth unchanged, across the edge just reached (non-divergent)
+__device__ __forceinline__ void edge_push(Lane &v) {
+    const float n2 = v.dx * v.dx + v.dy * v.dy;
+    if (n2 > 0.0f) {
+        const float k = EDGE_PUSH_MM * rsqrtf(n2);
+        v.px = fmaf(k, v.dx, v.px);
+        v.py = fmaf(k, v.dy, v.py);
+    }
 }
 
 // edge push in the block: along the scaled position's direction of travel
@@ -607,8 +640,10 @@ __device__ int slab_transport(Lane &v, Acc &acc, float scale, const float *tab, 
 
 // Methods B: between the block's entrance and exit planes the crossing
 // number at the VP's projected position decides, at every step, opening
-// (straight transport, no random numbers) or brass (brass tables).
-template <bool X>
+// (straight transport, no random numbers) or brass (brass tables).  D = false
+// compiles the plain (non-divergent) geometry only; D = true handles both, and
+// for a non-divergent block (scale 1, kw = 0) gives the same bits.
+template <bool X, bool D = true>
 __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab, const float2 *poly,
                                int nv, float rho_b, float zu, float zd, DF thick, const FieldDev &f_sdf) {
     v.pz = 0.0f;
@@ -619,7 +654,16 @@ __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab,
         const float tp = tpp.h;
         bool open = false;
         float te = INFINITY;
-        if (nv >= 3) {
+        if (nv >= 3 && !D) {
+            bool inside;
+            const float lb = sdf_bound(f_sdf, v.px, v.py, inside);
+            if (no_edge_within(lb, sqrtf(v.dx * v.dx + v.dy * v.dy), tp)) {
+                open = inside;
+            } else {
+                open = in_polygon(poly, nv, v.px, v.py);
+                te = edge_distance(poly, nv, v.px, v.py, v.dx, v.dy);
+            }
+        } else if (nv >= 3) {
             // opening scale at this depth (1 and kw = 0 for a non-divergent
             // block, where (bx, by) = p_xy and every expression below is the plain
             // beam's-eye-view one)
@@ -651,7 +695,8 @@ __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab,
                 return EX_GONE;
             }
             move<true, X>(v, {te, 0.0f});
-            edge_push_blk(v, f_sdf);
+            if constexpr (D) edge_push_blk(v, f_sdf);
+            else edge_push(v);
             continue;
         }
         const DF dg = te < tp ? DF{te, 0.0f} : tpp;
@@ -668,7 +713,10 @@ __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab,
             ledger_add(acc, L_ESCAPED, v.E + v.Elo, scale);
             return EX_GONE;
         }
-        if (st == ST_GEO) edge_push_blk(v, f_sdf);
+        if (st == ST_GEO) {
+            if constexpr (D) edge_push_blk(v, f_sdf);
+            else edge_push(v);
+        }
         if (v.pz >= thick.h) { v.pz = zd; v.pzlo = 0.0f; return EX_DOWN; }
         if (v.pz <= 0.0f) {
             v.pz = zu;
@@ -704,7 +752,7 @@ __device__ float dist_to_polygon(const float2 *poly, int nv, float x, float y) {
 // on the VP's ray and tmin is the ray parameter of the last exit plane
 enum { BL_STOP = 0, BL_PATIENT = 1, BL_DEFER = 2 };
 
-template <bool X>
+template <bool X, bool D = true>
 __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const float2 *poly,
                         const FieldDev &f, float &tmin, const SurDev *sur = nullptr, uint32_t tag = 0u) {
     tmin = -INFINITY;
@@ -730,7 +778,18 @@ __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const 
         const float qx = fmaf(t, v.dx, v.px), qy = fmaf(t, v.dy, v.py);
         const int nv = f.nv;
         bool open = false, through = false;
-        if (nv >= 3) {
+        if (nv >= 3 && !D) {
+            const float tx = f.blk_t / v.dz;
+            bool inside;
+            const float lb = sdf_bound(f, qx, qy, inside);
+            if (no_edge_within(lb, sqrtf(v.dx * v.dx + v.dy * v.dy), tx)) {
+                open = inside;
+                through = inside;
+            } else {
+                open = in_polygon(poly, nv, qx, qy);
+                through = open && edge_distance(poly, nv, qx, qy, v.dx, v.dy) >= tx;
+            }
+        } else if (nv >= 3) {
             const float tx = f.blk_t / v.dz;
             // opening scale on the upstream face (1, kw = 0: non-divergent)
             const float sc = f.fc0, kw = v.dz * f.fs;
@@ -751,7 +810,7 @@ __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const 
             tmin = (f.blk_zd - v.pz) / v.dz;
             return BL_PATIENT;
         }
-        if (!open && sur && sur->enabled && !f.div) {
+        if (!open && sur && sur->enabled && !(D && f.div)) {
             // enters through brass: far enough from the opening's edge, the
             // learned surrogate takes over the traversal (queued for it)
             const float de = nv >= 3 ? dist_to_polygon(poly, nv, qx, qy) : 1000.0f;
@@ -782,7 +841,7 @@ __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const 
         v.px = qx;
         v.py = qy;
         v.pz = f.blk_zu;
-        if (block_transport<X>(v, acc, scale, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl}, f) !=
+        if (block_transport<X, D>(v, acc, scale, tab, poly, nv, f.blk_rho, f.blk_zu, f.blk_zd, {f.blk_t, f.blk_tl}, f) !=
             EX_DOWN)
             return BL_STOP;
         tmin = 0.0f;
@@ -1166,10 +1225,11 @@ __device__ void tile_flush(long long *tile, const RowDev &row, const QueueDev &Q
 // alone, and the tallies are integer sums: the result does not depend on
 // the schedule.  The only waits between waves are for the wave that is
 // replacing the current row, which does so without waiting on anyone.
-template <bool X>
+template <bool X, bool D>
 // Physics mode: up to 1024 threads (16 waves at <= 128 VGPRs, one workgroup
 // per CU with a ~120 KiB tile); double-float mode: up to 768 (12 waves at
-// <= 168 VGPRs).
+// <= 168 VGPRs).  D: some field of the batch is divergent (virtual source or
+// divergent block); without, the plain geometry is compiled alone.
 __global__ __launch_bounds__(X ? 768 : 1024) void queue_kernel(GeomDev g, QueueDev Q) {
     __shared__ float tab[X ? TAB_FLOATS : TAB_HI_FLOATS];
     __shared__ float2 poly[POLY_LDS];
@@ -1304,9 +1364,9 @@ __global__ __launch_bounds__(X ? 768 : 1024) void queue_kernel(GeomDev g, QueueD
                         v.hist = (uint32_t)h;
                         v.nblk = 0;
                         v.nsteps = 0;
-                        source(v, sp, f.vsad);
+                        source(v, sp, D ? f.vsad : 0.0f);
                         float tmin;
-                        in = beamline<X>(v, acc, sp.scale, tab, fpoly, f, tmin, &Q.sur, (uint32_t)rl) == BL_PATIENT &&
+                        in = beamline<X, D>(v, acc, sp.scale, tab, fpoly, f, tmin, &Q.sur, (uint32_t)rl) == BL_PATIENT &&
                              patient_enter<X>(v, acc, sp.scale, g, f, sc.shift, tmin, ps);
                         if (!in) acc.steps += v.nsteps;
                         acc.hist += 1;
@@ -2069,8 +2129,13 @@ int queue_tile_cap(unsigned physics, int threads) {
 hipError_t launch_queue(const GeomDev &g, const QueueDev &Q, int blocks, int threads, hipStream_t s) {
     threads = queue_threads(Q.physics, threads);
     const size_t tile_bytes = (size_t)Q.tile_cap * sizeof(long long);
-    if (Q.physics == 0) hipLaunchKernelGGL(queue_kernel<true>, dim3(blocks), dim3(threads), tile_bytes, s, g, Q);
-    else hipLaunchKernelGGL(queue_kernel<false>, dim3(blocks), dim3(threads), tile_bytes, s, g, Q);
+    if (Q.physics == 0) {
+        if (Q.div) hipLaunchKernelGGL((queue_kernel<true, true>), dim3(blocks), dim3(threads), tile_bytes, s, g, Q);
+        else hipLaunchKernelGGL((queue_kernel<true, false>), dim3(blocks), dim3(threads), tile_bytes, s, g, Q);
+    } else {
+        if (Q.div) hipLaunchKernelGGL((queue_kernel<false, true>), dim3(blocks), dim3(threads), tile_bytes, s, g, Q);
+        else hipLaunchKernelGGL((queue_kernel<false, false>), dim3(blocks), dim3(threads), tile_bytes, s, g, Q);
+    }
     return hipGetLastError();
 }
 

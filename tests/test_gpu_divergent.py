@@ -114,3 +114,20 @@ def test_straight_parity_layer_aperture_head_ct(eng, orc):
         qg, kg, _, _, _ = gpu_q(eng, sub)
         qo, _, ko = orc.run_tally(sub)
         assert_straight_parity(qg, kg, qo, ko, ambiguous_mask(orc, sub))
+
+
+@pytest.mark.parametrize("physics", [0, I.PHYS_ALL])
+def test_divergent_csr_rows_sum_to_dense(eng, physics):
+    """The work-queue influence-matrix path with a divergent field (its
+    divergent specialisation): the rows sum to the dense tally bit for bit,
+    and the same holds on the plain specialisation for the plain field."""
+    for vsad, focus in ((2000.0, 2000.0), (0.0, 0.0)):
+        c = div_case(60_000, physics, vsad=vsad, focus=focus)
+        say(f"case {c.name} csr vs dense physics={physics}")
+        rp, col, val, q, k = eng.run_csr(c, fixed_point_bits=36)
+        eng.load_case(c)
+        eng.run_dose(c, sigma=False, fixed_point_bits=36)
+        qd, kd = eng.last_tally(0)
+        dense = np.zeros(c.geometry.nvox, np.int64)
+        np.add.at(dense, col, q)
+        assert np.array_equal(dense, qd.cpu().numpy().ravel())
