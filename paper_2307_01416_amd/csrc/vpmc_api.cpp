@@ -1808,8 +1808,8 @@ int vpmc_optimize(vpmc_ctx *c, const int64_t *row_ptr, const int32_t *col, const
             HIP_TRY(hipMemcpyAsync(B.work.ptr, work.data(), work.size() * 4, hipMemcpyHostToDevice, st));
         if ((rc2 = ensure(c, B.key, (size_t)std::max(expect, 1ll) * 4, 0))) return rc2;
         if ((rc2 = ensure(c, B.val, (size_t)std::max(expect, 1ll) * 4, 0))) return rc2;
-        HIP_TRY(opt_build_emit(D, B.off.ptr ? (const unsigned long long *)B.off.ptr : nullptr,
-                               (unsigned long long *)c->opt_cnt.ptr, (uint32_t *)B.key.ptr, (float *)B.val.ptr, st));
+        HIP_TRY(opt_build_emit(D, (const unsigned long long *)B.off.ptr, (unsigned long long *)c->opt_cnt.ptr,
+                               (uint32_t *)B.key.ptr, (float *)B.val.ptr, st));
         HIP_TRY(hipStreamSynchronize(st));   // the host vectors outlive the copies
         B.n_work = (long long)work.size();
         B.valid = true;
