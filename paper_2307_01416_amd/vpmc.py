@@ -585,6 +585,38 @@ class Engine:
         return vpmc_surrogate_train(self.ctx, np.concatenate(xs), np.concatenate(ys), np.concatenate(ts), epochs,
                                     batch, lr, seed)
 
+    def optimize(self, rp, col, val, n_scen: int, spots_per_field, nvox: int, roi, *, d_presc: float,
+                 w_target: float = 1.0, d_max: float, w_oar: float = 1.0, iters: int = 80, n_power: int = 20,
+                 mode: str = "MFO", x0=None, reuse: bool = False):
+        """Robust spot weights from the influence matrices of vpmc_run_batched
+        (rows ordered scenario, field, spot; torch CUDA tensors).  MFO: all
+        fields' spots together against d_presc.  SFO: every field alone
+        against d_presc / n_fields (its rows addressed inside the whole
+        layout).  Returns (x [spots], step constants)."""
+        torch = self.torch
+        dev = torch.device("cuda", self.device)
+        counts = [int(n) for n in spots_per_field]
+        total = sum(counts)
+        x = (torch.ones(total, dtype=torch.float64, device=dev) if x0 is None
+             else torch.as_tensor(x0, dtype=torch.float64, device=dev).clone())
+        flags = DEVICE_PTRS | (OPT_REUSE if reuse else 0)
+        common = dict(w_target=w_target, d_max=d_max, w_oar=w_oar, iters=iters, n_power=n_power,
+                      flags=flags, stream=self.stream_ptr())
+        if mode == "MFO":
+            L = vpmc_optimize(self.ctx, rp, col, val, n_scen, total, nvox, roi, x, d_presc=d_presc, **common)
+            return x, [L]
+        if mode != "SFO":
+            raise ValueError("mode is MFO or SFO")
+        Ls, off = [], 0
+        common["flags"] = DEVICE_PTRS          # each field builds its own index
+        for n in counts:
+            xf = x[off:off + n].contiguous()
+            Ls.append(vpmc_optimize(self.ctx, rp, col, val, n_scen, n, nvox, roi, xf,
+                                    d_presc=d_presc / len(counts), row_stride=total, row_offset=off, **common))
+            x[off:off + n] = xf
+            off += n
+        return x, Ls
+
     def last_let(self, scen_index: int = 0):
         """(numerator int64[nz, ny, nx] on the GPU, shift) of the last dense
         run with let=True; LET_d = numerator * 2^shift / last_tally q."""

@@ -174,3 +174,33 @@ def test_parity_13_scenarios_many_chunks(ctx):
     xg, hg, Lg, _ = gpu(ctx, P, x0, 60, n_power=20)
     xo, ho, Lo, _ = orc(P, x0, 60, n_power=20)
     check(xg, hg, Lg, xo, ho, Lo)
+
+
+def test_sfo_and_mfo_through_the_engine():
+    """SFO: each field alone against d_presc / n_fields on its own rows of
+    the (scenario, field, spot) layout; MFO: all spots against d_presc.
+    Both against the oracle on the same rows."""
+    import torch
+    from paper_2307_01416_amd import vpmc as V
+    P = I.opt_problem(seed=9, n_spots=20, n_scen=3)
+    fields = [8, 12]                      # two fields: spots 0..7 and 8..19 of every scenario
+    eng = V.Engine(0)
+    try:
+        t = lambda a: torch.from_numpy(a).cuda()
+        args = (t(P.row_ptr), t(P.col), t(P.val), 3, fields, P.nvox, t(P.roi))
+        par = dict(d_presc=2.0, d_max=0.8, w_oar=4.0, iters=60, n_power=30)
+        xm, _ = eng.optimize(*args, mode="MFO", x0=np.full(20, 50.0), **par)
+        xs, _ = eng.optimize(*args, mode="SFO", x0=np.full(20, 50.0), **par)
+        xm, xs = xm.cpu().numpy(), xs.cpu().numpy()
+    finally:
+        eng.close()
+    tm, om = (P.roi & 1) > 0, (P.roi & 2) > 0
+    A = OO.matrices_from_csr(P.row_ptr, P.col, P.val, 3, 20, P.nvox)
+    xo, _, _ = OO.fista(A, np.full(20, 50.0), tm, om, 2.0, 1.0, 0.8, 4.0, 60, 30)
+    np.testing.assert_allclose(xm, xo, rtol=0, atol=1e-5 * np.abs(xo).max())
+    off = 0
+    for n in fields:
+        Af = OO.matrices_from_csr(P.row_ptr, P.col, P.val, 3, n, P.nvox, row_stride=20, row_offset=off)
+        xf, _, _ = OO.fista(Af, np.full(n, 50.0), tm, om, 2.0 / len(fields), 1.0, 0.8, 4.0, 60, 30)
+        np.testing.assert_allclose(xs[off:off + n], xf, rtol=0, atol=1e-5 * np.abs(xf).max())
+        off += n
