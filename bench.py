@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--sur-samples", type=int, default=3_000_000)
     ap.add_argument("--sur-epochs", type=int, default=6)
     ap.add_argument("--no-optimize", action="store_true", help="skip the spot-weight optimiser measurement")
+    ap.add_argument("--let", action="store_true",
+                    help="also time the nominal plan dose with and without the dose-averaged LET tally")
     ap.add_argument("--dynamic-spacing", action="store_true",
                     help="also merge the head IM into coarser cells away from the target (dynamic voxel spacing)")
     ap.add_argument("--layer-apertures", action="store_true",
@@ -291,6 +293,43 @@ def dynamic_spacing_measure(eng, case, I, V, np, torch, a, shape):
                  f"{nnz}) in {dt:.3f} s")
         del rpc, cell, qc, valc, cm
     del rp, col, q
+    return out
+
+
+def let_measure(eng, case, I, V, np, torch, a):
+    """Dose-averaged LET tally on the head case: the nominal plan dose of all
+    fields (dense, no batches) with and without the LET numerator (one more
+    int64 tally per step), twice each, interleaved; the plan's LET_d in the
+    target and the organ at risk (sum over fields of the numerators over the
+    sum of the dose tallies, the same k for every field)."""
+    nom = I.Case("nominal", case.geometry, case.fields, [I.Scenario()], seed=case.seed, physics=case.physics)
+    eng.load_case(nom)
+    times = {False: [], True: []}
+    q_sum = ql_sum = None
+    k0 = None
+    for rep_ in range(2):
+        for let in (False, True):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for fi in range(len(nom.fields)):
+                eng.run_dose(nom, fi, n_batches=0, sigma=False, let=let, fixed_point_bits=36)
+                if let and rep_ == 1:
+                    q, k = eng.last_tally(0)
+                    ql, sh = eng.last_let(0)
+                    k0 = k
+                    q_sum = q.double() if q_sum is None else q_sum + q.double()
+                    ql_sum = ql.double() * 2.0 ** sh if ql_sum is None else ql_sum + ql.double() * 2.0 ** sh
+            torch.cuda.synchronize()
+            times[let].append(time.perf_counter() - t0)
+    roi = torch.from_numpy(I.head_structures(case, a.target_cc)).to(q_sum.device).reshape(q_sum.shape)
+    out = {"s_plan_dose_without_let": min(times[False]), "s_plan_dose_with_let": min(times[True]),
+           "let_cost": min(times[True]) / min(times[False]) - 1.0, "fixed_point_bits": k0}
+    for name, bit in (("target", 1), ("oar", 2)):
+        m = (roi & bit) != 0
+        out[f"let_d_kev_per_um_{name}"] = float(ql_sum[m].sum() / q_sum[m].sum())
+    progress(f"LET tally: plan dose {out['s_plan_dose_without_let']:.3f} s -> {out['s_plan_dose_with_let']:.3f} s "
+             f"(+{100 * out['let_cost']:.1f} %); LET_d target {out['let_d_kev_per_um_target']:.2f}, "
+             f"organ {out['let_d_kev_per_um_oar']:.2f} keV/um")
     return out
 
 
@@ -593,6 +632,8 @@ def main():
         out["optimizer"] = optimizer_measure(eng, case, I, V, np, torch, a, shape)
     if a.dynamic_spacing:
         out["dynamic_spacing"] = dynamic_spacing_measure(eng, case, I, V, np, torch, a, shape)
+    if a.let:
+        out["let"] = let_measure(eng, case, I, V, np, torch, a)
     if not a.no_cpu_baseline:
         progress("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(case, a.cpu_seconds, np)
