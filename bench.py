@@ -335,7 +335,7 @@ def let_measure(eng, case, I, V, np, torch, a):
 
 def resolution_study(a, np):
     """Dose-grid resolution (the paper's 2 mm vs 1 mm observation, Discussion;
-    IM memory, SURVEY's NEXT-4): the head case's spots, fields and scenarios
+    IM memory): the head case's spots, fields and scenarios
     on CT grids of 1x1x2, 1x1x1 and 2x2x2 mm over the same 256x256x320 mm
     volume, the same VPs per spot everywhere.  Per grid: seconds per
     13-scenario IM (one warm-up, one timed), non-zeros, CSR bytes, U of the

@@ -284,7 +284,7 @@ LET_SHIFT = 8
 
 def run_let(case, field_index: int = 0, scenario_index: int = 0, k: Optional[int] = None, spots=None,
             threads: int = 0, physics: Optional[int] = None, seed: Optional[int] = None):
-    """Dose tally and dose-averaged-LET numerator of one field/scenario (NEXT-3):
+    """Dose tally and dose-averaged-LET numerator of one field/scenario:
     (q int64[nz,ny,nx], qL int64[nz,ny,nx], k); LET_d = qL * 2^LET_SHIFT / q in
     keV/um, where each step's LET is its mean CSDA stopping power."""
     P = _Prepared(case, field_index, scenario_index)

@@ -1,5 +1,5 @@
-"""FP64 reference of dynamic voxel spacing for influence matrices (NEXT-4:
-the planning system stores organs at risk on coarser voxels to save IM
+"""FP64 reference of dynamic voxel spacing for influence matrices (the
+planning system stores organs at risk on coarser voxels to save IM
 memory, Methods C).  TEST INFRASTRUCTURE ONLY, like the rest of this
 package.
 

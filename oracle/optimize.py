@@ -1,5 +1,5 @@
 """FP64 reference of the robust spot-weight optimisation on the influence
-matrices (NEXT-1: the plan optimisation the paper's workflow runs on the
+matrices (the plan optimisation the paper's workflow runs on the
 13-scenario influence matrices, Methods E).  TEST INFRASTRUCTURE ONLY, like
 the rest of this package.
 

@@ -443,7 +443,7 @@ enum { ST_STOP = 0, ST_GEO = 1, ST_INNER = 2 };
 /* One condensed-history step.  *let: the step's linear energy transfer
  * (MeV/mm = keV/um), the mean CSDA stopping power over the step, dE_csda / s;
  * for a VP that stops, its energy over its residual path, E / (R / rho); at
- * the cut-off, the CSDA relation's slope on its first segment (NEXT-3 LET
+ * the cut-off, the CSDA relation's slope on its first segment (LET
  * tally: dose-averaged LET = sum(dep * let) / sum(dep) per voxel). */
 static int phys_step(vp_t *vp, int m, double rho_loss, double rho, double dg,
                      double *dep, double *esc, double *let)

@@ -1,4 +1,4 @@
-"""Dynamic voxel spacing (NEXT-4: coarser IM voxels for organs at risk,
+"""Dynamic voxel spacing (coarser IM voxels for organs at risk,
 Methods C) on the GPU against the FP64 reference, through the C ABI.  Inputs:
 seeded pencil-beam-like rows (int64 fixed-point energies at k = 40, rows of
 0 to ~10^3 entries, so runs cross the kernel's 64-entry windows), a seeded

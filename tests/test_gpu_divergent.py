@@ -1,5 +1,5 @@
 """Divergent aperture block, virtual source and energy-layer-specific
-apertures (NEXT-2, the paper's next steps in its Discussion) on the GPU
+apertures (the paper's next steps in its Discussion) on the GPU
 against the FP64 oracle, through the C ABI.
 
 Workload: config 2 geometry (water, 30 mm brass block 50 mm upstream of the

@@ -1,4 +1,4 @@
-"""Dose-averaged LET (NEXT-3) on the GPU against the FP64 oracle, through the
+"""Dose-averaged LET on the GPU against the FP64 oracle, through the
 C ABI: each step's LET is its mean CSDA stopping power, the voxel's numerator
 sum(dep * LET) is an int64 tally beside the dose tally.  Straight mode: the
 numerator and LET_d per voxel to 1e-5 relative (voxels above 1e-6 of the

@@ -1,4 +1,4 @@
-"""Spot-weight optimiser (NEXT-1: robust optimisation on the scenario
+"""Spot-weight optimiser (robust optimisation on the scenario
 influence matrices, Methods E) on the GPU against the FP64 oracle, through
 the C ABI, on seeded synthetic pencil-beam-like matrices (many 512-voxel
 chunks with a ragged last chunk, empty rows, 3 and 13 scenarios).

@@ -1,4 +1,4 @@
-"""Pins of the dynamic-voxel-spacing reference (NEXT-4), no GPU: the identity
+"""Pins of the dynamic-voxel-spacing reference, no GPU: the identity
 map returns the rows with the per-voxel dose; one cell per row gives the row
 sum and the mass-weighted mean dose; merging never changes a row's total
 energy; the run map of the inputs generator follows its structures."""

@@ -1,4 +1,4 @@
-"""Pins of the divergent aperture block and the virtual source (NEXT-2: the
+"""Pins of the divergent aperture block and the virtual source (the
 divergent block the paper names as its next step, Discussion), no GPU.
 
 A divergent block's walls are the planes through the focus and the edges of

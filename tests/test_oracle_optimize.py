@@ -1,4 +1,4 @@
-"""Pins of the FP64 reference optimiser (NEXT-1), no GPU: gradient by central
+"""Pins of the FP64 reference optimiser, no GPU: gradient by central
 differences; with only a prescription term on every voxel the problem is
 non-negative least squares, whose optimum scipy.optimize.nnls gives; the
 power-iteration Lipschitz bound against the exact largest eigenvalue."""
