@@ -147,7 +147,7 @@ struct vpmc_ctx {
         opt_poff, opt_resid, opt_fpart, opt_gpart, opt_vec, opt_scal, opt_err, opt_hist, opt_dose;
     long long opt_npieces = 0;
     // dynamic voxel spacing (vpmc_csr_cells)
-    DevBuf cl_rp, cl_map, cl_start, cl_mass, cl_cnt, cl_out, cl_col, cl_q, cl_ocell, cl_oq, cl_oval;
+    DevBuf cl_rp, cl_map, cl_start, cl_mass, cl_cnt, cl_out, cl_col, cl_q, cl_ocell, cl_oq, cl_oval, cl_piece;
     bool opt_valid = false;
     int opt_dims[5] = {0, 0, 0, 0, 0};   // n_scen, n_spots, row_stride, row_offset, nvox
     std::vector<int64_t> opt_rp_host;
@@ -1050,7 +1050,7 @@ void vpmc_destroy(vpmc_ctx *c) {
                           &c->opt_err, &c->opt_hist, &c->opt_dose, &c->opt_broi.off, &c->opt_broi.key,
                           &c->opt_broi.val, &c->opt_broi.work, &c->opt_bfull.off, &c->opt_bfull.key,
                           &c->opt_bfull.val, &c->opt_bfull.work, &c->cl_rp, &c->cl_map, &c->cl_start,
-                          &c->cl_mass, &c->cl_cnt, &c->cl_out, &c->cl_col, &c->cl_q, &c->cl_ocell, &c->cl_oq,
+                          &c->cl_mass, &c->cl_cnt, &c->cl_out, &c->cl_col, &c->cl_q, &c->cl_ocell, &c->cl_oq, &c->cl_piece,
                           &c->cl_oval})
             release(*b);
         for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
@@ -1981,12 +1981,24 @@ int vpmc_csr_cells(vpmc_ctx *c, const int64_t *row_ptr, int n_rows, const int32_
     if ((rc = ensure(c, c->cl_map, (size_t)nvox * 4, 0))) return rc;
     if ((rc = ensure(c, c->cl_start, ((size_t)n_cells + 1) * 4, 0))) return rc;
     if ((rc = ensure(c, c->cl_mass, (size_t)n_cells * 8, 0))) return rc;
-    if ((rc = ensure(c, c->cl_cnt, std::max<size_t>(R, 1) * 8, 0))) return rc;
-    if ((rc = ensure(c, c->cl_out, (R + 1) * 8, 0))) return rc;
+    // pieces of at most kCellPiece entries, row by row
+    std::vector<CellPiece> pcs;
+    std::vector<size_t> first_piece(R + 1);
+    for (size_t r = 0; r < R; ++r) {
+        first_piece[r] = pcs.size();
+        for (long long q0 = rp[r]; q0 < rp[r + 1]; q0 += kCellPiece)
+            pcs.push_back(CellPiece{q0, (int)std::min<long long>(kCellPiece, rp[r + 1] - q0), (int)r});
+    }
+    first_piece[R] = pcs.size();
+    const size_t NP = pcs.size();
+    if ((rc = ensure(c, c->cl_piece, std::max<size_t>(NP, 1) * sizeof(CellPiece), 0))) return rc;
+    if ((rc = ensure(c, c->cl_cnt, std::max<size_t>(NP, 1) * 8, 0))) return rc;
+    if ((rc = ensure(c, c->cl_out, (NP + 1) * 8, 0))) return rc;
     if ((rc = ensure(c, c->flags, 4, 0))) return rc;
     HIP_TRY(hipMemcpy(c->cl_rp.ptr, rp.data(), rp.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->cl_map.ptr, cmap.data(), cmap.size() * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->cl_start.ptr, cstart.data(), cstart.size() * 4, hipMemcpyHostToDevice));
+    if (NP) HIP_TRY(hipMemcpy(c->cl_piece.ptr, pcs.data(), NP * sizeof(CellPiece), hipMemcpyHostToDevice));
     const int32_t *d_col = col;
     const long long *d_q = (const long long *)q;
     if (!dev && nnz > 0) {
@@ -1999,21 +2011,24 @@ int vpmc_csr_cells(vpmc_ctx *c, const int64_t *row_ptr, int n_rows, const int32_
         d_q = (const long long *)c->cl_q.ptr;
     }
     HIP_TRY(hipMemset(c->flags.ptr, 0, 4));
-    HIP_TRY(launch_cell_count((const long long *)c->cl_rp.ptr, n_rows, d_col, (const int32_t *)c->cl_map.ptr, nvox,
-                              (unsigned long long *)c->cl_cnt.ptr, (unsigned *)c->flags.ptr, nullptr));
-    std::vector<unsigned long long> cnt(std::max<size_t>(R, 1));
+    HIP_TRY(launch_cell_count((const long long *)c->cl_rp.ptr, (const CellPiece *)c->cl_piece.ptr, (long long)NP,
+                              d_col, (const int32_t *)c->cl_map.ptr, nvox, (unsigned long long *)c->cl_cnt.ptr,
+                              (unsigned *)c->flags.ptr, nullptr));
+    std::vector<unsigned long long> cnt(std::max<size_t>(NP, 1));
     unsigned err = 0;
-    if (R) HIP_TRY(hipMemcpy(cnt.data(), c->cl_cnt.ptr, R * 8, hipMemcpyDeviceToHost));
+    if (NP) HIP_TRY(hipMemcpy(cnt.data(), c->cl_cnt.ptr, NP * 8, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(&err, c->flags.ptr, 4, hipMemcpyDeviceToHost));
     if (err & 1u) return fail(VPMC_E_ARG, "a column index is outside [0, nvox)");
     if (err & 2u) return fail(VPMC_E_ARG, "columns are not ascending within a row");
-    std::vector<int64_t> op(R + 1);
-    op[0] = 0;
-    for (size_t r = 0; r < R; ++r) op[r + 1] = op[r] + (int64_t)cnt[r];
+    // output offsets: per piece (its own runs) and per row
+    std::vector<int64_t> pout(NP + 1), op(R + 1);
+    pout[0] = 0;
+    for (size_t k = 0; k < NP; ++k) pout[k + 1] = pout[k] + (int64_t)cnt[k];
+    for (size_t r = 0; r <= R; ++r) op[r] = pout[first_piece[r]];
     HIP_TRY(hipMemcpy(row_ptr_out, op.data(), op.size() * 8, dev ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
     const long long nout = op[R];
     if (!cell_out && !q_out && !val_out) return VPMC_OK;
-    HIP_TRY(hipMemcpy(c->cl_out.ptr, op.data(), op.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->cl_out.ptr, pout.data(), pout.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(launch_cell_mass(c->geom, (const int32_t *)c->cl_start.ptr, n_cells, (double *)c->cl_mass.ptr, nullptr));
     int32_t *ocell = cell_out;
     long long *oq = (long long *)q_out;
@@ -2027,8 +2042,9 @@ int vpmc_csr_cells(vpmc_ctx *c, const int64_t *row_ptr, int n_rows, const int32_
         oq = q_out ? (long long *)c->cl_oq.ptr : nullptr;
         oval = val_out ? (float *)c->cl_oval.ptr : nullptr;
     }
-    HIP_TRY(launch_cell_emit((const long long *)c->cl_rp.ptr, n_rows, d_col, d_q, (const int32_t *)c->cl_map.ptr,
-                             (const long long *)c->cl_out.ptr, (const double *)c->cl_mass.ptr, ldexp(MEV_TO_J, -k),
+    HIP_TRY(launch_cell_emit((const long long *)c->cl_rp.ptr, (const CellPiece *)c->cl_piece.ptr, (long long)NP, d_col,
+                             d_q, (const int32_t *)c->cl_map.ptr, (const long long *)c->cl_out.ptr,
+                             (const double *)c->cl_mass.ptr, ldexp(MEV_TO_J, -k),
                              ocell, oq, oval, nullptr));
     HIP_TRY(hipDeviceSynchronize());
     if (!dev && nout > 0) {

@@ -261,13 +261,20 @@ hipError_t launch_csr_scatter(const int32_t *col, const long long *qv, unsigned 
 hipError_t launch_csr_values(const int32_t *col, const long long *qv, size_t n, const GeomDev &g,
                              double mev_scale, float *val, hipStream_t s);
 // dynamic voxel spacing: merge influence-matrix rows into cells (runs of
-// consecutive voxels of a non-decreasing voxel -> cell map)
+// consecutive voxels of a non-decreasing voxel -> cell map), a wavefront per
+// piece of at most kCellPiece entries of one row
+constexpr int kCellPiece = 4096;
+struct CellPiece {
+    long long begin;   // first entry (CSR index)
+    int len;
+    int row;
+};
 hipError_t launch_cell_mass(const GeomDev &g, const int32_t *cstart, int n_cells, double *mass, hipStream_t s);
-hipError_t launch_cell_count(const long long *rp, int n_rows, const int32_t *col, const int32_t *cmap, int nvox,
-                             unsigned long long *cnt, unsigned *err, hipStream_t s);
-hipError_t launch_cell_emit(const long long *rp, int n_rows, const int32_t *col, const long long *q,
-                            const int32_t *cmap, const long long *out_ptr, const double *mass, double mev_scale,
-                            int32_t *ocell, long long *oq, float *oval, hipStream_t s);
+hipError_t launch_cell_count(const long long *rp, const CellPiece *pcs, long long n_pieces, const int32_t *col,
+                             const int32_t *cmap, int nvox, unsigned long long *cnt, unsigned *err, hipStream_t s);
+hipError_t launch_cell_emit(const long long *rp, const CellPiece *pcs, long long n_pieces, const int32_t *col,
+                            const long long *q, const int32_t *cmap, const long long *pout, const double *mass,
+                            double mev_scale, int32_t *ocell, long long *oq, float *oval, hipStream_t s);
 
 // ------------------------------------------------- spot-weight optimiser
 #ifndef VPMC_OPT_CHUNK_BITS

@@ -1703,16 +1703,24 @@ __global__ void cell_mass_kernel(GeomDev g, const int32_t *cstart, int n_cells, 
     }
 }
 
-// cells per row (wavefront per row); flags columns outside the grid (bit 1)
-// and columns not ascending within a row (bit 2)
-__global__ __launch_bounds__(256) void cell_count_kernel(const long long *rp, int n_rows, const int32_t *col,
+// cells per piece (a wavefront per piece of at most kCellPiece entries of one
+// row): runs of one cell that start inside the piece; flags columns outside
+// the grid (bit 1) and columns not ascending within a row (bit 2)
+__global__ __launch_bounds__(256) void cell_count_kernel(const long long *rp, const CellPiece *pcs,
+                                                         long long n_pieces, const int32_t *col,
                                                          const int32_t *cmap, int nvox, unsigned long long *cnt,
                                                          unsigned *err) {
-    const int r = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
-    if (r >= n_rows) return;
+    const long long p = (long long)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
+    if (p >= n_pieces) return;
     const int lane = (int)(threadIdx.x & 63);
-    const long long b = rp[r], e = rp[r + 1];
+    const CellPiece pc = pcs[p];
+    const long long b = pc.begin, e = pc.begin + pc.len;
     int carry = -1, carry_col = -1;
+    if (b > rp[pc.row]) {
+        // the entry before the piece (checked by the piece that owns it)
+        carry_col = col[b - 1];
+        carry = (unsigned)carry_col < (unsigned)nvox ? cmap[carry_col] : -1;
+    }
     unsigned long long n = 0;
     for (long long i0 = b; i0 < e; i0 += 64) {
         const long long i = i0 + lane;
@@ -1724,53 +1732,69 @@ __global__ __launch_bounds__(256) void cell_count_kernel(const long long *rp, in
             else c = cmap[v];
         }
         int pv = __shfl_up(v, 1);
-        int pc = __shfl_up(c, 1);
+        int pc_ = __shfl_up(c, 1);
         if (lane == 0) {
             pv = carry_col;
-            pc = carry;
+            pc_ = carry;
         }
-        if (valid && i > b && v <= pv) atomicOr(err, 2u);
-        n += (unsigned long long)__popcll(__ballot(valid && c >= 0 && c != pc));
+        if (valid && (i > b || carry_col >= 0) && v <= pv) atomicOr(err, 2u);
+        n += (unsigned long long)__popcll(__ballot(valid && c >= 0 && c != pc_));
         carry = __shfl(c, 63);
         carry_col = __shfl(v, 63);
     }
-    if (lane == 0) cnt[r] = n;
+    if (lane == 0) cnt[p] = n;
 }
 
-// merged rows: a wavefront per row, segmented sums of the int64 energies over
-// each run of one cell (exact), carried across 64-entry windows; the value is
-// the cell's energy over its mass
-__global__ __launch_bounds__(256) void cell_emit_kernel(const long long *rp, int n_rows, const int32_t *col,
-                                                        const long long *q, const int32_t *cmap,
-                                                        const long long *out_ptr, const double *mass,
-                                                        double mev_scale, int32_t *ocell, long long *oq,
-                                                        float *oval) {
-    const int r = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
-    if (r >= n_rows) return;
+// merged rows, a wavefront per piece: the runs that start inside the piece
+// belong to it; segmented sums of their int64 energies (exact) over 64-entry
+// windows, carried across windows; the piece's last run is followed past the
+// piece's end up to the next start or the row's end.  The value is the
+// cell's energy over its mass.
+__global__ __launch_bounds__(256) void cell_emit_kernel(const long long *rp, const CellPiece *pcs, long long n_pieces,
+                                                        const int32_t *col, const long long *q, const int32_t *cmap,
+                                                        const long long *pout, const double *mass, double mev_scale,
+                                                        int32_t *ocell, long long *oq, float *oval) {
+    const long long p = (long long)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
+    if (p >= n_pieces) return;
     const int lane = (int)(threadIdx.x & 63);
-    const long long b = rp[r], e = rp[r + 1];
-    const long long o0 = out_ptr[r], o1 = out_ptr[r + 1];
-    int carry_cell = -1;
-    long long carry_sum = 0, starts_before = 0;
-    for (long long i0 = b; i0 < e; i0 += 64) {
+    const CellPiece pc = pcs[p];
+    const long long re = rp[pc.row + 1];
+    const long long b = pc.begin, e = pc.begin + pc.len;
+    const long long o0 = pout[p], o1 = pout[p + 1];
+    if (o0 == o1) return;   // no run starts in this piece
+    int carry_cell = b > rp[pc.row] ? cmap[col[b - 1]] : -1;
+    long long carry_sum = 0, starts_before = 0, e_eff = re;
+    auto put = [&](long long k, int c, long long sum) {
+        const long long pos = o0 + k;
+        if (k >= 0 && pos < o1) {
+            if (ocell) ocell[pos] = c;
+            if (oq) oq[pos] = sum;
+            if (oval) oval[pos] = (float)((double)sum * mev_scale / mass[c]);
+        }
+    };
+    for (long long i0 = b;; i0 += 64) {
         const long long i = i0 + lane;
-        const bool valid = i < e;
-        const int c = valid ? cmap[col[i]] : -1;
-        long long x = valid ? q[i] : 0;
-        int pc = __shfl_up(c, 1);
-        if (lane == 0) pc = carry_cell;
-        const bool start = valid && c != pc;
-        // the run left open at the end of the last window: continued by
-        // lane 0 (its sum carried in), or ended there (written now)
-        if (lane == 0 && valid && !start) x += carry_sum;
-        if (lane == 0 && start && carry_cell >= 0) {
-            const long long pos = o0 + starts_before - 1;
-            if (pos >= o0 && pos < o1) {
-                if (ocell) ocell[pos] = carry_cell;
-                if (oq) oq[pos] = carry_sum;
-                if (oval) oval[pos] = (float)((double)carry_sum * mev_scale / mass[carry_cell]);
+        const bool valid0 = i < re;
+        const int c = valid0 ? cmap[col[i]] : -1;
+        int pcl = __shfl_up(c, 1);
+        if (lane == 0) pcl = carry_cell;
+        const bool start0 = valid0 && c != pcl;
+        if (i0 + 64 > e) {
+            // the first start at or after the piece's end closes its last run
+            const unsigned long long m0 = __ballot(start0 && i >= e);
+            if (m0) {
+                const long long first = i0 + (long long)(__ffsll((long long)m0) - 1);
+                e_eff = first < e_eff ? first : e_eff;
             }
         }
+        const bool valid = valid0 && i < e_eff;
+        const bool start = start0 && valid;
+        const bool v0 = __shfl(valid ? 1 : 0, 0) != 0, s0 = __shfl(start ? 1 : 0, 0) != 0;
+        // the run left open by the last window ends here
+        if (lane == 0 && carry_cell >= 0 && (s0 || !v0)) put(starts_before - 1, carry_cell, carry_sum);
+        if (!v0) break;
+        long long x = valid ? q[i] : 0;
+        if (lane == 0 && !start) x += carry_sum;
         long long sum = x;
         int f = start ? 1 : 0;
         for (int d = 1; d < 64; d <<= 1) {
@@ -1780,21 +1804,12 @@ __global__ __launch_bounds__(256) void cell_emit_kernel(const long long *rp, int
             if (lane >= d) f |= fo;
         }
         const unsigned long long m = __ballot(start);
-        const long long last = (e - i0 < 64 ? e - i0 : 64) - 1;
+        const int last = (int)((e_eff - i0 < 64 ? e_eff - i0 : 64) - 1);
         const bool next_start = __shfl_down(start ? 1 : 0, 1) != 0;
-        const bool final_window = i0 + 64 >= e;
-        const bool ends = valid && ((lane < last && next_start) || (lane == last && final_window));
-        if (ends) {
-            const long long idx = starts_before + (long long)__popcll(m & ((2ull << lane) - 1ull)) - 1;
-            const long long pos = o0 + idx;
-            if (pos >= o0 && pos < o1) {
-                if (ocell) ocell[pos] = c;
-                if (oq) oq[pos] = sum;
-                if (oval) oval[pos] = (float)((double)sum * mev_scale / mass[c]);
-            }
-        }
-        carry_cell = __shfl(c, 63);
-        carry_sum = __shfl(sum, 63);
+        if (valid && lane < last && next_start)
+            put(starts_before + (long long)__popcll(m & ((2ull << lane) - 1ull)) - 1, c, sum);
+        carry_cell = __shfl(c, last);
+        carry_sum = __shfl(sum, last);
         starts_before += (long long)__popcll(m);
     }
 }
@@ -2207,21 +2222,22 @@ hipError_t launch_cell_mass(const GeomDev &g, const int32_t *cstart, int n_cells
     return hipGetLastError();
 }
 
-hipError_t launch_cell_count(const long long *rp, int n_rows, const int32_t *col, const int32_t *cmap, int nvox,
-                             unsigned long long *cnt, unsigned *err, hipStream_t s) {
-    if (n_rows == 0) return hipSuccess;
-    const int blocks = (int)(((long long)n_rows * 64 + 255) / 256);
-    hipLaunchKernelGGL(cell_count_kernel, dim3(blocks), dim3(256), 0, s, rp, n_rows, col, cmap, nvox, cnt, err);
+hipError_t launch_cell_count(const long long *rp, const CellPiece *pcs, long long n_pieces, const int32_t *col,
+                             const int32_t *cmap, int nvox, unsigned long long *cnt, unsigned *err, hipStream_t s) {
+    if (n_pieces == 0) return hipSuccess;
+    const long long blocks = (n_pieces * 64 + 255) / 256;
+    hipLaunchKernelGGL(cell_count_kernel, dim3((unsigned)blocks), dim3(256), 0, s, rp, pcs, n_pieces, col, cmap, nvox,
+                       cnt, err);
     return hipGetLastError();
 }
 
-hipError_t launch_cell_emit(const long long *rp, int n_rows, const int32_t *col, const long long *q,
-                            const int32_t *cmap, const long long *out_ptr, const double *mass, double mev_scale,
-                            int32_t *ocell, long long *oq, float *oval, hipStream_t s) {
-    if (n_rows == 0) return hipSuccess;
-    const int blocks = (int)(((long long)n_rows * 64 + 255) / 256);
-    hipLaunchKernelGGL(cell_emit_kernel, dim3(blocks), dim3(256), 0, s, rp, n_rows, col, q, cmap, out_ptr, mass,
-                       mev_scale, ocell, oq, oval);
+hipError_t launch_cell_emit(const long long *rp, const CellPiece *pcs, long long n_pieces, const int32_t *col,
+                            const long long *q, const int32_t *cmap, const long long *pout, const double *mass,
+                            double mev_scale, int32_t *ocell, long long *oq, float *oval, hipStream_t s) {
+    if (n_pieces == 0) return hipSuccess;
+    const long long blocks = (n_pieces * 64 + 255) / 256;
+    hipLaunchKernelGGL(cell_emit_kernel, dim3((unsigned)blocks), dim3(256), 0, s, rp, pcs, n_pieces, col, q, cmap,
+                       pout, mass, mev_scale, ocell, oq, oval);
     return hipGetLastError();
 }
 
