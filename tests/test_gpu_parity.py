@@ -243,7 +243,8 @@ def test_lateral_shift_bitwise_gpu(eng):
 
 # ------------------------------------------------------------- full physics
 def stat_compare(orc, case, dg, sg, r, label):
-    """3-sigma voxel test and the mean dose over the high-dose region; the
+    """3-sigma voxel test and the mean dose over the high-dose region (>= 50 %
+    of the maximum of the two runs' mean); the
     mean-dose tolerance is 0.5 % or three standard errors of the difference
     when the runs are noisier than that (error of the oracle's regional mean
     from its batches, the same for the GPU run)."""
@@ -253,7 +254,10 @@ def stat_compare(orc, case, dg, sg, r, label):
     comb = np.sqrt(sg ** 2 + so ** 2)
     within = np.abs(dg - do) <= 3.0 * comb
     frac = within[m].mean()
-    hi = do >= 0.5 * dmax
+    # the high-dose region is selected on the mean of the two doses: selecting
+    # it on one side's own (noisy) dose biases that side's regional mean up
+    avg = 0.5 * (dg + do)
+    hi = avg >= 0.5 * avg.max()
     ratio = dg[hi].mean() / do[hi].mean()
     bm = np.array([b[hi].mean() for b in r["batch_dose_gy"]])
     se_rel = bm.std(ddof=1) / np.sqrt(len(bm)) / do[hi].mean()
