@@ -74,12 +74,14 @@ def edge_distance(poly, x, y):
     return d
 
 
-def ambiguous_mask(orc, case, tol=1e-4):
+def ambiguous_mask(orc, case, tol=1e-4, spots=None, shift_mm=(0.0, 0.0, 0.0)):
     """Voxels an FP32/FP64 rounding difference of the source position could
     change: the whole track line of every history that starts within tol of a
     lateral voxel boundary (or within 2e-3 mm of an aperture polygon edge or
     the range-shifter rim), and the neighbouring lines.  Beams must be
-    axis-aligned."""
+    axis-aligned.  spots: the spot indices of field 0 to cover (all by
+    default); shift_mm: the scenario's isocentre shift (CT coordinates of a
+    point move by -shift)."""
     g = case.geometry
     f = case.fields[0]
     nx, ny, nz = g.shape
@@ -87,12 +89,13 @@ def ambiguous_mask(orc, case, tol=1e-4):
     ez = np.asarray(f.beam.ez)
     ax = int(np.argmax(np.abs(ez)))
     lat = [k for k in range(3) if k != ax]
-    for s in range(len(f.spots)):
+    origin = np.asarray(g.origin, np.float64) + np.asarray(shift_mm, np.float64)
+    for s in (range(len(f.spots)) if spots is None else spots):
         n = int(f.spots["n_histories"][s])
         x, y = source_xy_fp64(orc, case, s, n)
         p = np.asarray(f.beam.iso)[None, :] + x[:, None] * np.asarray(f.beam.ex)[None, :] \
             + y[:, None] * np.asarray(f.beam.ey)[None, :]
-        fr = (p - np.asarray(g.origin)[None, :]) / np.asarray(g.spacing)[None, :]
+        fr = (p - origin[None, :]) / np.asarray(g.spacing)[None, :]
         bad = np.zeros(n, bool)
         for k in lat:
             bad |= np.abs(fr[:, k] - np.rint(fr[:, k])) * g.spacing[k] < tol
