@@ -12,8 +12,9 @@ across it, at both range scalings, so the lateral voxel boundaries the
 rounding test uses are known.
 
 Full physics (properties that hold at any size): columns ascend in every
-row, and the rows of each sampled scenario sum to the dense tallies of its
-three fields bit for bit."""
+row, the rows of each sampled scenario sum to the dense tallies of its three
+fields bit for bit, and the dynamic-spacing merge of the whole IM keeps every
+row's exact total."""
 import numpy as np
 import pytest
 
@@ -79,12 +80,32 @@ def test_full_size_straight_rows_equal_oracle(eng, orc):
     torch.cuda.empty_cache()
 
 
-def test_full_size_physics_rows_sum_to_dense(eng):
+@pytest.fixture(scope="module")
+def physics_pass(eng):
     import torch
     case = I.config4(8.0, VPS_PER_SPOT)
     say("full-size full physics: 37 050 rows")
     rp, col, q, k = full_run(eng, case)
     say(f"  nnz {int(rp[-1])}, k {k}")
+    yield case, rp, col, q, k
+    del col, q
+    torch.cuda.empty_cache()
+
+
+def row_totals(rp, q, r0, r1):
+    """Exact int64 totals of rows r0 .. r1-1 (host row_ptr, device values)."""
+    a, b = int(rp[r0]), int(rp[r1])
+    qq = q[a:b].cpu().numpy()
+    lens = np.diff(rp[r0:r1 + 1])
+    out = np.zeros(r1 - r0, np.int64)
+    nz = lens > 0
+    if qq.size:
+        out[nz] = np.add.reduceat(qq, (rp[r0:r1] - a)[nz])
+    return out
+
+
+def test_full_size_physics_rows_sum_to_dense(eng, physics_pass):
+    case, rp, col, q, k = physics_pass
     n_per_scen = sum(len(f.spots) for f in case.fields)
     nvox = case.geometry.nvox
     for sc in (0, 10):
@@ -106,5 +127,34 @@ def test_full_size_physics_rows_sum_to_dense(eng):
             dense += qd.cpu().numpy().ravel()
         say(f"  scenario {sc}: {b - a} entries, dense sum {int(dense.sum())}")
         assert dense.any() and np.array_equal(acc, dense)
-    del col, q
+
+
+def test_full_size_dynamic_spacing_conserves_rows(eng, physics_pass):
+    """The cell merge of the whole IM (target voxels kept, organ at risk in
+    runs of 2, other voxels in runs of 4 along x): every row keeps its exact
+    int64 total, cells ascend within each row and stay below n_cells."""
+    import torch
+    from paper_2307_01416_amd import vpmc as V
+    case, rp, col, q, k = physics_pass
+    roi = I.head_structures(case, 8.0)
+    cmap, n_cells = I.dynamic_spacing_map(case.geometry.shape, roi, target=1, oar=2, other=4)
+    dev = col.device
+    rpd = torch.from_numpy(rp).to(dev)
+    rpc, cell, qc, val = V.vpmc_csr_cells(eng.ctx, rpd, col, q, k, torch.from_numpy(cmap).to(dev), n_cells,
+                                          V.DEVICE_PTRS)
+    torch.cuda.synchronize()
+    rpc = rpc.cpu().numpy()
+    say(f"  cells: {n_cells} for {case.geometry.nvox} voxels, entries {int(rp[-1])} -> {int(rpc[-1])}")
+    assert int(rpc[-1]) < int(rp[-1])
+    assert int(torch.sum(q).item()) == int(torch.sum(qc).item())
+    n_per_scen = sum(len(f.spots) for f in case.fields)
+    for sc in (0, 10):
+        r0, r1 = sc * n_per_scen, (sc + 1) * n_per_scen
+        assert np.array_equal(row_totals(rp, q, r0, r1), row_totals(rpc, qc, r0, r1))
+        a, b = int(rpc[r0]), int(rpc[r1])
+        cc = cell[a:b].cpu().numpy()
+        assert cc.size == 0 or (cc.min() >= 0 and cc.max() < n_cells)
+        down = np.nonzero(np.diff(cc) <= 0)[0] + 1
+        assert np.isin(down, rpc[r0:r1 + 1] - a).all()
+    del rpc, cell, qc, val
     torch.cuda.empty_cache()
