@@ -158,3 +158,39 @@ def test_full_size_dynamic_spacing_conserves_rows(eng, physics_pass):
         assert np.isin(down, rpc[r0:r1 + 1] - a).all()
     del rpc, cell, qc, val
     torch.cuda.empty_cache()
+
+
+def test_full_size_let_leaves_the_dose_tally_unchanged(eng, orc):
+    """The nominal plan of the full head case (three fields at the full VPs
+    per spot, full physics): each field's dose tally with the LET numerator
+    tallied beside it equals the tally without it bit for bit, and the plan's
+    LET_d per unit density (a dose-weighted mean of the steps' mass stopping
+    powers) lies within the range of those: about 0.4 keV/um per g/cm3 at
+    230 MeV up to about 30 for the last step below the 1 MeV cut-off (the
+    slope of the range table's first segment), checked as (0.3, 40) wherever
+    there is dose."""
+    case = I.config4(8.0, VPS_PER_SPOT)
+    nom = I.Case("nominal", case.geometry, case.fields, [I.Scenario()], seed=case.seed, physics=case.physics)
+    eng.load_case(nom)
+    q_sum = ql_sum = None
+    for fi in range(len(nom.fields)):
+        eng.run_dose(nom, fi, n_batches=0, sigma=False, let=False, fixed_point_bits=36)
+        q0, _ = eng.last_tally(0)
+        q0 = q0.cpu().numpy()
+        eng.run_dose(nom, fi, n_batches=0, sigma=False, let=True, fixed_point_bits=36)
+        q1, k = eng.last_tally(0)
+        ql, sh = eng.last_let(0)
+        q1, ql = q1.cpu().numpy(), ql.cpu().numpy()
+        say(f"  field {fi}: dose voxels {int((q1 > 0).sum())}, LET shift {sh}")
+        assert q1.any() and np.array_equal(q0, q1)
+        q_sum = q1.astype(np.float64) if q_sum is None else q_sum + q1
+        part = ql.astype(np.float64) * 2.0 ** sh
+        ql_sum = part if ql_sum is None else ql_sum + part
+    _, rho = orc.hu_lookup(case.geometry.hu)
+    rho = np.asarray(rho, np.float64).reshape(q_sum.shape)
+    m = q_sum > 1e-3 * q_sum.max()
+    let_d = ql_sum[m] / q_sum[m]
+    mass_let = let_d / rho[m]
+    say(f"  plan LET_d over {int(m.sum())} voxels: {let_d.min():.3f} - {let_d.max():.3f} keV/um, "
+        f"per unit density {mass_let.min():.3f} - {mass_let.max():.3f}")
+    assert mass_let.min() > 0.3 and mass_let.max() < 40.0
