@@ -13,8 +13,9 @@ rounding test uses are known.
 
 Full physics (properties that hold at any size): columns ascend in every
 row, the rows of each sampled scenario sum to the dense tallies of its three
-fields bit for bit, and the dynamic-spacing merge of the whole IM keeps every
-row's exact total."""
+fields bit for bit, the dynamic-spacing merge of the whole IM keeps every
+row's exact total, the optimiser's reported objective matches its weights,
+and the LET tally leaves the dose tally unchanged."""
 import numpy as np
 import pytest
 
@@ -38,15 +39,15 @@ def eng():
 
 
 def full_run(eng, case):
-    """The whole pass; returns (host row_ptr, device col, device q, k)."""
+    """The whole pass; returns (host row_ptr, device col, device FP32 Gy
+    values, device int64 tallies, k)."""
     import torch
     from paper_2307_01416_amd import vpmc as V
     rp, col, val, _, k = eng.run_csr(case, device_out=True, **SHAPE)
-    del val
     q = torch.empty(col.numel(), dtype=torch.int64, device=col.device)
     V.vpmc_copy_csr(eng.ctx, None, None, q)
     torch.cuda.synchronize()
-    return rp.cpu().numpy(), col, q, k
+    return rp.cpu().numpy(), col, val, q, k
 
 
 def test_full_size_straight_rows_equal_oracle(eng, orc):
@@ -55,7 +56,8 @@ def test_full_size_straight_rows_equal_oracle(eng, orc):
     n_rows = len(case.scenarios) * sum(len(f.spots) for f in case.fields)
     assert n_rows == 37_050 and case.geometry.shape == (256, 256, 160)
     say(f"full-size straight: rows {n_rows}, VPs {sum(int(f.spots['n_histories'].sum()) for f in case.fields) * 13}")
-    rp, col, q, k = full_run(eng, case)
+    rp, col, val, q, k = full_run(eng, case)
+    del val
     say(f"  nnz {int(rp[-1])}, k {k}")
     n_per_scen = sum(len(f.spots) for f in case.fields)
     nz, ny, nx = case.geometry.shape[2], case.geometry.shape[1], case.geometry.shape[0]
@@ -85,10 +87,10 @@ def physics_pass(eng):
     import torch
     case = I.config4(8.0, VPS_PER_SPOT)
     say("full-size full physics: 37 050 rows")
-    rp, col, q, k = full_run(eng, case)
+    rp, col, val, q, k = full_run(eng, case)
     say(f"  nnz {int(rp[-1])}, k {k}")
-    yield case, rp, col, q, k
-    del col, q
+    yield case, rp, col, val, q, k
+    del col, val, q
     torch.cuda.empty_cache()
 
 
@@ -105,7 +107,7 @@ def row_totals(rp, q, r0, r1):
 
 
 def test_full_size_physics_rows_sum_to_dense(eng, physics_pass):
-    case, rp, col, q, k = physics_pass
+    case, rp, col, _, q, k = physics_pass
     n_per_scen = sum(len(f.spots) for f in case.fields)
     nvox = case.geometry.nvox
     for sc in (0, 10):
@@ -135,7 +137,7 @@ def test_full_size_dynamic_spacing_conserves_rows(eng, physics_pass):
     int64 total, cells ascend within each row and stay below n_cells."""
     import torch
     from paper_2307_01416_amd import vpmc as V
-    case, rp, col, q, k = physics_pass
+    case, rp, col, _, q, k = physics_pass
     roi = I.head_structures(case, 8.0)
     cmap, n_cells = I.dynamic_spacing_map(case.geometry.shape, roi, target=1, oar=2, other=4)
     dev = col.device
@@ -158,6 +160,58 @@ def test_full_size_dynamic_spacing_conserves_rows(eng, physics_pass):
         assert np.isin(down, rpc[r0:r1 + 1] - a).all()
     del rpc, cell, qc, val
     torch.cuda.empty_cache()
+
+
+def test_full_size_optimiser_objective_matches_its_weights(eng, physics_pass):
+    """Spot-weight optimisation on the whole 13-scenario IM as the throughput
+    measurement runs it (start scaled to the prescription, 20 power and 80
+    FISTA iterations): the objective reported at the final weights equals the
+    objective recomputed from those weights and the same matrices in FP64
+    (the optimiser's dose sums are int64 fixed point at 2^-60 of their
+    bound: 1e-8 relative), its dose output equals the recomputed dose to
+    1e-6 of the maximum (FP32 output), and the objective falls."""
+    import torch
+    from paper_2307_01416_amd import vpmc as V
+    case, rp, col, val, _, _ = physics_pass
+    n_scen = len(case.scenarios)
+    n_spots = sum(len(f.spots) for f in case.fields)
+    nvox = case.geometry.nvox
+    dev = col.device
+    rpd = torch.from_numpy(rp).to(dev)
+    roi = torch.from_numpy(I.head_structures(case, 8.0)).to(dev)
+    par = dict(d_presc=2.0, w_target=1.0, d_max=1.0, w_oar=1.0)
+    dose = torch.empty((n_scen, nvox), dtype=torch.float32, device=dev)
+    x = torch.ones(n_spots, dtype=torch.float64, device=dev)
+    V.vpmc_optimize(eng.ctx, rpd, col, val, n_scen, n_spots, nvox, roi, x, iters=0, n_power=1,
+                    flags=V.DEVICE_PTRS, dose=dose, **par)
+    tm, om = (roi & 1) > 0, (roi & 2) > 0
+    x = torch.full((n_spots,), par["d_presc"] / float(dose[:, tm].mean()), dtype=torch.float64, device=dev)
+    hist = torch.zeros(81, dtype=torch.float64, device=dev)
+    L = V.vpmc_optimize(eng.ctx, rpd, col, val, n_scen, n_spots, nvox, roi, x, iters=80, n_power=20,
+                        flags=V.DEVICE_PTRS | V.OPT_REUSE, obj_hist=hist, dose=dose, **par)
+    torch.cuda.synchronize()
+    hist = hist.cpu().numpy()
+    assert L > 0 and bool((x >= 0).all())
+    F = 0.0
+    dmax_err = 0.0
+    for s in range(n_scen):
+        r0, r1 = s * n_spots, (s + 1) * n_spots
+        a, b = int(rp[r0]), int(rp[r1])
+        lens = torch.from_numpy(np.diff(rp[r0:r1 + 1])).to(dev)
+        w = torch.repeat_interleave(x, lens)
+        D = torch.zeros(nvox, dtype=torch.float64, device=dev)
+        D.index_add_(0, col[a:b].long(), val[a:b].double() * w)
+        del w
+        dt = D[tm] - par["d_presc"]
+        do = torch.clamp(D[om] - par["d_max"], min=0.0)
+        F += par["w_target"] * float((dt * dt).sum()) + par["w_oar"] * float((do * do).sum())
+        dmax_err = max(dmax_err, float((dose[s].double() - D).abs().max() / D.max()))
+    F /= n_scen
+    say(f"  optimiser on the full IM: F {hist[0]:.4f} -> {hist[-1]:.4f}, recomputed {F:.4f}, "
+        f"dose max err {dmax_err:.2e} of max, L {L:.4e}")
+    assert hist[-1] == pytest.approx(F, rel=1e-8)
+    assert dmax_err <= 1e-6
+    assert hist[-1] < 0.2 * hist[0]
 
 
 def test_full_size_let_leaves_the_dose_tally_unchanged(eng, orc):
