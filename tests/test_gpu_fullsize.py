@@ -248,3 +248,52 @@ def test_full_size_let_leaves_the_dose_tally_unchanged(eng, orc):
     say(f"  plan LET_d over {int(m.sum())} voxels: {let_d.min():.3f} - {let_d.max():.3f} keV/um, "
         f"per unit density {mass_let.min():.3f} - {mass_let.max():.3f}")
     assert mass_let.min() > 0.3 and mass_let.max() < 40.0
+
+
+def plan_dose(eng, case, seed, surrogate=False, mult=4):
+    """Nominal uniform-weight plan dose of all fields at mult x the VPs per
+    spot and its batch standard error (16 batches), FP64 numpy."""
+    fields = [I.Field(beam=f.beam, spots=f.spots.copy(), polygon=f.polygon, block=f.block, rs=f.rs,
+                      vsad_mm=f.vsad_mm) for f in case.fields]
+    for f in fields:
+        f.spots["n_histories"] = (f.spots["n_histories"].astype(np.uint64) * mult).astype(np.uint32)
+    nom = I.Case("nominal", case.geometry, fields, [I.Scenario()], seed=case.seed, physics=case.physics,
+                 n_batches=16)
+    eng.load_case(nom)
+    total = var = None
+    for fi in range(len(nom.fields)):
+        d, s, _ = eng.run_dose(nom, fi, n_batches=16, sigma=True, seed=seed, surrogate=surrogate)
+        d, s = d[0].double().cpu().numpy(), s[0].double().cpu().numpy()
+        total = d if total is None else total + d
+        var = s * s if var is None else var + s * s
+    return total, np.sqrt(var)
+
+
+def test_full_size_surrogate_plan_dose(eng):
+    """The learned aperture surrogate on the full head case, as the
+    throughput measurement compares it: trained on the GPU on plain brass
+    traversals near the three apertures' edges (3e6 samples, 6 epochs), the
+    nominal plan dose of the three fields at 4x the VPs per spot (U about
+    0.25 %) with the surrogate against an independent plain run: >= 99 % of
+    the voxels >= 10 % of the maximum within 3 combined standard errors,
+    gamma 1 %/1 mm >= 99 % (global, 10 % threshold), mean over the
+    high-dose region within 0.5 %."""
+    from gamma import gamma_pass_rate
+    from paper_2307_01416_amd import vpmc as V
+    case = I.config4(8.0, VPS_PER_SPOT)
+    losses = eng.train_surrogate(case, n=3_000_000, epochs=6, seed=3, fields=range(len(case.fields)))
+    assert losses[-1] < losses[0]
+    V.vpmc_surrogate_config(eng.ctx)
+    dp, sp = plan_dose(eng, case, seed=case.seed + 101)
+    ds, ss = plan_dose(eng, case, seed=case.seed + 202, surrogate=True)
+    m = dp >= 0.1 * dp.max()
+    frac = float(np.mean(np.abs(ds - dp)[m] <= 3.0 * np.sqrt(sp ** 2 + ss ** 2)[m]))
+    avg = 0.5 * (dp + ds)
+    hi = avg >= 0.5 * avg.max()
+    ratio = float(ds[hi].mean() / dp[hi].mean())
+    idx = np.nonzero(m)
+    box = tuple(slice(max(0, int(i.min()) - 2), int(i.max()) + 3) for i in idx)
+    rate = gamma_pass_rate(dp[box], ds[box], case.geometry.spacing, 0.01, 1.0)
+    say(f"  surrogate vs plain at full size: losses {losses[0]:.4f} -> {losses[-1]:.4f}, 3-sigma {frac:.4f}, "
+        f"gamma 1%/1mm {rate:.4f}, high-dose mean ratio {ratio:.5f}")
+    assert frac >= 0.99 and rate >= 0.99 and abs(ratio - 1.0) <= 0.005
