@@ -15,7 +15,9 @@ Full physics (properties that hold at any size): columns ascend in every
 row, the rows of each sampled scenario sum to the dense tallies of its three
 fields bit for bit, the dynamic-spacing merge of the whole IM keeps every
 row's exact total, the optimiser's reported objective matches its weights,
-and the LET tally leaves the dose tally unchanged."""
+the LET tally leaves the dose tally unchanged, and the divergent and
+energy-layer aperture IMs sum to their dense tallies.  The learned
+surrogate's plan dose is compared with a plain run statistically."""
 import numpy as np
 import pytest
 
@@ -248,6 +250,45 @@ def test_full_size_let_leaves_the_dose_tally_unchanged(eng, orc):
     say(f"  plan LET_d over {int(m.sum())} voxels: {let_d.min():.3f} - {let_d.max():.3f} keV/um, "
         f"per unit density {mass_let.min():.3f} - {mass_let.max():.3f}")
     assert mass_let.min() > 0.3 and mass_let.max() < 40.0
+
+
+@pytest.mark.parametrize("variant", ["divergent", "layer_apertures"])
+def test_full_size_variant_rows_sum_to_dense(eng, variant):
+    """The two aperture variants as the throughput measurement builds their
+    IMs: beam from a virtual source 2 m upstream with the blocks' walls
+    focused on it, and one 32-vertex aperture per energy layer (30 fields).
+    The rows of the nominal scenario sum to the dense tallies of all fields
+    bit for bit, and columns ascend in every row."""
+    import torch
+    layers = variant == "layer_apertures"
+    case = I.config4(8.0, VPS_PER_SPOT, layer_apertures=layers, n_vertices=32 if layers else 128)
+    if not layers:
+        for f in case.fields:
+            f.vsad_mm = 2000.0
+            f.block.focus_mm = 2000.0
+    rp, col, val, q, k = full_run(eng, case)
+    del val
+    n_per_scen = sum(len(f.spots) for f in case.fields)
+    assert n_per_scen * len(case.scenarios) == 37_050
+    a, b = int(rp[0]), int(rp[n_per_scen])
+    cc = col[a:b].cpu().numpy()
+    qq = q[a:b].cpu().numpy()
+    del col, q
+    torch.cuda.empty_cache()
+    down = np.nonzero(np.diff(cc) <= 0)[0] + 1
+    assert np.isin(down, rp[:n_per_scen + 1] - a).all()
+    nvox = case.geometry.nvox
+    acc = np.zeros(nvox, np.int64)
+    np.add.at(acc, cc, qq)
+    del cc, qq
+    dense = np.zeros(nvox, np.int64)
+    for fi in range(len(case.fields)):
+        eng.run_dose(case, fi, scenarios=[case.scenarios[0]], sigma=False, fixed_point_bits=k)
+        qd, kd = eng.last_tally(0)
+        assert kd == k
+        dense += qd.cpu().numpy().ravel()
+    say(f"  {variant}: fields {len(case.fields)}, nnz {int(rp[-1])}, nominal rows {b - a} entries")
+    assert dense.any() and np.array_equal(acc, dense)
 
 
 def plan_dose(eng, case, seed, surrogate=False, mult=4):
