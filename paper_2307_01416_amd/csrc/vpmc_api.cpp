@@ -144,8 +144,10 @@ struct vpmc_ctx {
         bool valid = false;
     } opt_broi, opt_bfull;
     DevBuf opt_rp, opt_col, opt_val, opt_roi, opt_amax, opt_cnt, opt_rcnt, opt_crp, opt_ccol, opt_cval, opt_piece,
-        opt_poff, opt_resid, opt_fpart, opt_gpart, opt_vec, opt_scal, opt_err, opt_hist, opt_dose;
+        opt_poff, opt_resid, opt_fpart, opt_gpart, opt_vec, opt_scal, opt_err, opt_hist, opt_dose, opt_sidx,
+        opt_rstruct;
     long long opt_npieces = 0;
+    int opt_nstruct = 0;
     // dynamic voxel spacing (vpmc_csr_cells)
     DevBuf cl_rp, cl_map, cl_start, cl_mass, cl_cnt, cl_out, cl_col, cl_q, cl_ocell, cl_oq, cl_oval, cl_piece;
     bool opt_valid = false;
@@ -1047,7 +1049,8 @@ void vpmc_destroy(vpmc_ctx *c) {
                           &c->sur_cnt, &c->sur_out, &c->opt_rp, &c->opt_col, &c->opt_val, &c->opt_roi, &c->opt_amax,
                           &c->opt_cnt, &c->opt_rcnt, &c->opt_crp, &c->opt_ccol, &c->opt_cval, &c->opt_piece,
                           &c->opt_poff, &c->opt_resid, &c->opt_fpart, &c->opt_gpart, &c->opt_vec, &c->opt_scal,
-                          &c->opt_err, &c->opt_hist, &c->opt_dose, &c->opt_broi.off, &c->opt_broi.key,
+                          &c->opt_err, &c->opt_hist, &c->opt_dose, &c->opt_sidx, &c->opt_rstruct,
+                          &c->opt_broi.off, &c->opt_broi.key,
                           &c->opt_broi.val, &c->opt_broi.work, &c->opt_bfull.off, &c->opt_bfull.key,
                           &c->opt_bfull.val, &c->opt_bfull.work, &c->cl_rp, &c->cl_map, &c->cl_start,
                           &c->cl_mass, &c->cl_cnt, &c->cl_out, &c->cl_col, &c->cl_q, &c->cl_ocell, &c->cl_oq, &c->cl_piece,
@@ -1858,6 +1861,18 @@ int vpmc_optimize(vpmc_ctx *c, const int64_t *row_ptr, const int32_t *col, const
         for (int v = 0; v < nvox; ++v)
             if (roi_h[(size_t)v]) keep[(size_t)(v / kOptChunk)] = 1;
         if ((rc = build_buckets(O, c->opt_broi, keep, kept))) return rc;
+        // the buckets hold voxel keys; the gradient's columns become indices
+        // among the structure voxels, its residual a compact array
+        std::vector<int32_t> sidx((size_t)nvox, -1);
+        int ns = 0;
+        for (int v = 0; v < nvox; ++v)
+            if (roi_h[(size_t)v]) sidx[(size_t)v] = ns++;
+        if ((rc = ensure(c, c->opt_sidx, (size_t)nvox * 4, 0))) return rc;
+        if ((rc = ensure(c, c->opt_rstruct, (size_t)n_scen * std::max(ns, 1) * 4, 0))) return rc;
+        HIP_TRY(hipMemcpyAsync(c->opt_sidx.ptr, sidx.data(), (size_t)nvox * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(opt_renumber((int32_t *)c->opt_ccol.ptr, kept, (const int32_t *)c->opt_sidx.ptr, nvox, st));
+        HIP_TRY(hipStreamSynchronize(st));   // the host vector outlives the copy
+        c->opt_nstruct = ns;
         memcpy(c->opt_dims, dims, sizeof dims);
         c->opt_rp_host.swap(rp);
         c->opt_roi_host.swap(roi_h);
@@ -1870,6 +1885,9 @@ int vpmc_optimize(vpmc_ctx *c, const int64_t *row_ptr, const int32_t *col, const
     O.piece = (const OptPiece *)c->opt_piece.ptr;
     O.n_pieces = c->opt_npieces;
     O.gpart = (double *)c->opt_gpart.ptr;
+    O.rstruct = (float *)c->opt_rstruct.ptr;
+    O.sidx = (const int32_t *)c->opt_sidx.ptr;
+    O.nstruct = c->opt_nstruct;
     F.piece = O.piece;
     F.n_pieces = O.n_pieces;
     F.gpart = O.gpart;

@@ -313,6 +313,9 @@ struct OptDev {
     const long long *piece_off;     // [n_scen * n_spots + 1] first piece of each compact row
     float *amax;                    // [n_scen * n_spots] largest |a| of each row
     float *resid;                   // [n_scen][nvox] residual of the last forward sweep
+    float *rstruct;                 // [n_scen][nstruct] the same on the structure voxels only (or NULL)
+    const int32_t *sidx;            // [nvox] index among the structure voxels, -1 elsewhere
+    int nstruct;                    // structure voxels
     double *fpart;                  // [n_work] objective partials
     double *gpart;                  // [n_pieces] piece products with the residual
     double *x, *y, *z, *gvec;       // [n_spots]
@@ -323,6 +326,7 @@ struct OptDev {
 hipError_t opt_build_count(const OptDev &O, unsigned long long *cnt, unsigned *err, hipStream_t st);
 hipError_t opt_roi_count(const OptDev &O, unsigned long long *rcnt, unsigned *err, hipStream_t st);
 hipError_t opt_roi_copy(const OptDev &O, const long long *rptr, int32_t *ccol, float *cval, hipStream_t st);
+hipError_t opt_renumber(int32_t *ccol, long long n, const int32_t *sidx, int nvox, hipStream_t st);
 hipError_t opt_build_scan(unsigned long long *cnt, unsigned long long *off, size_t n, hipStream_t st);
 hipError_t opt_build_emit(const OptDev &O, const unsigned long long *off, unsigned long long *cur, uint32_t *bkey,
                           float *bval, hipStream_t st);

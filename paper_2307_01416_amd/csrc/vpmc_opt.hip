@@ -155,6 +155,17 @@ __global__ void __launch_bounds__(kOptThreads) opt_roi_copy_kernel(OptDev O, con
     }
 }
 
+// Column renumbering of the structure-restricted rows: voxel -> its index
+// among the structure voxels (-1 for any other, which the gradient skips).
+__global__ void __launch_bounds__(kOptThreads) opt_renumber_kernel(int32_t *ccol, long long n, const int32_t *sidx,
+                                                                   int nvox) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = ccol[i];
+        ccol[i] = (unsigned)c < (unsigned)nvox ? sidx[c] : -1;
+    }
+}
+
 // Pass 2 over the rows: the entries of every segment are copied, as one
 // block, into the entry range of its (scenario, chunk) list: key (spot <<
 // kOptChunkBits | voxel - chunk base) and value.  A segment closes at the next segment
@@ -279,6 +290,11 @@ __global__ void __launch_bounds__(kFwdThreads) opt_forward_kernel(OptDev O, cons
             if (mode == 2 && dose_out) dose_out[(size_t)s * O.nvox + base + v] = (float)D;
         }
         res[v] = (float)r;
+        if (O.rstruct && m) {
+            // the structure voxels' residual, compact: what the gradient gathers
+            const int si = O.sidx[base + v];
+            if ((unsigned)si < (unsigned)O.nstruct) O.rstruct[(size_t)s * O.nstruct + si] = (float)r;
+        }
     }
     if (mode == 1) return;
     for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o);
@@ -301,7 +317,9 @@ __global__ void __launch_bounds__(kOptThreads) opt_grad_kernel(OptDev O) {
     const OptPiece q = O.piece[p];
     const int r = __builtin_amdgcn_readfirstlane(q.row);
     const int s = r / O.n_spots;
-    const float *res = O.resid + (size_t)s * O.nvox;
+    // columns renumbered to structure voxels: the residual gathered is the
+    // compact one (n_scen x nstruct floats, cache-resident)
+    const float *res = O.rstruct + (size_t)s * O.nstruct;
     const int lane = lane_id();
     const long long e = q.begin + q.len;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -316,7 +334,7 @@ __global__ void __launch_bounds__(kOptThreads) opt_grad_kernel(OptDev O) {
         }
         float rr[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) rr[u] = (unsigned)c[u] < (unsigned)O.nvox ? res[c[u]] : 0.0f;
+        for (int u = 0; u < 4; ++u) rr[u] = (unsigned)c[u] < (unsigned)O.nstruct ? res[c[u]] : 0.0f;
         a0 = fma((double)v[0], (double)rr[0], a0);
         a1 = fma((double)v[1], (double)rr[1], a1);
         a2 = fma((double)v[2], (double)rr[2], a2);
@@ -324,7 +342,7 @@ __global__ void __launch_bounds__(kOptThreads) opt_grad_kernel(OptDev O) {
     }
     for (; i < e; i += 64) {
         const int c0 = O.col[i];
-        const float r0 = (unsigned)c0 < (unsigned)O.nvox ? res[c0] : 0.0f;
+        const float r0 = (unsigned)c0 < (unsigned)O.nstruct ? res[c0] : 0.0f;
         a0 = fma((double)O.val[i], (double)r0, a0);
     }
     double a = (a0 + a1) + (a2 + a3);
@@ -459,6 +477,13 @@ hipError_t opt_roi_count(const OptDev &O, unsigned long long *rcnt, unsigned *er
     const long long rows = (long long)O.n_scen * O.n_spots;
     const int blocks = (int)((rows * 64 + kOptThreads - 1) / kOptThreads);
     hipLaunchKernelGGL(opt_roi_count_kernel, dim3(blocks), dim3(kOptThreads), 0, st, O, rcnt, err);
+    return hipGetLastError();
+}
+
+hipError_t opt_renumber(int32_t *ccol, long long n, const int32_t *sidx, int nvox, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const long long blocks = std::min<long long>((n + kOptThreads - 1) / kOptThreads, 65536);
+    hipLaunchKernelGGL(opt_renumber_kernel, dim3((unsigned)blocks), dim3(kOptThreads), 0, st, ccol, n, sidx, nvox);
     return hipGetLastError();
 }
 
