@@ -32,8 +32,13 @@ PINS = {
     "normal_quantile": "scipy.special.ndtr round trip, symmetry",
     "stopping_power": "NIST PSTAR water values (1 %), K from CODATA",
     "range": "scipy quad of 1/S (1e-10), Bragg-Kleeman band, brass 30 mm ~ 155 MeV",
-    "omega2": "coefficient from CODATA constants; slab exit-energy variance",
-    "scatter_power": "slab exit-angle variance = Fermi-Eyges A0; Highland with its log term",
+    "omega2": "coefficient from CODATA constants; slab exit-energy variance (water, brass 1-5 mm from the "
+              "elements' Z/A); propagated variance after 100 voxel steps of water",
+    "scatter_power": "slab exit-angle variance = Fermi-Eyges A0 (water; brass 1-5 mm at 100-200 MeV with X0 from "
+                     "the Cu/Zn mixture rule); Highland with its log term",
+    "voxel_hinge": "pencil beam through the voxel loop (hinge steps, end point kept in its voxel): exit moments "
+                   "= Fermi-Eyges A0, A1, A2 along two beam axes, no drift of the centre line",
+    "brass_constants": "X0 by the mixture rule, Z/A from Cu and Zn, I by Bragg additivity",
     "nuclear": "slab survival = exp(-rho sigma L) above 20 MeV",
     "crossing_number": "analytic circle and brute-force raster of concave polygons",
     "straight_transport": "exact IDD closed form E(z) = R^-1(R(E0) - rho z); range scaling",
@@ -45,6 +50,8 @@ PINS = {
     "hu_lookup": "breakpoints of the piecewise-linear calibration",
     "absolute_dosimetry": "parity unpinned (no measurement or comparison system available)",
     "mlp": "gradients vs central finite differences; mixture NLL vs scipy for one component",
+    "adam": "first step = lr sign(g); constant gradient = equal steps; alternating gradient = closed-form "
+            "momentum (Kingma & Ba)",
     "let": "entrance LET_d = NIST PSTAR stopping power; per-voxel LET_d = exact CSDA energy loss / path in "
            "straight water (closed form); rises with depth",
 }
@@ -101,6 +108,7 @@ def lib():
             ("orc_run", i64, [vp, vp, vp, i, i, vp, vp, vp, vp, i, vp]),
             ("orc_trace_history", None, [vp, vp, vp, i, i64, vp, vp, vp, vp, vp]),
             ("orc_slab_exit", None, [i, d, d, d, i, C.c_uint64, i64, vp, i]),
+            ("orc_patient_exit", None, [vp, vp, vp, i, i64, vp, vp, vp, i]),
             ("orc_fixed_point_k", i, [d]), ("orc_rs_thickness", d, [d]),
             ("orc_mev_to_joule", d, []),
             ("orc_polygon_distance", d, [vp, i, d, d]),
@@ -327,6 +335,22 @@ def trace_history(case, spot_index: int, h: int, field_index: int = 0, scenario_
                             spot_index, h, C.byref(P.scen), C.byref(o), _ptr(led), _ptr(grid),
                             _ptr(info))
     return led, info, grid
+
+
+def patient_exit(case, spot_index: int, n: int, field_index: int = 0, scenario_index: int = 0,
+                 physics: Optional[int] = None, seed: Optional[int] = None, threads: int = 0) -> np.ndarray:
+    """Exit states of histories 0..n-1 of one spot through source, beam line
+    and voxel loop: out[n][8] = {left the grid through a face, E, x, y, z
+    (CT frame), u, v, w}."""
+    P = _Prepared(case, field_index, scenario_index)
+    o = _Opts()
+    o.seed = case.seed if seed is None else seed
+    o.field_id = field_index
+    o.physics = case.physics if physics is None else physics
+    out = np.zeros((n, 8), np.float64)
+    lib().orc_patient_exit(C.byref(P.geom), C.byref(P.field), C.byref(P.spots[spot_index]), spot_index, n,
+                           C.byref(P.scen), C.byref(o), _ptr(out), threads)
+    return out
 
 
 def voxel_mass_g(case) -> np.ndarray:

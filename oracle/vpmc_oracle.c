@@ -787,7 +787,13 @@ static void patient(vp_t *vp, sink_t *sk, const orc_geom *g, const orc_field *f,
             vp->p[ax] = bnd;
             if (idx[ax] < 0 || idx[ax] >= n[ax]) { sink_ledger(sk, L_ESCAPED, vp->E); return; }
         }
-        for (int k = 0; k < 3; k++) {          /* keep the hinge end point in its voxel */
+        /* Keep the hinge end point in its voxel (reading: the paper's step
+         * loop is voxel by voxel; the deflected second half of a step may end
+         * up to s/2 * theta beyond a face of the voxel the step began in, and
+         * is moved back onto that face; the face crossed by a boundary-limited
+         * step is set exactly).  Its effect on the lateral spread is below
+         * the Fermi-Eyges pins' resolution (0.3 %). */
+        for (int k = 0; k < 3; k++) {
             double a = lo[k] + idx[k] * g->sp[k], b = lo[k] + (idx[k] + 1) * g->sp[k];
             if (vp->p[k] < a) vp->p[k] = a;
             if (vp->p[k] > b) vp->p[k] = b;
@@ -901,6 +907,32 @@ void orc_trace_history(const orc_geom *g, const orc_field *f, const orc_spot *sp
     one_history(g, f, sp, spot_index, h, sc, o, &sk, &vp);
     for (int l = 0; l < NLEDGER; l++) ledgers[l] = sk.led_fp[l];
     info[0] = vp.n_steps; info[1] = vp.n_nuc; info[2] = vp.nblk; info[3] = 0;
+}
+
+/* Exit states of histories 0 .. n-1 of one spot through the whole path
+ * (source, beam line, voxel loop), for the lateral-spread pins of the voxel
+ * transport: out[n][8] = {1 if the VP left the grid through a face (0 if it
+ * stopped or missed it), E, x, y, z (CT frame, mm), u, v, w}.  With the
+ * grid's downstream face at depth L, a pencil beam's exit moments are the
+ * Fermi-Eyges moments of the scattering power along its path. */
+void orc_patient_exit(const orc_geom *g, const orc_field *f, const orc_spot *sp, int spot_index, int64_t n,
+                      const orc_scen *sc, const orc_opts *o, double *out, int nthreads)
+{
+    orc_init();
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 256)
+#endif
+    for (int64_t h = 0; h < n; h++) {
+        sink_t sk;
+        vp_t vp;
+        memset(&sk, 0, sizeof sk);
+        one_history(g, f, sp, spot_index, h, sc, o, &sk, &vp);
+        double *q = out + 8 * h;
+        q[0] = (vp.E > 0.0 && sk.led_fp[L_ESCAPED] > 0.0) ? 1.0 : 0.0;
+        q[1] = vp.E;
+        for (int k = 0; k < 3; k++) { q[2 + k] = vp.p[k]; q[5 + k] = vp.d[k]; }
+    }
 }
 
 /* Thin-slab experiment for the physics pins: n VPs of energy e0 enter a slab

@@ -72,3 +72,50 @@ def test_forward_layout_one_hot_path(orc):
         others = np.delete(out[r], 7)
         ref = np.delete(np.linspace(-1.0, 1.0, 29), 7)
         np.testing.assert_allclose(others, ref, rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------- Adam
+# mlp_adam_step follows Kingma & Ba (ICLR 2015, Algorithm 1): biased moments
+# m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2, bias-corrected by
+# 1 - b^t, step lr * m_hat / (sqrt(v_hat) + eps).  Closed forms pin it.
+def _adam(orc, p, grads, lr, b1=0.9, b2=0.999, eps=1e-8):
+    import ctypes as C
+    p = np.array(p, np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    P = lambda a: a.ctypes.data_as(C.c_void_p)
+    for t, g in enumerate(grads, start=1):
+        g = np.ascontiguousarray(g, np.float64)
+        orc.lib().mlp_adam_step(P(p), P(g), P(m), P(v), p.size, t, lr, b1, b2, eps)
+    return p
+
+
+def test_adam_first_step_is_lr_times_sign(orc):
+    # from zero moments the bias corrections make m_hat = g, v_hat = g^2
+    rng = np.random.default_rng(3)
+    p0 = rng.normal(size=64)
+    g = rng.normal(size=64) * 10.0 ** rng.uniform(-4, 1, size=64)
+    p1 = _adam(orc, p0, [g], lr=1e-3)
+    np.testing.assert_allclose(p1, p0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-14, atol=1e-18)
+
+
+def test_adam_constant_gradient_steps_are_equal(orc):
+    # a constant gradient keeps m_hat = g and v_hat = g^2 at every step t
+    rng = np.random.default_rng(4)
+    p0 = rng.normal(size=32)
+    g = rng.normal(size=32)
+    p10 = _adam(orc, p0, [g] * 10, lr=2e-3)
+    np.testing.assert_allclose(p10, p0 - 10 * 2e-3 * g / (np.abs(g) + 1e-8), rtol=1e-13, atol=1e-16)
+
+
+def test_adam_alternating_gradient_momentum_closed_form(orc):
+    # g_t = (-1)^t c: m_t = (1 - b1) c (-1)^t (1 - (-b1)^t) / (1 + b1),
+    # v_t = c^2 (1 - b2^t), so v_hat = c^2 and the step is lr * m_hat_t / (c + eps)
+    b1, b2, lr, c = 0.9, 0.999, 1e-2, 0.37
+    T = 7
+    p = _adam(orc, [0.0], [np.array([(-1) ** t * c]) for t in range(1, T + 1)], lr=lr, b1=b1, b2=b2)
+    ref = 0.0
+    for t in range(1, T + 1):
+        m = (1 - b1) * c * (-1) ** t * (1 - (-b1) ** t) / (1 + b1)
+        ref -= lr * (m / (1 - b1 ** t)) / (c + 1e-8)
+    assert p[0] == pytest.approx(ref, rel=1e-13)
