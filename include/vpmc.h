@@ -43,7 +43,7 @@ extern "C" {
 #define VPMC_E_OOM -4      /* device memory (or opts.max_device_bytes) exhausted */
 #define VPMC_E_DEVICE -5   /* HIP runtime error */
 #define VPMC_E_RANGE -6    /* energy outside the tables or fixed-point overflow bound */
-#define VPMC_E_ABORTED -7  /* work-queue iteration cap reached */
+#define VPMC_E_ABORTED -7  /* work-queue iteration cap (vpmc_opts.queue_cap) reached */
 
 /* physics switches (0 = straight CSDA transport) */
 #define VPMC_STRAGGLE 1u
@@ -86,7 +86,9 @@ int vpmc_version(void);
 /* Load the patient or phantom voxel grid (Methods D.2 water phantoms, D.3
  * CT geometries).  kind VPMC_GEOM_WATER ignores hu (may be NULL);
  * VPMC_GEOM_HU copies nx*ny*nz int16 CT numbers (host pointer, or device
- * pointer with VPMC_DEVICE_PTRS).  nx*ny*nz must be < 2^31. */
+ * pointer with VPMC_DEVICE_PTRS).  nx*ny*nz must be < 2^31.  On a
+ * validation-only context only the grid's shape is kept (for the checks of
+ * later calls) and hu is not read. */
 int vpmc_load_geometry(vpmc_ctx *ctx, int kind, const int16_t *hu, int nx, int ny, int nz,
                        const float spacing_mm[3], const float origin_mm[3], unsigned flags);
 
@@ -170,6 +172,9 @@ typedef struct {
     int grid_blocks;        /* 0 = tuned default */
     int hist_per_lane;      /* CSR work-queue chunk = 64 * hist_per_lane histories; 0 = default 4 */
     int max_slots;          /* CSR rows resident at once (<= 1024); 0 = sized from memory */
+    uint64_t queue_cap;     /* CSR work queue: iterations (chunks drawn, row picks, waits) a
+                               wavefront may make before it gives up and the run returns
+                               VPMC_E_ABORTED with no rows written; 0 = 2^40 (no practical cap) */
 } vpmc_opts;
 
 /* Transport all histories of n_spots spots of field `field_id` for each of
@@ -184,7 +189,10 @@ typedef struct {
  *   filled; the total number of non-zeros is row_ptr[n_scen*n_spots]; then
  *   call vpmc_copy_csr.  dose_gy/sigma_gy may be NULL.
  * Errors: VPMC_E_STATE (no geometry/field), VPMC_E_ARG, VPMC_E_RANGE
- * (energy outside (1, 256] MeV or k too small), VPMC_E_OOM, VPMC_E_DEVICE. */
+ * (energy outside (1, 256] MeV or k too small), VPMC_E_OOM (the run's device
+ * scratch exceeds opts->max_device_bytes: checked before any HIP call for the
+ * dense grids and one CSR row slot, then by the allocator), VPMC_E_DEVICE,
+ * VPMC_E_ABORTED (CSR: opts->queue_cap reached). */
 int vpmc_run_spots(vpmc_ctx *ctx, int field_id, const vpmc_spot *spots, int n_spots,
                    const vpmc_scenario *scen, int n_scen, const vpmc_opts *opts, float *dose_gy,
                    float *sigma_gy, double *ledger_mev, int64_t *row_ptr);
@@ -246,6 +254,15 @@ int vpmc_surrogate_sample(vpmc_ctx *ctx, int field_id, const float *entries, int
                           unsigned physics, float *x, float *y, float *trans);
 int vpmc_surrogate_set_weights(vpmc_ctx *ctx, const float *params, int n_params);
 int vpmc_surrogate_get_weights(vpmc_ctx *ctx, float *params, int n_params);
+/* Weights by file (little-endian): the 8 bytes "VPMCMLP1", a uint32
+ * parameter count, then the FP32 parameters in the layout above.
+ * vpmc_surrogate_load(ctx, NULL) disables the network (runs with
+ * VPMC_SURROGATE then fail with VPMC_E_STATE until weights are set again).
+ * Errors: VPMC_E_ARG (unreadable or malformed file, wrong count, a value not
+ * finite, unwritable path), VPMC_E_STATE (validation-only context; save
+ * without weights), VPMC_E_DEVICE. */
+int vpmc_surrogate_load(vpmc_ctx *ctx, const char *weights_path);
+int vpmc_surrogate_save(vpmc_ctx *ctx, const char *weights_path);
 /* Use of the network in runs with VPMC_SURROGATE (Methods B; the
  * paper's block model is the plain transport, the network is this library's
  * replacement for the deep brass part of it).  A VP whose block entry point

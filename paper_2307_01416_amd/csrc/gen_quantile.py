@@ -2,8 +2,9 @@
 kernels for straggling (normal_quantile in vpmc_kernels.hip).
 
 z(u) = sqrt(2) erfinv(t), t = 2u - 1, with g(t) = erfinv(t) / t written as
-a function of w = -log(1 - t^2) = -log(4 u (1 - u)): a degree-8 polynomial
-in w - 2.5 for w < 5 and in sqrt(w) - 3 for w >= 5, fitted by weighted least
+a function of w = -log(1 - t^2) = -log(4 u (1 - u)) as in M. Giles'
+single-precision erfinv (GPU Computing Gems Jade Edition, 2011): a degree-8
+polynomial in w - 2.5 for w < 5 and in sqrt(w) - 3 for w >= 5, fitted by weighted least
 squares (relative error) to the FP64 function on Chebyshev nodes.  Prints
 the coefficients (highest power first) and the largest relative error of the
 FP32 evaluation over the uniform grid the kernels draw from,

@@ -294,6 +294,26 @@ int pick_k(const vpmc_opts *o, double T, int *k_out) {
     return VPMC_OK;
 }
 
+// Device bytes a dense run needs at least (tallies, batch grids, LET,
+// staging, spot tables); checked against max_device_bytes before any HIP
+// call.  The allocator re-checks with what the context already holds.
+size_t dense_bytes(size_t nvox, int n_scen, int n_spots, int B, bool let, bool dev_out, bool dose, bool sigma) {
+    size_t b = (size_t)n_scen * nvox * 8 * (let ? 2 : 1);
+    if (B > 1) b += nvox * 16;
+    b += (size_t)n_scen * NLEDGER * 8 + (size_t)std::max(1, n_spots) * sizeof(SpotDev) + 16 +
+         (size_t)B * (n_spots + 1) * 8;
+    if (!dev_out) b += (dose ? nvox * 4 : 0) + (sigma ? nvox * 4 : 0);
+    return b;
+}
+
+// Bytes of one resident influence-matrix row (dense int64 slot, touched-block
+// bytes, chunk counters); a CSR run keeps at least one and spends at most half
+// of max_device_bytes on them.
+size_t csr_slot_bytes(size_t nvox) {
+    const size_t nblk = (nvox + 31) / 32, nchunk = (nblk + 255) / 256;
+    return nblk * 32 * 8 + ((nblk + 255) & ~(size_t)255) + nchunk * 8 + 4;
+}
+
 // ---------------------------------------------------------------- CSR runner
 struct BatchField {
     int field_id;
@@ -468,7 +488,7 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     // slots: dense int64 grid + touched-block bytes per resident row
     const size_t nblk = (nvox + 31) / 32, nchunk = (nblk + 255) / 256;
     const size_t gstride = nblk * 32, mstride = (nblk + 255) & ~(size_t)255;
-    const size_t slot_bytes = gstride * 8 + mstride + nchunk * 8 + 4;
+    const size_t slot_bytes = csr_slot_bytes(nvox);
     size_t budget = cap ? (cap > c->bytes ? cap - c->bytes : 0) / 2 : ((size_t)24 << 30);
     int G = o->max_slots > 0 ? std::min(o->max_slots, kMaxSlots) : kMaxSlots;
     G = (int)std::min<size_t>((size_t)G, budget / slot_bytes);
@@ -581,6 +601,8 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     Q.ledger = (unsigned long long *)c->ledger.ptr;
     Q.stats = (unsigned long long *)c->stats.ptr;
     Q.tables = c->d_tables;
+    Q.iter_cap = o->queue_cap ? (unsigned long long)o->queue_cap : kDefaultQueueCap;
+    Q.flags = (unsigned int *)c->flags.ptr;
 
     if ((rc = ensure(c, c->q_stage, queue_stage_floats(q_blocks, q_threads, hpl) * sizeof(float), cap))) return rc;
     if ((rc = ensure(c, c->q_rownext, (size_t)std::max(R, 1) * 8, cap))) return rc;
@@ -713,7 +735,9 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
                                        (unsigned long long *)c->row_off.ptr, (unsigned long long *)c->row_nnz.ptr,
                                        (unsigned long long *)c->used.ptr, ~0ull, (unsigned int *)c->flags.ptr, st));
             unsigned long long used_now = 0;
+            unsigned int fl_now = 0;
             HIP_TRY(hipMemcpyAsync(&used_now, c->used.ptr, 8, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(&fl_now, c->flags.ptr, 4, hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, c->events[2], c->events[3]));
@@ -724,8 +748,9 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
                 if ((rc = grow_keep(c, c->csr_q, used_host * 8, ncap * 8, cap, st))) return rc;
                 c->csr_cap = ncap;
             }
-            HIP_TRY(emit_rows(Qe));
+            HIP_TRY(emit_rows(Qe));   // also clears the epoch's slots
             used_host = used_now;
+            if (fl_now & kFlagAborted) break;   // no further epochs: the run fails below
         }
     }
     unsigned int fl = 0;
@@ -741,7 +766,10 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     HIP_TRY(hipMemcpyAsync(stv, c->stats.ptr, 16, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (fl & 2u) return fail(VPMC_E_DEVICE, "influence-matrix count and emit passes disagree");
-    c->slots_dirty = false;
+    c->slots_dirty = false;   // every launched epoch was compacted, which clears its slots
+    if (fl & kFlagAborted)
+        return fail(VPMC_E_ABORTED, "a wavefront reached the work-queue cap of %llu iterations; no rows written",
+                    (unsigned long long)Q.iter_cap);
     std::vector<int64_t> rp((size_t)R + 1);
     for (int r = 0; r < R; ++r) rp[r] = (int64_t)roff[r];
     rp[R] = (int64_t)used_host;
@@ -859,6 +887,45 @@ int vpmc_surrogate_set_weights(vpmc_ctx *c, const float *params, int n) {
     HIP_TRY(hipDeviceSynchronize());
     c->mlp_ready = true;
     c->mlp_step = 0;
+    return VPMC_OK;
+}
+
+// Weights file: the 8 bytes "VPMCMLP1", a little-endian uint32 parameter
+// count, then that many little-endian FP32 parameters in the layout of
+// vpmc_surrogate_set_weights.
+static const char kMlpMagic[8] = {'V', 'P', 'M', 'C', 'M', 'L', 'P', '1'};
+
+int vpmc_surrogate_load(vpmc_ctx *c, const char *path) {
+    if (!c) return fail(VPMC_E_ARG, "ctx is NULL");
+    if (!path) {   // disable: runs with VPMC_SURROGATE fail until weights are set again
+        c->mlp_ready = false;
+        return VPMC_OK;
+    }
+    FILE *fp = fopen(path, "rb");
+    if (!fp) return fail(VPMC_E_ARG, "cannot open surrogate weights '%s'", path);
+    const int np = mlp_param_count();
+    char magic[8];
+    uint32_t n = 0;
+    std::vector<float> w(np);
+    const bool ok = fread(magic, 1, 8, fp) == 8 && memcmp(magic, kMlpMagic, 8) == 0 && fread(&n, 4, 1, fp) == 1 &&
+                    n == (uint32_t)np && fread(w.data(), 4, np, fp) == (size_t)np && fgetc(fp) == EOF;
+    fclose(fp);
+    if (!ok) return fail(VPMC_E_ARG, "'%s' is not a surrogate weights file of %d parameters", path, np);
+    return vpmc_surrogate_set_weights(c, w.data(), np);
+}
+
+int vpmc_surrogate_save(vpmc_ctx *c, const char *path) {
+    if (!c || !path) return fail(VPMC_E_ARG, "ctx/path is NULL");
+    const int np = mlp_param_count();
+    std::vector<float> w(np);
+    int rc = vpmc_surrogate_get_weights(c, w.data(), np);
+    if (rc) return rc;
+    FILE *fp = fopen(path, "wb");
+    if (!fp) return fail(VPMC_E_ARG, "cannot create '%s'", path);
+    const uint32_t n = (uint32_t)np;
+    const bool ok = fwrite(kMlpMagic, 1, 8, fp) == 8 && fwrite(&n, 4, 1, fp) == 1 &&
+                    fwrite(w.data(), 4, np, fp) == (size_t)np;
+    if (fclose(fp) != 0 || !ok) return fail(VPMC_E_ARG, "writing '%s' failed", path);
     return VPMC_OK;
 }
 
@@ -1118,12 +1185,20 @@ int vpmc_load_geometry(vpmc_ctx *c, int kind, const int16_t *hu, int nx, int ny,
         return fail(VPMC_E_ARG, "spacing must be positive");
     if (kind == VPMC_GEOM_HU && !hu) return fail(VPMC_E_ARG, "HU geometry needs hu data");
     if (flags & ~VPMC_DEVICE_PTRS) return fail(VPMC_E_ARG, "unknown flags");
-    if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
-    HIP_TRY(hipSetDevice(c->device));
     GeomDev g{};
     g.kind = kind;
     g.nx = nx; g.ny = ny; g.nz = nz;
     for (int k = 0; k < 3; ++k) { g.sp[k] = spacing_mm[k]; g.lo[k] = origin_mm[k]; }
+    if (c->device < 0) {
+        // validation-only context: the grid's shape is kept for the checks of
+        // later calls, the CT numbers are not read
+        c->geom = g;
+        c->nvox = nvox;
+        c->has_geom = true;
+        c->last_nscen = 0;
+        return VPMC_OK;
+    }
+    HIP_TRY(hipSetDevice(c->device));
     if (kind == VPMC_GEOM_HU) {
         int rc = ensure(c, c->hu_buf, nvox * sizeof(int16_t), 0);
         if (rc) return rc;
@@ -1253,20 +1328,93 @@ int vpmc_set_divergence(vpmc_ctx *c, int field_id, float vsad_mm, float focus_mm
     return VPMC_OK;
 }
 
-int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spots, const vpmc_scenario *scen,
-                   int n_scen, const vpmc_opts *o, float *dose_gy, float *sigma_gy, double *ledger_mev,
-                   int64_t *row_ptr) {
+}  // extern "C"
+
+namespace {
+
+// Checks shared by the dense and CSR runs of one field; T receives the
+// weighted energy bound of the spots (for the fixed-point exponent).
+int validate_run(const vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spots, const vpmc_scenario *scen,
+                 int n_scen, const vpmc_opts *o, double *T) {
     if (!c) return fail(VPMC_E_ARG, "ctx is NULL");
     if (!o) return fail(VPMC_E_ARG, "opts is NULL");
     if (!c->has_geom) return fail(VPMC_E_STATE, "no geometry loaded");
     if (field_id < 0 || field_id >= VPMC_MAX_FIELDS) return fail(VPMC_E_ARG, "field_id out of range");
     if (!c->fields[field_id].set) return fail(VPMC_E_STATE, "field %d has no aperture/beam set", field_id);
-    double T = 0.0;
     int rc;
-    if ((rc = validate_spots(spots, n_spots, &T))) return rc;
+    if ((rc = validate_spots(spots, n_spots, T))) return rc;
     if ((rc = validate_scen(scen, n_scen))) return rc;
     if (o->physics & ~VPMC_PHYS_ALL) return fail(VPMC_E_ARG, "unknown physics bits");
     if (o->n_batches < 0 || o->n_batches > 1024) return fail(VPMC_E_ARG, "n_batches outside [0, 1024]");
+    return VPMC_OK;
+}
+
+// Device spot records (scale = w/N * 2^k) and, per batch b, the prefix of
+// history counts per spot (history h of a spot belongs to batch h mod B).
+void dense_spot_tables(const vpmc_spot *spots, int n_spots, int k, int B, std::vector<SpotDev> &sd,
+                       std::vector<unsigned long long> &off) {
+    sd.assign(std::max(1, n_spots), SpotDev{});
+    off.assign((size_t)B * (n_spots + 1), 0ull);
+    for (int i = 0; i < n_spots; ++i) {
+        const vpmc_spot &s = spots[i];
+        SpotDev &d = sd[i];
+        d.x = s.x_mm; d.y = s.y_mm; d.e0 = s.energy_mev; d.sigma = s.sigma_mm; d.esig = s.energy_sigma_mev;
+        d.emax = (float)std::min((double)s.energy_mev + 6.0 * s.energy_sigma_mev, E_HI);
+        d.nh = s.n_histories;
+        d.scale = s.n_histories ? (float)ldexp((double)s.weight / (double)s.n_histories, k) : 0.0f;
+    }
+    for (int b = 0; b < B; ++b) {
+        unsigned long long *ob = off.data() + (size_t)b * (n_spots + 1);
+        for (int i = 0; i < n_spots; ++i) {
+            const unsigned long long nh = spots[i].n_histories;
+            const unsigned long long nb = nh > (unsigned long long)b ? (nh - b + B - 1) / B : 0ull;
+            ob[i + 1] = ob[i] + nb;
+        }
+    }
+}
+
+// Launch record of one batch of one scenario of a dense run.
+LaunchDev dense_launch(const vpmc_opts *o, int field_id, const vpmc_scenario &sc, const SpotDev *spots,
+                       const unsigned long long *ob, int n_spots, unsigned long long items, int b, int B,
+                       unsigned long long *tally, unsigned long long *let_tally, unsigned long long *ledger,
+                       unsigned long long *stats, const float *tables) {
+    LaunchDev L{};
+    L.spots = spots;
+    L.item_off = ob;
+    L.n_spots = n_spots;
+    L.n_items = items;
+    L.batch = b;
+    L.n_batches = B;
+    L.key0 = (uint32_t)(o->seed & 0xffffffffu);
+    L.key1 = (uint32_t)(o->seed >> 32) ^ (uint32_t)field_id;
+    L.physics = o->physics;
+    for (int q = 0; q < 3; ++q) L.shift[q] = sc.shift_mm[q];
+    L.range_scale = sc.range_scale;
+    L.tally = tally;
+    L.let_tally = let_tally;
+    L.ledger = ledger;
+    L.tables = tables;
+    L.stats = stats;
+    return L;
+}
+
+int dense_blocks(const vpmc_ctx *c, const vpmc_opts *o, unsigned long long items, int threads) {
+    unsigned long long want = (items + threads - 1) / threads;
+    const unsigned long long maxb = o->grid_blocks ? (unsigned long long)o->grid_blocks
+                                    : (c->tuned_dense_blocks ? (unsigned long long)c->tuned_dense_blocks : 4096ull);
+    return (int)std::min(want, maxb);
+}
+
+}  // namespace
+
+extern "C" {
+
+int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spots, const vpmc_scenario *scen,
+                   int n_scen, const vpmc_opts *o, float *dose_gy, float *sigma_gy, double *ledger_mev,
+                   int64_t *row_ptr) {
+    double T = 0.0;
+    int rc;
+    if ((rc = validate_run(c, field_id, spots, n_spots, scen, n_scen, o, &T))) return rc;
     if (o->block_threads && o->block_threads != 256 && o->block_threads != 512 &&
         !(o->output == VPMC_OUT_CSR && (o->block_threads == 768 || o->block_threads == 1024)))
         return fail(VPMC_E_ARG, "block_threads must be 0, 256 or 512 (768 or 1024 also for CSR output)");
@@ -1287,6 +1435,9 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
         if (sigma_gy) return fail(VPMC_E_ARG, "sigma_gy is not produced in CSR mode");
         int k = 0;
         if ((rc = pick_k(o, T, &k))) return rc;
+        if (o->max_device_bytes && o->max_device_bytes / 2 < csr_slot_bytes(c->nvox))
+            return fail(VPMC_E_OOM, "one influence-matrix row slot needs %zu bytes; max_device_bytes=%zu",
+                        csr_slot_bytes(c->nvox), o->max_device_bytes);
         if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
         HIP_TRY(hipSetDevice(c->device));
         std::vector<BatchField> bf{{field_id, spots, n_spots}};
@@ -1299,6 +1450,13 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
     if (!dose_gy && !sigma_gy && !ledger_mev) return fail(VPMC_E_ARG, "no output requested");
     int k = 0;
     if ((rc = pick_k(o, T, &k))) return rc;
+    {
+        const size_t need = dense_bytes(c->nvox, n_scen, n_spots, B, (o->flags & VPMC_LET) != 0,
+                                        (o->flags & VPMC_DEVICE_PTRS) != 0, dose_gy != nullptr, sigma_gy != nullptr);
+        if (o->max_device_bytes && need > o->max_device_bytes)
+            return fail(VPMC_E_OOM, "the dense run needs %zu bytes of device scratch; max_device_bytes=%zu", need,
+                        o->max_device_bytes);
+    }
     if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
 
     const size_t nvox = c->nvox;
@@ -1337,24 +1495,9 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
     }
 
     // spots and per-batch work offsets
-    std::vector<SpotDev> sd(std::max(1, n_spots));
-    std::vector<unsigned long long> off((size_t)B * (n_spots + 1), 0ull);
-    for (int i = 0; i < n_spots; ++i) {
-        const vpmc_spot &s = spots[i];
-        SpotDev &d = sd[i];
-        d.x = s.x_mm; d.y = s.y_mm; d.e0 = s.energy_mev; d.sigma = s.sigma_mm; d.esig = s.energy_sigma_mev;
-        d.emax = (float)std::min((double)s.energy_mev + 6.0 * s.energy_sigma_mev, E_HI);
-        d.nh = s.n_histories;
-        d.scale = s.n_histories ? (float)ldexp((double)s.weight / (double)s.n_histories, k) : 0.0f;
-    }
-    for (int b = 0; b < B; ++b) {
-        unsigned long long *ob = off.data() + (size_t)b * (n_spots + 1);
-        for (int i = 0; i < n_spots; ++i) {
-            const unsigned long long nh = spots[i].n_histories;
-            const unsigned long long nb = nh > (unsigned long long)b ? (nh - b + B - 1) / B : 0ull;
-            ob[i + 1] = ob[i] + nb;
-        }
-    }
+    std::vector<SpotDev> sd;
+    std::vector<unsigned long long> off;
+    dense_spot_tables(spots, n_spots, k, B, sd, off);
     HIP_TRY(hipMemcpyAsync(c->spots.ptr, sd.data(), sd.size() * sizeof(SpotDev), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(c->offsets.ptr, off.data(), off.size() * sizeof(unsigned long long),
                            hipMemcpyHostToDevice, st));
@@ -1384,27 +1527,12 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
             const unsigned long long *ob = (const unsigned long long *)c->offsets.ptr + (size_t)b * (n_spots + 1);
             const unsigned long long items = off[(size_t)b * (n_spots + 1) + n_spots];
             if (items == 0) continue;
-            LaunchDev L{};
-            L.spots = (const SpotDev *)c->spots.ptr;
-            L.item_off = ob;
-            L.n_spots = n_spots;
-            L.n_items = items;
-            L.batch = b;
-            L.n_batches = B;
-            L.key0 = (uint32_t)(o->seed & 0xffffffffu);
-            L.key1 = (uint32_t)(o->seed >> 32) ^ (uint32_t)field_id;
-            L.physics = o->physics;
-            for (int q = 0; q < 3; ++q) L.shift[q] = scen[sc].shift_mm[q];
-            L.range_scale = scen[sc].range_scale;
-            L.tally = B > 1 ? (unsigned long long *)c->qbatch.ptr : (unsigned long long *)tally;
-            L.let_tally = let_tally;   // every batch adds to the scenario's numerator
-            L.ledger = (unsigned long long *)c->ledger.ptr + (size_t)sc * NLEDGER;
-            L.tables = c->d_tables;
-            L.stats = (unsigned long long *)c->stats.ptr;
-            unsigned long long want = (items + threads - 1) / threads;
-            const unsigned long long maxb = o->grid_blocks ? (unsigned long long)o->grid_blocks
-                                            : (c->tuned_dense_blocks ? (unsigned long long)c->tuned_dense_blocks : 4096ull);
-            const int blocks = (int)std::min(want, maxb);
+            // every batch adds to the scenario's LET numerator
+            LaunchDev L = dense_launch(o, field_id, scen[sc], (const SpotDev *)c->spots.ptr, ob, n_spots, items, b, B,
+                                       B > 1 ? (unsigned long long *)c->qbatch.ptr : (unsigned long long *)tally,
+                                       let_tally, (unsigned long long *)c->ledger.ptr + (size_t)sc * NLEDGER,
+                                       (unsigned long long *)c->stats.ptr, c->d_tables);
+            const int blocks = dense_blocks(c, o, items, threads);
             if (sur_on) {
                 HIP_TRY(hipMemsetAsync(c->sur_cnt.ptr, 0, sizeof(unsigned long long), st));
                 L.sur.enabled = 1;
@@ -1514,6 +1642,9 @@ int vpmc_run_batched(vpmc_ctx *c, const int *field_ids, const vpmc_spot *const *
         return fail(VPMC_E_ARG, "block_threads must be 0, 256, 512, 768 or 1024");
     int k = 0;
     if ((rc = pick_k(o, T, &k))) return rc;
+    if (o->max_device_bytes && o->max_device_bytes / 2 < csr_slot_bytes(c->nvox))
+        return fail(VPMC_E_OOM, "one influence-matrix row slot needs %zu bytes; max_device_bytes=%zu",
+                    csr_slot_bytes(c->nvox), o->max_device_bytes);
     if (c->device < 0) return fail(VPMC_E_STATE, "validation-only context has no device");
     HIP_TRY(hipSetDevice(c->device));
     return run_csr(c, bf, scen, n_scen, o, k, dose_gy, ledger_mev, row_ptr);

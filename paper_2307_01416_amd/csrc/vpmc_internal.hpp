@@ -178,7 +178,11 @@ struct QueueDev {
     unsigned long long *stats;            // [2]
     const float *tables;
     SurDev sur;                           // surrogate queue (enabled = 0: off)
+    unsigned long long iter_cap;          // work-queue iterations a wavefront may make
+    unsigned int *flags;                  // bit 2 (value 4) set when a wavefront reached iter_cap
 };
+constexpr unsigned long long kDefaultQueueCap = 1ull << 40;   // far above any run's chunk count
+constexpr unsigned int kFlagAborted = 4u;
 
 // staging floats the queue kernel needs for a launch shape (per wave up to
 // 64 * kStageHpl VPs of 16 words)

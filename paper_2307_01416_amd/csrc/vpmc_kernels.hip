@@ -144,10 +144,13 @@ __device__ __forceinline__ NodePos node_pos_below(const float *tab, float E, int
 }
 
 // Standard normal quantile of u in (0, 1), z = sqrt(2) erfinv(2u - 1), for
-// the straggling draw: erfinv(t)/t as degree-8 polynomials in w - 2.5 (w < 5)
-// and sqrt(w) - 3 (w >= 5), w = -log(1 - t^2) = -log(4u(1 - u)); weighted
-// least-squares fits to the FP64 function (gen_quantile.py), largest
-// relative error 2.7e-7 over the uniform grid u = (k + 1/2) 2^-23.
+// the straggling draw.  The structure is M. Giles' single-precision erfinv
+// ("Approximating the erfinv function", GPU Computing Gems Jade Edition,
+// 2011): with w = -log(1 - t^2) = -log(4u(1 - u)), erfinv(t)/t is a
+// polynomial in w - 2.5 for w < 5 and in sqrt(w) - 3 above.  The degree-8
+// coefficients are this library's own weighted least-squares fits to the FP64
+// function (gen_quantile.py), largest relative error 2.7e-7 over the uniform
+// grid u = (k + 1/2) 2^-23.
 __device__ __forceinline__ float normal_quantile(float u) {
     const float t = 2.0f * u - 1.0f;
     const float w = -__logf(4.0f * u * (1.0f - u));
@@ -1252,7 +1255,15 @@ __global__ __launch_bounds__(X ? 768 : 1024) void queue_kernel(GeomDev g, QueueD
     StagedVP *const stg = reinterpret_cast<StagedVP *>(Q.stage) +
                           ((size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (size_t)(hps * 64);
     const unsigned long long chunk_h = 64ull * (unsigned long long)Q.hist_per_lane;
+    unsigned long long iters = 0;
     for (;;) {
+        // ---- bounded queue: a wavefront that has made iter_cap iterations
+        // (chunks, row picks, waits) leaves and reports it; it holds no row
+        // pick and no tile here, so the other waves finish as before
+        if (++iters > Q.iter_cap) {
+            if (lane == 0) atomicOr(Q.flags, kFlagAborted);
+            break;
+        }
         // ---- the workgroup's current row, and a chunk of it
         const uint32_t cur = __builtin_amdgcn_readfirstlane((uint32_t)(rd_lds64(&s_row) >> 32));
         if (cur == kRowEnd) break;

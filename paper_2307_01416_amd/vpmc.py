@@ -68,7 +68,7 @@ class vpmc_opts(C.Structure):
                 ("output", C.c_int), ("fixed_point_bits", C.c_int), ("flags", C.c_uint),
                 ("hip_stream", C.c_void_p), ("max_device_bytes", C.c_size_t),
                 ("block_threads", C.c_int), ("grid_blocks", C.c_int), ("hist_per_lane", C.c_int),
-                ("max_slots", C.c_int)]
+                ("max_slots", C.c_int), ("queue_cap", C.c_uint64)]
 
 
 class vpmc_opt_params(C.Structure):
@@ -116,6 +116,8 @@ def load() -> C.CDLL:
         "vpmc_surrogate_set_weights": (i, [vp, vp, i]),
         "vpmc_surrogate_config": (i, [vp, C.c_float, C.c_float, C.c_float]),
         "vpmc_surrogate_get_weights": (i, [vp, vp, i]),
+        "vpmc_surrogate_load": (i, [vp, C.c_char_p]),
+        "vpmc_surrogate_save": (i, [vp, C.c_char_p]),
         "vpmc_surrogate_forward": (i, [vp, vp, i, vp]),
         "vpmc_surrogate_loss_grad": (i, [vp, vp, vp, vp, i, vp, C.POINTER(C.c_double)]),
         "vpmc_surrogate_train": (i, [vp, vp, vp, vp, i, i, i, C.c_float, C.c_uint64, vp]),
@@ -247,13 +249,13 @@ def scenario_array(scen: Sequence[I.Scenario]):
 
 def make_opts(seed=0, physics=PHYS_ALL, n_batches=0, output=OUT_DOSE, fixed_point_bits=0,
               flags=0, stream=None, max_device_bytes=0, block_threads=0, grid_blocks=0,
-              hist_per_lane=0, max_slots=0) -> vpmc_opts:
+              hist_per_lane=0, max_slots=0, queue_cap=0) -> vpmc_opts:
     o = vpmc_opts()
     o.seed, o.physics, o.n_batches, o.output = seed, physics, n_batches, output
     o.fixed_point_bits, o.flags = fixed_point_bits, flags
     o.hip_stream = stream
     o.max_device_bytes, o.block_threads, o.grid_blocks = max_device_bytes, block_threads, grid_blocks
-    o.hist_per_lane, o.max_slots = hist_per_lane, max_slots
+    o.hist_per_lane, o.max_slots, o.queue_cap = hist_per_lane, max_slots, queue_cap
     return o
 
 
@@ -395,6 +397,14 @@ def vpmc_surrogate_get_weights(ctx) -> np.ndarray:
     return p
 
 
+def vpmc_surrogate_load(ctx, path: Optional[str]) -> None:
+    _check(load().vpmc_surrogate_load(ctx, None if path is None else os.fsencode(path)), ctx)
+
+
+def vpmc_surrogate_save(ctx, path: str) -> None:
+    _check(load().vpmc_surrogate_save(ctx, os.fsencode(path)), ctx)
+
+
 def vpmc_surrogate_sample(ctx, field_id: int, entries, seed: int = 0, physics: int = PHYS_ALL):
     """Plain brass traversals -> (x [n,8], y [n,3], trans [n])."""
     e = _f32(entries)
@@ -496,7 +506,7 @@ class Engine:
     def run_csr(self, case: I.Case, scenarios=None, fixed_point_bits: int = 0, physics: Optional[int] = None,
                 seed: Optional[int] = None, hist_per_lane: int = 0, max_slots: int = 0, grid_blocks: int = 0,
                 graph: bool = False, fields=None, dose: bool = False, copy: bool = True,
-                device_out: bool = False, block_threads: int = 0, surrogate: bool = False):
+                device_out: bool = False, block_threads: int = 0, surrogate: bool = False, queue_cap: int = 0):
         """Influence matrices of all fields x scenarios in one batched pass.
         Rows are ordered (scenario, field, spot).  Returns (row_ptr, col, val,
         q, k) as numpy arrays (col/val/q None when copy is False), plus the
@@ -521,7 +531,7 @@ class Engine:
                          physics=case.physics if physics is None else physics, output=OUT_CSR,
                          fixed_point_bits=fixed_point_bits, flags=flags, stream=self.stream_ptr(),
                          hist_per_lane=hist_per_lane, max_slots=max_slots, grid_blocks=grid_blocks,
-                         block_threads=block_threads)
+                         block_threads=block_threads, queue_cap=queue_cap)
         if device_out:
             opts.flags |= DEVICE_PTRS
             dev = torch.device("cuda", self.device)

@@ -51,8 +51,8 @@ def _rc(fn, *args):
 
 def test_validation_error_codes(vctx):
     g = I.water_geometry((10, 10, 10), (1.0, 1.0, 1.0))
-    # validation-only context: a well-formed geometry reaches the device step
-    assert _rc(V.vpmc_load_geometry, vctx, g) == V.E_STATE
+    # validation-only context: a well-formed geometry is kept (its shape only)
+    assert _rc(V.vpmc_load_geometry, vctx, g) == 0
     bad = I.water_geometry((0, 10, 10), (1.0, 1.0, 1.0))
     assert _rc(V.vpmc_load_geometry, vctx, bad) == V.E_ARG
     bad = I.water_geometry((10, 10, 10), (1.0, -1.0, 1.0))
@@ -215,3 +215,62 @@ def test_csr_cells_validation(vctx):
     assert call(flags=8) == V.E_ARG
     assert call(rp_=None) == V.E_ARG
     assert call() == V.E_STATE            # no geometry (a validation-only context has none)
+
+
+def _run_ctx(vctx, shape=(100, 100, 100)):
+    V.vpmc_load_geometry(vctx, I.water_geometry(shape, (1.0, 1.0, 1.0)))
+    V.vpmc_set_aperture(vctx, 0, _field(I.circle_polygon(20.0, 64)))
+
+
+def test_run_errors_before_device(vctx):
+    """E_RANGE (energy outside the tables, fixed-point bound) and E_OOM
+    (opts.max_device_bytes) come from host checks, before the missing device
+    is noticed (E_STATE last)."""
+    _run_ctx(vctx)
+    scen = V.scenario_array([I.Scenario()])
+    dose = np.zeros(10, np.float32)
+
+    def run(spots, **kw):
+        return _rc(V.vpmc_run_spots, vctx, 0, V.spot_array(spots), len(spots), scen, 1, V.make_opts(**kw), dose)
+
+    ok = I.make_spots([(0, 0)], 150.0, 3.0, 1000)
+    assert run(ok) == V.E_STATE
+    assert run(I.make_spots([(0, 0)], 300.0, 3.0, 1000)) == V.E_RANGE       # above the tables
+    assert run(I.make_spots([(0, 0)], 1.0, 3.0, 1000)) == V.E_RANGE         # at the cut-off
+    heavy = I.make_spots([(0, 0)], 150.0, 3.0, 1000, weight=1e12)
+    assert run(heavy) == V.E_RANGE                                          # no k >= 16 fits int64
+    assert run(ok, fixed_point_bits=62) == V.E_RANGE                        # this k overflows
+    # dense: 1e6 voxels x 8 B of tally alone exceed 4 MB; with batches 24 B per voxel
+    assert run(ok, max_device_bytes=4 << 20) == V.E_OOM
+    assert run(ok, max_device_bytes=16 << 20) == V.E_STATE
+    assert run(ok, max_device_bytes=16 << 20, n_batches=16) == V.E_OOM
+    # CSR: one row slot (8 B per voxel) must fit in half the cap
+    rp = np.zeros(2, np.int64)
+    o = V.make_opts(output=V.OUT_CSR, max_device_bytes=12 << 20)
+    assert _rc(V.vpmc_run_spots, vctx, 0, V.spot_array(ok), 1, scen, 1, o, None, None, None, rp) == V.E_OOM
+    arrays = [V.spot_array(ok)]
+    assert _rc(V.vpmc_run_batched, vctx, [0], arrays, scen, 1, o, None, None, rp) == V.E_OOM
+    o = V.make_opts(output=V.OUT_CSR, max_device_bytes=20 << 20)
+    assert _rc(V.vpmc_run_batched, vctx, [0], arrays, scen, 1, o, None, None, rp) == V.E_STATE
+
+
+def test_surrogate_weights_file_validation(vctx, tmp_path):
+    L = V.load()
+    assert L.vpmc_surrogate_load(vctx, None) == 0                       # disable
+    assert _rc(V.vpmc_surrogate_load, vctx, str(tmp_path / "missing.bin")) == V.E_ARG
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"NOTMLP00" + np.uint32(3).tobytes() + np.zeros(3, np.float32).tobytes())
+    assert _rc(V.vpmc_surrogate_load, vctx, str(bad)) == V.E_ARG
+    n = V.vpmc_surrogate_param_count()
+    short = tmp_path / "short.bin"
+    short.write_bytes(b"VPMCMLP1" + np.uint32(n).tobytes() + np.zeros(n - 1, np.float32).tobytes())
+    assert _rc(V.vpmc_surrogate_load, vctx, str(short)) == V.E_ARG
+    nanw = np.zeros(n, np.float32)
+    nanw[5] = np.nan
+    f = tmp_path / "nan.bin"
+    f.write_bytes(b"VPMCMLP1" + np.uint32(n).tobytes() + nanw.tobytes())
+    assert _rc(V.vpmc_surrogate_load, vctx, str(f)) == V.E_ARG
+    good = tmp_path / "good.bin"
+    good.write_bytes(b"VPMCMLP1" + np.uint32(n).tobytes() + np.zeros(n, np.float32).tobytes())
+    assert _rc(V.vpmc_surrogate_load, vctx, str(good)) == V.E_STATE    # parsed; no device to hold it
+    assert _rc(V.vpmc_surrogate_save, vctx, str(tmp_path / "out.bin")) == V.E_STATE

@@ -1,0 +1,150 @@
+"""Failure paths and tuning on the GPU, each forced from the host so every
+kernel still exits normally: the work-queue iteration cap (VPMC_E_ABORTED,
+no rows written, the context usable after it and its next run bitwise a
+fresh context's), the device-memory cap (VPMC_E_OOM from the allocator), the
+autotuner (a legal launch shape whose rows are bitwise the default shape's),
+and the surrogate's weights file round trip."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2307_01416_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2307_01416_amd import vpmc as V
+    e = V.Engine(0)
+    yield e
+    e.close()
+
+
+def small_case(n=3000, physics=I.PHYS_ALL):
+    c = I.config2(20.0, True, histories_per_case=n * 10, physics=physics, shape=(48, 48, 160))
+    c.fields[0].spots = c.fields[0].spots[:: max(1, len(c.fields[0].spots) // 10)]
+    c.fields[0].spots["n_histories"] = n
+    c.scenarios = [I.Scenario(), I.Scenario(shift_mm=(1.0, 0.0, 0.0), range_scale=0.965)]
+    return c
+
+
+def _csr(eng, c, **kw):
+    return eng.run_csr(c, fixed_point_bits=36, **kw)
+
+
+def test_queue_cap_aborts_and_leaves_the_context_clean(eng):
+    from paper_2307_01416_amd import vpmc as V
+    c = small_case()
+    say("case queue cap 2 iterations per wavefront")
+    with pytest.raises(V.VpmcError) as ei:
+        _csr(eng, c, queue_cap=2)
+    assert ei.value.code == V.E_ABORTED and "queue" in str(ei.value)
+    # nothing to copy after the failed run
+    with pytest.raises(V.VpmcError):
+        V.vpmc_copy_csr(eng.ctx, np.zeros(1, np.int32), np.zeros(1, np.float32), None)
+    # the same context then gives the rows of a fresh context, bit for bit
+    rp1, col1, _, q1, _ = _csr(eng, c)
+    fresh = V.Engine(0)
+    try:
+        rp2, col2, _, q2, _ = fresh.run_csr(c, fixed_point_bits=36)
+    finally:
+        fresh.close()
+    assert np.array_equal(rp1, rp2) and np.array_equal(col1, col2) and np.array_equal(q1, q2)
+    # a cap above what the run needs changes nothing
+    rp3, col3, _, q3, _ = _csr(eng, c, queue_cap=1 << 20)
+    assert np.array_equal(rp1, rp3) and np.array_equal(col1, col3) and np.array_equal(q1, q3)
+    say(f"  aborted cleanly; {int(rp1[-1])} entries after it equal a fresh context's")
+
+
+def test_device_memory_cap(eng):
+    from paper_2307_01416_amd import vpmc as V
+    import torch
+    c = small_case()
+    eng.load_case(c)
+    nx, ny, nz = c.geometry.shape
+    nvox = nx * ny * nz
+    dose = torch.full((1, nz, ny, nx), -1.0, dtype=torch.float32, device="cuda")
+    led = np.full((1, V.NLEDGER), -1.0)
+    spots = c.fields[0].spots
+    say("case memory cap dense")
+    # dense: the tally alone (8 B per voxel) exceeds the cap; outputs untouched
+    o = V.make_opts(physics=c.physics, flags=V.DEVICE_PTRS, stream=eng.stream_ptr(), max_device_bytes=4 * nvox)
+    with pytest.raises(V.VpmcError) as ei:
+        V.vpmc_run_spots(eng.ctx, 0, V.spot_array(spots), len(spots), V.scenario_array(c.scenarios[:1]), 1, o,
+                         dose, None, led)
+    assert ei.value.code == V.E_OOM
+    assert bool((dose == -1.0).all()) and np.all(led == -1.0)
+    say("case memory cap CSR")
+    # CSR: the cap passes the host check (two row slots: 8 B per voxel padded
+    # to blocks of 32, a mark byte per block, chunk counters) but not what the
+    # context already holds (tables and earlier scratch)
+    nblk = (nvox + 31) // 32
+    slot = nblk * 32 * 8 + ((nblk + 255) // 256) * 256 + ((nblk + 255) // 256) * 8 + 4
+    rp = np.full(len(spots) * len(c.scenarios) + 1, -7, np.int64)
+    o = V.make_opts(physics=c.physics, output=V.OUT_CSR, stream=eng.stream_ptr(), fixed_point_bits=36,
+                    max_device_bytes=2 * slot + 4096)
+    with pytest.raises(V.VpmcError) as ei:
+        V.vpmc_run_batched(eng.ctx, [0], [V.spot_array(spots)], V.scenario_array(c.scenarios), len(c.scenarios), o,
+                           None, None, rp)
+    assert ei.value.code == V.E_OOM and np.all(rp == -7)
+    # the context keeps working and gives the bits of an uncapped run
+    d1, _, _ = eng.run_dose(c, 0, scenarios=c.scenarios[:1], n_batches=0, sigma=False, fixed_point_bits=36)
+    fresh = V.Engine(0)
+    try:
+        d2, _, _ = fresh.run_dose(c, 0, scenarios=c.scenarios[:1], n_batches=0, sigma=False, fixed_point_bits=36)
+        assert torch.equal(d1, d2) and float(d1.max()) > 0
+    finally:
+        fresh.close()
+
+
+def test_autotune_gives_a_legal_shape_with_the_same_rows(eng):
+    from paper_2307_01416_amd import vpmc as V
+    c = small_case(n=6000)
+    eng.load_case(c)
+    f = c.fields[0]
+    say("case autotune")
+    base = V.make_opts(seed=c.seed, physics=c.physics, output=V.OUT_CSR)
+    best = V.vpmc_autotune(eng.ctx, 0, V.spot_array(f.spots), len(f.spots), V.scenario_array(c.scenarios[:1]),
+                           base, sample_histories=200_000)
+    say(f"  hist_per_lane={best.hist_per_lane} grid_blocks={best.grid_blocks} threads={best.block_threads}")
+    assert best.hist_per_lane in (1, 2, 4, 8)
+    assert best.block_threads in (512, 1024)
+    assert 1 <= best.grid_blocks <= 256 * 16
+    assert best.seed == base.seed and best.physics == base.physics and best.output == base.output
+    tuned = _csr(eng, c, hist_per_lane=best.hist_per_lane, grid_blocks=best.grid_blocks,
+                 block_threads=best.block_threads)
+    default = _csr(eng, c, hist_per_lane=4, grid_blocks=256, block_threads=1024)
+    for a, b in zip(tuned[:4], default[:4]):
+        if a is not None:
+            assert np.array_equal(a, b)
+
+
+def test_surrogate_weights_file_round_trip(eng, tmp_path):
+    from paper_2307_01416_amd import vpmc as V
+    w = V.surrogate_init(seed=5)
+    V.vpmc_surrogate_set_weights(eng.ctx, w)
+    path = str(tmp_path / "sur.bin")
+    V.vpmc_surrogate_save(eng.ctx, path)
+    x = np.random.default_rng(1).normal(size=(256, 8)).astype(np.float32)
+    out1 = V.vpmc_surrogate_forward(eng.ctx, x)
+    other = V.Engine(0)
+    try:
+        V.vpmc_surrogate_load(other.ctx, path)
+        assert np.array_equal(V.vpmc_surrogate_get_weights(other.ctx), w)
+        assert np.array_equal(V.vpmc_surrogate_forward(other.ctx, x), out1)
+        V.vpmc_surrogate_load(other.ctx, None)   # disabled: surrogate runs are refused
+        c = small_case()
+        with pytest.raises(V.VpmcError) as ei:
+            other.run_dose(c, 0, scenarios=c.scenarios[:1], n_batches=0, sigma=False, surrogate=True)
+        assert ei.value.code == V.E_STATE
+    finally:
+        other.close()

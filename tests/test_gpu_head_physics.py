@@ -1,0 +1,66 @@
+"""Full-physics parity on the synthetic head CT (Methods D.3 and E): one
+spot of each of the three coplanar fields (gantry 90, 180, 270 degrees, brass
+aperture and range shifter), nominal and under shifted, range-scaled robust
+scenarios, through air, bone and brain voxels, against the FP64 oracle.
+
+The oracle's doses (4e7 VPs per case, U about 0.23 %) are stored by
+tests/golden/make_head_physics.py; the GPU runs 1.6e8 VPs with another seed.
+Bar (the benchmark spec's): >= 99 % of the non-air voxels at or above 10 % of the
+maximum within 3 combined standard errors, gamma 1 %/1 mm on >= 99 %, mean
+dose over the high-dose region within a fixed 0.5 %.  Air voxels (HU < -900)
+are left out of every part: a nuclear event's local deposit in an air voxel
+is ~2e4 times a proton's ordinary deposit there, so dose to air is a train
+of rare spikes, not a planning quantity."""
+import sys
+
+import numpy as np
+import pytest
+
+import head_cases as H
+from test_gpu_parity import say, stat_compare
+
+pytestmark = pytest.mark.gpu
+
+GPU_HISTORIES = 4 * H.ORACLE_HISTORIES
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2307_01416_amd import vpmc as V
+    e = V.Engine(0)
+    yield e
+    e.close()
+
+
+@pytest.mark.parametrize("name", list(H.CASES))
+def test_head_full_physics_vs_oracle(eng, name):
+    c = H.case(name, GPU_HISTORIES, H.GPU_SEED)
+    nx, ny, nz = c.geometry.shape
+    gold = H.load_golden(name, (nz, ny, nx))
+    assert str(gold["input_hash"]) == H.input_hash(c), "stored oracle dose is for other inputs"
+    say(f"case head {name}: oracle {int(gold['n_histories']):.2g} VPs (U {float(gold['uncertainty']):.4f}), "
+        f"GPU {GPU_HISTORIES:.2g} VPs")
+    sys.stdout.flush()
+    eng.load_case(c)
+    dose, sig, led = eng.run_dose(c, 0, n_batches=H.N_BATCHES, sigma=True)
+    dg = dose[0].cpu().numpy().astype(np.float64)
+    sg = sig[0].cpu().numpy().astype(np.float64)
+    del dose, sig
+    body = H.body_mask(c)
+    do, so = gold["dose"], gold["sigma"]
+    assert abs(do[body].max() - float(gold["body_max_gy"])) <= 1e-6 * float(gold["body_max_gy"])
+    bidx = gold["batch_idx"].astype(np.int64)
+    bdose = gold["batch_dose_gy"].astype(np.float64)
+
+    def batch_means(hi):
+        sel = np.isin(bidx, np.flatnonzero(hi.ravel()))
+        return bdose[:, sel].mean(axis=1)
+
+    frac, ratio, rate, u_g, u_o = stat_compare(dg, sg, do, so, c.geometry.spacing, name, batch_means=batch_means,
+                                               region=body)
+    assert u_o <= 0.003 and u_g <= 0.002
+    # energy balance of the beam line (range shifter, block) agrees statistically
+    e_or = gold["ledger_mev"]
+    np.testing.assert_allclose(led[0, 1:3], e_or[1:3], rtol=0.01, atol=1e-3 * e_or.sum())

@@ -2,9 +2,11 @@
 
 Deterministic (straight) mode: per-voxel relative agreement 1e-5 for voxels
 above 1e-6 of the maximum, with an absolute floor of 1e-11 of the maximum.
-Histories whose FP64 source position lies within 1e-4 mm of a voxel boundary
-(or of the aperture edge) may land differently in FP32; their columns are
-excluded and counted.
+A history whose FP64 start lies within 5e-5 mm of a lateral voxel boundary,
+an aperture edge or the range shifter's rim may take the other side of it in
+FP32: every voxel's bound grows by what the oracle deposits differently when
+that history's start is mirrored across the boundary, and the voxels without
+such an allowance must hold 95 % of the dose (straight_bound.py).
 
 Full physics: independent seeds; >= 99 % of voxels above 10 % of the maximum
 within 3 combined standard errors; mean dose over the high-dose region within
@@ -17,6 +19,7 @@ import numpy as np
 import pytest
 
 from paper_2307_01416_amd import inputs as I
+from straight_bound import BAND_MM, allowance, assert_straight_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -46,91 +49,12 @@ def gpu_q(eng, case, scen_index=0, physics=None, seed=None, k=None, grid_blocks=
     return q.cpu().numpy(), kk, dose[0].cpu().numpy(), (sig[0].cpu().numpy() if sig is not None else None), led[0]
 
 
-def source_xy_fp64(orc, case, spot_index, n):
-    """FP64 source positions of the first n histories of a spot (beam frame)."""
-    f = case.fields[0]
-    sp = f.spots[spot_index]
-    key = [case.seed & 0xFFFFFFFF, ((case.seed >> 32) & 0xFFFFFFFF) ^ 0]
-    xs = np.empty(n)
-    ys = np.empty(n)
-    for h in range(n):
-        w = orc.philox([0, h, spot_index, 0], key)
-        u0, u1 = orc.uniform(int(w[0])), orc.uniform(int(w[1]))
-        r = math.sqrt(-2.0 * math.log(u0))
-        xs[h] = float(sp["x_mm"]) + float(sp["sigma_mm"]) * r * math.cos(2 * math.pi * u1)
-        ys[h] = float(sp["y_mm"]) + float(sp["sigma_mm"]) * r * math.sin(2 * math.pi * u1)
-    return xs, ys
-
-
-def edge_distance(poly, x, y):
-    """Distance (mm) of BEV points (x, y) to the nearest polygon edge."""
-    a = np.asarray(poly, np.float64)
-    b = np.roll(a, -1, axis=0)
-    d = np.full(x.shape, np.inf)
-    for (ax_, ay_), (bx_, by_) in zip(a, b):
-        ex, ey = bx_ - ax_, by_ - ay_
-        t = np.clip(((x - ax_) * ex + (y - ay_) * ey) / (ex * ex + ey * ey), 0.0, 1.0)
-        d = np.minimum(d, np.hypot(x - ax_ - t * ex, y - ay_ - t * ey))
-    return d
-
-
-def ambiguous_mask(orc, case, tol=1e-4, spots=None, shift_mm=(0.0, 0.0, 0.0)):
-    """Voxels an FP32/FP64 rounding difference of the source position could
-    change: the whole track line of every history that starts within tol of a
-    lateral voxel boundary (or within 2e-3 mm of an aperture polygon edge or
-    the range-shifter rim), and the neighbouring lines.  Beams must be
-    axis-aligned.  spots: the spot indices of field 0 to cover (all by
-    default); shift_mm: the scenario's isocentre shift (CT coordinates of a
-    point move by -shift)."""
-    g = case.geometry
-    f = case.fields[0]
-    nx, ny, nz = g.shape
-    mask = np.zeros((nz, ny, nx), bool)
-    ez = np.asarray(f.beam.ez)
-    ax = int(np.argmax(np.abs(ez)))
-    lat = [k for k in range(3) if k != ax]
-    origin = np.asarray(g.origin, np.float64) + np.asarray(shift_mm, np.float64)
-    for s in (range(len(f.spots)) if spots is None else spots):
-        n = int(f.spots["n_histories"][s])
-        x, y = source_xy_fp64(orc, case, s, n)
-        p = np.asarray(f.beam.iso)[None, :] + x[:, None] * np.asarray(f.beam.ex)[None, :] \
-            + y[:, None] * np.asarray(f.beam.ey)[None, :]
-        fr = (p - origin[None, :]) / np.asarray(g.spacing)[None, :]
-        bad = np.zeros(n, bool)
-        for k in lat:
-            bad |= np.abs(fr[:, k] - np.rint(fr[:, k])) * g.spacing[k] < tol
-        r = np.hypot(x, y)
-        if f.polygon is not None:
-            bad |= edge_distance(f.polygon, x, y) < 2e-3
-        if f.rs is not None:
-            bad |= np.abs(r - 0.5 * f.rs.diameter_mm) < 2e-3
-        for h in np.nonzero(bad)[0]:
-            c = np.floor(fr[h]).astype(int)
-            for d0 in (-1, 0, 1):
-                for d1 in (-1, 0, 1):
-                    idx = [slice(None)] * 3
-                    i0, i1 = c[lat[0]] + d0, c[lat[1]] + d1
-                    if not (0 <= i0 < g.shape[lat[0]] and 0 <= i1 < g.shape[lat[1]]):
-                        continue
-                    idx[2 - lat[0]] = i0
-                    idx[2 - lat[1]] = i1
-                    mask[tuple(idx)] = True
-    return mask
-
-
-def assert_straight_parity(q_gpu, k_gpu, q_or, k_or, excluded=None):
-    a = q_gpu.astype(np.float64) * 2.0 ** -k_gpu
-    b = q_or.astype(np.float64) * 2.0 ** -k_or
-    dmax = b.max()
-    assert dmax > 0
-    keep = np.ones(b.shape, bool) if excluded is None else ~excluded
-    hi = (b > 1e-6 * dmax) & keep
-    rel = np.abs(a[hi] - b[hi]) / b[hi]
-    lo = (~(b > 1e-6 * dmax)) & keep
-    say(f"  straight parity: {hi.sum()} voxels, max rel {rel.max():.3e}, "
-        f"excluded voxels {0 if excluded is None else int(excluded.sum())}")
-    assert rel.max() <= 1e-5
-    assert np.all(np.abs(a[lo] - b[lo]) <= 1e-11 * dmax)
+def straight_check(orc, case, qg, kg, qo, ko, scenario_index=0, spots=None):
+    """Straight parity with the per-history allowance of the histories whose
+    FP32 start may round across a boundary (straight_bound.py)."""
+    allow, n_amb = allowance(orc, case, 0, scenario_index, spots)
+    say(f"  {n_amb} histories start within {BAND_MM:g} mm of a voxel boundary, aperture edge or RS rim")
+    assert_straight_parity(qg, kg, qo, ko, allow, say=say)
 
 
 # ------------------------------------------------------------- straight mode
@@ -140,7 +64,7 @@ def test_straight_parity_config1(eng, orc):
     qg, kg, dose, _, led = gpu_q(eng, c)
     qo, lo, ko = orc.run_tally(c)
     assert kg == ko
-    assert_straight_parity(qg, kg, qo, ko, ambiguous_mask(orc, c))
+    straight_check(orc, c, qg, kg, qo, ko)
     # dose conversion: FP32 dose equals the oracle conversion of the GPU tally
     ref = orc.q_to_gy(c, qg, kg)
     m = ref > 0
@@ -154,7 +78,7 @@ def test_straight_parity_range_scaled(eng, orc, scale):
     say(f"case config1 straight range_scale={scale}")
     qg, kg, _, _, _ = gpu_q(eng, c)
     qo, _, ko = orc.run_tally(c)
-    assert_straight_parity(qg, kg, qo, ko, ambiguous_mask(orc, c))
+    straight_check(orc, c, qg, kg, qo, ko)
 
 
 @pytest.mark.parametrize("opening,rs", [(10.0, True), (20.0, False), (40.0, True)])
@@ -163,22 +87,37 @@ def test_straight_parity_water_aperture(eng, orc, opening, rs):
     say(f"case config2-small straight opening={opening} rs={rs} spots={len(c.fields[0].spots)}")
     qg, kg, _, _, lg = gpu_q(eng, c)
     qo, lo, ko = orc.run_tally(c)
-    assert_straight_parity(qg, kg, qo, ko, ambiguous_mask(orc, c))
+    straight_check(orc, c, qg, kg, qo, ko)
     e_or = lo * 2.0 ** -ko
     np.testing.assert_allclose(lg[1:3], e_or[1:3], rtol=1e-5, atol=1e-9 * e_or.sum())
 
 
-@pytest.mark.parametrize("grid", [((128, 128, 80), (2.0, 2.0, 2.0)), ((256, 256, 320), (1.0, 1.0, 1.0))])
-def test_straight_parity_head_ct(eng, orc, grid):
-    """Head CT at 2 mm and at 1 mm (the resolution study's finest grid)."""
-    g = I.head_ct(0, shape=grid[0], spacing=grid[1])
-    c = I.config3(8.0, 400, physics=0, geometry=g, gantries=(90.0,))
+HEAD_STRAIGHT = [
+    # (grid, gantry, scenario index in scenarios_13): the headline 1x1x2 mm CT
+    # for all three fields (beams along -x, -y, +x), two of them also under a
+    # shifted, range-scaled scenario; the 2 mm and 1 mm grids of the
+    # resolution study for the first field
+    ("1x1x2", 90.0, 0), ("1x1x2", 180.0, 0), ("1x1x2", 270.0, 0),
+    ("1x1x2", 180.0, 5), ("1x1x2", 270.0, 12),
+    ("2x2x2", 90.0, 0), ("1x1x1", 90.0, 0),
+]
+HEAD_GRIDS = {"1x1x2": ((256, 256, 160), (1.0, 1.0, 2.0)), "2x2x2": ((128, 128, 80), (2.0, 2.0, 2.0)),
+              "1x1x1": ((256, 256, 320), (1.0, 1.0, 1.0))}
+
+
+@pytest.mark.parametrize("grid,gantry,scen", HEAD_STRAIGHT)
+def test_straight_parity_head_ct(eng, orc, grid, gantry, scen):
+    """Head CT, one field (gantry 90, 180 or 270), every 40th spot or so."""
+    shape, spacing = HEAD_GRIDS[grid]
+    g = I.head_ct(0, shape=shape, spacing=spacing)
+    sc = I.scenarios_13()
+    c = I.config3(8.0, 400, physics=0, geometry=g, gantries=(gantry,), scenarios=[sc[0], sc[scen]])
     f = c.fields[0]
     f.spots = f.spots[:: max(1, len(f.spots) // 24)]
-    say(f"case head straight grid={grid[1]} spots={len(f.spots)}")
-    qg, kg, _, _, _ = gpu_q(eng, c)
-    qo, _, ko = orc.run_tally(c)
-    assert_straight_parity(qg, kg, qo, ko, ambiguous_mask(orc, c))
+    say(f"case head straight grid={grid} gantry={gantry} scenario={scen} spots={len(f.spots)}")
+    qg, kg, _, _, _ = gpu_q(eng, c, scen_index=1 if scen else 0)
+    qo, _, ko = orc.run_tally(c, scenario_index=1 if scen else 0)
+    straight_check(orc, c, qg, kg, qo, ko, scenario_index=1 if scen else 0)
 
 
 # ------------------------------------------------------------- determinism
@@ -245,60 +184,81 @@ def test_lateral_shift_bitwise_gpu(eng):
 
 
 # ------------------------------------------------------------- full physics
-def stat_compare(orc, case, dg, sg, r, label):
-    """3-sigma voxel test and the mean dose over the high-dose region (>= 50 %
-    of the maximum of the two runs' mean); the
-    mean-dose tolerance is 0.5 % or three standard errors of the difference
-    when the runs are noisier than that (error of the oracle's regional mean
-    from its batches, the same for the GPU run)."""
-    do, so = r["dose_gy"], r["sigma_gy"]
-    dmax = do.max()
-    m = do >= 0.1 * dmax
+def stat_compare(dg, sg, do, so, spacing, label, batch_means=None, region=None, gamma=True):
+    """The full-physics acceptance: >= 99 % of the voxels at or above 10 % of
+    the oracle's maximum within 3 combined standard errors; mean dose over the
+    high-dose region (>= 50 % of the maximum of the two runs' mean) within a
+    fixed 0.5 %; gamma 1 %/1 mm (global, 10 % threshold, oracle as reference)
+    passing on >= 99 % of the points.  region (optional) restricts every part
+    to a voxel mask (the non-air voxels of a CT).  batch_means(hi) returns the
+    oracle's per-batch means over the region hi (reported standard error)."""
+    from gamma import gamma_pass_rate
+    reg = np.ones(do.shape, bool) if region is None else region
+    dmax = do[reg].max()
+    m = reg & (do >= 0.1 * dmax)
     comb = np.sqrt(sg ** 2 + so ** 2)
     within = np.abs(dg - do) <= 3.0 * comb
     frac = within[m].mean()
     # the high-dose region is selected on the mean of the two doses: selecting
     # it on one side's own (noisy) dose biases that side's regional mean up
     avg = 0.5 * (dg + do)
-    hi = avg >= 0.5 * avg.max()
+    hi = reg & (avg >= 0.5 * avg[reg].max())
     ratio = dg[hi].mean() / do[hi].mean()
-    bm = np.array([b[hi].mean() for b in r["batch_dose_gy"]])
-    se_rel = bm.std(ddof=1) / np.sqrt(len(bm)) / do[hi].mean()
-    tol = max(0.005, 3.0 * np.sqrt(2.0) * se_rel)
-    say(f"  {label}: 3-sigma fraction {frac:.4f} over {m.sum()} voxels; mean-dose ratio {ratio:.5f} "
-        f"(tol {tol:.4f}, regional s.e. {se_rel:.4f}); U_gpu {np.mean(sg[hi] / dg[hi]):.4f} "
-        f"U_or {np.mean(so[hi] / do[hi]):.4f}")
+    se = float("nan")
+    if batch_means is not None:
+        bm = np.asarray(batch_means(hi))
+        se = bm.std(ddof=1) / np.sqrt(len(bm)) / do[hi].mean()
+    u_g, u_o = np.mean(sg[hi] / dg[hi]), np.mean(so[hi] / do[hi])
+    rate = float("nan")
+    if gamma:
+        # the box around the reference points, 2 voxels wider than the DTA's
+        # reach on every side (outside it the evaluated dose is not needed)
+        nzyx = np.nonzero(m)
+        box = tuple(slice(max(0, int(a.min()) - 2), int(a.max()) + 3) for a in nzyx)
+        ref = np.where(reg, do, 0.0)[box]
+        ev = np.where(reg, dg, np.nan)[box]
+        rate = gamma_pass_rate(ref, ev, spacing, 0.01, 1.0)
+    say(f"  {label}: 3-sigma fraction {frac:.4f} over {int(m.sum())} voxels; mean-dose ratio {ratio:.5f} "
+        f"over {int(hi.sum())} voxels (oracle regional s.e. {se:.5f}); gamma 1%/1mm {rate:.4f}; "
+        f"U_gpu {u_g:.4f} U_or {u_o:.4f}")
     assert frac >= 0.99
-    assert abs(ratio - 1.0) <= tol
-    return frac, ratio
+    assert abs(ratio - 1.0) <= 0.005
+    if gamma:
+        assert rate >= 0.99
+    return frac, ratio, rate, u_g, u_o
+
+
+def stat_compare_oracle(dg, sg, r, case, label, gamma=True):
+    """stat_compare against an oracle.dose(..., keep_batches=True) result."""
+    return stat_compare(dg, sg, r["dose_gy"], r["sigma_gy"], case.geometry.spacing, label,
+                        batch_means=lambda hi: [b[hi].mean() for b in r["batch_dose_gy"]], gamma=gamma)
 
 
 def test_full_physics_config1_statistical(eng, orc):
-    from gamma import gamma_pass_rate
-    n = 2_000_000
-    c = I.config1(n_histories=n, seed=0)
-    say("case config1 full physics 2e6")
+    # 1e7 oracle VPs (U about 0.25 %), the GPU at 4x that
+    n = 10_000_000
+    c = I.config1(n_histories=4 * n, seed=0)
+    say("case config1 full physics: oracle 1e7, GPU 4e7")
     _, _, dg, sg, _ = gpu_q(eng, c, n_batches=16)
     co = I.config1(n_histories=n, seed=12345)
     r = orc.dose(co, n_batches=16, keep_batches=True)
-    stat_compare(orc, c, dg, sg, r, "config1")
-    rate = gamma_pass_rate(r["dose_gy"], dg, c.geometry.spacing, 0.01, 1.0)
-    say(f"  gamma 1%/1mm pass rate {rate:.4f}")
-    assert rate >= 0.99
-    # batch sigma of the GPU agrees with the oracle's
+    stat_compare_oracle(dg, sg, r, c, "config1")
+    # batch sigma of the GPU agrees with the oracle's (scaled to equal VPs)
     hi = r["dose_gy"] >= 0.5 * r["dose_gy"].max()
-    assert np.mean(sg[hi]) / np.mean(r["sigma_gy"][hi]) == pytest.approx(1.0, abs=0.1)
+    assert 2.0 * np.mean(sg[hi]) / np.mean(r["sigma_gy"][hi]) == pytest.approx(1.0, abs=0.1)
 
 
-@pytest.mark.parametrize("opening,rs", [(10.0, True), (30.0, False)])
+@pytest.mark.parametrize("opening,rs", [(10.0, True), (40.0, False)])
 def test_full_physics_water_aperture_statistical(eng, orc, opening, rs):
-    n = 3_000_000
-    c = I.config2(opening, rs, histories_per_case=n, shape=(64, 64, 200), seed=0)
-    say(f"case config2-small full physics opening={opening} rs={rs}")
+    """Config 2 at its stated size: 200x200x300 at 1 mm, 1e7 oracle VPs per
+    case (the GPU at 4x)."""
+    n = 10_000_000
+    c = I.config2(opening, rs, histories_per_case=4 * n, seed=0)
+    say(f"case config2 full physics opening={opening} rs={rs}: oracle 1e7, GPU 4e7")
     _, _, dg, sg, lg = gpu_q(eng, c, n_batches=16)
-    co = I.config2(opening, rs, histories_per_case=n, shape=(64, 64, 200), seed=777)
+    co = I.config2(opening, rs, histories_per_case=n, seed=777)
     r = orc.dose(co, n_batches=16, keep_batches=True)
-    stat_compare(orc, c, dg, sg, r, f"config2 {opening} {rs}")
+    stat_compare_oracle(dg, sg, r, c, f"config2 {opening} {rs}")
     # energy balance agrees statistically (block and range shifter ledgers)
     e_or = r["ledger_mev"]
     np.testing.assert_allclose(lg[1:3], e_or[1:3], rtol=0.01, atol=1e-3 * e_or.sum())

@@ -2,17 +2,18 @@
 energies (Methods D.1: the paper's beamlet validation at 97 energies, with
 and without the range shifter), on the GPU against the FP64 oracle.  Water
 64 x 64 x 300 at 1 mm (the sweep's lateral extent, the paper's depth).
-Straight mode: every 8th energy, per-voxel parity at 1e-5 outside the track
-lines that start within rounding of a voxel boundary or of the opening's
-edge (energies that stop before the water give no dose on either side).
-Full physics: 110.7, 169.8 and 228.8 MeV with the range shifter, the statistical bar of the other physics tests (3 sigma on
->= 99 % of the voxels above 10 %, mean dose within 0.5 % or 3 standard
-errors)."""
+Straight mode: every 8th energy, per-voxel parity at 1e-5 plus the allowance
+of the histories that start within rounding of a voxel boundary, the
+opening's edge or the range shifter's rim (energies that stop before the
+water give no dose on either side).  Full physics: 110.7, 169.7 and 228.8 MeV
+with the range shifter, the bar of the other physics tests (3 sigma on
+>= 99 % of the voxels above 10 %, mean dose within a fixed 0.5 %, gamma
+1 %/1 mm on >= 99 %)."""
 import numpy as np
 import pytest
 
 from paper_2307_01416_amd import inputs as I
-from test_gpu_parity import ambiguous_mask, assert_straight_parity, gpu_q, say, stat_compare
+from test_gpu_parity import gpu_q, say, stat_compare_oracle, straight_check
 
 pytestmark = pytest.mark.gpu
 SHAPE = (64, 64, 300)
@@ -40,18 +41,20 @@ def test_edge_sweep_straight(eng, orc, rs):
             say("  no dose in the water on either side" if qg.max() == 0 else "  GPU dose where the oracle has none")
             assert qg.max() == 0
             continue
-        assert_straight_parity(qg, kg, qo, ko, ambiguous_mask(orc, c))
+        straight_check(orc, c, qg, kg, qo, ko)
 
 
 @pytest.mark.parametrize("index", [24, 60, 96])
 def test_edge_sweep_full_physics(eng, orc, index):
-    n = 400_000
-    c = I.edge_beamlet_sweep(True, histories=n, physics=I.PHYS_ALL, shape=SHAPE)[index]
+    """Beamlet on the 10 mm opening's edge behind the range shifter at 110.7,
+    169.7 and 228.8 MeV: 6.4e6 oracle VPs (the GPU at 4x)."""
+    n = 6_400_000
+    c = I.edge_beamlet_sweep(True, histories=4 * n, physics=I.PHYS_ALL, shape=SHAPE)[index]
     c.n_batches = 16
-    say(f"case {c.name} full physics")
+    say(f"case {c.name} full physics: oracle {n:.2g}, GPU {4 * n:.2g}")
     _, _, dg, sg, _ = gpu_q(eng, c, n_batches=16)
     co = I.edge_beamlet_sweep(True, histories=n, physics=I.PHYS_ALL, shape=SHAPE)[index]
     co.seed = 999          # an independent oracle run
     co.n_batches = 16
     r = orc.dose(co, n_batches=16, keep_batches=True)
-    stat_compare(orc, c, dg, sg, r, c.name)
+    stat_compare_oracle(dg, sg, r, c, c.name)
