@@ -197,6 +197,34 @@ int vpmc_run_spots(vpmc_ctx *ctx, int field_id, const vpmc_spot *spots, int n_sp
                    const vpmc_scenario *scen, int n_scen, const vpmc_opts *opts, float *dose_gy,
                    float *sigma_gy, double *ledger_mev, int64_t *row_ptr);
 
+/* Allocation-free dense run, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same transport, batches and dose conversion as a dense
+ * vpmc_run_spots with the same arguments, with the same bits out; every
+ * intermediate (ledgers, counters, spot records, batch offsets, the int64
+ * tally and, with n_batches >= 2, the batch tally and the FP64 sum of
+ * squares) lives in one static device array of 32 MiB per GPU, which the
+ * library holds until the process ends.  It calls no hipMalloc or hipFree.
+ *   opts->output must be VPMC_OUT_DOSE and opts->flags exactly
+ *   VPMC_DEVICE_PTRS: dose_gy [n_scen][nvox] and sigma_gy (needs
+ *   n_batches >= 2) are device pointers, either may be NULL; ledger_mev
+ *   [n_scen][6] is host memory or NULL.  With ledger_mev the call returns
+ *   after the work is done; without it the work is left queued on
+ *   opts->hip_stream.  opts->max_device_bytes is ignored.
+ *   Size limit: 8 B per voxel (24 B with batches) + 28 B per spot + 8 B per
+ *   spot and batch + 48 B per scenario, each piece rounded up to 256 B,
+ *   must fit in 32 MiB: about 4.1e6 voxels without batches, 1.39e6 with.
+ * The array keeps the last call's contents (each call clears what it needs);
+ * calls that overlap on one GPU, from any context or stream, race on it.
+ * vpmc_last_tally, vpmc_last_let and vpmc_last_stats keep describing the
+ * last vpmc_run_spots / vpmc_run_batched call.
+ * Errors: as vpmc_run_spots; VPMC_E_ARG for CSR output or any flag other
+ * than VPMC_DEVICE_PTRS; VPMC_E_OOM if the run does not fit in the scratch
+ * (outputs untouched). */
+int vpmc_run_spots_noalloc(vpmc_ctx *ctx, int field_id, const vpmc_spot *spots, int n_spots,
+                           const vpmc_scenario *scen, int n_scen, const vpmc_opts *opts, float *dose_gy,
+                           float *sigma_gy, double *ledger_mev);
+
 /* All robust scenarios x fields x spots in one work-queue pass (Methods C
  * and E: influence matrices of every scenario for robust optimisation).
  * Rows are ordered (scenario, field in the order given, spot); spots[f] holds

@@ -102,6 +102,7 @@ Raster polygon_raster(const std::vector<float2> &poly, double margin) {
 struct vpmc_ctx {
     int device = -1;
     float *d_tables = nullptr;
+    void *scratch = nullptr;   // device address of this GPU's static scratch (vpmc_run_spots_noalloc)
     // geometry
     bool has_geom = false;
     GeomDev geom{};
@@ -1091,6 +1092,12 @@ int vpmc_create(vpmc_ctx **out, int hip_device) {
             return fail(VPMC_E_DEVICE, "table upload failed: %s", hipGetErrorString(e));
         }
         c->bytes = sizeof(float) * TAB_FLOATS;
+        // the static scratch's device address on this device (current here)
+        if ((e = scratch_device_ptr(hip_device, &c->scratch)) != hipSuccess) {
+            (void)hipFree(c->d_tables);
+            delete c;
+            return fail(VPMC_E_DEVICE, "scratch address lookup failed: %s", hipGetErrorString(e));
+        }
     }
     *out = c;
     return VPMC_OK;
@@ -1597,6 +1604,92 @@ int vpmc_run_spots(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spot
     c->last_k = k;
     c->last_let = want_let;
     c->last_nscen = n_scen;
+    return VPMC_OK;
+}
+
+int vpmc_run_spots_noalloc(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spots,
+                           const vpmc_scenario *scen, int n_scen, const vpmc_opts *o, float *dose_gy,
+                           float *sigma_gy, double *ledger_mev) {
+    double T = 0.0;
+    int rc;
+    if ((rc = validate_run(c, field_id, spots, n_spots, scen, n_scen, o, &T))) return rc;
+    if (o->output != VPMC_OUT_DOSE) return fail(VPMC_E_ARG, "the allocation-free run writes dense dose only");
+    if (o->flags != VPMC_DEVICE_PTRS)
+        return fail(VPMC_E_ARG, "the allocation-free run takes flags == VPMC_DEVICE_PTRS (device dose/sigma)");
+    if (o->block_threads && o->block_threads != 256 && o->block_threads != 512)
+        return fail(VPMC_E_ARG, "block_threads must be 0, 256 or 512");
+    if (o->grid_blocks < 0) return fail(VPMC_E_ARG, "grid_blocks < 0");
+    const int B = o->n_batches >= 2 ? o->n_batches : 1;
+    if (sigma_gy && B < 2) return fail(VPMC_E_ARG, "sigma_gy needs n_batches >= 2");
+    if (!dose_gy && !sigma_gy && !ledger_mev) return fail(VPMC_E_ARG, "no output requested");
+    int k = 0;
+    if ((rc = pick_k(o, T, &k))) return rc;
+    // scratch layout (256-byte aligned pieces): ledger [n_scen][6], stats [2],
+    // spots, batch offsets [B][n_spots + 1], tally [nvox], and with batches
+    // the batch tally [nvox] and the FP64 sum of squares [nvox]
+    const size_t nvox = c->nvox;
+    auto a256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_led = 0;
+    const size_t o_stats = o_led + a256((size_t)n_scen * NLEDGER * 8);
+    const size_t o_spots = o_stats + a256(2 * 8);
+    const size_t o_off = o_spots + a256((size_t)std::max(1, n_spots) * sizeof(SpotDev));
+    const size_t o_tally = o_off + a256((size_t)B * (n_spots + 1) * 8);
+    const size_t o_qb = o_tally + a256(nvox * 8);
+    const size_t o_s2 = o_qb + (B > 1 ? a256(nvox * 8) : 0);
+    const size_t need = o_s2 + (B > 1 ? a256(nvox * 8) : 0);
+    if (need > kScratchBytes)
+        return fail(VPMC_E_OOM, "the run needs %zu bytes of scratch; the static scratch holds %zu "
+                    "(8 B per voxel, 24 B with batches, plus spots and ledgers)", need, kScratchBytes);
+    if (c->device < 0 || !c->scratch) return fail(VPMC_E_STATE, "validation-only context has no device");
+
+    hipStream_t st = (hipStream_t)o->hip_stream;
+    HIP_TRY(hipSetDevice(c->device));
+    unsigned char *base = (unsigned char *)c->scratch;
+    unsigned long long *led_d = (unsigned long long *)(base + o_led);
+    unsigned long long *stats_d = (unsigned long long *)(base + o_stats);
+    SpotDev *spots_d = (SpotDev *)(base + o_spots);
+    unsigned long long *off_d = (unsigned long long *)(base + o_off);
+    long long *tally = (long long *)(base + o_tally);
+    unsigned long long *qb = B > 1 ? (unsigned long long *)(base + o_qb) : nullptr;
+    double *s2 = B > 1 ? (double *)(base + o_s2) : nullptr;
+
+    std::vector<SpotDev> sd;
+    std::vector<unsigned long long> off;
+    dense_spot_tables(spots, n_spots, k, B, sd, off);
+    HIP_TRY(hipMemcpyAsync(spots_d, sd.data(), sd.size() * sizeof(SpotDev), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(off_d, off.data(), off.size() * sizeof(unsigned long long), hipMemcpyHostToDevice, st));
+    // the scratch keeps the previous call's contents: clear with fill kernels
+    HIP_TRY(launch_fill_u64(led_d, (size_t)n_scen * NLEDGER, 0ull, st));
+    HIP_TRY(launch_fill_u64(stats_d, 2, 0ull, st));
+
+    const FieldDev &fd = c->fields[field_id].dev;
+    const int threads = o->block_threads ? o->block_threads : (c->tuned_dense_threads ? c->tuned_dense_threads : 256);
+    const double mev_scale = ldexp(MEV_TO_J, -k);
+    for (int sc = 0; sc < n_scen; ++sc) {
+        HIP_TRY(launch_fill_u64((unsigned long long *)tally, nvox, 0ull, st));
+        if (B > 1) {
+            HIP_TRY(launch_fill_u64(qb, nvox, 0ull, st));
+            HIP_TRY(launch_fill_u64((unsigned long long *)s2, nvox, 0ull, st));   // all-zero bits = 0.0
+        }
+        for (int b = 0; b < B; ++b) {
+            const unsigned long long items = off[(size_t)b * (n_spots + 1) + n_spots];
+            if (items == 0) continue;
+            LaunchDev L = dense_launch(o, field_id, scen[sc], spots_d, off_d + (size_t)b * (n_spots + 1), n_spots,
+                                       items, b, B, B > 1 ? qb : (unsigned long long *)tally, nullptr,
+                                       led_d + (size_t)sc * NLEDGER, stats_d, c->d_tables);
+            HIP_TRY(launch_transport(c->geom, fd, L, dense_blocks(c, o, items, threads), threads, st));
+            if (B > 1) HIP_TRY(launch_fold_batch(qb, tally, s2, nvox, st));
+        }
+        float *dd = dose_gy ? dose_gy + (size_t)sc * nvox : nullptr;
+        float *ss = sigma_gy ? sigma_gy + (size_t)sc * nvox : nullptr;
+        if (dd || ss) HIP_TRY(launch_dose(tally, s2, B, c->geom, mev_scale, dd, ss, nvox, st));
+    }
+    if (ledger_mev) {
+        std::vector<long long> led((size_t)n_scen * NLEDGER);
+        HIP_TRY(hipMemcpyAsync(led.data(), led_d, led.size() * sizeof(long long), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (size_t i = 0; i < led.size(); ++i) ledger_mev[i] = ldexp((double)led[i], -k);
+    }
     return VPMC_OK;
 }
 

@@ -346,4 +346,13 @@ hipError_t launch_fold_batch(unsigned long long *q_batch, long long *q_total, do
 hipError_t launch_dose(const long long *q, const double *s2, int n_batches, const GeomDev &g,
                        double mev_scale, float *dose, float *sigma, size_t n, hipStream_t s);
 
+// Static device scratch of the allocation-free dense run
+// (vpmc_run_spots_noalloc): a file-scope __device__ array in
+// vpmc_kernels.hip, one copy per GPU, held until the process ends.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+constexpr int kMaxScratchDevices = 64;
+// Device address of the scratch on `device`, which must be the current
+// device: looked up once per device with hipGetSymbolAddress and kept.
+hipError_t scratch_device_ptr(int device, void **out);
+
 }  // namespace vpmc

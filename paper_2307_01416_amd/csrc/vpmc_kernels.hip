@@ -9,6 +9,8 @@
 // atomic, which makes the tally independent of execution order.
 #include <math.h>
 
+#include <mutex>
+
 #include "vpmc_internal.hpp"
 
 namespace vpmc {
@@ -2291,6 +2293,31 @@ hipError_t launch_dose(const long long *q, const double *s2, int B, const GeomDe
     const int blocks = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
     hipLaunchKernelGGL(dose_kernel, dim3(blocks), dim3(256), 0, s, q, s2, B, g, mev_scale, dose, sigma, n);
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free dense run.  In host code the name `scratch`
+// is only a host-side stand-in for the array: kernels and copies get the
+// device address from scratch_device_ptr(), never the name itself.
+static __device__ __align__(256) unsigned long long scratch[kScratchBytes / sizeof(unsigned long long)];
+
+hipError_t scratch_device_ptr(int device, void **out) {
+    static std::mutex mu;
+    static void *addr[kMaxScratchDevices] = {};
+    if (!out || device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;   // the symbol is looked up on the current device
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 }  // namespace vpmc

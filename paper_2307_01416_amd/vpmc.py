@@ -104,6 +104,7 @@ def load() -> C.CDLL:
         "vpmc_set_aperture": (i, [vp, i, vp, vp, i, vp, vp]),
         "vpmc_set_divergence": (i, [vp, i, C.c_float, C.c_float]),
         "vpmc_run_spots": (i, [vp, i, vp, i, vp, i, vp, vp, vp, vp, vp]),
+        "vpmc_run_spots_noalloc": (i, [vp, i, vp, i, vp, i, vp, vp, vp, vp]),
         "vpmc_copy_csr": (i, [vp, vp, vp, vp]),
         "vpmc_last_tally": (i, [vp, i, vp, C.POINTER(C.c_int), u]),
         "vpmc_last_let": (i, [vp, i, vp, C.POINTER(C.c_int), u]),
@@ -264,6 +265,13 @@ def vpmc_run_spots(ctx, field_id: int, spots, n_spots: int, scen, n_scen: int, o
     _check(load().vpmc_run_spots(ctx, field_id, C.cast(spots, C.c_void_p) if spots is not None else None,
                                  n_spots, C.cast(scen, C.c_void_p) if scen is not None else None, n_scen,
                                  C.byref(opts), _ptr(dose), _ptr(sigma), _ptr(ledger), _ptr(row_ptr)), ctx)
+
+
+def vpmc_run_spots_noalloc(ctx, field_id: int, spots, n_spots: int, scen, n_scen: int, opts: vpmc_opts,
+                           dose=None, sigma=None, ledger=None) -> None:
+    _check(load().vpmc_run_spots_noalloc(ctx, field_id, C.cast(spots, C.c_void_p) if spots is not None else None,
+                                         n_spots, C.cast(scen, C.c_void_p) if scen is not None else None, n_scen,
+                                         C.byref(opts), _ptr(dose), _ptr(sigma), _ptr(ledger)), ctx)
 
 
 def vpmc_run_batched(ctx, field_ids: Sequence[int], spot_arrays: Sequence, scen, n_scen: int,

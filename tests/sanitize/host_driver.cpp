@@ -107,6 +107,17 @@ int main() {
     o.max_device_bytes = 0;
     vpmc_opts best{};
     EXPECT(vpmc_autotune(c, 0, spots, 3, scen, &o, 100000, &best), VPMC_E_STATE);
+    o.output = VPMC_OUT_DOSE;
+    o.flags = VPMC_DEVICE_PTRS;
+    EXPECT(vpmc_run_spots_noalloc(c, 0, spots, 3, scen, 2, &o, dose.data(), nullptr, nullptr), VPMC_E_STATE);
+    o.n_batches = 16;   // 1e6 voxels x 24 B fit in the 32 MiB scratch
+    EXPECT(vpmc_run_spots_noalloc(c, 0, spots, 3, scen, 2, &o, dose.data(), dose.data(), nullptr), VPMC_E_STATE);
+    EXPECT(vpmc_load_geometry(c, VPMC_GEOM_WATER, nullptr, 128, 128, 100, sp, org, 0), VPMC_OK);
+    EXPECT(vpmc_run_spots_noalloc(c, 0, spots, 3, scen, 2, &o, dose.data(), dose.data(), nullptr), VPMC_E_OOM);
+    EXPECT(vpmc_load_geometry(c, VPMC_GEOM_WATER, nullptr, 100, 100, 100, sp, org, 0), VPMC_OK);
+    o.flags = 0;
+    EXPECT(vpmc_run_spots_noalloc(c, 0, spots, 3, scen, 2, &o, dose.data(), nullptr, nullptr), VPMC_E_ARG);
+
     // influence-matrix consumers: the optimiser's and the cell merge's scans
     const int nvox = 100 * 100 * 100;
     std::vector<int64_t> orp = {0, 3, 5, 9};

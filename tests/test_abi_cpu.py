@@ -254,6 +254,27 @@ def test_run_errors_before_device(vctx):
     assert _rc(V.vpmc_run_batched, vctx, [0], arrays, scen, 1, o, None, None, rp) == V.E_STATE
 
 
+def test_noalloc_validation_before_device(vctx):
+    """The allocation-free run: dense output with device pointers only, and a
+    run beyond its 32 MiB static scratch is refused before the device."""
+    _run_ctx(vctx, (128, 128, 100))      # 1.64e6 voxels: fits without batches, not with 16
+    scen = V.scenario_array([I.Scenario()])
+    ok = V.spot_array(I.make_spots([(0, 0)], 150.0, 3.0, 1000))
+    dose = np.zeros(1, np.float32)   # never dereferenced: every call here fails before the device
+
+    def run(**kw):
+        return _rc(V.vpmc_run_spots_noalloc, vctx, 0, ok, 1, scen, 1, V.make_opts(**kw), dose)
+
+    assert run(flags=V.DEVICE_PTRS) == V.E_STATE
+    assert run(flags=V.DEVICE_PTRS, n_batches=16) == V.E_OOM
+    assert run(flags=0) == V.E_ARG                                  # host pointers
+    assert run(flags=V.DEVICE_PTRS | V.LET) == V.E_ARG
+    assert run(flags=V.DEVICE_PTRS, output=V.OUT_CSR) == V.E_ARG
+    L = V.load()
+    assert L.vpmc_run_spots_noalloc(vctx, 0, ok, 1, scen, 1, C.byref(V.make_opts(flags=V.DEVICE_PTRS)),
+                                    None, None, None) == V.E_ARG   # no output
+
+
 def test_surrogate_weights_file_validation(vctx, tmp_path):
     L = V.load()
     assert L.vpmc_surrogate_load(vctx, None) == 0                       # disable
