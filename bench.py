@@ -23,13 +23,22 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# VALU lane-operations per condensed-history step counted from the algorithm
-# (Philox4x32-10 ~100 integer ops, uniform/normal conversion ~40, three table
-# interpolations ~35, CSDA loss ~10, hinge rotation ~35, voxel traversal ~15,
-# nuclear test ~5, fixed-point tally ~5, position updates ~10)
-ALG_OPS_PER_STEP = 255.0
-# gfx950: 256 CUs x 64 FP32 lanes per clock x 2.4 GHz, single-issue VALU
+# VALU lane-operations per condensed-history step counted from the method
+# (the survey's ~300): Philox4x32-10 ~100 integer ops, uniform conversions 8,
+# normal quantile 25, Box-Muller with log/sqrt/sin/cos at quarter rate 22,
+# energy-segment search and four table interpolations 35, CSDA loss 12,
+# hinge rotation 35, voxel traversal (three face distances, index update) 25,
+# nuclear test 8, fixed-point tally 8, position and energy updates 12,
+# range-out and step-length logic 10
+ALG_OPS_PER_STEP = 300.0
+# gfx950: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one VALU lane-operation per
+# lane and clock (non-packed; packed FP32 is switched off at build time)
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# the published FP32 vector peak (packed FMA: 2 flops x 2 per lane and clock)
+FP32_PEAK_FLOPS = 157.3e12
+# wave64 VALU instructions issued per second over the chip: 1024 SIMDs, 4
+# clocks each
+VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4.0
 HBM_PEAK = 8.0e12   # MI355X HBM3E, bytes/s
 TARGET_U = 0.005
 
@@ -79,8 +88,9 @@ def parse():
                     help="keep --histories-per-spot as given (skip the scaling to 0.5 %% uncertainty)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate comparison")
-    ap.add_argument("--sur-samples", type=int, default=3_000_000)
-    ap.add_argument("--sur-epochs", type=int, default=6)
+    ap.add_argument("--no-per-spot", action="store_true", help="skip the per-spot plain-launch baseline")
+    ap.add_argument("--sur-samples", type=int, default=100_000_000)
+    ap.add_argument("--sur-epochs", type=int, default=2)
     ap.add_argument("--no-optimize", action="store_true", help="skip the spot-weight optimiser measurement")
     ap.add_argument("--let", action="store_true",
                     help="also time the nominal plan dose with and without the dose-averaged LET tally")
@@ -152,11 +162,13 @@ def plan_uncertainty(eng, case, I, V, np):
 
 def surrogate_comparison(eng, case, I, V, np, a, shape, plain_s, plain_steps):
     """The learned aperture surrogate on the same influence matrices: train
-    it on the GPU (plain brass traversals near the three apertures' edges),
-    time one 13-scenario IM with it, and compare the nominal plan dose with
-    and without it (independent seeds): fraction of voxels >= 10 % of the
-    maximum within 3 combined standard errors, gamma 1 %/1 mm (global, 10 %
-    threshold), high-dose mean ratio."""
+    it on the GPU (plain brass traversals near the three apertures' edges,
+    a.sur_samples of them), then time the 13-scenario IM with it exactly as
+    the plain one was timed (a.warmup untimed, a.steps timed), and compare the
+    nominal plan dose with and without it (independent seeds, 4x the IM's
+    histories): fraction of voxels >= 10 % of the maximum within 3 combined
+    standard errors, gamma 1 %/1 mm (global, 10 % threshold), high-dose mean
+    ratio; a second plain run gives the gamma noise floor."""
     import torch
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from gamma import gamma_pass_rate
@@ -164,17 +176,26 @@ def surrogate_comparison(eng, case, I, V, np, a, shape, plain_s, plain_steps):
     losses = eng.train_surrogate(case, n=a.sur_samples, epochs=a.sur_epochs, seed=3,
                                  fields=range(len(case.fields)))
     train_s = time.perf_counter() - t0
-    progress(f"surrogate trained in {train_s:.1f} s, losses {[round(float(x), 4) for x in losses]}")
+    progress(f"surrogate trained on {a.sur_samples:.3g} traversals in {train_s:.1f} s, "
+             f"losses {[round(float(x), 4) for x in losses]}")
     V.vpmc_surrogate_config(eng.ctx)
     eng.load_case(case)
+    for _ in range(a.warmup):
+        _, col, val, _, _ = eng.run_csr(case, device_out=True, surrogate=True, **shape)
+        del col, val
     torch.cuda.synchronize()
+    sts = []
     t0 = time.perf_counter()
-    _, col, val, _, _ = eng.run_csr(case, device_out=True, surrogate=True, **shape)
-    st = V.vpmc_last_stats(eng.ctx)
-    del col, val
+    for _ in range(a.steps):
+        _, col, val, _, _ = eng.run_csr(case, device_out=True, surrogate=True, **shape)
+        sts.append(V.vpmc_last_stats(eng.ctx))
+        del col, val
     torch.cuda.synchronize()
-    sur_s = time.perf_counter() - t0
-    progress(f"IM with surrogate: {sur_s:.2f} s (plain {plain_s:.2f} s), deferred {st['deferred']}")
+    sur_s = (time.perf_counter() - t0) / a.steps
+    deferred = sum(st["deferred"] for st in sts) / a.steps
+    hist = sum(st["histories"] for st in sts) / a.steps
+    steps = sum(st["steps"] for st in sts) / a.steps
+    progress(f"IM with surrogate: {sur_s:.3f} s (plain {plain_s:.3f} s), deferred {deferred:.0f} of {hist:.0f}")
     # accuracy at 4x the influence matrix's histories (U ~ 0.25 %), against an
     # independent plain run; a second plain run gives the noise floor
     dp, sp = plan_dose(eng, case, I, seed=case.seed + 101, mult=4)
@@ -193,11 +214,45 @@ def surrogate_comparison(eng, case, I, V, np, a, shape, plain_s, plain_steps):
     progress(f"surrogate vs plain: 3-sigma {frac:.4f}, gamma 1%/1mm {rate:.4f} (plain vs plain {floor:.4f}), "
              f"mean ratio {ratio:.5f}")
     return {"s_per_13_scenario_im": sur_s, "speedup_vs_plain": plain_s / sur_s,
-            "deferred_fraction": st["deferred"] / max(1, st["histories"]), "training_s": train_s,
+            "deferred_fraction": deferred / max(1.0, hist), "training_s": train_s,
             "training_traversals": a.sur_samples, "epochs": a.sur_epochs,
             "plan_dose_3sigma_fraction": frac, "plan_dose_gamma_1pct_1mm": rate,
             "plan_dose_gamma_plain_vs_plain": floor, "plan_dose_mean_ratio": ratio, "plan_dose_histories_x": 4,
-            "steps_ratio": st["steps"] / max(1, plain_steps)}
+            "steps_ratio": steps / max(1.0, plain_steps), "timed_steps": a.steps, "warmup": a.warmup}
+
+
+def per_spot_baseline(eng, case, I, V, np, stride=50):
+    """The influence matrices as one plain launch per row (one vpmc_run_spots
+    call in CSR mode per scenario x field x spot, the way a per-spot engine
+    builds them): every stride-th row is run and timed, and the time of the
+    whole matrix is extrapolated from their mean."""
+    import torch
+    eng.load_case(case)
+    rows = [(s, f, j) for s in range(len(case.scenarios)) for f in range(len(case.fields))
+            for j in range(len(case.fields[f].spots))]
+    sample = rows[::stride]
+    rp = np.zeros(2, np.int64)
+    led = np.zeros((1, V.NLEDGER))
+
+    def one(s, f, j):
+        spot = case.fields[f].spots[j:j + 1]
+        opts = V.make_opts(seed=case.seed, physics=case.physics, output=V.OUT_CSR, stream=eng.stream_ptr())
+        V.vpmc_run_spots(eng.ctx, f, V.spot_array(spot), 1, V.scenario_array([case.scenarios[s]]), 1, opts,
+                         None, None, led, rp)
+
+    one(*sample[0])   # warm-up (buffers sized)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in sample:
+        one(*r)
+    torch.cuda.synchronize()
+    per_row = (time.perf_counter() - t0) / len(sample)
+    progress(f"per-spot plain launches: {1e3 * per_row:.2f} ms per row over {len(sample)} sampled rows, "
+             f"{per_row * len(rows):.1f} s per IM extrapolated")
+    return {"s_per_13_scenario_im_extrapolated": per_row * len(rows), "ms_per_row": 1e3 * per_row,
+            "rows_timed": len(sample), "rows": len(rows),
+            "what": "one vpmc_run_spots call (CSR, one spot, one scenario) per row, rows sampled every "
+                    f"{stride}th, same histories and seed, time extrapolated to all rows"}
 
 
 def optimizer_measure(eng, case, I, V, np, torch, a, shape):
@@ -606,28 +661,42 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": measured_traffic(),
                      "kernel": "queue_kernel", "avg_launch_ms": 1e3 * transport_s / max(1, launches),
-                     "steps_per_s": steps_total / transport_s},
+                     "steps_per_s": steps_total / transport_s, "alg_ops_per_step": ALG_OPS_PER_STEP,
+                     "frac_of_fp32_flops_peak": achieved / FP32_PEAK_FLOPS},
         "transport_fraction_of_wall": transport_s / dt,
         "paper_context": "VPMC 41.6 s for 13 influence matrices (mean of 3 patients, 1-2 fields), "
                          "EPYC 7543 + 4x A100",
         "device": torch.cuda.get_device_name(0),
     }
-    # roof time of the transport: the method's one tally atomic per step at
-    # the measured atomic rate (pencil-beam address pattern, own kernel) or
-    # its VALU work at the chip's rate, whichever is longer
+    # what bounds the launch as built (from the committed counters of this
+    # kernel source): its VALU instructions at the chip's issue rate, and its
+    # memory-side int64 atomics (deposits outside the LDS row tile) at the
+    # rate the atomic probe measures on the head grid
     rate = V.vpmc_atomic_rate(eng.ctx, case.geometry.shape, 1 << 28)
     t_launch = transport_s / max(1, launches)
-    t_atomic = steps_total / max(1, launches) / rate
-    t_valu = ALG_OPS_PER_STEP * steps_total / max(1, launches) / VALU_PEAK_OPS
-    out["roof_time"] = {"atomic_rate_per_s": rate, "atomics_per_launch": steps_total / max(1, launches),
-                        "t_atomic_ms": 1e3 * t_atomic, "t_valu_ms": 1e3 * t_valu,
-                        "t_roof_ms": 1e3 * max(t_atomic, t_valu), "t_launch_ms": 1e3 * t_launch,
-                        "frac": max(t_atomic, t_valu) / t_launch}
-    progress(f"atomic rate {rate:.3e}/s: roof {1e3 * max(t_atomic, t_valu):.2f} ms per launch "
-             f"(atomics {1e3 * t_atomic:.2f}, VALU {1e3 * t_valu:.2f}) vs {1e3 * t_launch:.2f} ms measured")
+    insts = measured_traffic(key="valu_insts_per_launch")
+    atomics = measured_traffic(key="memside_atomics_per_launch")
+    floor = {"atomic_rate_per_s": rate, "t_launch_ms": 1e3 * t_launch,
+             "valu_insts_per_launch": insts, "memside_atomics_per_launch": atomics}
+    if insts is not None and atomics is not None:
+        t_issue, t_atom = insts / VALU_ISSUE_PEAK, atomics / rate
+        floor.update({"t_valu_issue_ms": 1e3 * t_issue, "t_memside_atomics_ms": 1e3 * t_atom,
+                      "bound": "valu_issue" if t_issue >= t_atom else "memside_atomics",
+                      "frac": max(t_issue, t_atom) / t_launch,
+                      "valu_lane_slots_per_step": insts * 64 * max(1, launches) / steps_total})
+        progress(f"launch {1e3 * t_launch:.2f} ms: VALU issue floor {1e3 * t_issue:.2f} ms, memory-side atomics "
+                 f"{1e3 * t_atom:.2f} ms")
+    out["issue_floor"] = floor
+    if not a.no_per_spot:
+        ps = per_spot_baseline(eng, case, I, V, np)
+        ps["batched_speedup"] = ps["s_per_13_scenario_im_extrapolated"] / (dt / a.steps)
+        out["per_spot_baseline"] = ps
     if not a.no_surrogate:
         out["surrogate"] = surrogate_comparison(eng, case, I, V, np, a, shape, dt / a.steps,
                                                 steps_total / a.steps)
+        if "per_spot_baseline" in out:
+            out["surrogate"]["batched_surrogate_speedup_vs_per_spot"] = (
+                out["per_spot_baseline"]["s_per_13_scenario_im_extrapolated"] / out["surrogate"]["s_per_13_scenario_im"])
     if not a.no_optimize:
         out["optimizer"] = optimizer_measure(eng, case, I, V, np, torch, a, shape)
     if a.dynamic_spacing:

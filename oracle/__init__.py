@@ -106,7 +106,8 @@ def lib():
             ("orc_uniform", d, [C.c_uint32]), ("orc_normal_quantile", d, [d]),
             ("orc_in_polygon", i, [vp, i, d, d]), ("orc_edge_distance", d, [vp, i, d, d, d, d]),
             ("orc_run", i64, [vp, vp, vp, i, i, vp, vp, vp, vp, i, vp]),
-            ("orc_trace_history", None, [vp, vp, vp, i, i64, vp, vp, vp, vp, vp]),
+            ("orc_trace_history", None, [vp, vp, vp, i, i64, vp, vp, vp, vp, vp, vp, vp]),
+            ("orc_move_allowance", None, [vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, i]),
             ("orc_slab_exit", None, [i, d, d, d, i, C.c_uint64, i64, vp, i]),
             ("orc_patient_exit", None, [vp, vp, vp, i, i64, vp, vp, vp, i]),
             ("orc_fixed_point_k", i, [d]), ("orc_rs_thickness", d, [d]),
@@ -322,8 +323,15 @@ def let_d(q, qL):
 
 
 def trace_history(case, spot_index: int, h: int, field_index: int = 0, scenario_index: int = 0,
-                  want_grid: bool = False, physics: Optional[int] = None):
+                  want_grid: bool = False, physics: Optional[int] = None, want_let: bool = False,
+                  move=None):
+    """One history in FP64: (ledgers MeV [6], info [steps, nuclear events,
+    random blocks, 0], per-voxel deposits MeV [nvox] or None); with want_let
+    also the per-voxel sum of deposit x LET (MeV keV/um) [nvox].  move
+    (dx, dy[, dE]) moves the start in the source plane (mm; a virtual source's
+    direction is taken from the moved start) and adds dE MeV to its energy."""
     P = _Prepared(case, field_index, scenario_index)
+    mv = None if move is None else _move3(move)
     o = _Opts()
     o.seed = case.seed
     o.field_id = field_index
@@ -331,10 +339,52 @@ def trace_history(case, spot_index: int, h: int, field_index: int = 0, scenario_
     led = np.zeros(6, np.float64)
     info = np.zeros(4, np.int64)
     grid = np.zeros(case.geometry.nvox, np.float64) if want_grid else None
+    glet = np.zeros(case.geometry.nvox, np.float64) if want_let else None
     lib().orc_trace_history(C.byref(P.geom), C.byref(P.field), C.byref(P.spots[spot_index]),
                             spot_index, h, C.byref(P.scen), C.byref(o), _ptr(led), _ptr(grid),
-                            _ptr(info))
+                            _ptr(info), _ptr(glet), _ptr(mv))
+    if want_let:
+        return led, info, grid, glet
     return led, info, grid
+
+
+def _move3(m) -> np.ndarray:
+    m = np.asarray(m, np.float64).ravel()
+    return np.concatenate([m, np.zeros(3 - m.size)]) if m.size < 3 else m[:3].copy()
+
+
+def move_allowance(case, entries, field_index: int = 0, scenario_index: int = 0, want_let: bool = False,
+                   threads: int = 0, physics: Optional[int] = None):
+    """Start-move allowance of straight-mode comparisons: entries is a list of
+    (spot, history, [(dx, dy[, dE]), ...]); every history is transported as
+    drawn and with its start moved by each (dx, dy) (mm, source plane) and
+    its energy by dE (MeV), and per
+    voxel the largest |moved - as drawn| deposit times the spot's w/N is
+    summed over the entries.  Returns allow [nz, ny, nx] (MeV w/N) and, with
+    want_let, the same for the deposit x LET numerator."""
+    P = _Prepared(case, field_index, scenario_index)
+    o = _Opts()
+    o.seed = case.seed
+    o.field_id = field_index
+    o.physics = case.physics if physics is None else physics
+    n = len(entries)
+    spot = np.array([e[0] for e in entries], np.int32)
+    hist = np.array([e[1] for e in entries], np.int64)
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum([len(e[2]) for e in entries])
+    moves = np.array([tuple(m) + (0.0,) * (3 - len(m)) for e in entries for m in e[2]],
+                     np.float64).reshape(-1, 3)
+    nvox = case.geometry.nvox
+    allow = np.zeros(nvox, np.float64)
+    allow_l = np.zeros(nvox, np.float64) if want_let else None
+    if n:
+        lib().orc_move_allowance(C.byref(P.geom), C.byref(P.field), C.cast(P.spots, C.c_void_p),
+                                 C.byref(P.scen), C.byref(o), n, _ptr(spot), _ptr(hist), _ptr(off),
+                                 _ptr(moves), _ptr(allow), _ptr(allow_l), threads)
+    nx, ny, nz = case.geometry.shape
+    if want_let:
+        return allow.reshape(nz, ny, nx), allow_l.reshape(nz, ny, nx)
+    return allow.reshape(nz, ny, nx)
 
 
 def patient_exit(case, spot_index: int, n: int, field_index: int = 0, scenario_index: int = 0,

@@ -378,7 +378,10 @@ typedef struct {
     int64_t *qL;                /* [nvox] LET numerator or NULL */
     int64_t led_q[NLEDGER];     /* per-thread fixed-point ledgers */
     double *grid_fp;            /* trace: FP64 per-voxel deposits or NULL */
+    double *grid_let_fp;        /* trace: FP64 per-voxel LET numerator (deposit x LET) or NULL */
     double led_fp[NLEDGER];     /* trace: FP64 ledgers */
+    int track_touch;            /* trace: list the voxels given their first deposit */
+    int64_t *touch, n_touch, cap_touch;
 } sink_t;
 
 /* deposit e (MeV) in voxel v by a step of LET `let` (MeV/mm = keV/um): the
@@ -388,7 +391,16 @@ static void sink_grid(sink_t *s, int64_t v, double e, double let)
 {
     if (e == 0.0) return;
     s->led_fp[L_GRID] += e;
+    if (s->track_touch && s->grid_fp[v] == 0.0) {
+        if (s->n_touch == s->cap_touch) {
+            s->cap_touch = s->cap_touch ? 2 * s->cap_touch : 1024;
+            s->touch = (int64_t *)realloc(s->touch, (size_t)s->cap_touch * sizeof(int64_t));
+            if (!s->touch) abort();
+        }
+        s->touch[s->n_touch++] = v;
+    }
     if (s->grid_fp) s->grid_fp[v] += e;
+    if (s->grid_let_fp) s->grid_let_fp[v] += e * let;
     int64_t q = llrint(e * s->scale);
     s->led_q[L_GRID] += q;
     if (s->q && q) __atomic_fetch_add(&s->q[v], q, __ATOMIC_RELAXED);
@@ -807,13 +819,17 @@ static void patient(vp_t *vp, sink_t *sk, const orc_geom *g, const orc_field *f,
  * starts on its ray at the beam-frame origin plane, direction +z, or with a
  * virtual source vsad upstream of that plane (scanned beams diverge from it)
  * along the line from the virtual source through its start point. */
-static void source(vp_t *vp, const orc_spot *sp, const orc_field *f)
+static void source(vp_t *vp, const orc_spot *sp, const orc_field *f, const double *move)
 {
     double u[4], z1, z2;
     draw_block(vp, u);
     box_muller(u[0], u[1], &z1, &z2);
     vp->p[0] = sp->x + sp->sigma * z1;
     vp->p[1] = sp->y + sp->sigma * z2;
+    if (move) {                 /* test support: start moved in the source plane (mm) */
+        vp->p[0] += move[0];
+        vp->p[1] += move[1];
+    }
     vp->p[2] = 0.0;
     vp->d[0] = 0.0; vp->d[1] = 0.0; vp->d[2] = 1.0;
     if (f->vsad > 0.0) {
@@ -831,10 +847,12 @@ static void source(vp_t *vp, const orc_spot *sp, const orc_field *f)
         if (e < E_LO) e = E_LO;
         vp->E = e;
     }
+    if (move) vp->E += move[2];   /* test support: start energy offset (MeV) */
 }
 
-static void one_history(const orc_geom *g, const orc_field *f, const orc_spot *sp, int spot_index,
-                        int64_t h, const orc_scen *sc, const orc_opts *o, sink_t *sk, vp_t *vp)
+static void one_history_moved(const orc_geom *g, const orc_field *f, const orc_spot *sp, int spot_index,
+                              int64_t h, const orc_scen *sc, const orc_opts *o, sink_t *sk, vp_t *vp,
+                              const double *move)
 {
     memset(vp, 0, sizeof *vp);
     vp->key[0] = (uint32_t)(o->seed & 0xffffffffu);
@@ -842,10 +860,16 @@ static void one_history(const orc_geom *g, const orc_field *f, const orc_spot *s
     vp->spot = (uint32_t)spot_index;
     vp->hist = (uint32_t)h;
     vp->physics = o->physics;
-    source(vp, sp, f);
+    source(vp, sp, f, move);
     double tmin;
     if (!beamline(vp, sk, f, &tmin)) return;
     patient(vp, sk, g, f, sc, tmin);
+}
+
+static void one_history(const orc_geom *g, const orc_field *f, const orc_spot *sp, int spot_index,
+                        int64_t h, const orc_scen *sc, const orc_opts *o, sink_t *sk, vp_t *vp)
+{
+    one_history_moved(g, f, sp, spot_index, h, sc, o, sk, vp, NULL);
 }
 
 /* Run all histories h of spots [s_begin, s_end) in the requested batch.
@@ -893,20 +917,129 @@ int64_t orc_run(const orc_geom *g, const orc_field *f, const orc_spot *spots, in
 }
 
 /* One history with FP64 bookkeeping for invariant tests: ledgers[6] in MeV
- * (index 0 = patient grid), grid_fp[nvox] (optional) FP64 deposits, info[4] =
- * {steps, nuclear events, random blocks used, 0}. */
+ * (index 0 = patient grid), grid_fp[nvox] (optional) FP64 deposits,
+ * grid_let_fp[nvox] (optional) the FP64 sum of deposit x LET (MeV x keV/um)
+ * per voxel, info[4] = {steps, nuclear events, random blocks used, 0};
+ * move[3] (optional) moves the start in the source plane (move[0], move[1]
+ * in mm, before a virtual source's direction is taken from it) and adds
+ * move[2] MeV to its energy. */
 void orc_trace_history(const orc_geom *g, const orc_field *f, const orc_spot *sp, int spot_index,
                        int64_t h, const orc_scen *sc, const orc_opts *o, double *ledgers,
-                       double *grid_fp, int64_t *info)
+                       double *grid_fp, int64_t *info, double *grid_let_fp, const double *move)
 {
     orc_init();
     sink_t sk;
     memset(&sk, 0, sizeof sk);
     sk.grid_fp = grid_fp;
+    sk.grid_let_fp = grid_let_fp;
     vp_t vp;
-    one_history(g, f, sp, spot_index, h, sc, o, &sk, &vp);
+    one_history_moved(g, f, sp, spot_index, h, sc, o, &sk, &vp, move);
     for (int l = 0; l < NLEDGER; l++) ledgers[l] = sk.led_fp[l];
     info[0] = vp.n_steps; info[1] = vp.n_nuc; info[2] = vp.nblk; info[3] = 0;
+}
+
+/* Start-rounding allowance of the straight-mode comparisons (test support).
+ * Entry j names history hist[j] of spot spot[j] and the start moves
+ * moves[3*m .. 3*m+2] (mm in the source plane, then MeV of energy; see
+ * orc_trace_history) for m in [move_off[j], move_off[j+1]).  The history is
+ * transported once as drawn and
+ * once per move; per voxel the largest |moved - as drawn| deposit, times the
+ * spot's w/N, is added to allow[nvox] (MeV w/N), and likewise the deposit x
+ * LET numerator to allow_let[nvox] when that is non-NULL.  In straight mode a
+ * history draws no random numbers after its source, so a moved copy is the
+ * same history started elsewhere. */
+void orc_move_allowance(const orc_geom *g, const orc_field *f, const orc_spot *spots, const orc_scen *sc,
+                        const orc_opts *o, int64_t n, const int32_t *spot, const int64_t *hist,
+                        const int64_t *move_off, const double *moves, double *allow, double *allow_let,
+                        int nthreads)
+{
+    orc_init();
+    const int64_t nvox = (int64_t)g->nx * g->ny * g->nz;
+    const int want_let = allow_let != NULL;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+    {
+        double *base = (double *)calloc((size_t)nvox, sizeof(double));
+        double *var = (double *)calloc((size_t)nvox, sizeof(double));
+        double *worst = (double *)calloc((size_t)nvox, sizeof(double));
+        double *base_l = want_let ? (double *)calloc((size_t)nvox, sizeof(double)) : NULL;
+        double *var_l = want_let ? (double *)calloc((size_t)nvox, sizeof(double)) : NULL;
+        double *worst_l = want_let ? (double *)calloc((size_t)nvox, sizeof(double)) : NULL;
+        int64_t *hit = NULL, n_hit = 0, cap_hit = 0;    /* voxels whose worst is set */
+        sink_t sb, sv;
+        memset(&sb, 0, sizeof sb);
+        memset(&sv, 0, sizeof sv);
+        sb.track_touch = sv.track_touch = 1;
+        if (!base || !var || !worst || (want_let && (!base_l || !var_l || !worst_l))) abort();
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+        for (int64_t j = 0; j < n; j++) {
+            const orc_spot *sp = &spots[spot[j]];
+            vp_t vp;
+            sb.grid_fp = base;
+            sb.grid_let_fp = base_l;
+            sb.n_touch = 0;
+            one_history_moved(g, f, sp, spot[j], hist[j], sc, o, &sb, &vp, NULL);
+            for (int64_t m = move_off[j]; m < move_off[j + 1]; m++) {
+                sv.grid_fp = var;
+                sv.grid_let_fp = var_l;
+                sv.n_touch = 0;
+                one_history_moved(g, f, sp, spot[j], hist[j], sc, o, &sv, &vp, moves + 3 * m);
+                /* voxels reached by either copy */
+                for (int pass = 0; pass < 2; pass++) {
+                    const int64_t *t = pass ? sv.touch : sb.touch;
+                    const int64_t nt = pass ? sv.n_touch : sb.n_touch;
+                    for (int64_t i = 0; i < nt; i++) {
+                        const int64_t v = t[i];
+                        const double d = fabs(var[v] - base[v]);
+                        const double dl = want_let ? fabs(var_l[v] - base_l[v]) : 0.0;
+                        if ((d > 0.0 || dl > 0.0) && worst[v] == 0.0 && (!want_let || worst_l[v] == 0.0)) {
+                            if (n_hit == cap_hit) {
+                                cap_hit = cap_hit ? 2 * cap_hit : 1024;
+                                hit = (int64_t *)realloc(hit, (size_t)cap_hit * sizeof(int64_t));
+                                if (!hit) abort();
+                            }
+                            hit[n_hit++] = v;
+                        }
+                        if (d > worst[v]) worst[v] = d;
+                        if (want_let && dl > worst_l[v]) worst_l[v] = dl;
+                    }
+                }
+                for (int64_t i = 0; i < sv.n_touch; i++) {
+                    var[sv.touch[i]] = 0.0;
+                    if (want_let) var_l[sv.touch[i]] = 0.0;
+                }
+            }
+            const double w = sp->weight / (double)sp->nh;
+            for (int64_t i = 0; i < n_hit; i++) {
+                const int64_t v = hit[i];
+                const double a = w * worst[v];
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+                allow[v] += a;
+                if (want_let) {
+                    const double al = w * worst_l[v];
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+                    allow_let[v] += al;
+                    worst_l[v] = 0.0;
+                }
+                worst[v] = 0.0;
+            }
+            n_hit = 0;
+            for (int64_t i = 0; i < sb.n_touch; i++) {
+                base[sb.touch[i]] = 0.0;
+                if (want_let) base_l[sb.touch[i]] = 0.0;
+            }
+        }
+        free(sb.touch); free(sv.touch); free(hit);
+        free(base); free(var); free(worst); free(base_l); free(var_l); free(worst_l);
+    }
 }
 
 /* Exit states of histories 0 .. n-1 of one spot through the whole path

@@ -48,7 +48,7 @@ struct FieldState {
     bool set = false;
     FieldDev dev{};
     std::vector<float2> poly;
-    DevBuf poly_buf, sdf_buf;
+    DevBuf poly_buf, sdf_buf, cell_off_buf, cell_edge_buf, cell_ref_buf;
 };
 
 // Signed distance (FP64, + inside) from the cell centres of a raster over
@@ -95,6 +95,73 @@ Raster polygon_raster(const std::vector<float2> &poly, double margin) {
             r.d[(size_t)j * r.nx + i] = (float)(in ? std::sqrt(best) : -std::sqrt(best));
         }
     return r;
+}
+
+// Per raster cell near the boundary: a reference point (FP32, at least
+// 1e-4 mm from every edge, within 0.01 mm of the cell centre) with its side
+// by the crossing-number rule, and the edges (k, k+1) within kListRadius of
+// it.  A point p of the cell is on the reference point's side unless listed
+// edges cross the segment from it to p, and a ray from p meets no unlisted
+// edge within kListRadius - |p - ref|, so the kernels test a handful of edges
+// instead of every edge there.  Cells farther than kListRadius + h from the
+// boundary get no reference point (the raster's distance bound decides them).
+// off[cell]: bits 0-29 the first entry of the cell in edge[], bit 30 a
+// reference point exists, bit 31 it is inside; the next cell's bits 0-29 end
+// the list.
+struct CellLists {
+    std::vector<uint32_t> off;
+    std::vector<uint16_t> edge;
+    std::vector<float2> ref;
+};
+
+bool crossing_inside(const std::vector<float2> &poly, double x, double y) {
+    const int nv = (int)poly.size();
+    bool in = false;
+    for (int a = nv - 1, b = 0; b < nv; a = b++) {
+        const double ax = poly[a].x, ay = poly[a].y, bx = poly[b].x, by = poly[b].y;
+        if ((ay > y) != (by > y)) {
+            const double xc = ax + (y - ay) * (bx - ax) / (by - ay);
+            if (x < xc) in = !in;
+        }
+    }
+    return in;
+}
+
+double segment_distance(const float2 &a, const float2 &b, double x, double y) {
+    const double ex = (double)b.x - a.x, ey = (double)b.y - a.y, l2 = ex * ex + ey * ey;
+    double t = l2 > 0.0 ? ((x - a.x) * ex + (y - a.y) * ey) / l2 : 0.0;
+    t = std::min(std::max(t, 0.0), 1.0);
+    const double dx = x - a.x - t * ex, dy = y - a.y - t * ey;
+    return std::sqrt(dx * dx + dy * dy);
+}
+
+CellLists cell_lists(const std::vector<float2> &poly, const Raster &r, double radius) {
+    const int nv = (int)poly.size();
+    CellLists L;
+    L.off.assign((size_t)r.nx * r.ny + 1, 0u);
+    L.ref.assign((size_t)r.nx * r.ny, make_float2(0.f, 0.f));
+    for (int j = 0; j < r.ny; ++j)
+        for (int i = 0; i < r.nx; ++i) {
+            const size_t cell = (size_t)j * r.nx + i;
+            L.off[cell] = (uint32_t)L.edge.size();
+            if (std::fabs((double)r.d[cell]) > radius + r.h) continue;   // no edge within reach of the cell
+            // reference point: the cell centre in FP32, moved (by at most
+            // 0.01 mm) off any edge it lies within 1e-4 mm of
+            float2 q = make_float2((float)(r.x0 + (i + 0.5) * r.h), (float)(r.y0 + (j + 0.5) * r.h));
+            for (int tries = 0; tries < 8; ++tries) {
+                double dmin = 1e300;
+                for (int k = 0; k < nv; ++k) dmin = std::min(dmin, segment_distance(poly[k], poly[(k + 1) % nv], q.x, q.y));
+                if (dmin > 1e-4) break;
+                q = make_float2(q.x + 0.0013f, q.y + 0.0009f);
+            }
+            L.ref[cell] = q;
+            L.off[cell] |= 0x40000000u;
+            if (crossing_inside(poly, q.x, q.y)) L.off[cell] |= 0x80000000u;
+            for (int k = 0; k < nv; ++k)
+                if (segment_distance(poly[k], poly[(k + 1) % nv], q.x, q.y) <= radius) L.edge.push_back((uint16_t)k);
+        }
+    L.off[(size_t)r.nx * r.ny] = (uint32_t)L.edge.size();
+    return L;
 }
 
 }  // namespace
@@ -490,7 +557,16 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     const size_t nblk = (nvox + 31) / 32, nchunk = (nblk + 255) / 256;
     const size_t gstride = nblk * 32, mstride = (nblk + 255) & ~(size_t)255;
     const size_t slot_bytes = csr_slot_bytes(nvox);
+    // row slots: half of the cap, else 40 % of the free device memory up to
+    // 96 GiB (about 1100 head rows of 84 MB: fewer, longer epochs, so the
+    // tail of each epoch's last chunks weighs less)
     size_t budget = cap ? (cap > c->bytes ? cap - c->bytes : 0) / 2 : ((size_t)24 << 30);
+    if (!cap) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+            budget = std::max(budget, std::min((size_t)(0.4 * (double)(free_b + (c->n_slots ? c->slot_grid.cap : 0))),
+                                               (size_t)96 << 30));
+    }
     int G = o->max_slots > 0 ? std::min(o->max_slots, kMaxSlots) : kMaxSlots;
     G = (int)std::min<size_t>((size_t)G, budget / slot_bytes);
     G = std::min(G, std::max(R, 1));
@@ -1113,6 +1189,9 @@ void vpmc_destroy(vpmc_ctx *c) {
         for (auto &f : c->fields) {
             release(f.poly_buf);
             release(f.sdf_buf);
+            release(f.cell_off_buf);
+            release(f.cell_edge_buf);
+            release(f.cell_ref_buf);
         }
         for (DevBuf *b : {&c->tallies, &c->let_tallies, &c->qbatch, &c->s2, &c->ledger, &c->spots, &c->offsets,
                           &c->stage_dose, &c->stage_sigma, &c->stats, &c->slot_grid, &c->slot_mark, &c->slot_cnt,
@@ -1289,6 +1368,13 @@ int vpmc_set_aperture(vpmc_ctx *c, int field_id, const vpmc_beam *beam, const fl
         d.sdf_nx = ras.nx;
         d.sdf_ny = ras.ny;
     }
+    CellLists lists;
+    if (poly.size() >= 3) {
+        lists = cell_lists(poly, ras, kListRadius);
+        // a ray from p (within h sqrt(2) of its cell's reference point) meets
+        // no unlisted edge within this path length in the BEV plane
+        d.list_reach = (float)(kListRadius - (0.5 * ras.h * 1.4142135623730951 + 0.011) - 1e-3);
+    }
     if (c->device >= 0 && !poly.empty()) {
         HIP_TRY(hipSetDevice(c->device));
         if ((rc = ensure(c, f.poly_buf, poly.size() * sizeof(float2), 0))) return rc;
@@ -1296,10 +1382,24 @@ int vpmc_set_aperture(vpmc_ctx *c, int field_id, const vpmc_beam *beam, const fl
         if (!ras.d.empty()) {
             if ((rc = ensure(c, f.sdf_buf, ras.d.size() * sizeof(float), 0))) return rc;
             HIP_TRY(hipMemcpy(f.sdf_buf.ptr, ras.d.data(), ras.d.size() * sizeof(float), hipMemcpyHostToDevice));
+            if ((rc = ensure(c, f.cell_off_buf, lists.off.size() * sizeof(uint32_t), 0)) ||
+                (rc = ensure(c, f.cell_ref_buf, lists.ref.size() * sizeof(float2), 0)) ||
+                (rc = ensure(c, f.cell_edge_buf, std::max<size_t>(1, lists.edge.size()) * sizeof(uint16_t), 0)))
+                return rc;
+            HIP_TRY(hipMemcpy(f.cell_off_buf.ptr, lists.off.data(), lists.off.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(f.cell_ref_buf.ptr, lists.ref.data(), lists.ref.size() * sizeof(float2),
+                              hipMemcpyHostToDevice));
+            if (!lists.edge.empty())
+                HIP_TRY(hipMemcpy(f.cell_edge_buf.ptr, lists.edge.data(), lists.edge.size() * sizeof(uint16_t),
+                                  hipMemcpyHostToDevice));
         }
     }
     d.poly = (const float2 *)f.poly_buf.ptr;
     d.sdf = ras.d.empty() ? nullptr : (const float *)f.sdf_buf.ptr;
+    d.cell_off = ras.d.empty() ? nullptr : (const uint32_t *)f.cell_off_buf.ptr;
+    d.cell_ref = ras.d.empty() ? nullptr : (const float2 *)f.cell_ref_buf.ptr;
+    d.cell_edge = ras.d.empty() ? nullptr : (const uint16_t *)f.cell_edge_buf.ptr;
     f.dev = d;
     f.poly = std::move(poly);
     f.set = true;

@@ -53,6 +53,7 @@ constexpr float EDGE_PUSH_MM = 1e-4f;      // push across an aperture edge in th
 constexpr int MAX_STEPS = 1000000;         // safety bound on steps per VP
 constexpr int MAX_BLOCK_ITER = 10000;      // bound on crossing-number tests per block traversal
 constexpr double kSdfMargin = 8.0;         // mm of aperture distance raster beyond the polygon's box
+constexpr double kListRadius = 1.9;        // mm: edges listed per raster cell around its reference point
 constexpr double MEV_TO_J = 1.602176634e-13;
 
 enum { L_GRID = 0, L_RS = 1, L_BLOCK = 2, L_ESCAPED = 3, L_NUC = 4, NLEDGER = 6 };
@@ -74,6 +75,13 @@ struct FieldDev {
     const float *sdf;
     float sdf_x0, sdf_y0, sdf_ih, sdf_r, sdf_far;
     int sdf_nx, sdf_ny;
+    // per raster cell near the boundary: edge lists around a reference point
+    // whose side is known (bit 31 of cell_off), for exact tests on a handful
+    // of edges; valid for BEV paths up to list_reach from the point
+    const uint32_t *cell_off;
+    const uint16_t *cell_edge;
+    const float2 *cell_ref;
+    float list_reach;
     float blk_zu, blk_zd, blk_rho, blk_t, blk_tl;
     int has_rs;
     float rs_zu, rs_zd, rs_r2, rs_rho, rs_rhol, rs_t, rs_tl;   // *_l: low parts of the FP64 values

@@ -523,6 +523,54 @@ __device__ __forceinline__ bool no_edge_within(float lb, float lat, float t) {
     return lb > 0.0f && lat * t < lb * (1.0f - 1e-5f) - 1e-4f;
 }
 
+// The exact side of (x, y) and the path length along (u, v) to the first
+// edge, from the edges listed for the point's raster cell (non-divergent
+// block): the cell's reference point has a known side, each listed edge that
+// the segment from it to (x, y) crosses flips the side (half-open
+// orientation tests), and no unlisted edge lies within list_reach of (x, y).
+// Returns 0 (the caller takes the loops over every edge) when the cell has
+// no reference point, 1 when te is the exact first-edge distance or the
+// caller's path length t ends before any edge, and 2 when only the side is
+// known: the first listed hit and t both lie beyond list_reach laterally
+// (lat = |(u, v)|), so an unlisted edge may come first and the caller takes
+// the loop over every edge for te.  A listed hit within list_reach is the
+// first hit: an earlier one would lie closer to (x, y), so on a listed edge.
+// Each listed edge's crossing arithmetic is edge_distance's.
+__device__ __forceinline__ int listed_edges(const FieldDev &f, const float2 *poly, int nv, float x, float y,
+                                            float u, float v, float lat, float t, bool &inside, float &te) {
+    if (!f.cell_off) return 0;
+    const float fx = (x - f.sdf_x0) * f.sdf_ih, fy = (y - f.sdf_y0) * f.sdf_ih;
+    if (!(fx >= 0.0f && fy >= 0.0f && fx < (float)f.sdf_nx && fy < (float)f.sdf_ny)) return 0;
+    const int cell = (int)fy * f.sdf_nx + (int)fx;
+    const uint32_t o0 = f.cell_off[cell], o1 = f.cell_off[cell + 1] & 0x3fffffffu;
+    if (!(o0 & 0x40000000u)) return 0;
+    const float2 r = f.cell_ref[cell];
+    bool in = (o0 & 0x80000000u) != 0u;
+    float best = INFINITY;
+    const float sx = x - r.x, sy = y - r.y;
+    for (uint32_t k = o0 & 0x3fffffffu; k < o1; ++k) {
+        const int e = f.cell_edge[k];
+        const float2 a = poly[e], b = poly[e + 1 < nv ? e + 1 : 0];
+        const float ex = b.x - a.x, ey = b.y - a.y;
+        const float o_r = ex * (r.y - a.y) - ey * (r.x - a.x);
+        const float o_p = ex * (y - a.y) - ey * (x - a.x);
+        const float o_a = sx * (a.y - r.y) - sy * (a.x - r.x);
+        const float o_b = sx * (b.y - r.y) - sy * (b.x - r.x);
+        if ((o_r > 0.0f) != (o_p > 0.0f) && (o_a > 0.0f) != (o_b > 0.0f)) in = !in;
+        const float den = u * ey - v * ex;
+        if (den != 0.0f) {
+            const float wx = a.x - x, wy = a.y - y;
+            const float inv = 1.0f / den;
+            const float th = (wx * ey - wy * ex) * inv;
+            const float lam = (wx * v - wy * u) * inv;
+            if (th > 0.0f && lam >= 0.0f && lam <= 1.0f) best = fminf(best, th);
+        }
+    }
+    inside = in;
+    te = best;
+    return lat * fminf(best, t) <= f.list_reach ? 1 : 2;
+}
+
 // path length along (u, v) until the beam's-eye-view ray from (x, y) meets an
 // edge (a non-divergent block)
 __device__ __forceinline__ float edge_distance(const float2 *poly, int nv, float x, float y, float u,
@@ -646,8 +694,9 @@ __device__ int slab_transport(Lane &v, Acc &acc, float scale, const float *tab, 
 // Methods B: between the block's entrance and exit planes the crossing
 // number at the VP's projected position decides, at every step, opening
 // (straight transport, no random numbers) or brass (brass tables).  D = false
-// compiles the plain (non-divergent) geometry only; D = true handles both, and
-// for a non-divergent block (scale 1, kw = 0) gives the same bits.
+// compiles the plain (non-divergent) geometry only; D = true adds the
+// divergent block's.  A non-divergent block takes the same code, and so gives
+// the same bits, in both.
 template <bool X, bool D = true>
 __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab, const float2 *poly,
                                int nv, float rho_b, float zu, float zd, DF thick, const FieldDev &f_sdf) {
@@ -659,19 +708,20 @@ __device__ int block_transport(Lane &v, Acc &acc, float scale, const float *tab,
         const float tp = tpp.h;
         bool open = false;
         float te = INFINITY;
-        if (nv >= 3 && !D) {
+        if (nv >= 3 && !(D && f_sdf.div)) {
             bool inside;
             const float lb = sdf_bound(f_sdf, v.px, v.py, inside);
-            if (no_edge_within(lb, sqrtf(v.dx * v.dx + v.dy * v.dy), tp)) {
+            const float lat = sqrtf(v.dx * v.dx + v.dy * v.dy);
+            if (no_edge_within(lb, lat, tp)) {
                 open = inside;
             } else {
-                open = in_polygon(poly, nv, v.px, v.py);
-                te = edge_distance(poly, nv, v.px, v.py, v.dx, v.dy);
+                const int ls = listed_edges(f_sdf, poly, nv, v.px, v.py, v.dx, v.dy, lat, tp, open, te);
+                if (ls == 0) open = in_polygon(poly, nv, v.px, v.py);
+                if (ls != 1) te = edge_distance(poly, nv, v.px, v.py, v.dx, v.dy);
             }
         } else if (nv >= 3) {
-            // opening scale at this depth (1 and kw = 0 for a non-divergent
-            // block, where (bx, by) = p_xy and every expression below is the plain
-            // beam's-eye-view one)
+            // divergent block: opening scale at this depth and its rate of
+            // change along the ray
             const float sc = fmaf(v.pz, f_sdf.fs, f_sdf.fc0), kw = v.dz * f_sdf.fs;
             const float isc = 1.0f / sc;
             const float bx = v.px * isc, by = v.py * isc;
@@ -783,20 +833,24 @@ __device__ int beamline(Lane &v, Acc &acc, float scale, const float *tab, const 
         const float qx = fmaf(t, v.dx, v.px), qy = fmaf(t, v.dy, v.py);
         const int nv = f.nv;
         bool open = false, through = false;
-        if (nv >= 3 && !D) {
+        if (nv >= 3 && !(D && f.div)) {
             const float tx = f.blk_t / v.dz;
             bool inside;
             const float lb = sdf_bound(f, qx, qy, inside);
-            if (no_edge_within(lb, sqrtf(v.dx * v.dx + v.dy * v.dy), tx)) {
+            const float lat = sqrtf(v.dx * v.dx + v.dy * v.dy);
+            float te = INFINITY;
+            if (no_edge_within(lb, lat, tx)) {
                 open = inside;
                 through = inside;
             } else {
-                open = in_polygon(poly, nv, qx, qy);
-                through = open && edge_distance(poly, nv, qx, qy, v.dx, v.dy) >= tx;
+                const int ls = listed_edges(f, poly, nv, qx, qy, v.dx, v.dy, lat, tx, open, te);
+                if (ls == 0) open = in_polygon(poly, nv, qx, qy);
+                if (open && ls != 1) te = edge_distance(poly, nv, qx, qy, v.dx, v.dy);
+                through = open && te >= tx;
             }
         } else if (nv >= 3) {
             const float tx = f.blk_t / v.dz;
-            // opening scale on the upstream face (1, kw = 0: non-divergent)
+            // divergent block: opening scale on the upstream face
             const float sc = f.fc0, kw = v.dz * f.fs;
             const float isc = 1.0f / sc;
             const float bx = qx * isc, by = qy * isc;
@@ -871,12 +925,22 @@ constexpr float kCalX[4] = {-1000.0f, 0.0f, 1000.0f, 1500.0f};
 template <bool X>
 __device__ __forceinline__ DF hu_density(int hu, int &m) {
     const int hc = min(max(hu, -1000), 3071);
+    m = hu < -900 ? MAT_AIR : hu < 150 ? MAT_WATER : MAT_BONE;
+    if (!X) {
+        // physics mode: the same piecewise-linear calibration as a sum of
+        // clamped segments (register arithmetic; a per-segment lookup of the
+        // nodes compiles to two dependent memory loads per step)
+        const float x = (float)hc;
+        float r = fmaf(kCalB[0].h, fminf(x, 0.0f) + 1000.0f, kCalY[0].h);
+        r = fmaf(kCalB[1].h, fminf(fmaxf(x, 0.0f), 1000.0f), r);
+        r = fmaf(kCalB[2].h, fminf(fmaxf(x - 1000.0f, 0.0f), 500.0f), r);
+        r = fmaf(kCalB[3].h, fmaxf(x - 1500.0f, 0.0f), r);
+        return {r, 0.0f};
+    }
     const int k = hc <= 0 ? 0 : hc <= 1000 ? 1 : hc <= 1500 ? 2 : 3;
     const PairC y = k == 0 ? kCalY[0] : k == 1 ? kCalY[1] : k == 2 ? kCalY[2] : kCalY[3];
     const PairC b = k == 0 ? kCalB[0] : k == 1 ? kCalB[1] : k == 2 ? kCalB[2] : kCalB[3];
     const float x0 = k == 0 ? kCalX[0] : k == 1 ? kCalX[1] : k == 2 ? kCalX[2] : kCalX[3];
-    m = hu < -900 ? MAT_AIR : hu < 150 ? MAT_WATER : MAT_BONE;
-    if (!X) return {fmaf(b.h, (float)hc - x0, y.h), 0.0f};
     return df_add({y.h, y.l}, df_mul_f({b.h, b.l}, (float)hc - x0));
 }
 
@@ -1485,9 +1549,26 @@ __global__ __launch_bounds__(X ? 768 : 1024) void queue_kernel(GeomDev g, QueueD
 // a multiple of 256, so the word stays inside the row's marks), the marked
 // blocks are listed in ascending order in the wave's LDS, and then the two
 // half-waves read two blocks' 32 slot values (coalesced 256 B each) at a
-// time.  The waves of the launch stride over the epoch's (row, chunk) pairs,
-// consecutive waves on consecutive chunks; a chunk without marks costs one
-// load and a ballot.
+// time, kCsrUnroll such pairs in flight before any is used.  A wave visits
+// kCsrGroup consecutive (row, chunk) pairs at once, their mark words loaded
+// together; the waves of the launch stride over the epoch's groups,
+// consecutive waves on consecutive groups.  A chunk without marks costs one
+// load (in flight with its group's) and a ballot.
+constexpr int kCsrGroup = 4, kCsrUnroll = 4;
+
+// mark words of the pairs [g * kCsrGroup, ...) of an epoch (0 past the end)
+__device__ __forceinline__ void group_marks(const QueueDev &Q, size_t gi, size_t npair, int lane,
+                                            uint32_t (&w)[kCsrGroup]) {
+#pragma unroll
+    for (int j = 0; j < kCsrGroup; ++j) {
+        const size_t pair = gi * kCsrGroup + j;
+        w[j] = 0u;
+        if (pair < npair) {
+            const size_t row = pair / Q.nchunk, chunk = pair - row * Q.nchunk;
+            w[j] = *reinterpret_cast<const uint32_t *>(Q.mark + row * Q.mstride + chunk * 256 + 4 * lane);
+        }
+    }
+}
 
 // lists the marked blocks of a chunk (offsets 0..255) in ascending order;
 // returns their count
@@ -1518,24 +1599,36 @@ __global__ __launch_bounds__(256) void csr_count_kernel(QueueDev Q, unsigned int
     const int lane = threadIdx.x & 63, wv_id = threadIdx.x >> 6;
     int *list = lists[wv_id];
     const size_t npair = (size_t)Q.n_rows * Q.nchunk;
+    const size_t ngroup = (npair + kCsrGroup - 1) / kCsrGroup;
     const size_t nwave = (size_t)gridDim.x * 4;
-    for (size_t pair = (size_t)blockIdx.x * 4 + wv_id; pair < npair; pair += nwave) {
-        const size_t row = pair / Q.nchunk, chunk = pair - row * Q.nchunk;
-        const size_t b0 = chunk * 256;
-        const uint8_t *mark = Q.mark + row * Q.mstride;
-        const uint32_t w = *reinterpret_cast<const uint32_t *>(mark + b0 + 4 * lane);
-        unsigned int c = 0;
-        if (__ballot(w != 0u) != 0ull) {
-            const unsigned long long *grid = Q.grid + row * Q.gstride;
-            const int nm = chunk_blocks(w, lane, list);
-            for (int p = 0; 2 * p < nm; ++p) {
-                const int idx = 2 * p + (lane >> 5);
-                if (idx < nm) c += grid[(b0 + list[idx]) * 32 + (lane & 31)] != 0ull;
+    for (size_t gi = (size_t)blockIdx.x * 4 + wv_id; gi < ngroup; gi += nwave) {
+        uint32_t w[kCsrGroup];
+        group_marks(Q, gi, npair, lane, w);
+#pragma unroll
+        for (int j = 0; j < kCsrGroup; ++j) {
+            const size_t pair = gi * kCsrGroup + j;
+            if (pair >= npair) break;
+            unsigned int c = 0;
+            if (__ballot(w[j] != 0u) != 0ull) {
+                const size_t row = pair / Q.nchunk, chunk = pair - row * Q.nchunk;
+                const size_t b0 = chunk * 256;
+                const unsigned long long *grid = Q.grid + row * Q.gstride;
+                const int nm = chunk_blocks(w[j], lane, list);
+                for (int p = 0; 2 * p < nm; p += kCsrUnroll) {
+                    unsigned long long q[kCsrUnroll];
+#pragma unroll
+                    for (int u = 0; u < kCsrUnroll; ++u) {
+                        const int idx = 2 * (p + u) + (lane >> 5);
+                        q[u] = idx < nm ? grid[(b0 + list[idx]) * 32 + (lane & 31)] : 0ull;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kCsrUnroll; ++u) c += q[u] != 0ull;
+                }
+                for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+                __builtin_amdgcn_wave_barrier();   // list reused by the next chunk
             }
-            for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-            __builtin_amdgcn_wave_barrier();   // list reused by the next chunk
+            if (lane == 0) cnt[pair] = c;
         }
-        if (lane == 0) cnt[pair] = c;
     }
 }
 
@@ -1608,35 +1701,51 @@ __global__ __launch_bounds__(256) void csr_emit_kernel(QueueDev Q, const unsigne
     const int lane = threadIdx.x & 63, wv_id = threadIdx.x >> 6;
     int *list = lists[wv_id];
     const size_t npair = (size_t)Q.n_rows * Q.nchunk;
+    const size_t ngroup = (npair + kCsrGroup - 1) / kCsrGroup;
     const size_t nwave = (size_t)gridDim.x * 4;
-    for (size_t pair = (size_t)blockIdx.x * 4 + wv_id; pair < npair; pair += nwave) {
-        const size_t row = pair / Q.nchunk, chunk = pair - row * Q.nchunk;
-        const size_t b0 = chunk * 256;
-        uint8_t *mark = Q.mark + row * Q.mstride;
-        const uint32_t w = *reinterpret_cast<const uint32_t *>(mark + b0 + 4 * lane);
-        if (__ballot(w != 0u) == 0ull) continue;
-        unsigned long long *grid = Q.grid + row * Q.gstride;
-        const int nm = chunk_blocks(w, lane, list);
-        const unsigned long long rb = row_off[Q.row_begin + row];
-        const bool write = rb + row_nnz[Q.row_begin + row] <= capacity;
-        const unsigned long long p0 = rb + coff[pair];
-        unsigned long long pos = p0;
-        for (int p = 0; 2 * p < nm; ++p) {
-            const int idx = 2 * p + (lane >> 5);
-            const size_t v = idx < nm ? (b0 + list[idx]) * 32 + (lane & 31) : 0;
-            const unsigned long long q = idx < nm ? grid[v] : 0ull;
-            const unsigned long long bal = __ballot(q != 0ull);
-            if (q != 0ull && write) {
-                const unsigned long long at = pos + __popcll(bal & ((1ull << lane) - 1ull));
-                col[at] = (int32_t)v;
-                qv[at] = (long long)q;
+    for (size_t gi = (size_t)blockIdx.x * 4 + wv_id; gi < ngroup; gi += nwave) {
+        uint32_t w[kCsrGroup];
+        group_marks(Q, gi, npair, lane, w);
+#pragma unroll
+        for (int j = 0; j < kCsrGroup; ++j) {
+            const size_t pair = gi * kCsrGroup + j;
+            if (pair >= npair) break;
+            if (__ballot(w[j] != 0u) == 0ull) continue;
+            const size_t row = pair / Q.nchunk, chunk = pair - row * Q.nchunk;
+            const size_t b0 = chunk * 256;
+            uint8_t *mark = Q.mark + row * Q.mstride;
+            unsigned long long *grid = Q.grid + row * Q.gstride;
+            const int nm = chunk_blocks(w[j], lane, list);
+            const unsigned long long rb = row_off[Q.row_begin + row];
+            const bool write = rb + row_nnz[Q.row_begin + row] <= capacity;
+            const unsigned long long p0 = rb + coff[pair];
+            unsigned long long pos = p0;
+            for (int p = 0; 2 * p < nm; p += kCsrUnroll) {
+                unsigned long long q[kCsrUnroll];
+                size_t v[kCsrUnroll];
+#pragma unroll
+                for (int u = 0; u < kCsrUnroll; ++u) {
+                    const int idx = 2 * (p + u) + (lane >> 5);
+                    v[u] = idx < nm ? (b0 + list[idx]) * 32 + (lane & 31) : 0;
+                    q[u] = idx < nm ? grid[v[u]] : 0ull;
+                }
+#pragma unroll
+                for (int u = 0; u < kCsrUnroll; ++u) {
+                    const int idx = 2 * (p + u) + (lane >> 5);
+                    const unsigned long long bal = __ballot(q[u] != 0ull);
+                    if (q[u] != 0ull && write) {
+                        const unsigned long long at = pos + __popcll(bal & ((1ull << lane) - 1ull));
+                        col[at] = (int32_t)v[u];
+                        qv[at] = (long long)q[u];
+                    }
+                    if (idx < nm) grid[v[u]] = 0ull;
+                    pos += __popcll(bal);
+                }
             }
-            if (idx < nm) grid[v] = 0ull;
-            pos += __popcll(bal);
+            if (w[j] != 0u) *reinterpret_cast<uint32_t *>(mark + b0 + 4 * lane) = 0u;
+            if (lane == 0 && pos - p0 != cnt[pair]) atomicOr(flags, 2u);
+            __builtin_amdgcn_wave_barrier();   // list reused by the next chunk
         }
-        if (w != 0u) *reinterpret_cast<uint32_t *>(mark + b0 + 4 * lane) = 0u;
-        if (lane == 0 && pos - p0 != cnt[pair]) atomicOr(flags, 2u);
-        __builtin_amdgcn_wave_barrier();   // list reused by the next chunk
     }
 }
 
@@ -2167,11 +2276,12 @@ hipError_t launch_queue(const GeomDev &g, const QueueDev &Q, int blocks, int thr
     return hipGetLastError();
 }
 
-// workgroups (4 waves each) of the compaction passes: one wave per (row,
-// chunk) pair up to 4096 workgroups, the waves striding over the rest
+// workgroups (4 waves each) of the compaction passes: one wave per group of
+// kCsrGroup (row, chunk) pairs up to 4096 workgroups, the waves striding over
+// the rest
 static unsigned csr_pass_blocks(const QueueDev &Q) {
-    const size_t npair = (size_t)Q.n_rows * Q.nchunk;
-    return (unsigned)std::max<size_t>(1, std::min<size_t>((npair + 3) / 4, 4096));
+    const size_t ngroup = ((size_t)Q.n_rows * Q.nchunk + kCsrGroup - 1) / kCsrGroup;
+    return (unsigned)std::max<size_t>(1, std::min<size_t>((ngroup + 3) / 4, 4096));
 }
 
 hipError_t launch_csr_count(const QueueDev &Q, unsigned int *cnt, hipStream_t s) {

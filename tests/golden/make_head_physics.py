@@ -9,8 +9,9 @@ non-air voxels whose dose is at least 5 % of the non-air maximum, the dose
 and its batch standard error (FP32, Gy per VP), the per-batch doses of the
 voxels at or above 25 % (for the error of a regional mean), the non-air
 maximum, the uncertainty U (mean sigma/D over non-air voxels >= 50 % of the
-maximum), the energy ledger, and the hashes of the inputs and of the oracle's
-source so that a stale file is detected.
+maximum), the energy ledger, the hash of the inputs and a fingerprint of the
+oracle's results (head_cases.oracle_fingerprint) so that a stale file is
+detected.
 """
 from __future__ import annotations
 
@@ -58,7 +59,7 @@ def make(name: str, threads: int) -> None:
         seed=np.int64(H.ORACLE_SEED),
         n_batches=np.int64(H.N_BATCHES),
         input_hash=np.array(H.input_hash(c)),
-        oracle_hash=np.array(H.oracle_source_hash()),
+        oracle_fingerprint=np.array(H.oracle_fingerprint()),
         seconds=np.float64(dt),
         threads=np.int64(threads),
     )

@@ -10,8 +10,9 @@ beam hits the brass), or the central spot of the most distal layer.
 The FP64 oracle's doses of these cases are expensive at the history counts
 the 0.25 % uncertainty target asks for (about 4e7 VPs per spot), so they are
 written once by ``tests/golden/make_head_physics.py`` (which calls only the
-oracle and these seeded inputs) and stored with the hashes of the inputs and
-of the oracle's source; a CPU test checks that both are still current.
+oracle and these seeded inputs) and stored with the hash of the inputs and a
+fingerprint of the oracle's results; a CPU test checks that both are still
+current.
 """
 from __future__ import annotations
 
@@ -101,10 +102,19 @@ def input_hash(c) -> str:
     return h.hexdigest()
 
 
-def oracle_source_hash() -> str:
+def oracle_fingerprint() -> str:
+    """What the oracle computes, not how its source reads: the SHA-256 of the
+    int64 tally and ledgers of 3000 full-physics histories of the aperture-edge
+    head case (range shifter, brass, air, bone and brain, a shifted and
+    range-scaled scenario) on one thread.  Any change of the transport's
+    arithmetic changes these bits; edits that leave it alone do not."""
+    import oracle
+    c = case("g90_xplus_r1035_edge", 3000, 7)
+    q, led, k = oracle.run_tally(c, threads=1)
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "oracle", "vpmc_oracle.c"), "rb") as fh:
-        h.update(fh.read())
+    h.update(np.ascontiguousarray(q).tobytes())
+    h.update(np.ascontiguousarray(led).tobytes())
+    h.update(np.int64(k).tobytes())
     return h.hexdigest()
 
 

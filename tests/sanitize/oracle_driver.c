@@ -3,8 +3,8 @@
  * unit with the sanitizers on, and every entry point the tests use is driven
  * over small cases that reach each code path (water and CT grids, the block
  * with a concave opening, the range shifter, divergence and a virtual source,
- * batches, the LET numerator, traces, slab and block experiments, the
- * network).  Exit status 0 with no sanitizer report; the energy balance of
+ * batches, the LET numerator, traces, start-move allowances, slab and block
+ * experiments, the network).  Exit status 0 with no sanitizer report; the energy balance of
  * every run is checked so the cases really transport. */
 #include "../../oracle/vpmc_oracle.c"
 #include "../../oracle/vpmc_mlp.c"
@@ -41,9 +41,27 @@ static void run_case(const orc_geom *g, orc_field *f, const orc_scen *sc, int ph
     for (int j = 0; j < NLEDGER; j++) e += ldexp((double)led[j], -o.k);
     CHECK(grid_sum == led[0]);
     CHECK(fabs(e - 390.0) < 0.5);
-    double *grid = calloc((size_t)nvox, sizeof *grid), ledg[NLEDGER];
+    double *grid = calloc((size_t)nvox, sizeof *grid), *glet = calloc((size_t)nvox, sizeof *glet), ledg[NLEDGER];
     int64_t info[4];
-    orc_trace_history(g, f, &sp[0], 0, 7, sc, &o, ledg, grid, info);
+    const double mv[3] = {1e-3, -2e-3, 1e-4};
+    orc_trace_history(g, f, &sp[0], 0, 7, sc, &o, ledg, grid, info, glet, mv);
+    free(glet);
+    /* start-move allowance: two histories, one and two moves, with LET */
+    {
+        const int32_t ms[2] = {0, 1};
+        const int64_t mh[2] = {3, 11}, moff[3] = {0, 1, 3};
+        const double moves[9] = {0.25, 0.0, 0.0, 0.0, -0.25, 0.0, 0.25, 0.25, 0.5};
+        double *al = calloc((size_t)nvox, sizeof *al), *all = calloc((size_t)nvox, sizeof *all);
+        orc_move_allowance(g, f, sp, sc, &o, 2, ms, mh, moff, moves, al, all, 2);
+        double tot = 0.0;
+        for (int64_t i = 0; i < nvox; i++) {
+            CHECK(al[i] >= 0.0 && all[i] >= 0.0);
+            tot += al[i];
+        }
+        CHECK(tot <= 2.0 * (150.0 / 600 + 2.0 * 120.0 / 400));
+        free(al);
+        free(all);
+    }
     double *ex = malloc(8 * 50 * sizeof *ex);
     orc_patient_exit(g, f, &sp[1], 1, 50, sc, &o, ex, 2);
     free(ex);

@@ -7,10 +7,14 @@ boundary, of an edge of the aperture polygon or of the range shifter's rim
 may therefore take the other side of it on the GPU.  For each such history the
 oracle transports it twice more with its start moved across each of those
 boundaries (mirror image, the rest of the history unchanged: straight mode
-draws no random numbers after the source); the largest difference between the
+draws no random numbers after the source; the move is applied to the FP64
+start itself, oracle.move_allowance); the largest difference between the
 original and a moved copy's per-voxel deposits bounds what the FP32 rounding
-of that history's start can change in each voxel.  The parity test then
-demands, in every voxel,
+of that history's start can change in each voxel.  Tracks that are tilted
+(virtual source, divergent block) cross boundaries at depths that depend on
+the start continuously, so there every history is moved by BAND_MM along the
+eight directions of the source plane's square (shift_allowance).  The parity
+test then demands, in every voxel,
 
     |D_gpu - D_or| <= 1e-5 D_or + allowance + 1e-11 D_max,
 
@@ -26,7 +30,6 @@ three of them stay below 5e-5 mm.
 """
 from __future__ import annotations
 
-import copy
 import itertools
 import math
 
@@ -113,33 +116,66 @@ def ambiguous_moves(orc, case, field_index=0, scenario_index=0, spots=None, band
     return out
 
 
-def allowance(orc, case, field_index=0, scenario_index=0, spots=None, band=BAND_MM):
+def _combined(mv):
+    """Every non-empty combination of a history's moves, summed."""
+    out = []
+    for r in range(1, len(mv) + 1):
+        for combo in itertools.combinations(mv, r):
+            out.append((sum(m[0] for m in combo), sum(m[1] for m in combo)))
+    return out
+
+
+def allowance(orc, case, field_index=0, scenario_index=0, spots=None, band=BAND_MM, with_let=False):
     """(allowance [nz, ny, nx] in tally units q * 2^-k = MeV * w/N, number of
-    ambiguous histories)."""
-    g = case.geometry
-    nx, ny, nz = g.shape
-    allow = np.zeros(nx * ny * nz)
+    ambiguous histories); with_let: also the allowance of the dose-averaged
+    LET's numerator (deposit x LET, MeV keV/um * w/N) as a third item.  Each
+    ambiguous history is transported with its start moved across every
+    combination of the boundaries it lies near (oracle.move_allowance)."""
     moves = ambiguous_moves(orc, case, field_index, scenario_index, spots, band)
+    entries = [(s, h, _combined(mv)) for (s, h), mv in sorted(moves.items())]
+    res = orc.move_allowance(case, entries, field_index, scenario_index, want_let=with_let)
+    if with_let:
+        return res[0], len(moves), res[1]
+    return res, len(moves)
+
+
+SHIFTS = [(sx, sy) for sx in (-1, 0, 1) for sy in (-1, 0, 1) if sx or sy]
+
+
+DIR_REL = 4e-7
+
+
+def shift_allowance(orc, case, field_index=0, scenario_index=0, delta=BAND_MM, dir_rel=DIR_REL):
+    """Allowance for tilted tracks (virtual source, divergent block): every
+    history is moved by delta along the eight directions of the source
+    plane's square (axes and diagonals).  A tilted track crosses lateral voxel
+    boundaries and tilted walls at depths that move by delta / tilt when its
+    start moves by delta, so no history is exempt; the moved copies bound
+    what the FP32 start, whose error stays within delta on either axis, can
+    move between voxels.
+
+    With a virtual source the direction itself comes from the FP32 start
+    through a sum of squares, a square root, a reciprocal and a product
+    (relative error below dir_rel = 4e-7), and the path length per unit depth
+    follows it: every depth-energy relation moves by at most dir_rel of the
+    water-equivalent path, which is less than the CSDA range R(E).  Each
+    history is therefore also transported with its energy moved by
+    +-dir_rel R(E) S(E) (E the spot's highest energy, water), and that
+    allowance is added to the lateral one."""
     f = case.fields[field_index]
-    for (s, h), mv in moves.items():
-        _, _, base = orc.trace_history(case, s, h, field_index, scenario_index, want_grid=True)
-        worst = np.zeros_like(base)
-        for r in range(1, len(mv) + 1):
-            for combo in itertools.combinations(mv, r):
-                dx = sum(m[0] for m in combo)
-                dy = sum(m[1] for m in combo)
-                c2 = copy.copy(case)
-                c2.fields = list(case.fields)
-                f2 = copy.copy(f)
-                f2.spots = f.spots.copy()
-                f2.spots["x_mm"][s] = np.float32(float(f.spots["x_mm"][s]) + dx)
-                f2.spots["y_mm"][s] = np.float32(float(f.spots["y_mm"][s]) + dy)
-                c2.fields[field_index] = f2
-                _, _, var = orc.trace_history(c2, s, h, field_index, scenario_index, want_grid=True)
-                np.maximum(worst, np.abs(var - base), out=worst)
-        w = float(f.spots["weight"][s]) / float(f.spots["n_histories"][s])
-        allow += worst * w
-    return allow.reshape(nz, ny, nx), len(moves)
+    lat, ene = [], []
+    for s in range(len(f.spots)):
+        mv = [(delta * sx, delta * sy) for sx, sy in SHIFTS]
+        n = int(f.spots["n_histories"][s])
+        lat.extend((s, h, mv) for h in range(n))
+        if f.vsad_mm > 0.0:
+            e = float(f.spots["energy_mev"][s]) + 6.0 * float(f.spots["energy_sigma_mev"][s])
+            de = dir_rel * float(orc.csda_range(0, e)) * float(orc.stopping_power(0, e))
+            ene.extend((s, h, [(0.0, 0.0, de), (0.0, 0.0, -de)]) for h in range(n))
+    allow = orc.move_allowance(case, lat, field_index, scenario_index)
+    if ene:
+        allow = allow + orc.move_allowance(case, ene, field_index, scenario_index)
+    return allow
 
 
 def assert_straight_parity(q_gpu, k_gpu, q_or, k_or, allow=None, max_allow_share=2e-3, say=print):
@@ -160,9 +196,13 @@ def assert_straight_parity(q_gpu, k_gpu, q_or, k_or, allow=None, max_allow_share
     strict = al == 0
     rel = err[hi & strict] / b[hi & strict]
     bad = err > bound
-    say(f"  straight parity: {int(hi.sum())} voxels above 1e-6 of max, max rel {rel.max():.3e} over "
+    say(f"  straight parity: {int(hi.sum())} voxels above 1e-6 of max, max rel {rel.max() if rel.size else 0.0:.3e} over "
         f"{int((hi & strict).sum())} without allowance; {int((~strict).sum())} voxels with allowance "
         f"(its sum {share:.2e} of the dose, those voxels' dose share {b[~strict].sum() / b.sum():.2e}); "
         f"worst bound use {float(np.max(err / bound)):.3f}")
+    if bad.any():
+        w = np.unravel_index(int(np.argmax(err / bound)), b.shape)
+        say(f"  worst voxel {tuple(int(i) for i in w)}: gpu {a[w]:.9e} oracle {b[w]:.9e} "
+            f"allowance {al[w]:.3e} bound {bound[w]:.3e}")
     assert not bad.any(), f"{int(bad.sum())} voxels outside the bound"
     assert share <= max_allow_share

@@ -5,26 +5,26 @@ against the FP64 oracle, through the C ABI.
 Workload: config 2 geometry (water, 30 mm brass block 50 mm upstream of the
 surface, 20 mm circular opening, 45 mm WET range shifter) with the beam
 diverging from a virtual source 2 m upstream and the block's walls focused
-on it (and the block alone focused, beam parallel).
+on it (and the block alone focused, beam parallel; and the beam alone
+divergent, block walls parallel).
 
-Straight mode (for a parallel beam the voxels where a history starting
-within FP32 rounding of a lateral voxel boundary, an aperture edge or the
-range shifter's rim could change the deposits are excluded first): tracks
-are tilted, so a track's crossing of a lateral voxel boundary moves by the
-FP32 rounding of its position (1e-5 mm), which moves about S x 1e-5 MeV
-between two voxels: per-voxel agreement is checked at 1e-3 on 99.9 % of the
-voxels above 10 % of the maximum, depth slices (sums over the lateral plane,
-which such shifts do not change) at 2e-5, the block and range-shifter
-ledgers at 1e-4 (one VP of the ~1e5 in the brass taking the other side of a
-wall at a rounding tie moves ~1e-5 of it).  Full physics: the bar of the
-other physics parity tests (3 sigma on >= 99 % of the voxels above 10 %,
-mean dose over the high-dose region within a fixed 0.5 %, gamma 1 %/1 mm on
->= 99 %)."""
+Straight mode: the straight-mode bar of the other tests, 1e-5 per voxel
+above 1e-6 of the maximum plus a per-voxel allowance, here for every history:
+a tilted track's crossings of lateral voxel boundaries and of tilted walls
+move along it by (start error) / tilt, so each history is transported by the
+oracle with its start moved by the FP32 rounding band along the eight
+directions of the source plane's square, and the largest change of its
+deposits in each voxel is its allowance there (straight_bound.shift_allowance;
+the allowances add up to at most 0.2 % of the dose).  Depth slices (sums over
+the lateral plane, which such moves do not change) are held to 2e-5, the
+block and range-shifter ledgers to 1e-4.  Full physics: the bar of the other
+physics parity tests (3 sigma on >= 99 % of the voxels above 10 %, mean dose
+over the high-dose region within a fixed 0.5 %, gamma 1 %/1 mm on >= 99 %)."""
 import numpy as np
 import pytest
 
 from paper_2307_01416_amd import inputs as I
-from straight_bound import allowance, assert_straight_parity
+from straight_bound import assert_straight_parity, shift_allowance
 from test_gpu_parity import gpu_q, say, stat_compare_oracle, straight_check
 
 pytestmark = pytest.mark.gpu
@@ -55,24 +55,16 @@ def test_straight_parity_divergent(eng, orc, vsad, focus):
     say(f"case {c.name} straight")
     qg, kg, _, _, lg = gpu_q(eng, c)
     qo, led_o, ko = orc.run_tally(c)
+    assert_straight_parity(qg, kg, qo, ko, shift_allowance(orc, c), say=say)
     a = qg.astype(np.float64) * 2.0 ** -kg
     b = qo.astype(np.float64) * 2.0 ** -ko
-    hi = b > 0.1 * b.max()
-    if vsad == 0.0:
-        # parallel beam: whole track lines that start at a lateral voxel
-        # boundary (FP32 vs FP64 source position) are excluded, as in the
-        # other straight-mode tests
-        hi &= allowance(orc, c)[0] == 0
-    rel = np.abs(a[hi] - b[hi]) / b[hi]
     sa = a.reshape(200, -1).sum(1)
     sb = b.reshape(200, -1).sum(1)
     m = sb > 1e-3 * sb.max()
     srel = np.abs(sa[m] - sb[m]) / sb[m]
     lo = led_o.astype(np.float64) * 2.0 ** -ko
     lrel = np.abs(np.asarray(lg[1:3]) - lo[1:3]) / np.maximum(lo[1:3], 1e-300)
-    say(f"  voxels: {np.mean(rel <= 1e-3):.5f} within 1e-3 (max {rel.max():.2e}); slices max rel {srel.max():.2e}; "
-        f"RS/block ledgers rel {lrel}")
-    assert np.mean(rel <= 1e-3) >= 0.999
+    say(f"  slices max rel {srel.max():.2e}; RS/block ledgers rel {lrel}")
     assert srel.max() <= 2e-5
     assert np.all(lrel <= 1e-4)
 

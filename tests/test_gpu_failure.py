@@ -100,6 +100,7 @@ def test_device_memory_cap(eng):
     d1, _, _ = eng.run_dose(c, 0, scenarios=c.scenarios[:1], n_batches=0, sigma=False, fixed_point_bits=36)
     fresh = V.Engine(0)
     try:
+        fresh.load_case(c)
         d2, _, _ = fresh.run_dose(c, 0, scenarios=c.scenarios[:1], n_batches=0, sigma=False, fixed_point_bits=36)
         assert torch.equal(d1, d2) and float(d1.max()) > 0
     finally:

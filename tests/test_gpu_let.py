@@ -39,19 +39,17 @@ def check_straight(orc, case, qg, qlg, kg, sh):
     qo, qlo, ko = orc.run_let(case)
     assert kg == ko and sh == orc.LET_SHIFT
     # a history starting within rounding of a boundary may deposit on the
-    # other side of it: its dose difference (the allowance) times the largest
-    # LET_d in the voxel's 3x3x3 neighbourhood (straight mode: every history
-    # has the same energy at a given depth) bounds its numerator difference;
-    # LET_d itself is compared where no such history deposits
-    allow, _ = allowance(orc, case)
+    # other side of it: the oracle's allowances of the dose and of the LET
+    # numerator (that history's start mirrored across the boundary) bound the
+    # differences there; LET_d itself is compared where no such history deposits
+    allow, _, allow_l = allowance(orc, case, with_let=True)
     keep = allow == 0
     b = qo.astype(np.float64)
-    let_or = orc.let_d(qo, qlo)
-    from scipy.ndimage import maximum_filter
-    al_num = 1.05 * maximum_filter(let_or, size=3) * allow * 2.0 ** (ko - orc.LET_SHIFT)
+    al_num = allow_l * 1.001 * 2.0 ** (ko - orc.LET_SHIFT) + np.where(allow_l > 0, 1e3, 0.0)
     num_err = np.abs(qlg.astype(np.float64) - qlo.astype(np.float64))
-    assert np.all(num_err <= 1e-5 * qlo.astype(np.float64) + al_num + 2.0)
-    assert np.all(np.abs(qg.astype(np.float64) - b) <= 1e-5 * b + allow * 2.0 ** ko * 1.001 + 1e3)
+    assert np.all(num_err <= 1e-5 * qlo.astype(np.float64) + al_num + 1e-11 * qlo.max() + 2.0)
+    al_q = allow * 1.001 * 2.0 ** ko + np.where(allow > 0, 1e3, 0.0)
+    assert np.all(np.abs(qg.astype(np.float64) - b) <= 1e-5 * b + al_q + 1e-11 * b.max() + 1.0)
     hi = (b > 1e-6 * b.max()) & keep
     num_g, num_o = qlg.astype(np.float64)[hi], qlo.astype(np.float64)[hi]
     rel_num = np.abs(num_g - num_o) / np.maximum(num_o, 1.0)

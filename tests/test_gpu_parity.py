@@ -5,8 +5,8 @@ above 1e-6 of the maximum, with an absolute floor of 1e-11 of the maximum.
 A history whose FP64 start lies within 5e-5 mm of a lateral voxel boundary,
 an aperture edge or the range shifter's rim may take the other side of it in
 FP32: every voxel's bound grows by what the oracle deposits differently when
-that history's start is mirrored across the boundary, and the voxels without
-such an allowance must hold 95 % of the dose (straight_bound.py).
+that history's start is mirrored across the boundary, and the allowances
+may add up to at most 0.2 % of the dose (straight_bound.py).
 
 Full physics: independent seeds; >= 99 % of voxels above 10 % of the maximum
 within 3 combined standard errors; mean dose over the high-dose region within
