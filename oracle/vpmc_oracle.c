@@ -56,7 +56,7 @@
 #define NUC_F_LOCAL 0.10         /* share of E deposited on a nuclear event (R2) */
 #define NUC_F_ESCAPE 0.30        /* share carried away by neutral secondaries (R2) */
 #define NUC_SIGMA_RAD 0.15       /* deflection of the leading secondary (R2) */
-#define EDGE_PUSH_MM 1e-6        /* push across an aperture edge, in the aperture plane (R5) */
+#define EDGE_PUSH_MM 1e-4        /* push across an aperture edge, in the aperture plane (R5) */
 #define MAX_ITER 1000000         /* safety bound on steps per VP */
 #define MAX_BLOCK_ITER 10000     /* safety bound on crossing-number tests per block traversal */
 #define LET_SHIFT 8              /* LET numerator in units of 2^(8-k) MeV keV/um (LET <= 256 keV/um) */
