@@ -28,7 +28,7 @@
  *   Methods E   - robust scenarios: range (stopping-power) scaling and
  *                 isocentre shifts.
  * Where the paper is silent the readings used here are the ones listed in
- * the design notes (R1-R21); each is named at the point of use.
+ * the design notes (R1-R28); each is named at the point of use.
  */
 #include <math.h>
 #include <stdint.h>
