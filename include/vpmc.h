@@ -245,11 +245,12 @@ int vpmc_run_batched(vpmc_ctx *ctx, const int *field_ids, const vpmc_spot *const
  * bits).  Runs a bounded sample of the given spots (every s-th spot with its
  * own history count, s chosen so that the sample holds about
  * sample_histories VPs) in the output mode of *base for each candidate
- * shape, keeps the one with the shortest
- * transport time per history, writes it into *best (a copy of *base with
- * hist_per_lane, grid_blocks and block_threads filled) and remembers it for
- * later runs on this context whose opts leave them at 0.  Candidates (CSR):
- * hist_per_lane in {1,2,4,8} x workgroups of 1024 or 512 threads (768 or 512
+ * shape (each timed twice, the faster time counting), keeps the one with
+ * the shortest transport time per history, writes it into *best (a copy of
+ * *base with hist_per_lane, grid_blocks and block_threads filled) and
+ * remembers it for later runs on this context whose opts leave them at 0.
+ * Candidates (CSR): hist_per_lane in {1,2,3,4,6,8} x workgroups of 1024 or
+ * 512 threads (768 or 512
  * in straight mode), as many as fill every CU at its full wave occupancy;
  * (dense): {4,8,16,32} x CUs x 256 threads of work per launch in workgroups of
  * 256 or 512 threads. */

@@ -156,24 +156,38 @@ __device__ __forceinline__ NodePos node_pos_below(const float *tab, float E, int
 __device__ __forceinline__ float normal_quantile(float u) {
     const float t = 2.0f * u - 1.0f;
     const float w = -__logf(4.0f * u * (1.0f - u));
-    const float s1 = w - 2.5f, s2 = sqrt_hw(w) - 3.0f;
-    float a = 2.798955610e-08f, b = -2.393541571e-04f;
-    a = fmaf(a, s1, 3.430734327e-07f);  b = fmaf(b, s2, 1.079666834e-04f);
-    a = fmaf(a, s1, -3.522236486e-06f); b = fmaf(b, s2, 1.402476381e-03f);
-    a = fmaf(a, s1, -4.389634286e-06f); b = fmaf(b, s2, -3.678024843e-03f);
-    a = fmaf(a, s1, 2.185773789e-04f);  b = fmaf(b, s2, 5.716959691e-03f);
-    a = fmaf(a, s1, -1.253729840e-03f); b = fmaf(b, s2, -7.622124629e-03f);
-    a = fmaf(a, s1, -4.177678720e-03f); b = fmaf(b, s2, 9.441883054e-03f);
-    a = fmaf(a, s1, 2.466407436e-01f);  b = fmaf(b, s2, 1.001674163e+00f);
-    a = fmaf(a, s1, 1.501409417e+00f);  b = fmaf(b, s2, 2.832976859e+00f);
-    return 1.41421356237f * (w < 5.0f ? a : b) * t;
+    float p;
+    if (w < 5.0f) {   // central part (all but 0.34 % of the draws)
+        const float s1 = w - 2.5f;
+        float a = 2.798955610e-08f;
+        a = fmaf(a, s1, 3.430734327e-07f);
+        a = fmaf(a, s1, -3.522236486e-06f);
+        a = fmaf(a, s1, -4.389634286e-06f);
+        a = fmaf(a, s1, 2.185773789e-04f);
+        a = fmaf(a, s1, -1.253729840e-03f);
+        a = fmaf(a, s1, -4.177678720e-03f);
+        a = fmaf(a, s1, 2.466407436e-01f);
+        p = fmaf(a, s1, 1.501409417e+00f);
+    } else {
+        const float s2 = sqrt_hw(w) - 3.0f;
+        float b = -2.393541571e-04f;
+        b = fmaf(b, s2, 1.079666834e-04f);
+        b = fmaf(b, s2, 1.402476381e-03f);
+        b = fmaf(b, s2, -3.678024843e-03f);
+        b = fmaf(b, s2, 5.716959691e-03f);
+        b = fmaf(b, s2, -7.622124629e-03f);
+        b = fmaf(b, s2, 9.441883054e-03f);
+        b = fmaf(b, s2, 1.001674163e+00f);
+        p = fmaf(b, s2, 2.832976859e+00f);
+    }
+    return 1.41421356237f * p * t;
 }
 
 // 1 - exp(-x) for x >= 0 (nuclear removal over a step): the series to x^5
 // below 1/8 (truncation below x^6/720), else through exp
 __device__ __forceinline__ float one_minus_exp_neg(float x) {
-    const float s = x * (1.0f - x * (0.5f - x * (0.16666667f - x * (0.041666668f - x * 0.0083333338f))));
-    return x < 0.125f ? s : 1.0f - __expf(-x);
+    if (x < 0.125f) return x * (1.0f - x * (0.5f - x * (0.16666667f - x * (0.041666668f - x * 0.0083333338f))));
+    return 1.0f - __expf(-x);
 }
 
 __device__ __forceinline__ float node_lerp(const float *y, NodePos p) {
