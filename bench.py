@@ -594,16 +594,20 @@ def main():
         shape = dict(hist_per_lane=h, grid_blocks=b, block_threads=t)
     elif not a.no_autotune:
         # launch shape of the work queue (hist_per_lane, workgroups, threads)
-        # from a sample of field 1's spots; kept on the context
-        f0 = case.fields[0]
-        best = V.vpmc_autotune(eng.ctx, 0, V.spot_array(f0.spots), len(f0.spots), V.scenario_array([I.Scenario()]),
-                               V.make_opts(seed=case.seed, physics=case.physics, output=V.OUT_CSR),
-                               sample_histories=int(2e7))
-        progress(f"autotune: hist_per_lane={best.hist_per_lane} grid_blocks={best.grid_blocks} "
+        # from each field's spots; kept on the context (histories per lane
+        # per field, used by the epochs of that field)
+        picks = []
+        for fi, fl in enumerate(case.fields):
+            best = V.vpmc_autotune(eng.ctx, fi, V.spot_array(fl.spots), len(fl.spots),
+                                   V.scenario_array([I.Scenario()]),
+                                   V.make_opts(seed=case.seed, physics=case.physics, output=V.OUT_CSR),
+                                   sample_histories=int(2e7))
+            picks.append(best.hist_per_lane)
+        progress(f"autotune: hist_per_lane per field={picks} grid_blocks={best.grid_blocks} "
                  f"threads={best.block_threads}")
     shape_used = dict(shape)
     if not a.shape and not a.no_autotune:
-        shape_used = dict(hist_per_lane=best.hist_per_lane, grid_blocks=best.grid_blocks,
+        shape_used = dict(hist_per_lane_per_field=picks, grid_blocks=best.grid_blocks,
                           block_threads=best.block_threads)
     n_rows = len(case.scenarios) * sum(len(fl.spots) for fl in case.fields)
     n_hist_step = len(case.scenarios) * sum(int(np.sum(fl.spots["n_histories"])) for fl in case.fields)

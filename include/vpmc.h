@@ -248,7 +248,10 @@ int vpmc_run_batched(vpmc_ctx *ctx, const int *field_ids, const vpmc_spot *const
  * shape (each timed twice, the faster time counting), keeps the one with
  * the shortest transport time per history, writes it into *best (a copy of
  * *base with hist_per_lane, grid_blocks and block_threads filled) and
- * remembers it for later runs on this context whose opts leave them at 0.
+ * remembers it for later runs on this context whose opts leave them at 0;
+ * in CSR mode hist_per_lane is also remembered for field_id, and each epoch
+ * of a batched run takes the value of the field that holds most of its rows
+ * (the best chunk size depends on the beam direction).
  * Candidates (CSR): hist_per_lane in {1,2,3,4,6,8} x workgroups of 1024 or
  * 512 threads (768 or 512
  * in straight mode), as many as fill every CU at its full wave occupancy;

@@ -196,6 +196,7 @@ struct vpmc_ctx {
     unsigned csr_flags = 0;
     // autotuned launch shapes (0 = not tuned)
     int tuned_csr_hpl = 0, tuned_csr_blocks = 0, tuned_dense_blocks = 0;
+    int tuned_csr_hpl_field[VPMC_MAX_FIELDS] = {};   // per field (CSR), 0 = not tuned
     int tuned_csr_threads = 0, tuned_dense_threads = 0;
     hipStream_t cap_stream = nullptr;   // private stream for graph capture
     // aperture surrogate
@@ -478,8 +479,13 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     const bool dev_out = (o->flags & VPMC_DEVICE_PTRS) != 0;
     const size_t cap = o->max_device_bytes;
     hipStream_t st = (hipStream_t)o->hip_stream;
-    const int hpl = o->hist_per_lane > 0 ? o->hist_per_lane : (c->tuned_csr_hpl ? c->tuned_csr_hpl : 4);
-    const unsigned long long chunk = 64ull * hpl;
+    // histories per lane: the caller's, else the one tuned for a field, else
+    // the last tuned one, else 4 (per epoch: the field with most of its rows)
+    auto field_hpl = [&](uint32_t field_id) {
+        if (o->hist_per_lane > 0) return o->hist_per_lane;
+        if (field_id < VPMC_MAX_FIELDS && c->tuned_csr_hpl_field[field_id]) return c->tuned_csr_hpl_field[field_id];
+        return c->tuned_csr_hpl ? c->tuned_csr_hpl : 4;
+    };
     int rc;
 
     // fields, polygons, spots (flattened), rows in (scenario, field, spot) order
@@ -585,13 +591,25 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
         c->slots_dirty = false;
     }
 
-    // epochs and their chunk prefixes
+    // epochs, their histories per lane and chunk prefixes
     const int E = (R + G - 1) / std::max(G, 1);
     std::vector<unsigned long long> choff;
     std::vector<size_t> ep_choff(E);
     std::vector<unsigned long long> ep_chunks(E);
+    std::vector<int> ep_hpl(E);
+    int hpl_max = 1;
     for (int e = 0; e < E; ++e) {
         const int r0 = e * G, r1 = std::min(R, r0 + G);
+        int best_f = -1, best_n = 0;
+        for (int r = r0; r < r1;) {   // rows of one field are contiguous within a scenario
+            int r2 = r;
+            while (r2 < r1 && rows[r2].field_id == rows[r].field_id) ++r2;
+            if (r2 - r > best_n) { best_n = r2 - r; best_f = (int)rows[r].field_id; }
+            r = r2;
+        }
+        ep_hpl[e] = field_hpl(best_f < 0 ? 0u : (uint32_t)best_f);
+        hpl_max = std::max(hpl_max, ep_hpl[e]);
+        const unsigned long long chunk = 64ull * (unsigned long long)ep_hpl[e];
         ep_choff[e] = choff.size();
         unsigned long long acc = 0;
         choff.push_back(0);
@@ -658,7 +676,7 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
         Q.sur.rec = (DeferRec *)c->sur_rec.ptr;
     }
     Q.rows = (const RowDev *)c->rows.ptr;
-    Q.hist_per_lane = hpl;
+    Q.hist_per_lane = hpl_max;
     Q.fields = (const FieldDev *)c->fields_tab.ptr;
     Q.poly_off = (const int *)c->poly_off.ptr;
     Q.polys = (const float2 *)c->polys.ptr;
@@ -681,7 +699,7 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
     Q.iter_cap = o->queue_cap ? (unsigned long long)o->queue_cap : kDefaultQueueCap;
     Q.flags = (unsigned int *)c->flags.ptr;
 
-    if ((rc = ensure(c, c->q_stage, queue_stage_floats(q_blocks, q_threads, hpl) * sizeof(float), cap))) return rc;
+    if ((rc = ensure(c, c->q_stage, queue_stage_floats(q_blocks, q_threads, hpl_max) * sizeof(float), cap))) return rc;
     if ((rc = ensure(c, c->q_rownext, (size_t)std::max(R, 1) * 8, cap))) return rc;
     Q.stage = (float *)c->q_stage.ptr;
     Q.refill_min = kRefillMin;
@@ -707,6 +725,7 @@ int run_csr(vpmc_ctx *c, const std::vector<BatchField> &bf, const vpmc_scenario 
         Qe.n_rows = std::min(R, (e + 1) * G) - e * G;
         Qe.chunk_off = (const unsigned long long *)c->chunk_off.ptr + ep_choff[e];
         Qe.n_chunks = ep_chunks[e];
+        Qe.hist_per_lane = ep_hpl[e];
         Qe.head = (unsigned long long *)c->heads.ptr + e;
         Qe.row_next = (unsigned long long *)c->q_rownext.ptr + Qe.row_begin;
         return Qe;
@@ -1913,6 +1932,7 @@ int vpmc_autotune(vpmc_ctx *c, int field_id, const vpmc_spot *spots, int n_spots
     pick.block_threads = cand[bi].threads;
     if (csr) {
         c->tuned_csr_hpl = pick.hist_per_lane;
+        c->tuned_csr_hpl_field[field_id] = pick.hist_per_lane;
         c->tuned_csr_blocks = pick.grid_blocks;
         c->tuned_csr_threads = pick.block_threads;
     } else {
