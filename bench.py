@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # VALU lane-operations per condensed-history step counted from the method
-# (the survey's ~300): Philox4x32-10 ~100 integer ops, uniform conversions 8,
+# (about 300): Philox4x32-10 ~100 integer ops, uniform conversions 8,
 # normal quantile 25, Box-Muller with log/sqrt/sin/cos at quarter rate 22,
 # energy-segment search and four table interpolations 35, CSDA loss 12,
 # hinge rotation 35, voxel traversal (three face distances, index update) 25,

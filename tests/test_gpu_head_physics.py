@@ -5,7 +5,7 @@ scenarios, through air, bone and brain voxels, against the FP64 oracle.
 
 The oracle's doses (4e7 VPs per case, U about 0.23 %) are stored by
 tests/golden/make_head_physics.py; the GPU runs 1.6e8 VPs with another seed.
-Bar (the benchmark spec's): >= 99 % of the non-air voxels at or above 10 % of the
+Bar: >= 99 % of the non-air voxels at or above 10 % of the
 maximum within 3 combined standard errors, gamma 1 %/1 mm on >= 99 %, mean
 dose over the high-dose region within a fixed 0.5 %.  Air voxels (HU < -900)
 are left out of every part: a nuclear event's local deposit in an air voxel
