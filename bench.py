@@ -45,6 +45,7 @@ TARGET_U = 0.005
 
 PROFILE = os.path.join(ROOT, "profiles", "queue_kernel_head_im.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2307_01416_amd", "csrc", "vpmc_kernels.hip")
+BUILD_SCRIPT = os.path.join(ROOT, "paper_2307_01416_amd", "build.py")
 
 
 OPT_PROFILE = os.path.join(ROOT, "profiles", "optimizer_head_im.md")
@@ -66,6 +67,11 @@ def measured_traffic(profile=PROFILE, src_path=KERNEL_SRC, key="traffic_bytes_pe
     m = re.search(key + r":\s*([0-9.eE+]+)", text)
     h = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
     if not m or not h or h.group(1) != src:
+        return None
+    # counters that depend on the code generation also name the build script
+    # (its compiler flags) they were taken with
+    b = re.search(r"build_sha256:\s*([0-9a-f]{64})", text)
+    if b and b.group(1) != hashlib.sha256(open(BUILD_SCRIPT, "rb").read()).hexdigest():
         return None
     return float(m.group(1))
 

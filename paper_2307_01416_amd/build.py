@@ -19,6 +19,12 @@ def build(verbose: bool = False) -> str:
            "-ffp-contract=off",
            # packed FP32 instructions stay off (see the build notes)
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           # FP32 denormals flush to zero: no transported quantity comes near
+           # 1e-38 (positions, energies, densities, table values, fixed-point
+           # scales), and the logarithms, square roots and reciprocals of the
+           # step then need no denormal range checks (same bits on the head
+           # influence matrix, ~1.3 % less transport time)
+           "-fgpu-flush-denormals-to-zero",
            "-o", LIB + ".tmp"] + [os.path.join(HERE, s) for s in SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
